@@ -1,0 +1,183 @@
+"""FP64 CPU oracle of voxel Monte Carlo photon transport -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps oracle/libmcx_oracle.so (plain C, double
+precision) with ctypes and adds the post-processing step of the paper's
+workflow (normalising the read-back tally into fluence) written out in
+numpy.  Nothing here is shared with, or imported from, the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import time
+
+import numpy as np
+
+from . import build as _build
+
+LEDGER = ["absorbed", "escaped", "detected", "timeout", "rr_gain", "rr_loss", "capped",
+          "launched"]
+COUNTS = ["launched", "escaped", "detected", "timeout", "rr_dead", "capped", "scatters",
+          "face_events", "fresnel_draws", "tir", "reflections", "rr_tests", "rr_survived",
+          "deposits", "events", "max_events", "entries"]
+DIGEST = ["reason", "nscat", "events", "voxel", "w", "t", "blocks", "det"]
+C_MM_PER_NS = 299.792458
+
+
+class _Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double),
+                ("labels", C.c_void_p), ("nmedia", C.c_int32), ("media", C.c_void_p),
+                ("src_pos", C.c_double * 3), ("src_dir", C.c_double * 3),
+                ("ndet", C.c_int32), ("det", C.c_void_p),
+                ("t0", C.c_double), ("dt", C.c_double), ("ngates", C.c_int32),
+                ("reflect", C.c_int32), ("n_out", C.c_double), ("rr_threshold", C.c_double),
+                ("rr_m", C.c_double), ("max_events", C.c_uint64)]
+
+
+class _Output(C.Structure):
+    _fields_ = [("tally", C.c_void_p), ("deposits", C.c_void_p),
+                ("ledger", C.c_double * len(LEDGER)), ("counts", C.c_int64 * len(COUNTS)),
+                ("det_rec", C.c_void_p), ("det_photon", C.c_void_p), ("det_cap", C.c_uint64),
+                ("det_total", C.c_uint64), ("det_written", C.c_uint64),
+                ("digest", C.c_void_p), ("ndigest", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        # MCX_ORACLE_LIB lets a checker point the wrapper at another build of
+        # this same source (e.g. a deliberately broken copy, to verify that
+        # the pins catch it).
+        path = os.environ.get("MCX_ORACLE_LIB") or _build.build(force=False)
+        L = C.CDLL(path)
+        L.orc_run.argtypes = [C.POINTER(_Problem), C.c_uint64, C.c_uint64, C.c_uint64, C.c_int,
+                              C.POINTER(_Output)]
+        L.orc_run.restype = C.c_int
+        L.orc_validate.argtypes = [C.POINTER(_Problem)]
+        L.orc_validate.restype = C.c_int
+        L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                        C.POINTER(C.c_uint32)]
+        L.orc_uniform.argtypes = [C.c_uint32]
+        L.orc_uniform.restype = C.c_double
+        L.orc_hg_cos.argtypes = [C.c_double, C.c_double]
+        L.orc_hg_cos.restype = C.c_double
+        L.orc_scatter_dir.argtypes = [C.POINTER(C.c_double), C.c_double, C.c_double,
+                                      C.POINTER(C.c_double)]
+        L.orc_fresnel.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_fresnel.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _pack(p):
+    """Marshal a workloads.Problem into the C struct; the arrays are kept
+    alive by the returned tuple."""
+    labels = np.ascontiguousarray(p.labels, np.uint8)
+    media = np.ascontiguousarray(p.media, np.float64)
+    det = np.ascontiguousarray(p.detectors, np.float64).reshape(-1, 4)
+    nz, ny, nx = labels.shape
+    s = _Problem()
+    s.nx, s.ny, s.nz, s.h = nx, ny, nz, p.h
+    s.labels = labels.ctypes.data
+    s.nmedia = media.shape[0]
+    s.media = media.ctypes.data
+    s.src_pos = (C.c_double * 3)(*p.src_pos)
+    s.src_dir = (C.c_double * 3)(*p.src_dir)
+    s.ndet = det.shape[0]
+    s.det = det.ctypes.data if det.size else None
+    s.t0, s.dt, s.ngates = p.t0, p.dt, p.ngates
+    s.reflect = int(bool(p.reflect))
+    s.n_out, s.rr_threshold, s.rr_m = p.n_out, p.rr_threshold, p.rr_m
+    s.max_events = int(p.max_events)
+    return s, (labels, media, det)
+
+
+def validate(p) -> int:
+    s, keep = _pack(p)
+    return lib().orc_validate(C.byref(s))
+
+
+def run(p, nphoton: int, seed: int, first: int = 0, nthreads: int | None = None,
+        deposits: bool = False, det_cap: int = 1 << 20, ndigest: int = 0) -> dict:
+    """Simulate photons [first, first+nphoton) and return the raw tally
+    (ngates, nz, ny, nx) in weight*mm, the ledger, counters, detector
+    records and optional per-photon digests."""
+    if nthreads is None:
+        nthreads = min(os.cpu_count() or 1, 16)
+    s, keep = _pack(p)
+    tally = np.zeros(p.tally_shape, np.float64)
+    dep = np.zeros(p.tally_shape, np.int64) if deposits else None
+    rec = np.zeros((det_cap, p.record_len), np.float32)
+    rec_ph = np.zeros(det_cap, np.uint64)
+    dig = np.zeros((ndigest, len(DIGEST)), np.float64) if ndigest else None
+    o = _Output()
+    o.tally = tally.ctypes.data
+    o.deposits = dep.ctypes.data if dep is not None else None
+    o.det_rec = rec.ctypes.data if det_cap else None
+    o.det_photon = rec_ph.ctypes.data if det_cap else None
+    o.det_cap = det_cap
+    o.digest = dig.ctypes.data if dig is not None else None
+    o.ndigest = ndigest
+    t = time.perf_counter()
+    rc = lib().orc_run(C.byref(s), first, nphoton, seed, nthreads, C.byref(o))
+    wall = time.perf_counter() - t
+    if rc != 0:
+        raise ValueError(f"oracle rejected the problem (code {rc})")
+    nw = int(o.det_written)
+    return {"tally": tally, "deposits": dep,
+            "ledger": dict(zip(LEDGER, list(o.ledger))),
+            "counts": dict(zip(COUNTS, list(o.counts))),
+            "records": rec[:nw].copy(), "record_photon": rec_ph[:nw].copy(),
+            "det_total": int(o.det_total), "digest": dig, "wall_s": wall,
+            "nthreads": nthreads, "nphoton": nphoton, "seed": seed, "first": first}
+
+
+# ---------------------------------------------------------------- pieces
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def uniform(word: int) -> float:
+    return lib().orc_uniform(int(word) & 0xFFFFFFFF)
+
+
+def hg_cos(g: float, u: float) -> float:
+    return lib().orc_hg_cos(g, u)
+
+
+def scatter_dir(v, cos_theta: float, u_phi: float):
+    vin = (C.c_double * 3)(*v)
+    out = (C.c_double * 3)()
+    lib().orc_scatter_dir(vin, cos_theta, u_phi, out)
+    return np.array(list(out))
+
+
+def fresnel(n1: float, n2: float, cos_i: float) -> float:
+    return lib().orc_fresnel(n1, n2, cos_i)
+
+
+# ------------------------------------------------------ post-processing
+
+def normalise(tally: np.ndarray, nphoton: int, h: float, dt: float, kind: int) -> np.ndarray:
+    """The paper's post-processing of the read-back map.  kind 0: raw tally
+    (weight*mm per cell); 1: fluence per launched photon, 1/mm^2 (tally /
+    (N h^3)); 2: fluence rate, 1/(mm^2 ns) (fluence / gate width)."""
+    if kind == 0:
+        return tally.copy()
+    phi = tally / (float(nphoton) * h ** 3)
+    return phi if kind == 1 else phi / dt
+
+
+def absorbed_fraction(tally: np.ndarray, p, nphoton: int) -> float:
+    """Sum over cells of mua(voxel) * tally, per launched photon."""
+    mua = np.asarray(p.media, np.float64)[:, 0][p.labels]
+    return float((tally.sum(axis=0) * mua).sum() / nphoton)
