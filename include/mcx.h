@@ -1,0 +1,208 @@
+/*
+ * mcx.h -- C ABI of the MI355X voxel Monte Carlo photon-transport library
+ * (libmcx.so, HIP for gfx950).
+ *
+ * What the library computes is the paper's per-thread photon simulation
+ * (Yu, Nina-Paravecino, Kaeli and Fang, "Scalable and massively parallel
+ * Monte Carlo photon transport simulations for heterogeneous computing
+ * platforms"): from domain settings, optical properties, a source,
+ * detectors and random seeds (the problem statement before Fig. 1) it
+ * produces 3-D time-resolved fluence maps and detected-photon data, then
+ * post-processes them.  The benchmark domains of the paper's Fig. 2
+ * experiments (60 mm cube, optional 15 mm sphere, pencil beam, Fresnel
+ * boundaries, atomic deposits) are expressible directly.
+ *
+ * Conventions shared by every entry point:
+ *  - Units: mm, 1/mm, ns.  Coordinates start at the grid corner; voxel
+ *    (i, j, k) covers [i, i+1) x [j, j+1) x [k, k+1) voxel edges.
+ *  - Volumes and fluence maps are x-fastest: cell = i + nx*(j + ny*k); a
+ *    fluence map is [gate][k][j][i], ngates*nx*ny*nz cells.
+ *  - Ownership: inputs are deep-copied by mcx_create; the caller may free
+ *    them on return.  Outputs go to caller-owned buffers whose capacity is
+ *    passed in; the library never frees caller memory.  Pointers named
+ *    `host_*` are host memory, pointers named `dev_*` are device memory on
+ *    the context's device.
+ *  - Errors: every call returns an mcx_status and never throws.  On error
+ *    mcx_last_error() (thread-local) describes it.  Argument validation
+ *    happens before any HIP call, so invalid input is reported without a
+ *    GPU.  A context is used by one host thread at a time.
+ *  - Random numbers: photon k of a run with seed S draws from the
+ *    counter-based Philox4x32-10 generator with key (S mod 2^32, S div 2^32)
+ *    and counter (k mod 2^32, k div 2^32, b, 0); block b = 0 launches the
+ *    photon and each scattering event or Fresnel test takes the next b.  A
+ *    run over photons [first, first+n) therefore produces exactly the same
+ *    photons however it is split or scheduled.
+ */
+#ifndef MCX_H
+#define MCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcx_ctx mcx_ctx; /* opaque; owns all of its device memory */
+
+typedef enum {
+  MCX_OK = 0,
+  MCX_EINVAL = -1,  /* invalid argument; nothing was changed */
+  MCX_ENOMEM = -2,  /* host or device allocation failed */
+  MCX_ENODEV = -3,  /* no usable HIP device */
+  MCX_EDEVICE = -4, /* a HIP call failed; the context should be destroyed */
+  MCX_ESTATE = -5,  /* call not valid in the context's current state */
+  MCX_ERANGE = -6   /* caller buffer too small */
+} mcx_status;
+
+/* Optical properties of one medium: absorption and scattering coefficients
+ * (1/mm), Henyey-Greenstein anisotropy g in [-1, 1], refractive index >= 1. */
+typedef struct {
+  float mua, mus, g, n;
+} mcx_medium;
+
+/* Voxelised domain.  labels[nx*ny*nz] holds medium indices into media[];
+ * label 0 is the outside (its media row is ignored), so nmedia counts the
+ * outside row too (2 <= nmedia <= 256). */
+typedef struct {
+  int32_t nx, ny, nz;
+  float voxel_mm;
+  const uint8_t *labels;
+  const mcx_medium *media;
+  int32_t nmedia;
+} mcx_volume;
+
+/* Pencil beam: start point (mm, inside a voxel with label != 0) and unit
+ * direction (|dir| within 1e-5 of 1). */
+typedef struct {
+  float pos[3];
+  float dir[3];
+} mcx_source;
+
+/* Disk detector: an escaping photon whose exit point lies within `radius`
+ * (mm) of `pos` is recorded (first detector in index order wins). */
+typedef struct {
+  float pos[3];
+  float radius;
+} mcx_detector;
+
+/* Time gates: ngates gates of width dt_ns starting at t0_ns; photons start at
+ * t0_ns and end at t0_ns + ngates*dt_ns. */
+typedef struct {
+  float t0_ns;
+  float dt_ns;
+  int32_t ngates;
+} mcx_gates;
+
+/* Options; fill with mcx_default_options() then override. */
+typedef struct {
+  int32_t reflect;        /* 1: Fresnel reflect/refract where n changes, incl. at escape */
+  float n_outside;        /* refractive index of label 0 and off-grid (default 1.0) */
+  float rr_threshold;     /* Russian roulette when w < this after a scattering (1e-4) */
+  float rr_m;             /* roulette: survive with probability 1/M, w *= M (10) */
+  uint64_t max_detected;  /* detected-photon record capacity (default 1<<20) */
+  uint64_t max_events;    /* per-photon segment cap, a safety stop (default 1e8) */
+  int32_t device;         /* HIP device ordinal (default 0) */
+  int32_t block_size;     /* threads per workgroup, multiple of 64; 0 = library default */
+  int32_t blocks_per_cu;  /* resident workgroups per compute unit; 0 = occupancy maximum */
+  int32_t refill_chunk;   /* photons a wave takes per refill grab; 0 = library default */
+  uint64_t ndigest;       /* per-photon digest rows kept for photons [first, first+ndigest) */
+  int32_t lds_window_cells; /* cells around the source summed per workgroup in LDS before they
+                               reach the map; 0 = library default (4096), < 0 = none */
+} mcx_options;
+
+/* Run statistics, accumulated since the last mcx_reset / mcx_run. */
+typedef struct {
+  uint64_t launched, escaped, detected, timeout, rr_dead, capped;
+  uint64_t scatters, face_events, fresnel_draws, reflections, rr_tests, rr_survived;
+  uint64_t events;          /* segments simulated (lane iterations with a live photon) */
+  uint64_t lane_slots;      /* wave iterations x 64 (events / lane_slots = lane utilisation) */
+  uint64_t flushes;         /* cell visits added to the map by a global atomic (not via LDS) */
+  uint64_t det_records;     /* records written (<= max_detected) */
+  uint64_t det_dropped;     /* detected photons without room for a record */
+  double w_launched, w_escaped, w_detected, w_timeout, w_rr_gain, w_rr_loss, w_capped;
+  double tally_sum;         /* FP64 sum of all raw tally cells (weight*mm) */
+  double absorbed_grid;     /* FP64 sum of mua(voxel)*tally, i.e. absorbed weight */
+  double kernel_ms;         /* transport kernel time of the last run (HIP events) */
+  double run_ms;            /* whole last run: clear + transport + reductions */
+  int32_t grid_blocks, block_size;
+} mcx_run_stats;
+
+/* Output kinds for mcx_fluence*. */
+enum {
+  MCX_RAW = 0,          /* weight*mm deposited per cell */
+  MCX_FLUENCE = 1,      /* per launched photon, 1/mm^2: raw / (N h^3) */
+  MCX_FLUENCE_RATE = 2  /* per launched photon, 1/(mm^2 ns): fluence / dt */
+};
+
+void mcx_default_options(mcx_options *opt);
+
+/* Validate and deep-copy the problem, pick the device, allocate the tally
+ * (one FP64 sum per cell, 8 bytes) and upload.
+ * `det` may be NULL when ndet == 0; `opt` may be NULL for defaults.
+ * Errors: MCX_EINVAL (bad argument, message says which), MCX_ENODEV,
+ * MCX_ENOMEM, MCX_EDEVICE.  *out is set only on MCX_OK. */
+mcx_status mcx_create(const mcx_volume *vol, const mcx_source *src, const mcx_detector *det,
+                      int32_t ndet, const mcx_gates *gates, const mcx_options *opt,
+                      mcx_ctx **out);
+
+/* Clear tallies, detector records, ledger and counters, run photons
+ * [0, nphoton) with `seed`, reduce, and wait.  Blocking. */
+mcx_status mcx_run(mcx_ctx *ctx, uint64_t nphoton, uint64_t seed);
+
+/* Enqueue photons [first, first+n) with `seed` on `hip_stream` (a
+ * hipStream_t; NULL = the context's own stream), accumulating into the
+ * current tallies; returns without waiting.  Runs with different seeds may
+ * be accumulated; the normalisation divides by the total photon count. */
+mcx_status mcx_run_range(mcx_ctx *ctx, uint64_t first, uint64_t n, uint64_t seed,
+                         void *hip_stream);
+
+/* Clear tallies, records, ledger and counters (enqueued on hip_stream). */
+mcx_status mcx_reset(mcx_ctx *ctx, void *hip_stream);
+
+/* Wait for all work enqueued on the context's stream. */
+mcx_status mcx_sync(mcx_ctx *ctx);
+
+/* Number of fluence cells (ngates*nx*ny*nz). */
+uint64_t mcx_ncells(const mcx_ctx *ctx);
+
+/* Normalised map (kind = MCX_RAW / MCX_FLUENCE / MCX_FLUENCE_RATE), computed
+ * on the GPU in FP64 from the FP64 tally and rounded once.  host_out
+ * must hold ncells >= mcx_ncells() values (else MCX_ERANGE).  Blocking. */
+mcx_status mcx_fluence(mcx_ctx *ctx, int32_t kind, float *host_out, uint64_t ncells);
+mcx_status mcx_fluence_f64(mcx_ctx *ctx, int32_t kind, double *host_out, uint64_t ncells);
+
+/* Same, written to device memory on hip_stream (NULL = own stream); async. */
+mcx_status mcx_fluence_device(mcx_ctx *ctx, int32_t kind, float *dev_out, uint64_t ncells,
+                              void *hip_stream);
+
+/* Detected-photon records, each 4 + (nmedia - 1) floats:
+ * {detector index, scattering count, exit weight, exit time (ns),
+ *  pathlength in medium 1, ..., pathlength in medium nmedia-1 (mm)},
+ * plus the photon index of each record in host_photon (may be NULL).
+ * Copies min(cap, records) rows; *nrec = rows copied, *ndropped = detected
+ * photons that found the record buffer full.  Record order is unspecified.
+ * Blocking. */
+mcx_status mcx_detected(mcx_ctx *ctx, float *host_rec, uint64_t *host_photon, uint64_t cap,
+                        uint64_t *nrec, uint64_t *ndropped);
+
+/* Statistics of the runs since the last reset (waits for the stream). */
+mcx_status mcx_stats(mcx_ctx *ctx, mcx_run_stats *out);
+
+/* Per-photon digests (needs opt.ndigest > 0): rows of 8 doubles
+ * {end reason (1 escape, 2 time, 3 roulette, 4 cap), scatterings,
+ *  segments, last voxel, final weight, final time, random blocks used,
+ *  detector or -1} for photons first..first+ndigest-1 of the last run.
+ * Blocking. */
+mcx_status mcx_digest(mcx_ctx *ctx, double *host_out, uint64_t nrows);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *mcx_last_error(void);
+
+/* Release the context and all its device memory.  NULL is ignored. */
+void mcx_destroy(mcx_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCX_H */

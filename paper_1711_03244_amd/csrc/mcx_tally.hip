@@ -1,0 +1,115 @@
+// Tally maintenance kernels: clearing, the FP64 reductions of the finished
+// map (total deposit and absorbed weight) and normalisation to fluence.
+// All are grid-stride loops over the FP64 cells with coalesced 8-byte
+// accesses.
+#include "mcx_internal.hpp"
+
+namespace mcx {
+namespace {
+
+__global__ void clear_kernel(double* tally, uint64_t ncells, double* ledger,
+                             unsigned long long* counts, unsigned long long* det_count,
+                             double* reduce) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < ncells;
+       i += stride)
+    tally[i] = 0.0;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < kLedgerN) ledger[threadIdx.x] = 0.0;
+    if (threadIdx.x < kCountN) counts[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) *det_count = 0ull;
+    if (threadIdx.x < 2) reduce[threadIdx.x] = 0.0;
+  }
+}
+
+__global__ void reset_counter_kernel(unsigned long long* counter) { *counter = 0ull; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// out[0] += sum over cells, out[1] += sum of mua(label) * cell: total
+// deposited weight*mm and the absorbed weight it implies.  Per-thread and
+// per-block sums in FP64.
+__global__ void __launch_bounds__(256) reduce_kernel(const double* tally, const uint8_t* labels,
+                                                     const float4* media, uint32_t nvox,
+                                                     uint64_t ncells, double* out) {
+  __shared__ double part[2][4];
+  double a = 0.0, b = 0.0;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < ncells;
+       i += stride) {
+    const double v = tally[i];
+    a += v;
+    b += static_cast<double>(media[labels[i % nvox]].x) * v;
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[0][wv] = a;
+    part[1][wv] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int k = 0; k < static_cast<int>(blockDim.x >> 6); ++k) {
+      sa += part[0][k];
+      sb += part[1][k];
+    }
+    unsafeAtomicAdd(out, sa);
+    unsafeAtomicAdd(out + 1, sb);
+  }
+}
+
+template <typename T>
+__global__ void normalise_kernel(const double* tally, uint64_t ncells, double scale, T* out) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < ncells;
+       i += stride)
+    out[i] = static_cast<T>(tally[i] * scale);
+}
+
+int grid_for(uint64_t n, int block, int cap) {
+  const uint64_t g = (n + block - 1) / block;
+  return static_cast<int>(g < static_cast<uint64_t>(cap) ? (g ? g : 1) : cap);
+}
+
+}  // namespace
+
+hipError_t launch_clear(double* tally, uint64_t ncells, double* ledger,
+                        unsigned long long* counts, unsigned long long* det_count,
+                        double* reduce, hipStream_t s) {
+  clear_kernel<<<grid_for(ncells, 256, 8192), 256, 0, s>>>(tally, ncells, ledger, counts,
+                                                           det_count, reduce);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s) {
+  reset_counter_kernel<<<1, 1, 0, s>>>(counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* tally, const uint8_t* labels, const float4* media,
+                         uint32_t nvox, int ngates, double* out2, hipStream_t s) {
+  const uint64_t n = static_cast<uint64_t>(nvox) * ngates;
+  reduce_kernel<<<grid_for(n, 256, 4096), 256, 0, s>>>(tally, labels, media, nvox, n, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalise_f32(const double* tally, uint64_t ncells, double scale, float* out,
+                                hipStream_t s) {
+  normalise_kernel<float><<<grid_for(ncells, 256, 8192), 256, 0, s>>>(tally, ncells, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalise_f64(const double* tally, uint64_t ncells, double scale, double* out,
+                                hipStream_t s) {
+  normalise_kernel<double><<<grid_for(ncells, 256, 8192), 256, 0, s>>>(tally, ncells, scale,
+                                                                       out);
+  return hipGetLastError();
+}
+
+}  // namespace mcx

@@ -1,0 +1,597 @@
+// Persistent photon-transport kernel for gfx950 (MI355X).
+//
+// One lane carries one photon at a time through the paper's per-thread
+// simulation loop (problem statement and Fig. 1 workflow): launch, free
+// path, voxel hops, absorption deposits into a time-gated fluence map,
+// Henyey-Greenstein scattering, Fresnel reflection/refraction or escape,
+// Russian roulette and detector capture.  The paper's in-workgroup dynamic
+// load balancing (a shared photon quota that threads decrement to start
+// their next photon) becomes wave-level refill: whenever lanes of a wave
+// finish, the wave hands them the next photon indices from a chunk it took
+// from a global 64-bit counter, so a wave keeps all 64 lanes busy until the
+// photon supply runs out.
+//
+// Per-lane state stays in registers; the media table, detectors, the
+// per-lane partial pathlengths and an FP64 energy ledger live in LDS.
+// Deposits made while a photon stays in one tally cell are summed in a
+// register and flushed once when it leaves the cell.  Flushes into the
+// densest cells -- a box of cells around the source, the "window" -- go to
+// an FP64 copy of those cells in LDS, summed per workgroup and added to the
+// map once when the workgroup finishes; all other flushes are one
+// non-returning FP64 atomic add on the map.  Device-memory atomics on
+// gfx950 execute at the memory side at a fixed rate per address, so the
+// window is what keeps the cells next to a pencil beam, which every photon
+// visits, from serialising the whole launch.
+#include <math.h>
+
+#include "mcx_internal.hpp"
+
+namespace mcx {
+namespace {
+
+constexpr float kInf = __builtin_huge_valf();
+
+// ----------------------------------------------------------- random numbers
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds; each
+// multiplies counter words 0 and 2 by the round constants and rebuilds the
+// counter from the high halves xored with the other words and the key and
+// from the low halves; the key advances by the Weyl constants per round.
+struct Words {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+    c1 = static_cast<uint32_t>(p1);
+    c3 = static_cast<uint32_t>(p0);
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return {c0, c1, c2, c3};
+}
+
+// Odd multiple of 2^-24 in (0, 1); exact in FP32.
+__device__ __forceinline__ float unit_open(uint32_t x) {
+  return static_cast<float>((x >> 8) | 1u) * 0x1p-24f;
+}
+
+// ------------------------------------------------------------- wave helpers
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), lane);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), lane);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_count(bool p) {
+  return static_cast<uint32_t>(__popcll(__ballot(p)));
+}
+
+// ------------------------------------------------------------------ physics
+// Distance along the direction to the face a velocity component points at;
+// `face` is the local coordinate gap, `r` = h/|v| (only used when v != 0).
+__device__ __forceinline__ float face_dist(float f, float v, float r) {
+  const float gap = fmaxf(v > 0.f ? 1.f - f : f, 0.f);
+  return v != 0.f ? gap * r : kInf;
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ float inv_speed(float h, float v) {
+  return v != 0.f ? h * rcp(fabsf(v)) : kInf;
+}
+
+// Cosine of the Henyey-Greenstein deflection from its inverse CDF, written
+// over a common denominator so that g = 0 needs no special case:
+// cos = (2u(1+g^2)(1-g+gu) - (1-g)^2) / (1-g+2gu)^2.
+// hg = (1-g, 2g, 2(1+g^2), (1-g)^2).
+__device__ __forceinline__ float hg_cos(float g, float4 hg, float u) {
+  const float a = fmaf(hg.y, u, hg.x);
+  const float num = hg.z * u * fmaf(g, u, hg.x) - hg.w;
+  const float c = num * rcp(a * a);
+  return fminf(1.f, fmaxf(-1.f, c));
+}
+
+// Turn v by polar cosine ct and azimuth 2*pi*u, the azimuth measured in the
+// branchless orthonormal basis of Duff et al., JCGT 6(1) 2017, then
+// renormalise.
+__device__ __forceinline__ void scatter_dir(float& vx, float& vy, float& vz, float ct, float u) {
+  const float st = sqrtf((1.f - ct) * (1.f + ct));
+  float sp, cp;
+  sincospif(2.f * u, &sp, &cp);
+  const float sg = copysignf(1.f, vz);
+  const float a = -rcp(sg + vz);
+  const float b = vx * vy * a;
+  const float t1x = 1.f + sg * vx * vx * a, t1y = sg * b, t1z = -sg * vx;
+  const float t2x = b, t2y = sg + vy * vy * a, t2z = -vy;
+  const float nx = ct * vx + st * (cp * t1x + sp * t2x);
+  const float ny = ct * vy + st * (cp * t1y + sp * t2y);
+  const float nz = ct * vz + st * (cp * t1z + sp * t2z);
+  const float inv = __builtin_amdgcn_rsqf(nx * nx + ny * ny + nz * nz);
+  vx = nx * inv;
+  vy = ny * inv;
+  vz = nz * inv;
+}
+
+// Unpolarised Fresnel reflectance (mean of the s and p terms).
+__device__ __forceinline__ float fresnel_r(float n1, float n2, float ci, float ct) {
+  const float rs = (n1 * ci - n2 * ct) * rcp(n1 * ci + n2 * ct);
+  const float rp = (n1 * ct - n2 * ci) * rcp(n1 * ct + n2 * ci);
+  return 0.5f * (rs * rs + rp * rp);
+}
+
+// Add a finished cell visit to the map: into the workgroup's LDS window
+// when the cell lies in it, else one FP64 atomic add (no return value, so
+// the wave does not wait for it).
+__device__ __forceinline__ void deposit(double* tally, double* s_win, uint32_t cell, int slot,
+                                       float v) {
+  if (slot >= 0)
+    atomicAdd(s_win + slot, static_cast<double>(v));
+  else
+    unsafeAtomicAdd(tally + cell, static_cast<double>(v));
+}
+
+enum : int { kEvTime = 0, kEvScat = 1, kEvCross = 2 };
+enum : int { kAlive = 0, kEndEscape = 1, kEndTime = 2, kEndRoulette = 3, kEndCapped = 4 };
+
+template <bool kDetect, bool kDiag>
+__global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P) {
+  extern __shared__ float4 s_tab[];
+  __shared__ double s_led[kLedgerN];
+  __shared__ unsigned long long s_cnt[kCountN];
+
+  const int ntab = 3 * P.nmedia + P.ndet;
+  const int wcells = P.wnx * P.wny * P.wnz * P.wng;
+  double* s_win = reinterpret_cast<double*>(s_tab + ntab);
+  for (int i = threadIdx.x; i < ntab; i += blockDim.x) s_tab[i] = P.media[i];
+  for (int i = threadIdx.x; i < wcells; i += blockDim.x) s_win[i] = 0.0;
+  if (threadIdx.x < kLedgerN) s_led[threadIdx.x] = 0.0;
+  if (threadIdx.x < kCountN) s_cnt[threadIdx.x] = 0ull;
+  __syncthreads();
+  const float4* s_med = s_tab;                 // (mua, mus, g, n)
+  const float4* s_der = s_tab + P.nmedia;      // (1/mus, n/c, c/n, 1/mua)
+  const float4* s_hg = s_tab + 2 * P.nmedia;   // HG constants
+  const float4* s_det = s_tab + 3 * P.nmedia;  // (x, y, z, r^2)
+  float* s_len = reinterpret_cast<float*>(s_win + wcells) + threadIdx.x;  // [m * blockDim]
+  const uint32_t bdim = blockDim.x;
+
+  const uint32_t lane = __lane_id();
+  const uint32_t stride_y = static_cast<uint32_t>(P.nx);
+  const uint32_t stride_z = static_cast<uint32_t>(P.nx) * static_cast<uint32_t>(P.ny);
+  const uint32_t src_lin = P.src_ix + stride_y * P.src_iy + stride_z * P.src_iz;
+  const float src_rx = inv_speed(P.h, P.src_vx), src_ry = inv_speed(P.h, P.src_vy),
+              src_rz = inv_speed(P.h, P.src_vz);
+
+  // photon state
+  bool alive = false;
+  int ix = 0, iy = 0, iz = 0, m = 0;
+  uint32_t lin = 0;
+  float fx = 0.f, fy = 0.f, fz = 0.f, vx = 0.f, vy = 0.f, vz = 1.f;
+  float rx = kInf, ry = kInf, rz = kInf;
+  float w = 0.f, t = 0.f, s = 0.f;
+  uint32_t klo = 0, khi = 0, blk = 0, nev = 0, nscat = 0;
+  uint32_t acc_cell = 0xffffffffu;
+  int acc_slot = -1;
+  float acc = 0.f;
+
+  // wave-uniform refill pool: photon offsets [pool_next, pool_end) from P.first
+  uint64_t pool_next = 0, pool_end = 0;
+  bool dry = false;
+  // per-wave counts of frequent events (scalar registers); rare events are
+  // counted in LDS by the lanes they happen to
+  uint32_t c_launch = 0, c_scat = 0, c_face = 0, c_fres = 0, c_ev = 0, c_slots = 0, c_flush = 0;
+
+  for (;;) {
+    // ---------------------------------------------------------------- refill
+    bool launched = false;
+    const uint64_t dead = __ballot(!alive);
+    if (dead != 0 && !dry) {
+      const uint64_t need = static_cast<uint64_t>(__popcll(dead));
+      const uint64_t rem = pool_end - pool_next;
+      uint64_t nbase = 0;
+      bool grabbed = false;
+      if (rem < need) {
+        const int leader = __ffsll(static_cast<long long>(dead)) - 1;
+        unsigned long long got = 0;
+        if (static_cast<int>(lane) == leader)
+          got = atomicAdd(P.photon_counter, static_cast<unsigned long long>(P.chunk));
+        nbase = readlane_u64(got, leader);
+        grabbed = true;
+        if (nbase >= P.nphoton) dry = true;
+      }
+      if (!alive) {
+        const uint64_t rank = rank_below(dead);
+        uint64_t idx = 0;
+        bool ok = false;
+        if (rank < rem) {
+          idx = pool_next + rank;
+          ok = true;
+        } else if (grabbed && !dry) {
+          idx = nbase + (rank - rem);
+          ok = idx < P.nphoton;
+        }
+        if (ok) {
+          const uint64_t k = P.first + idx;
+          klo = static_cast<uint32_t>(k);
+          khi = static_cast<uint32_t>(k >> 32);
+          const Words r = philox4x32_10(klo, khi, 0u, 0u, P.key0, P.key1);
+          s = -logf(unit_open(r.x));
+          blk = 1;
+          ix = P.src_ix;
+          iy = P.src_iy;
+          iz = P.src_iz;
+          lin = src_lin;
+          m = P.src_label;
+          fx = P.src_fx;
+          fy = P.src_fy;
+          fz = P.src_fz;
+          vx = P.src_vx;
+          vy = P.src_vy;
+          vz = P.src_vz;
+          rx = src_rx;
+          ry = src_ry;
+          rz = src_rz;
+          w = 1.f;
+          t = P.t0;
+          nev = 0;
+          nscat = 0;
+          acc_cell = 0xffffffffu;
+          acc_slot = -1;
+          acc = 0.f;
+          if constexpr (kDetect) {
+            for (int mm = 0; mm < P.nmedia; ++mm) s_len[mm * bdim] = 0.f;
+          }
+          alive = true;
+          launched = true;
+        }
+      }
+      if (grabbed) {
+        if (dry) {
+          pool_next = pool_end;
+        } else {
+          const uint64_t end = nbase + P.chunk < P.nphoton ? nbase + P.chunk : P.nphoton;
+          const uint64_t nxt = nbase + (need - rem);
+          pool_next = nxt < end ? nxt : end;
+          pool_end = end;
+        }
+      } else {
+        pool_next += need;
+      }
+    }
+    c_launch += static_cast<uint32_t>(wave_count(launched));
+    if (__ballot(alive) == 0) break;
+    c_slots += 64;
+    c_ev += static_cast<uint32_t>(wave_count(alive));
+
+    // ----------------------------------------------------------------- event
+    int end = kAlive;
+    int det_hit = -1;
+    bool f_scat = false, f_face = false, f_fres = false, f_flush = false;
+    if (alive) {
+      if (nev >= P.max_events) {
+        end = kEndCapped;
+      } else {
+        ++nev;
+        const float4 md = s_med[m];  // mua, mus, g, n
+        const float4 dd = s_der[m];  // 1/mus, n/c, c/n, 1/mua
+        const float ds = md.y > 0.f ? s * dd.x : kInf;
+        const float dx = face_dist(fx, vx, rx), dy = face_dist(fy, vy, ry),
+                    dz = face_dist(fz, vz, rz);
+        int ax;
+        float dv;
+        if (dx <= dy && dx <= dz) {
+          ax = 0;
+          dv = dx;
+        } else if (dy <= dz) {
+          ax = 1;
+          dv = dy;
+        } else {
+          ax = 2;
+          dv = dz;
+        }
+        const float dtime = fmaxf((P.t_end - t) * dd.z, 0.f);
+        int ev;
+        float l;
+        if (dtime < fminf(ds, dv)) {
+          ev = kEvTime;
+          l = dtime;
+        } else if (ds <= dv) {
+          ev = kEvScat;
+          l = ds;
+        } else {
+          ev = kEvCross;
+          l = dv;
+        }
+
+        // absorption along the segment, booked at the segment-start gate
+        int gate = static_cast<int>(floorf((t - P.t0) * P.inv_dt));
+        gate = min(max(gate, 0), P.ngates - 1);
+        const uint32_t cell = static_cast<uint32_t>(gate) * P.nvox + lin;
+        const float q = -expm1f(-md.x * l);  // 1 - exp(-mua l)
+        const float dep = md.x > 0.f ? w * q * dd.w : w * l;
+        if (cell != acc_cell) {
+          if (acc_cell != 0xffffffffu && acc != 0.f) {
+            deposit(P.tally, s_win, acc_cell, acc_slot, acc);
+            f_flush = acc_slot < 0;
+          }
+          const uint32_t ux = static_cast<uint32_t>(ix - P.wx0);
+          const uint32_t uy = static_cast<uint32_t>(iy - P.wy0);
+          const uint32_t uz = static_cast<uint32_t>(iz - P.wz0);
+          const bool inwin = ux < static_cast<uint32_t>(P.wnx) &&
+                             uy < static_cast<uint32_t>(P.wny) &&
+                             uz < static_cast<uint32_t>(P.wnz) && gate < P.wng;
+          acc_slot = inwin ? static_cast<int>(((gate * P.wnz + uz) * P.wny + uy) * P.wnx + ux) : -1;
+          acc_cell = cell;
+          acc = dep;
+        } else {
+          acc += dep;
+        }
+        w = w - w * q;
+
+        // move
+        const float lh = l * P.inv_h;
+        fx = __builtin_amdgcn_fmed3f(fmaf(lh, vx, fx), 0.f, 1.f);
+        fy = __builtin_amdgcn_fmed3f(fmaf(lh, vy, fy), 0.f, 1.f);
+        fz = __builtin_amdgcn_fmed3f(fmaf(lh, vz, fz), 0.f, 1.f);
+        t = fmaf(l, dd.y, t);
+        s = ev == kEvScat ? 0.f : fmaxf(fmaf(-md.y, l, s), 0.f);
+        if constexpr (kDetect) s_len[m * bdim] += l;
+
+        if (ev == kEvTime) {
+          end = kEndTime;
+        } else {
+          // crossing set-up: neighbour voxel, its medium, Fresnel terms
+          bool need_rng = ev == kEvScat;
+          bool tir = false, fres = false;
+          float va = 0.f, vb1 = 0.f, vb2 = 0.f, eta = 1.f, cos_t = 0.f, refl_p = 0.f;
+          int step = 0, m2 = 0;
+          uint32_t qlin = 0;
+          if (ev == kEvCross) {
+            va = ax == 0 ? vx : (ax == 1 ? vy : vz);
+            vb1 = ax == 0 ? vy : (ax == 1 ? vz : vx);
+            vb2 = ax == 0 ? vz : (ax == 1 ? vx : vy);
+            step = va > 0.f ? 1 : -1;
+            const int qa = (ax == 0 ? ix : (ax == 1 ? iy : iz)) + step;
+            const int na = ax == 0 ? P.nx : (ax == 1 ? P.ny : P.nz);
+            const uint32_t stride = ax == 0 ? 1u : (ax == 1 ? stride_y : stride_z);
+            qlin = step > 0 ? lin + stride : lin - stride;
+            m2 = (qa >= 0 && qa < na) ? P.labels[qlin] : 0;
+            const float n1 = md.w;
+            const float n2 = m2 != 0 ? s_med[m2].w : P.n_out;
+            fres = P.reflect && n2 != n1;
+            if (fres) {
+              eta = n1 * rcp(n2);
+              const float st2 = eta * eta * (vb1 * vb1 + vb2 * vb2);
+              if (st2 >= 1.f) {
+                tir = true;
+              } else {
+                cos_t = sqrtf(1.f - st2);
+                refl_p = fresnel_r(n1, n2, fabsf(va), cos_t);
+                need_rng = true;
+              }
+            }
+          }
+          Words r = {0u, 0u, 0u, 0u};
+          if (need_rng) {
+            r = philox4x32_10(klo, khi, blk, 0u, P.key0, P.key1);
+            ++blk;
+          }
+
+          if (ev == kEvScat) {
+            f_scat = true;
+            ++nscat;
+            const float ct = hg_cos(md.z, s_hg[m], unit_open(r.x));
+            scatter_dir(vx, vy, vz, ct, unit_open(r.y));
+            rx = inv_speed(P.h, vx);
+            ry = inv_speed(P.h, vy);
+            rz = inv_speed(P.h, vz);
+            s = -logf(unit_open(r.z));
+            if (w < P.rr_threshold) {
+              atomicAdd(&s_cnt[kCntRrTests], 1ull);
+              if (unit_open(r.w) < P.rr_p) {
+                atomicAdd(&s_cnt[kCntRrSurvived], 1ull);
+                atomicAdd(&s_led[kLedRrGain], static_cast<double>((P.rr_m - 1.f) * w));
+                w *= P.rr_m;
+              } else {
+                end = kEndRoulette;
+              }
+            }
+          } else {
+            // CROSS on axis ax: the photon sits on the face
+            f_face = true;
+            f_fres = need_rng;
+            const float face = step > 0 ? 1.f : 0.f;
+            if (ax == 0) fx = face; else if (ax == 1) fy = face; else fz = face;
+            const bool reflect = tir || (need_rng && unit_open(r.x) < refl_p);
+            if (reflect) {
+              atomicAdd(&s_cnt[kCntReflections], 1ull);
+              if (ax == 0) vx = -vx; else if (ax == 1) vy = -vy; else vz = -vz;
+            } else if (m2 == 0) {
+              end = kEndEscape;
+            } else {
+              if (fres) {
+                // refraction: tangential components scale by n1/n2
+                const float na_ = static_cast<float>(step) * cos_t;
+                if (ax == 0) {
+                  vy *= eta; vz *= eta; vx = na_;
+                } else if (ax == 1) {
+                  vz *= eta; vx *= eta; vy = na_;
+                } else {
+                  vx *= eta; vy *= eta; vz = na_;
+                }
+                rx = inv_speed(P.h, vx);
+                ry = inv_speed(P.h, vy);
+                rz = inv_speed(P.h, vz);
+              }
+              const float enter = step > 0 ? 0.f : 1.f;
+              if (ax == 0) {
+                ix += step; fx = enter;
+              } else if (ax == 1) {
+                iy += step; fy = enter;
+              } else {
+                iz += step; fz = enter;
+              }
+              lin = qlin;
+              m = m2;
+            }
+          }
+        }
+      }
+
+      if (end != kAlive) {
+        if (acc != 0.f && acc_cell != 0xffffffffu) {
+          deposit(P.tally, s_win, acc_cell, acc_slot, acc);
+          f_flush = acc_slot < 0;
+        }
+        const double wd = static_cast<double>(w);
+        const int end_slot = end == kEndEscape ? kCntEscaped
+                             : end == kEndTime ? kCntTimeout
+                             : end == kEndRoulette ? kCntRrDead : kCntCapped;
+        atomicAdd(&s_cnt[end_slot], 1ull);
+        if (end == kEndEscape) {
+          atomicAdd(&s_led[kLedEscaped], wd);
+          if constexpr (kDetect) {
+            const float px = P.h * (static_cast<float>(ix) + fx);
+            const float py = P.h * (static_cast<float>(iy) + fy);
+            const float pz = P.h * (static_cast<float>(iz) + fz);
+            for (int d = 0; d < P.ndet; ++d) {
+              const float4 D = s_det[d];
+              const float ex = px - D.x, ey = py - D.y, ez = pz - D.z;
+              if (ex * ex + ey * ey + ez * ez <= D.w) {
+                det_hit = d;
+                break;
+              }
+            }
+            if (det_hit >= 0) {
+              atomicAdd(&s_cnt[kCntDetected], 1ull);
+              atomicAdd(&s_led[kLedDetected], wd);
+              const unsigned long long slot = atomicAdd(P.det_count, 1ull);
+              if (slot < P.det_cap) {
+                float* rec = P.det_rec + slot * static_cast<uint64_t>(P.rec_len);
+                rec[0] = static_cast<float>(det_hit);
+                rec[1] = static_cast<float>(nscat);
+                rec[2] = w;
+                rec[3] = t;
+                for (int mm = 1; mm < P.nmedia; ++mm) rec[3 + mm] = s_len[mm * bdim];
+                P.det_photon[slot] = (static_cast<uint64_t>(khi) << 32) | klo;
+              }
+            }
+          }
+        } else if (end == kEndTime) {
+          atomicAdd(&s_led[kLedTimeout], wd);
+        } else if (end == kEndRoulette) {
+          atomicAdd(&s_led[kLedRrLoss], wd);
+        } else {
+          atomicAdd(&s_led[kLedCapped], wd);
+        }
+        if constexpr (kDiag) {
+          const uint64_t k = (static_cast<uint64_t>(khi) << 32) | klo;
+          if (k >= P.first && k - P.first < P.ndigest) {
+            double* row = P.digest + (k - P.first) * kDigestN;
+            row[0] = end;
+            row[1] = nscat;
+            row[2] = nev;
+            row[3] = lin;
+            row[4] = w;
+            row[5] = t;
+            row[6] = blk;
+            row[7] = det_hit;
+          }
+        }
+        alive = false;
+      }
+    }
+
+    c_scat += wave_count(f_scat);
+    c_face += wave_count(f_face);
+    c_fres += wave_count(f_fres);
+    c_flush += wave_count(f_flush);
+  }
+
+  if (lane == 0) {
+    atomicAdd(&s_cnt[kCntLaunched], static_cast<unsigned long long>(c_launch));
+    atomicAdd(&s_cnt[kCntScatters], static_cast<unsigned long long>(c_scat));
+    atomicAdd(&s_cnt[kCntFaceEvents], static_cast<unsigned long long>(c_face));
+    atomicAdd(&s_cnt[kCntFresnel], static_cast<unsigned long long>(c_fres));
+    atomicAdd(&s_cnt[kCntEvents], static_cast<unsigned long long>(c_ev));
+    atomicAdd(&s_cnt[kCntLaneSlots], static_cast<unsigned long long>(c_slots));
+    atomicAdd(&s_cnt[kCntFlushes], static_cast<unsigned long long>(c_flush));
+  }
+  __syncthreads();
+  // add the workgroup's window sums to the map
+  for (int i = threadIdx.x; i < wcells; i += blockDim.x) {
+    const double v = s_win[i];
+    if (v != 0.0) {
+      int r = i;
+      const int x = r % P.wnx;
+      r /= P.wnx;
+      const int y = r % P.wny;
+      r /= P.wny;
+      const int z = r % P.wnz;
+      const int g = r / P.wnz;
+      const uint32_t cell = static_cast<uint32_t>(g) * P.nvox + (P.wx0 + x) +
+                            stride_y * (P.wy0 + y) + stride_z * (P.wz0 + z);
+      unsafeAtomicAdd(P.tally + cell, v);
+    }
+  }
+  if (threadIdx.x < kLedgerN) unsafeAtomicAdd(P.ledger + threadIdx.x, s_led[threadIdx.x]);
+  if (threadIdx.x < kCountN) atomicAdd(P.counts + threadIdx.x, s_cnt[threadIdx.x]);
+}
+
+}  // namespace
+
+size_t transport_smem_bytes(int nmedia, int ndet, int block, bool detect, int window_cells) {
+  size_t b = static_cast<size_t>(3 * nmedia + ndet) * sizeof(float4);
+  b += static_cast<size_t>(window_cells) * sizeof(double);
+  if (detect) b += static_cast<size_t>(nmedia) * block * sizeof(float);
+  return b;
+}
+
+template <bool D, bool G>
+static const void* kernel_ptr() {
+  return reinterpret_cast<const void*>(&transport_kernel<D, G>);
+}
+
+static const void* pick(bool detect, bool diag) {
+  if (detect) return diag ? kernel_ptr<true, true>() : kernel_ptr<true, false>();
+  return diag ? kernel_ptr<false, true>() : kernel_ptr<false, false>();
+}
+
+hipError_t transport_occupancy(int* blocks_per_cu, int block, size_t smem, bool detect,
+                               bool diag) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pick(detect, diag), block,
+                                                      smem);
+}
+
+hipError_t launch_transport(const TransportParams& p, int grid, int block, hipStream_t st,
+                            bool detect, bool diag) {
+  const size_t smem =
+      transport_smem_bytes(p.nmedia, p.ndet, block, detect, p.wnx * p.wny * p.wnz * p.wng);
+  if (detect) {
+    if (diag)
+      transport_kernel<true, true><<<grid, block, smem, st>>>(p);
+    else
+      transport_kernel<true, false><<<grid, block, smem, st>>>(p);
+  } else {
+    if (diag)
+      transport_kernel<false, true><<<grid, block, smem, st>>>(p);
+    else
+      transport_kernel<false, false><<<grid, block, smem, st>>>(p);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mcx

@@ -1,0 +1,201 @@
+// Microbenchmarks behind the transport kernel's design choices on gfx950:
+//  - global atomic add throughput: FP32 with and without a returned value,
+//    FP64 without a return, on distinct addresses spread over working sets
+//    that fit L2 (4 MB per XCD), the MALL, or only HBM, and on a few hot
+//    addresses shared by every wave;
+//  - FP32 VALU issue rate (dependent FMA chains) and the Philox block rate,
+//    to anchor the ALU roofline of the transport kernel.
+// Prints one JSON object per measurement.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define CHECK(x)                                                                    \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) {                                                         \
+      fprintf(stderr, "%s:%d %s: %s\n", __FILE__, __LINE__, #x, hipGetErrorString(e_)); \
+      exit(1);                                                                      \
+    }                                                                               \
+  } while (0)
+
+__device__ __forceinline__ uint32_t mix(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Each thread performs `iters` atomics; the index is a hash of (thread,
+// iteration) masked to `mask` (a power of two minus one), or fixed among
+// `hot` addresses when hot > 0.
+template <int kMode>
+__global__ void __launch_bounds__(256) atomic_kernel(float* f32, double* f64, uint32_t mask,
+                                                     uint32_t hot, int iters, float* sink) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  float acc = 0.f;
+  for (int i = 0; i < iters; ++i) {
+    const uint32_t h = mix(tid * 0x9E3779B9u + i);
+    const uint32_t idx = hot ? (h % hot) * 32u : (h & mask);
+    const float v = 1.0f + (h & 0xff) * 1e-3f;
+    if constexpr (kMode == 0) {         // FP32, no return
+      unsafeAtomicAdd(f32 + idx, v);
+    } else if constexpr (kMode == 1) {  // FP32, returned value used
+      acc += unsafeAtomicAdd(f32 + idx, v);
+    } else {                            // FP64, no return
+      unsafeAtomicAdd(f64 + idx, static_cast<double>(v));
+    }
+  }
+  if (kMode == 1 && acc == -1.f) sink[0] = acc;
+}
+
+// Independent FMA chains: 8 per thread, `iters` rounds.
+__global__ void __launch_bounds__(256) fma_kernel(float* out, int iters, float a, float b) {
+  float x[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = threadIdx.x * 1e-3f + k;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = fmaf(x[k], a, b);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += x[k];
+  if (s == -1.f) out[0] = s;
+}
+
+__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                             uint32_t& c3, uint32_t k0, uint32_t k1) {
+  const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+  const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+  const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+  const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+  c1 = static_cast<uint32_t>(p1);
+  c3 = static_cast<uint32_t>(p0);
+  c0 = n0;
+  c2 = n2;
+}
+
+__global__ void __launch_bounds__(256) philox_kernel(uint32_t* out, int iters, uint32_t key0,
+                                                     uint32_t key1) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t acc = 0;
+  for (int i = 0; i < iters; ++i) {
+    uint32_t c0 = tid, c1 = 0, c2 = static_cast<uint32_t>(i), c3 = 0, k0 = key0, k1 = key1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+      philox_round(c0, c1, c2, c3, k0, k1);
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    acc ^= c0 ^ c1 ^ c2 ^ c3;
+  }
+  if (acc == 0x12345678u) out[0] = acc;
+}
+
+static float time_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  CHECK(hipEventElapsedTime(&ms, a, b));
+  return ms;
+}
+
+int main(int argc, char** argv) {
+  int cus = 0;
+  CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+  const int block = 256, per_cu = 8;
+  const int grid = cus * per_cu;
+  const uint64_t threads = static_cast<uint64_t>(grid) * block;
+  const int iters = 64;
+  const size_t max_bytes = 1ull << 30;  // 1 GiB of FP64 cells at most
+  float* f32 = nullptr;
+  double* f64 = nullptr;
+  float* sink = nullptr;
+  CHECK(hipMalloc(&f32, max_bytes));
+  CHECK(hipMalloc(&f64, max_bytes));
+  CHECK(hipMalloc(&sink, 64));
+  CHECK(hipMemset(f32, 0, max_bytes));
+  CHECK(hipMemset(f64, 0, max_bytes));
+  hipEvent_t e0, e1;
+  CHECK(hipEventCreate(&e0));
+  CHECK(hipEventCreate(&e1));
+
+  const char* modes[3] = {"f32_noret", "f32_ret", "f64_noret"};
+  // working sets in bytes of FP64 cells (FP32 uses half the bytes, same count)
+  const uint64_t sets[] = {1ull << 20, 2ull << 20, 64ull << 20, 512ull << 20};
+  for (int mode = 0; mode < 3; ++mode) {
+    for (uint64_t ws : sets) {
+      const uint32_t cells = static_cast<uint32_t>(ws / 8);
+      const uint32_t mask = cells - 1;
+      for (int rep = 0; rep < 2; ++rep) {
+        CHECK(hipEventRecord(e0));
+        if (mode == 0) atomic_kernel<0><<<grid, block>>>(f32, f64, mask, 0, iters, sink);
+        if (mode == 1) atomic_kernel<1><<<grid, block>>>(f32, f64, mask, 0, iters, sink);
+        if (mode == 2) atomic_kernel<2><<<grid, block>>>(f32, f64, mask, 0, iters, sink);
+        CHECK(hipEventRecord(e1));
+        CHECK(hipEventSynchronize(e1));
+        if (rep == 1) {
+          const double ms = time_ms(e0, e1);
+          printf("{\"bench\": \"atomic\", \"mode\": \"%s\", \"cells\": %u, \"working_set_MB\": %.1f, "
+                 "\"atomics_per_s\": %.4g, \"ms\": %.3f}\n",
+                 modes[mode], cells, cells * (mode == 2 ? 8.0 : 4.0) / 1048576.0,
+                 threads * iters / (ms * 1e-3), ms);
+        }
+      }
+    }
+    for (uint32_t hot : {1u, 8u, 64u, 512u}) {
+      for (int rep = 0; rep < 2; ++rep) {
+        const int it = hot < 64 ? 4 : iters;
+        CHECK(hipEventRecord(e0));
+        if (mode == 0) atomic_kernel<0><<<grid, block>>>(f32, f64, 0, hot, it, sink);
+        if (mode == 1) atomic_kernel<1><<<grid, block>>>(f32, f64, 0, hot, it, sink);
+        if (mode == 2) atomic_kernel<2><<<grid, block>>>(f32, f64, 0, hot, it, sink);
+        CHECK(hipEventRecord(e1));
+        CHECK(hipEventSynchronize(e1));
+        if (rep == 1) {
+          const double ms = time_ms(e0, e1);
+          printf("{\"bench\": \"atomic_hot\", \"mode\": \"%s\", \"hot_addresses\": %u, "
+                 "\"atomics_per_s\": %.4g, \"ms\": %.3f}\n",
+                 modes[mode], hot, threads * it / (ms * 1e-3), ms);
+        }
+      }
+    }
+  }
+
+  {
+    const int it = 4096;
+    for (int rep = 0; rep < 2; ++rep) {
+      CHECK(hipEventRecord(e0));
+      fma_kernel<<<grid, block>>>(sink, it, 0.999f, 0.001f);
+      CHECK(hipEventRecord(e1));
+      CHECK(hipEventSynchronize(e1));
+      if (rep == 1) {
+        const double ms = time_ms(e0, e1);
+        const double lane_ops = static_cast<double>(threads) * it * 8;
+        printf("{\"bench\": \"fma_f32\", \"lane_fma_per_s\": %.4g, \"tflops\": %.2f, \"ms\": %.3f}\n",
+               lane_ops / (ms * 1e-3), 2 * lane_ops / (ms * 1e-3) / 1e12, ms);
+      }
+    }
+  }
+  {
+    const int it = 256;
+    for (int rep = 0; rep < 2; ++rep) {
+      CHECK(hipEventRecord(e0));
+      philox_kernel<<<grid, block>>>(reinterpret_cast<uint32_t*>(sink), it, 1u, 0u);
+      CHECK(hipEventRecord(e1));
+      CHECK(hipEventSynchronize(e1));
+      if (rep == 1) {
+        const double ms = time_ms(e0, e1);
+        printf("{\"bench\": \"philox4x32_10\", \"blocks_per_s\": %.4g, \"ms\": %.3f}\n",
+               static_cast<double>(threads) * it / (ms * 1e-3), ms);
+      }
+    }
+  }
+  CHECK(hipFree(f32));
+  CHECK(hipFree(f64));
+  CHECK(hipFree(sink));
+  return 0;
+}

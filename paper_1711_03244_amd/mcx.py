@@ -1,0 +1,317 @@
+"""ctypes binding of libmcx.so, the C ABI declared in include/mcx.h.
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library.  The functions keep the C names; :class:`Simulation` bundles them
+for a :class:`paper_1711_03244_amd.workloads.Problem`.  PyTorch is used only
+when the caller hands over device tensors or streams.
+
+Importing this module does not load the library; the first call does, and it
+raises if ``libmcx.so`` has not been built (``python -m
+paper_1711_03244_amd.build``).  There is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcx.so")
+
+MCX_OK, MCX_EINVAL, MCX_ENOMEM, MCX_ENODEV, MCX_EDEVICE, MCX_ESTATE, MCX_ERANGE = (
+    0, -1, -2, -3, -4, -5, -6)
+MCX_RAW, MCX_FLUENCE, MCX_FLUENCE_RATE = 0, 1, 2
+STATUS_NAMES = {0: "MCX_OK", -1: "MCX_EINVAL", -2: "MCX_ENOMEM", -3: "MCX_ENODEV",
+                -4: "MCX_EDEVICE", -5: "MCX_ESTATE", -6: "MCX_ERANGE"}
+DIGEST = ["reason", "nscat", "events", "voxel", "w", "t", "blocks", "det"]
+
+EXPORTS = ["mcx_default_options", "mcx_create", "mcx_run", "mcx_run_range", "mcx_reset",
+           "mcx_sync", "mcx_ncells", "mcx_fluence", "mcx_fluence_f64", "mcx_fluence_device",
+           "mcx_detected", "mcx_stats", "mcx_digest", "mcx_last_error", "mcx_destroy"]
+
+
+class McxError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class mcx_medium(C.Structure):
+    _fields_ = [("mua", C.c_float), ("mus", C.c_float), ("g", C.c_float), ("n", C.c_float)]
+
+
+class mcx_volume(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("voxel_mm", C.c_float),
+                ("labels", C.c_void_p), ("media", C.c_void_p), ("nmedia", C.c_int32)]
+
+
+class mcx_source(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("dir", C.c_float * 3)]
+
+
+class mcx_detector(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("radius", C.c_float)]
+
+
+class mcx_gates(C.Structure):
+    _fields_ = [("t0_ns", C.c_float), ("dt_ns", C.c_float), ("ngates", C.c_int32)]
+
+
+class mcx_options(C.Structure):
+    _fields_ = [("reflect", C.c_int32), ("n_outside", C.c_float), ("rr_threshold", C.c_float),
+                ("rr_m", C.c_float), ("max_detected", C.c_uint64), ("max_events", C.c_uint64),
+                ("device", C.c_int32), ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("refill_chunk", C.c_int32), ("ndigest", C.c_uint64),
+                ("lds_window_cells", C.c_int32)]
+
+
+class mcx_run_stats(C.Structure):
+    _fields_ = ([(n, C.c_uint64) for n in
+                 ["launched", "escaped", "detected", "timeout", "rr_dead", "capped", "scatters",
+                  "face_events", "fresnel_draws", "reflections", "rr_tests", "rr_survived",
+                  "events", "lane_slots", "flushes", "det_records", "det_dropped"]]
+                + [(n, C.c_double) for n in
+                   ["w_launched", "w_escaped", "w_detected", "w_timeout", "w_rr_gain",
+                    "w_rr_loss", "w_capped", "tally_sum", "absorbed_grid", "kernel_ms",
+                    "run_ms"]]
+                + [("grid_blocks", C.c_int32), ("block_size", C.c_int32)])
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libmcx.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                               "`python -m paper_1711_03244_amd.build`")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7
+        # and loads it by path, so load it first and let libmcx bind to the
+        # same copy (same soname) instead of pulling in a second runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        vp, u64, i32 = C.c_void_p, C.c_uint64, C.c_int32
+        sig = {
+            "mcx_default_options": (None, [C.POINTER(mcx_options)]),
+            "mcx_create": (C.c_int, [C.POINTER(mcx_volume), C.POINTER(mcx_source),
+                                     C.POINTER(mcx_detector), i32, C.POINTER(mcx_gates),
+                                     C.POINTER(mcx_options), C.POINTER(vp)]),
+            "mcx_run": (C.c_int, [vp, u64, u64]),
+            "mcx_run_range": (C.c_int, [vp, u64, u64, u64, vp]),
+            "mcx_reset": (C.c_int, [vp, vp]),
+            "mcx_sync": (C.c_int, [vp]),
+            "mcx_ncells": (u64, [vp]),
+            "mcx_fluence": (C.c_int, [vp, i32, vp, u64]),
+            "mcx_fluence_f64": (C.c_int, [vp, i32, vp, u64]),
+            "mcx_fluence_device": (C.c_int, [vp, i32, vp, u64, vp]),
+            "mcx_detected": (C.c_int, [vp, vp, vp, u64, C.POINTER(u64), C.POINTER(u64)]),
+            "mcx_stats": (C.c_int, [vp, C.POINTER(mcx_run_stats)]),
+            "mcx_digest": (C.c_int, [vp, vp, u64]),
+            "mcx_last_error": (C.c_char_p, []),
+            "mcx_destroy": (None, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != MCX_OK:
+        raise McxError(status, mcx_last_error())
+
+
+def mcx_last_error() -> str:
+    return lib().mcx_last_error().decode()
+
+
+def mcx_default_options(**overrides) -> mcx_options:
+    o = mcx_options()
+    lib().mcx_default_options(C.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+class _Inputs:
+    """C structs for a Problem; holds the arrays they point into."""
+
+    def __init__(self, p):
+        self.labels = np.ascontiguousarray(p.labels, np.uint8)
+        self.media = np.ascontiguousarray(p.media, np.float32)
+        nz, ny, nx = self.labels.shape
+        self.vol = mcx_volume(nx, ny, nz, p.h, self.labels.ctypes.data, self.media.ctypes.data,
+                              self.media.shape[0])
+        self.src = mcx_source((C.c_float * 3)(*p.src_pos), (C.c_float * 3)(*p.src_dir))
+        dets = np.ascontiguousarray(p.detectors, np.float32).reshape(-1, 4)
+        self.ndet = dets.shape[0]
+        self.det = (mcx_detector * max(1, self.ndet))()
+        for i, d in enumerate(dets):
+            self.det[i] = mcx_detector((C.c_float * 3)(*d[:3]), float(d[3]))
+        self.gates = mcx_gates(p.t0, p.dt, p.ngates)
+
+
+def mcx_create(p, **options) -> C.c_void_p:
+    """Create a context for a workloads.Problem; keyword arguments override
+    mcx_options fields (block_size, refill_chunk, ndigest, device, ...)."""
+    o = mcx_default_options(reflect=int(bool(p.reflect)), n_outside=p.n_out,
+                            rr_threshold=p.rr_threshold, rr_m=p.rr_m,
+                            max_events=int(p.max_events))
+    for k, v in options.items():
+        setattr(o, k, v)
+    inp = _Inputs(p)
+    ctx = C.c_void_p()
+    _check(lib().mcx_create(C.byref(inp.vol), C.byref(inp.src),
+                            inp.det if inp.ndet else None, inp.ndet, C.byref(inp.gates),
+                            C.byref(o), C.byref(ctx)))
+    return ctx
+
+
+def mcx_run(ctx, nphoton: int, seed: int):
+    _check(lib().mcx_run(ctx, int(nphoton), int(seed)))
+
+
+def mcx_run_range(ctx, first: int, n: int, seed: int, stream=None):
+    _check(lib().mcx_run_range(ctx, int(first), int(n), int(seed), _stream(stream)))
+
+
+def mcx_reset(ctx, stream=None):
+    _check(lib().mcx_reset(ctx, _stream(stream)))
+
+
+def mcx_sync(ctx):
+    _check(lib().mcx_sync(ctx))
+
+
+def mcx_ncells(ctx) -> int:
+    return int(lib().mcx_ncells(ctx))
+
+
+def mcx_fluence(ctx, kind: int = MCX_FLUENCE, out: Optional[np.ndarray] = None) -> np.ndarray:
+    n = mcx_ncells(ctx)
+    if out is None:
+        out = np.empty(n, np.float32)
+    assert out.dtype == np.float32 and out.flags.c_contiguous
+    _check(lib().mcx_fluence(ctx, int(kind), out.ctypes.data, out.size))
+    return out
+
+
+def mcx_fluence_f64(ctx, kind: int = MCX_FLUENCE, out: Optional[np.ndarray] = None) -> np.ndarray:
+    n = mcx_ncells(ctx)
+    if out is None:
+        out = np.empty(n, np.float64)
+    assert out.dtype == np.float64 and out.flags.c_contiguous
+    _check(lib().mcx_fluence_f64(ctx, int(kind), out.ctypes.data, out.size))
+    return out
+
+
+def mcx_fluence_device(ctx, kind: int, tensor, stream=None):
+    """Write the normalised map into a contiguous float32 torch tensor on the
+    context's device (enqueued on `stream`, default torch's current stream)."""
+    import torch
+    assert tensor.is_cuda and tensor.dtype == torch.float32 and tensor.is_contiguous()
+    if stream is None:
+        stream = torch.cuda.current_stream(tensor.device)
+    _check(lib().mcx_fluence_device(ctx, int(kind), C.c_void_p(tensor.data_ptr()),
+                                    tensor.numel(), _stream(stream)))
+    return tensor
+
+
+def mcx_detected(ctx, cap: int, rec_len: int):
+    rec = np.zeros((cap, rec_len), np.float32)
+    ph = np.zeros(cap, np.uint64)
+    nrec, ndrop = C.c_uint64(), C.c_uint64()
+    _check(lib().mcx_detected(ctx, rec.ctypes.data if cap else None, ph.ctypes.data if cap else None,
+                              cap, C.byref(nrec), C.byref(ndrop)))
+    n = int(nrec.value)
+    return rec[:n].copy(), ph[:n].copy(), int(ndrop.value)
+
+
+def mcx_stats(ctx) -> dict:
+    s = mcx_run_stats()
+    _check(lib().mcx_stats(ctx, C.byref(s)))
+    return {name: getattr(s, name) for name, _ in mcx_run_stats._fields_}
+
+
+def mcx_digest(ctx, nrows: int) -> np.ndarray:
+    out = np.zeros((nrows, len(DIGEST)), np.float64)
+    _check(lib().mcx_digest(ctx, out.ctypes.data, nrows))
+    return out
+
+
+def mcx_destroy(ctx):
+    if ctx:
+        lib().mcx_destroy(ctx)
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return C.c_void_p(s)
+    handle = getattr(s, "cuda_stream", None)  # torch.cuda.Stream
+    return C.c_void_p(handle if handle is not None else int(s))
+
+
+class Simulation:
+    """One context for one Problem."""
+
+    def __init__(self, problem, **options):
+        self.problem = problem
+        self.ctx = mcx_create(problem, **options)
+        self.ndigest = int(options.get("ndigest", 0))
+
+    def run(self, nphoton: int, seed: int) -> "Simulation":
+        mcx_run(self.ctx, nphoton, seed)
+        return self
+
+    def run_range(self, first: int, n: int, seed: int, stream=None) -> "Simulation":
+        mcx_run_range(self.ctx, first, n, seed, stream)
+        return self
+
+    def reset(self):
+        mcx_reset(self.ctx)
+
+    def sync(self):
+        mcx_sync(self.ctx)
+
+    def fluence(self, kind: int = MCX_FLUENCE, f64: bool = False) -> np.ndarray:
+        f = mcx_fluence_f64(self.ctx, kind) if f64 else mcx_fluence(self.ctx, kind)
+        return f.reshape(self.problem.tally_shape)
+
+    def detected(self, cap: Optional[int] = None):
+        if cap is None:
+            cap = int(self.stats()["det_records"])
+        return mcx_detected(self.ctx, cap, self.problem.record_len)
+
+    def stats(self) -> dict:
+        return mcx_stats(self.ctx)
+
+    def digest(self, nrows: Optional[int] = None) -> np.ndarray:
+        return mcx_digest(self.ctx, self.ndigest if nrows is None else nrows)
+
+    def close(self):
+        if self.ctx:
+            mcx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -36,7 +36,7 @@ class Problem:
     n_out: float = 1.0
     rr_threshold: float = 1e-4
     rr_m: float = 10.0
-    max_events: int = 100_000_000
+    max_events: int = 10_000_000
     name: str = ""
 
     def __post_init__(self):

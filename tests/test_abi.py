@@ -1,0 +1,128 @@
+"""The C ABI on the CPU: the library loads, exports every function that
+include/mcx.h declares, and rejects invalid input before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1711_03244_amd import mcx, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mcx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["mcx_create", "mcx_run", "mcx_run_range", "mcx_fluence", "mcx_detected",
+              "mcx_stats", "mcx_destroy", "mcx_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mcx.lib()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(declared_functions()) == set(mcx.EXPORTS)
+
+
+def test_default_options():
+    o = mcx.mcx_default_options()
+    assert o.rr_threshold == pytest.approx(1e-4) and o.rr_m == 10.0
+    assert o.n_outside == 1.0 and o.max_detected == 1 << 20 and o.reflect == 0
+
+
+def test_struct_sizes_match_header_layout():
+    # natural alignment of the C structs in include/mcx.h
+    assert C.sizeof(mcx.mcx_medium) == 16
+    assert C.sizeof(mcx.mcx_volume) == 4 * 4 + 8 + 8 + 8
+    assert C.sizeof(mcx.mcx_source) == 24
+    assert C.sizeof(mcx.mcx_detector) == 16
+    assert C.sizeof(mcx.mcx_gates) == 12
+    assert C.sizeof(mcx.mcx_options) == 4 * 4 + 8 + 8 + 4 * 4 + 8 + 8
+    assert C.sizeof(mcx.mcx_run_stats) == 17 * 8 + 11 * 8 + 8
+
+
+BAD = {
+    "source outside grid": dict(src_pos=(70.0, 1.0, 1.0)),
+    "direction not unit": dict(src_dir=(0.0, 0.0, 0.9)),
+    "zero gates": dict(ngates=0),
+    "negative dt": dict(dt=-1.0),
+    "roulette M": dict(rr_m=1.0),
+    "n outside < 1": dict(n_out=0.5),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BAD))
+def test_invalid_problem_rejected(case):
+    kw = dict(src_pos=(3.5, 3.5, 0.0))
+    kw.update(BAD[case])
+    p = W.cube_homogeneous(n=8).replace(**kw)
+    with pytest.raises(mcx.McxError) as e:
+        mcx.mcx_create(p)
+    assert e.value.status == mcx.MCX_EINVAL
+    assert mcx.mcx_last_error()
+
+
+def test_invalid_media_rejected():
+    p = W.cube_homogeneous(n=8).replace(src_pos=(3.5, 3.5, 0.0))
+    for row in [(-0.1, 1.0, 0.0, 1.37), (0.1, 1.0, 1.5, 1.37), (0.1, 1.0, 0.0, 0.9),
+                (float("nan"), 1.0, 0.0, 1.37)]:
+        with pytest.raises(mcx.McxError) as e:
+            mcx.mcx_create(W.with_medium(p, 1, row))
+        assert e.value.status == mcx.MCX_EINVAL
+
+
+def test_label_out_of_range_and_source_in_air_rejected():
+    p = W.cube_homogeneous(n=8).replace(src_pos=(3.5, 3.5, 0.0))
+    lab = p.labels.copy()
+    lab[4, 4, 4] = 7
+    with pytest.raises(mcx.McxError):
+        mcx.mcx_create(p.replace(labels=lab))
+    lab = p.labels.copy()
+    lab[0, 3, 3] = 0
+    with pytest.raises(mcx.McxError) as e:
+        mcx.mcx_create(p.replace(labels=lab))
+    assert "label 0" in str(e.value)
+
+
+def test_bad_detector_rejected():
+    p = W.cube_sphere(n=20)
+    d = p.detectors.copy()
+    d[1, 3] = 0.0
+    with pytest.raises(mcx.McxError) as e:
+        mcx.mcx_create(p.replace(detectors=d))
+    assert e.value.status == mcx.MCX_EINVAL
+
+
+def test_bad_launch_options_rejected():
+    p = W.cube_homogeneous(n=8).replace(src_pos=(3.5, 3.5, 0.0))
+    for kw in [dict(block_size=100), dict(block_size=2048), dict(refill_chunk=5),
+               dict(max_events=0)]:
+        with pytest.raises(mcx.McxError) as e:
+            mcx.mcx_create(p, **kw)
+        assert e.value.status == mcx.MCX_EINVAL
+
+
+def test_no_device_reported_without_gpu():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    p = W.cube_homogeneous(n=8).replace(src_pos=(3.5, 3.5, 0.0))
+    with pytest.raises(mcx.McxError) as e:
+        mcx.mcx_create(p)
+    assert e.value.status == mcx.MCX_ENODEV
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = mcx.lib()
+    assert lib.mcx_run(None, 10, 1) == mcx.MCX_EINVAL
+    assert lib.mcx_sync(None) == mcx.MCX_EINVAL
+    assert lib.mcx_ncells(None) == 0
+    lib.mcx_destroy(None)
