@@ -1,0 +1,119 @@
+"""Throughput benchmark of the photon-transport hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--photons N]
+                    [--no-cpu-baseline] [--head-photons M]
+
+Workload: the paper's heterogeneous cube benchmark as configured here -- a
+60 x 60 x 60 grid of 1 mm voxels, background mua 0.005/mm, mus 1.0/mm,
+g 0.01, n 1.37 and a centred 15 mm sphere with mua 0.002/mm, mus 5.0/mm,
+g 0.9, n 1.37, Fresnel boundaries, pencil beam at (29.5, 29.5, 0) along +z,
+50 gates of 0.1 ns and four 1 mm disk detectors, 1e8 photons per step.
+Inputs are synthetic (the phantom is generated, not read).  A step is one
+full pass of the path: clear, transport (launch, free paths, hops, deposits,
+scattering, boundaries, roulette, detection, ledger), FP64 reductions and
+normalisation of the map into a device tensor.  Problem creation and upload
+(the paper's host overhead) happen once, before the timed region.
+
+Prints one JSON line.  `roofline` is the transport kernel's algorithmic VALU
+work over its HIP-event time; `atomic_roofline` its memory-side atomic rate;
+`cpu_baseline` the FP64 oracle on the host cores over a prefix of the same
+photons.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "photons/ms at 60³ & head volume; time-to-equal-error denoised vs plain MC"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--photons", type=int, default=100_000_000)
+    ap.add_argument("--cpu-photons", type=int, default=3_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the transport on a single "
+              "MI355X (photons shard across GPUs by index range, which is not run here); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1711_03244_amd import mcx, roofline, workloads as W
+
+    p = W.cube_sphere()
+    N = args.photons
+    t_create = time.perf_counter()
+    sim = mcx.Simulation(p)
+    create_ms = (time.perf_counter() - t_create) * 1e3
+    out = torch.empty(p.tally_shape, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(i):
+        mcx.mcx_reset(sim.ctx)
+        mcx.mcx_run_range(sim.ctx, 0, N, args.seed + i)
+        mcx.mcx_fluence_device(sim.ctx, mcx.MCX_FLUENCE_RATE, out, stream=0)
+        return sim.stats()  # waits for the context's stream
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    kernel_ms, stats = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st = step(i)
+        kernel_ms.append(st["kernel_ms"])
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ms_per_step = wall_ms / args.steps
+    value = N * args.steps / wall_ms
+
+    last = stats[-1]
+    ksec = sum(kernel_ms) / len(kernel_ms) / 1e3
+    roof = roofline.valu_roofline(last, ksec)
+    roof["traffic"] = roofline.measured_traffic(N)
+    atom = roofline.atomic_roofline(last, ksec)
+    sim.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nthreads = min(os.cpu_count() or 1, 16)
+        r = oracle.run(p, args.cpu_photons, args.seed, nthreads=nthreads)
+        cpu = {"value": args.cpu_photons / (r["wall_s"] * 1e3), "unit": "photons/ms",
+               "cores": nthreads, "kind": "oracle",
+               "sample": f"photons 0..{args.cpu_photons - 1} of the same workload and seed "
+                         f"({r['wall_s']:.1f} s, FP64, {nthreads} threads)"}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "photons/ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cube60_sphere_b2a", "grid": [60, 60, 60], "voxel_mm": 1.0,
+                   "photons_per_step": N, "gates": 50, "gate_ns": 0.1, "detectors": 4,
+                   "reflect": True, "seed": args.seed, "tally": "fp64"},
+        "kernel_ms_per_step": sum(kernel_ms) / len(kernel_ms),
+        "kernel_photons_per_ms": N / (sum(kernel_ms) / len(kernel_ms)),
+        "create_ms": create_ms,
+        "events_per_photon": last["events"] / N,
+        "lane_utilisation": last["events"] / max(1, last["lane_slots"]),
+        "roofline": roof,
+        "atomic_roofline": atom,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,13 +97,51 @@ __global__ void __launch_bounds__(256) philox_kernel(uint32_t* out, int iters, u
   if (acc == 0x12345678u) out[0] = acc;
 }
 
+// Plain streaming copy, the reference for HBM byte counters: reads and
+// writes `n` float4 values once.
+__global__ void __launch_bounds__(256) copy_kernel(const float4* __restrict__ in,
+                                                   float4* __restrict__ out, uint64_t n) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += stride)
+    out[i] = in[i];
+}
+
 static float time_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   CHECK(hipEventElapsedTime(&ms, a, b));
   return ms;
 }
 
+static int run_copy() {
+  const uint64_t bytes = 1ull << 30;  // 1 GiB read + 1 GiB written
+  const uint64_t n = bytes / sizeof(float4);
+  float4 *a = nullptr, *b = nullptr;
+  CHECK(hipMalloc(&a, bytes));
+  CHECK(hipMalloc(&b, bytes));
+  CHECK(hipMemset(a, 1, bytes));
+  CHECK(hipMemset(b, 0, bytes));
+  hipEvent_t e0, e1;
+  CHECK(hipEventCreate(&e0));
+  CHECK(hipEventCreate(&e1));
+  for (int rep = 0; rep < 3; ++rep) {
+    CHECK(hipEventRecord(e0));
+    copy_kernel<<<8192, 256>>>(a, b, n);
+    CHECK(hipEventRecord(e1));
+    CHECK(hipEventSynchronize(e1));
+    const double ms = time_ms(e0, e1);
+    printf("{\"bench\": \"copy\", \"bytes_read\": %llu, \"bytes_written\": %llu, "
+           "\"GBps\": %.1f, \"ms\": %.3f}\n",
+           static_cast<unsigned long long>(bytes), static_cast<unsigned long long>(bytes),
+           2.0 * bytes / (ms * 1e-3) / 1e9, ms);
+  }
+  CHECK(hipFree(a));
+  CHECK(hipFree(b));
+  return 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc > 1 && strcmp(argv[1], "copy") == 0) return run_copy();
   int cus = 0;
   CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
   const int block = 256, per_cu = 8;
