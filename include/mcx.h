@@ -109,6 +109,7 @@ typedef struct {
   uint64_t ndigest;       /* per-photon digest rows kept for photons [first, first+ndigest) */
   int32_t lds_window_cells; /* cells around the source summed per workgroup in LDS before they
                                reach the map; 0 = library default (4096), < 0 = none */
+  int32_t accurate_math;  /* 0: hardware transcendentals (~1 ulp); 1: device math library */
 } mcx_options;
 
 /* Run statistics, accumulated since the last mcx_reset / mcx_run. */

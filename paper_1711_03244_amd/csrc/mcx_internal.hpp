@@ -66,13 +66,15 @@ struct TransportParams {
   uint64_t ndigest;
 };
 
-hipError_t launch_transport(const TransportParams& p, int grid, int block, hipStream_t s,
-                            bool detect, bool diag);
+// `p` is the host copy (used for the launch shape); `dev_params` must hold the
+// same bytes in device memory by the time the kernel runs (copied on `s`).
+hipError_t launch_transport(const TransportParams& p, TransportParams* dev_params, int grid,
+                            int block, hipStream_t s, bool detect, bool diag, bool accurate);
 // Shared-memory bytes the transport kernel needs for a launch shape.
 size_t transport_smem_bytes(int nmedia, int ndet, int block, bool detect, int window_cells);
 // Occupancy query (resident workgroups per CU) for a launch shape.
 hipError_t transport_occupancy(int* blocks_per_cu, int block, size_t smem, bool detect,
-                               bool diag);
+                               bool diag, bool accurate);
 
 hipError_t launch_clear(double* tally, uint64_t ncells, double* ledger,
                         unsigned long long* counts, unsigned long long* det_count,

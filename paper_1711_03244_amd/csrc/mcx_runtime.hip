@@ -21,6 +21,7 @@ namespace {
 
 constexpr double kCmmPerNs = 299.792458;  // speed of light in vacuum, mm/ns
 constexpr int kDefaultChunk = 256;
+constexpr int kParamSlots = 32;  // device copies of launch parameters, used round-robin
 constexpr int kDefaultWindow = 4096;  // FP64 cells, 32 KB of LDS
 
 thread_local std::string g_error;
@@ -70,6 +71,8 @@ struct mcx_ctx {
   float4* d_table = nullptr;
   double* d_tally = nullptr;
   unsigned long long* d_counter = nullptr;
+  mcx::TransportParams* d_params = nullptr;  // kParamSlots slots
+  uint64_t launches = 0;
   double* d_ledger = nullptr;
   unsigned long long* d_counts = nullptr;
   unsigned long long* d_det_count = nullptr;
@@ -104,6 +107,7 @@ void mcx_default_options(mcx_options* o) {
   o->refill_chunk = 0;
   o->ndigest = 0;
   o->lds_window_cells = 0;
+  o->accurate_math = 0;
 }
 
 const char* mcx_last_error(void) { return g_error.c_str(); }
@@ -179,7 +183,7 @@ static mcx_status validate(const mcx_volume* vol, const mcx_source* src, const m
 
 static void release(mcx_ctx* c) {
   if (!c) return;
-  void* bufs[] = {c->d_labels,  c->d_table, c->d_tally, c->d_counter,    c->d_ledger,
+  void* bufs[] = {c->d_labels,  c->d_table, c->d_tally, c->d_counter, c->d_params, c->d_ledger,
                   c->d_counts,  c->d_det_count, c->d_reduce, c->d_rec, c->d_rec_photon,
                   c->d_digest,  c->d_stage32, c->d_stage64};
   for (void* b : bufs)
@@ -209,6 +213,7 @@ static mcx_status setup(mcx_ctx* c, const mcx_volume* vol) {
   HIP_TRY(hipMalloc(&c->d_table, c->table.size() * sizeof(float4)));
   HIP_TRY(hipMalloc(&c->d_tally, ncells * sizeof(double)));
   HIP_TRY(hipMalloc(&c->d_counter, sizeof(unsigned long long)));
+  HIP_TRY(hipMalloc(&c->d_params, kParamSlots * sizeof(mcx::TransportParams)));
   HIP_TRY(hipMalloc(&c->d_ledger, mcx::kLedgerN * sizeof(double)));
   HIP_TRY(hipMalloc(&c->d_counts, mcx::kCountN * sizeof(unsigned long long)));
   HIP_TRY(hipMalloc(&c->d_det_count, sizeof(unsigned long long)));
@@ -237,7 +242,7 @@ static mcx_status setup(mcx_ctx* c, const mcx_volume* vol) {
     const int blk = c->opt.block_size > 0 ? c->opt.block_size : b;
     const size_t smem = mcx::transport_smem_bytes(c->nmedia, c->ndet, blk, c->detect, wcells);
     int occ = 0;
-    HIP_TRY(mcx::transport_occupancy(&occ, blk, smem, c->detect, c->diag));
+    HIP_TRY(mcx::transport_occupancy(&occ, blk, smem, c->detect, c->diag, c->opt.accurate_math != 0));
     if (occ * blk / 64 > best_waves) {
       best_waves = occ * blk / 64;
       best_block = blk;
@@ -423,9 +428,15 @@ static mcx_status enqueue(mcx_ctx* c, uint64_t first, uint64_t n, uint64_t seed,
   p.digest = c->d_digest;
   p.ndigest = c->diag ? c->opt.ndigest : 0;
 
+  // Each launch reads its parameters from its own device slot, so launches
+  // queued back to back (even on different streams, up to kParamSlots deep)
+  // never see each other's parameters.
+  mcx::TransportParams* slot = c->d_params + (c->launches++ % kParamSlots);
+  HIP_TRY(hipMemcpyAsync(slot, &p, sizeof(p), hipMemcpyHostToDevice, st));
   HIP_TRY(mcx::launch_reset_counter(c->d_counter, st));
   HIP_TRY(hipEventRecord(c->ev_k0, st));
-  HIP_TRY(mcx::launch_transport(p, c->grid, c->block, st, c->detect, c->diag));
+  HIP_TRY(mcx::launch_transport(p, slot, c->grid, c->block, st, c->detect, c->diag,
+                                c->opt.accurate_math != 0));
   HIP_TRY(hipEventRecord(c->ev_k1, st));
   HIP_TRY(hipMemsetAsync(c->d_reduce, 0, 2 * sizeof(double), st));
   HIP_TRY(mcx::launch_reduce(c->d_tally, c->d_labels, c->d_table, c->nvox, c->ngates,

@@ -90,6 +90,55 @@ __device__ __forceinline__ float face_dist(float f, float v, float r) {
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Transcendentals in two flavours: the hardware instructions (the paper's
+// "native math", within ~1 ulp on gfx950; sin/cos take revolutions, so
+// 2*pi*u needs no scaling) or the device math library.
+template <bool kNative>
+__device__ __forceinline__ float neg_log(float u) {  // -ln u, u in (0, 1)
+  if constexpr (kNative)
+    return __builtin_amdgcn_logf(u) * -0.69314718055994531f;
+  else
+    return -logf(u);
+}
+
+template <bool kNative>
+__device__ __forceinline__ void sincos_turn(float u, float* s, float* c) {  // of 2*pi*u
+  if constexpr (kNative) {
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
+  } else {
+    sincospif(2.f * u, s, c);
+  }
+}
+
+template <bool kNative>
+__device__ __forceinline__ float fsqrt(float x) {
+  if constexpr (kNative)
+    return __builtin_amdgcn_sqrtf(x);
+  else
+    return sqrtf(x);
+}
+
+// 1 - exp(-x) for x >= 0 without cancellation: its alternating series to the
+// x^7 term below 0.25 (truncation < 2e-9 relative), 1 - exp(-x) above.
+template <bool kNative>
+__device__ __forceinline__ float one_minus_exp(float x) {
+  if constexpr (kNative) {
+    if (x < 0.25f) {
+      float r = fmaf(x, 1.f / 5040.f, -1.f / 720.f);
+      r = fmaf(x, r, 1.f / 120.f);
+      r = fmaf(x, r, -1.f / 24.f);
+      r = fmaf(x, r, 1.f / 6.f);
+      r = fmaf(x, r, -0.5f);
+      r = fmaf(x, r, 1.f);
+      return x * r;
+    }
+    return 1.f - __builtin_amdgcn_exp2f(x * -1.4426950408889634f);
+  } else {
+    return -expm1f(-x);
+  }
+}
+
 __device__ __forceinline__ float inv_speed(float h, float v) {
   return v != 0.f ? h * rcp(fabsf(v)) : kInf;
 }
@@ -108,10 +157,11 @@ __device__ __forceinline__ float hg_cos(float g, float4 hg, float u) {
 // Turn v by polar cosine ct and azimuth 2*pi*u, the azimuth measured in the
 // branchless orthonormal basis of Duff et al., JCGT 6(1) 2017, then
 // renormalise.
+template <bool kNative>
 __device__ __forceinline__ void scatter_dir(float& vx, float& vy, float& vz, float ct, float u) {
-  const float st = sqrtf((1.f - ct) * (1.f + ct));
+  const float st = fsqrt<kNative>((1.f - ct) * (1.f + ct));
   float sp, cp;
-  sincospif(2.f * u, &sp, &cp);
+  sincos_turn<kNative>(u, &sp, &cp);
   const float sg = copysignf(1.f, vz);
   const float a = -rcp(sg + vz);
   const float b = vx * vy * a;
@@ -147,8 +197,12 @@ __device__ __forceinline__ void deposit(double* tally, double* s_win, uint32_t c
 enum : int { kEvTime = 0, kEvScat = 1, kEvCross = 2 };
 enum : int { kAlive = 0, kEndEscape = 1, kEndTime = 2, kEndRoulette = 3, kEndCapped = 4 };
 
-template <bool kDetect, bool kDiag>
-__global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P) {
+template <bool kDetect, bool kDiag, bool kNative>
+__global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* params) {
+  // The parameter block lives in device memory and is read where used
+  // (scalar loads that hit the scalar cache) rather than held in scalar
+  // registers for the whole persistent loop.
+  const TransportParams& P = *params;
   extern __shared__ float4 s_tab[];
   __shared__ double s_led[kLedgerN];
   __shared__ unsigned long long s_cnt[kCountN];
@@ -183,9 +237,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
   float rx = kInf, ry = kInf, rz = kInf;
   float w = 0.f, t = 0.f, s = 0.f;
   uint32_t klo = 0, khi = 0, blk = 0, nev = 0, nscat = 0;
-  uint32_t acc_cell = 0xffffffffu;
-  int acc_slot = -1;
-  float acc = 0.f;
+  // two most recent tally cells of this photon, most recent first
+  uint32_t acc_cell = 0xffffffffu, old_cell = 0xffffffffu;
+  int acc_slot = -1, old_slot = -1;
+  float acc = 0.f, old_acc = 0.f;
 
   // wave-uniform refill pool: photon offsets [pool_next, pool_end) from P.first
   uint64_t pool_next = 0, pool_end = 0;
@@ -228,7 +283,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
           klo = static_cast<uint32_t>(k);
           khi = static_cast<uint32_t>(k >> 32);
           const Words r = philox4x32_10(klo, khi, 0u, 0u, P.key0, P.key1);
-          s = -logf(unit_open(r.x));
+          s = neg_log<kNative>(unit_open(r.x));
           blk = 1;
           ix = P.src_ix;
           iy = P.src_iy;
@@ -251,6 +306,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
           acc_cell = 0xffffffffu;
           acc_slot = -1;
           acc = 0.f;
+          old_cell = 0xffffffffu;
+          old_slot = -1;
+          old_acc = 0.f;
           if constexpr (kDetect) {
             for (int mm = 0; mm < P.nmedia; ++mm) s_len[mm * bdim] = 0.f;
           }
@@ -279,7 +337,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
     // ----------------------------------------------------------------- event
     int end = kAlive;
     int det_hit = -1;
-    bool f_scat = false, f_face = false, f_fres = false, f_flush = false;
+    bool f_scat = false, f_face = false, f_fres = false, f_flush = false, f_flush2 = false;
     if (alive) {
       if (nev >= P.max_events) {
         end = kEndCapped;
@@ -320,13 +378,28 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
         int gate = static_cast<int>(floorf((t - P.t0) * P.inv_dt));
         gate = min(max(gate, 0), P.ngates - 1);
         const uint32_t cell = static_cast<uint32_t>(gate) * P.nvox + lin;
-        const float q = -expm1f(-md.x * l);  // 1 - exp(-mua l)
+        const float q = one_minus_exp<kNative>(md.x * l);  // 1 - exp(-mua l)
         const float dep = md.x > 0.f ? w * q * dd.w : w * l;
-        if (cell != acc_cell) {
-          if (acc_cell != 0xffffffffu && acc != 0.f) {
-            deposit(P.tally, s_win, acc_cell, acc_slot, acc);
-            f_flush = acc_slot < 0;
+        if (cell == acc_cell) {
+          acc += dep;
+        } else if (cell == old_cell) {
+          // back in the previous cell: swap the two entries
+          const float ta = acc;
+          const int ts = acc_slot;
+          acc = old_acc + dep;
+          acc_slot = old_slot;
+          old_acc = ta;
+          old_slot = ts;
+          old_cell = acc_cell;
+          acc_cell = cell;
+        } else {
+          if (old_cell != 0xffffffffu && old_acc != 0.f) {
+            deposit(P.tally, s_win, old_cell, old_slot, old_acc);
+            f_flush = old_slot < 0;
           }
+          old_cell = acc_cell;
+          old_slot = acc_slot;
+          old_acc = acc;
           const uint32_t ux = static_cast<uint32_t>(ix - P.wx0);
           const uint32_t uy = static_cast<uint32_t>(iy - P.wy0);
           const uint32_t uz = static_cast<uint32_t>(iz - P.wz0);
@@ -336,8 +409,6 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
           acc_slot = inwin ? static_cast<int>(((gate * P.wnz + uz) * P.wny + uy) * P.wnx + ux) : -1;
           acc_cell = cell;
           acc = dep;
-        } else {
-          acc += dep;
         }
         w = w - w * q;
 
@@ -378,7 +449,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
               if (st2 >= 1.f) {
                 tir = true;
               } else {
-                cos_t = sqrtf(1.f - st2);
+                cos_t = fsqrt<kNative>(1.f - st2);
                 refl_p = fresnel_r(n1, n2, fabsf(va), cos_t);
                 need_rng = true;
               }
@@ -394,11 +465,11 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
             f_scat = true;
             ++nscat;
             const float ct = hg_cos(md.z, s_hg[m], unit_open(r.x));
-            scatter_dir(vx, vy, vz, ct, unit_open(r.y));
+            scatter_dir<kNative>(vx, vy, vz, ct, unit_open(r.y));
             rx = inv_speed(P.h, vx);
             ry = inv_speed(P.h, vy);
             rz = inv_speed(P.h, vz);
-            s = -logf(unit_open(r.z));
+            s = neg_log<kNative>(unit_open(r.z));
             if (w < P.rr_threshold) {
               atomicAdd(&s_cnt[kCntRrTests], 1ull);
               if (unit_open(r.w) < P.rr_p) {
@@ -455,6 +526,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
         if (acc != 0.f && acc_cell != 0xffffffffu) {
           deposit(P.tally, s_win, acc_cell, acc_slot, acc);
           f_flush = acc_slot < 0;
+        }
+        if (old_acc != 0.f && old_cell != 0xffffffffu) {
+          deposit(P.tally, s_win, old_cell, old_slot, old_acc);
+          f_flush2 = old_slot < 0;
         }
         const double wd = static_cast<double>(w);
         const int end_slot = end == kEndEscape ? kCntEscaped
@@ -518,7 +593,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams P
     c_scat += wave_count(f_scat);
     c_face += wave_count(f_face);
     c_fres += wave_count(f_fres);
-    c_flush += wave_count(f_flush);
+    c_flush += wave_count(f_flush) + wave_count(f_flush2);
   }
 
   if (lane == 0) {
@@ -560,38 +635,33 @@ size_t transport_smem_bytes(int nmedia, int ndet, int block, bool detect, int wi
   return b;
 }
 
-template <bool D, bool G>
+template <bool D, bool G, bool A>
 static const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&transport_kernel<D, G>);
+  return reinterpret_cast<const void*>(&transport_kernel<D, G, !A>);
 }
 
-static const void* pick(bool detect, bool diag) {
-  if (detect) return diag ? kernel_ptr<true, true>() : kernel_ptr<true, false>();
-  return diag ? kernel_ptr<false, true>() : kernel_ptr<false, false>();
+static const void* pick(bool detect, bool diag, bool accurate) {
+  if (accurate) {
+    if (detect) return diag ? kernel_ptr<true, true, true>() : kernel_ptr<true, false, true>();
+    return diag ? kernel_ptr<false, true, true>() : kernel_ptr<false, false, true>();
+  }
+  if (detect) return diag ? kernel_ptr<true, true, false>() : kernel_ptr<true, false, false>();
+  return diag ? kernel_ptr<false, true, false>() : kernel_ptr<false, false, false>();
 }
 
 hipError_t transport_occupancy(int* blocks_per_cu, int block, size_t smem, bool detect,
-                               bool diag) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pick(detect, diag), block,
-                                                      smem);
+                               bool diag, bool accurate) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
+                                                      pick(detect, diag, accurate), block, smem);
 }
 
-hipError_t launch_transport(const TransportParams& p, int grid, int block, hipStream_t st,
-                            bool detect, bool diag) {
+hipError_t launch_transport(const TransportParams& p, TransportParams* dev_params, int grid,
+                            int block, hipStream_t st, bool detect, bool diag, bool accurate) {
   const size_t smem =
       transport_smem_bytes(p.nmedia, p.ndet, block, detect, p.wnx * p.wny * p.wnz * p.wng);
-  if (detect) {
-    if (diag)
-      transport_kernel<true, true><<<grid, block, smem, st>>>(p);
-    else
-      transport_kernel<true, false><<<grid, block, smem, st>>>(p);
-  } else {
-    if (diag)
-      transport_kernel<false, true><<<grid, block, smem, st>>>(p);
-    else
-      transport_kernel<false, false><<<grid, block, smem, st>>>(p);
-  }
-  return hipGetLastError();
+  const void* fn = pick(detect, diag, accurate);
+  void* args[] = {const_cast<TransportParams**>(&dev_params)};
+  return hipLaunchKernel(fn, dim3(grid), dim3(block), args, smem, st);
 }
 
 }  // namespace mcx

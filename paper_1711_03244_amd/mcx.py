@@ -64,7 +64,7 @@ class mcx_options(C.Structure):
                 ("rr_m", C.c_float), ("max_detected", C.c_uint64), ("max_events", C.c_uint64),
                 ("device", C.c_int32), ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_chunk", C.c_int32), ("ndigest", C.c_uint64),
-                ("lds_window_cells", C.c_int32)]
+                ("lds_window_cells", C.c_int32), ("accurate_math", C.c_int32)]
 
 
 class mcx_run_stats(C.Structure):

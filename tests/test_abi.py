@@ -45,7 +45,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(mcx.mcx_source) == 24
     assert C.sizeof(mcx.mcx_detector) == 16
     assert C.sizeof(mcx.mcx_gates) == 12
-    assert C.sizeof(mcx.mcx_options) == 4 * 4 + 8 + 8 + 4 * 4 + 8 + 8
+    assert C.sizeof(mcx.mcx_options) == 4 * 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4
     assert C.sizeof(mcx.mcx_run_stats) == 17 * 8 + 11 * 8 + 8
 
 
