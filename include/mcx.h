@@ -129,6 +129,30 @@ typedef struct {
   int32_t grid_blocks, block_size;
 } mcx_run_stats;
 
+/* One simulation of a batch (mcx_batch_create): everything mcx_create takes
+ * for one problem, with the boundary settings per simulation. */
+typedef struct {
+  mcx_volume vol;
+  mcx_source src;
+  const mcx_detector *det; /* may be NULL when ndet == 0 */
+  int32_t ndet;
+  mcx_gates gates;
+  int32_t reflect;         /* Fresnel reflect/refract where n changes */
+  float n_outside;         /* refractive index of label 0 and off-grid */
+} mcx_sim;
+
+/* Result of mcx_autotune. */
+typedef struct {
+  int32_t block_size;       /* chosen threads per workgroup */
+  int32_t refill_chunk;     /* chosen photons per job */
+  int32_t lds_window_cells; /* chosen LDS window (-1 = none) */
+  int32_t candidates;       /* launch shapes timed */
+  double default_ms;        /* pilot kernel time with the default shape */
+  double best_ms;           /* pilot kernel time with the chosen shape */
+  double ms_per_photon;     /* slope a of T = a n + T0 fitted from two pilot sizes */
+  double overhead_ms;       /* intercept T0 of that fit */
+} mcx_tune_result;
+
 /* Output kinds for mcx_fluence*. */
 enum {
   MCX_RAW = 0,          /* weight*mm deposited per cell */
@@ -147,6 +171,59 @@ mcx_status mcx_create(const mcx_volume *vol, const mcx_source *src, const mcx_de
                       int32_t ndet, const mcx_gates *gates, const mcx_options *opt,
                       mcx_ctx **out);
 
+/* Many independent simulations in one context, served by one persistent
+ * launch per run (each wave works on one simulation at a time and moves on
+ * when its lanes are done), as in the batched workload of the project (256
+ * cubes of different sizes and photon counts).  Validation, ownership and
+ * errors as for mcx_create; simulation i's messages are prefixed with its
+ * index.  The single-simulation calls below act on simulation 0, and
+ * mcx_run / mcx_run_range run every simulation of the context with the same
+ * photon range and seed. */
+mcx_status mcx_batch_create(const mcx_sim *sims, int32_t nsims, const mcx_options *opt,
+                            mcx_ctx **out);
+int32_t mcx_batch_size(const mcx_ctx *ctx);
+uint64_t mcx_batch_ncells(const mcx_ctx *ctx, int32_t sim);
+
+/* Clear, then run photons [0, nphoton[i]) of simulation i with seed[i], all
+ * in one launch (split only past 2^31 photons per simulation); blocking. */
+mcx_status mcx_batch_run(mcx_ctx *ctx, const uint64_t *nphoton, const uint64_t *seed);
+
+/* Enqueue photons [first[i], first[i] + n[i]) (first may be NULL for 0) of
+ * every simulation with seed[i] on hip_stream, accumulating; async. */
+mcx_status mcx_batch_run_range(mcx_ctx *ctx, const uint64_t *first, const uint64_t *n,
+                               const uint64_t *seed, void *hip_stream);
+
+/* Normalised map, statistics, detector records and digests of simulation
+ * `sim` (as mcx_fluence, mcx_fluence_f64, mcx_stats, mcx_detected and
+ * mcx_digest for one simulation; kernel_ms and run_ms are those of the whole
+ * launch).  MCX_EINVAL when sim is not in [0, mcx_batch_size). */
+mcx_status mcx_batch_fluence(mcx_ctx *ctx, int32_t sim, int32_t kind, float *host_out,
+                             uint64_t ncells);
+mcx_status mcx_batch_fluence_f64(mcx_ctx *ctx, int32_t sim, int32_t kind, double *host_out,
+                                 uint64_t ncells);
+mcx_status mcx_batch_stats(mcx_ctx *ctx, int32_t sim, mcx_run_stats *out);
+mcx_status mcx_batch_detected(mcx_ctx *ctx, int32_t sim, float *host_rec, uint64_t *host_photon,
+                              uint64_t cap, uint64_t *nrec, uint64_t *ndropped);
+mcx_status mcx_batch_digest(mcx_ctx *ctx, int32_t sim, double *host_out, uint64_t nrows);
+
+/* Launch shape: threads per workgroup (0 = the size that keeps the most waves
+ * resident), photons per job (0 = default 256), LDS window cells (0 = default
+ * 4096, < 0 = none; single-simulation contexts only).  Waits for the stream. */
+mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk,
+                          int32_t lds_window_cells);
+
+/* Autotuner: times pilot launches of pilot_photons[i] photons (seed[i]) per
+ * simulation over block sizes {64, 256, 448, 512, 1024} x jobs of {64, 256,
+ * 1024, 4096} photons (1 to 64 photons per lane) x deposit schemes {direct
+ * global atomics, LDS window of 4096 or 8192 cells} (windows only for one
+ * simulation), keeps the fastest shape, and fits the linear device runtime
+ * model T = a n + T0 of the paper's device-level load balancing (the study
+ * of Fig. 3(b)) from pilots of n and n/2 photons.  Results do not depend on the shape (the
+ * random numbers are keyed by photon index); tallies are cleared on return.
+ * Blocking. */
+mcx_status mcx_autotune(mcx_ctx *ctx, const uint64_t *pilot_photons, const uint64_t *seed,
+                        mcx_tune_result *out);
+
 /* Clear tallies, detector records, ledger and counters, run photons
  * [0, nphoton) with `seed`, reduce, and wait.  Blocking. */
 mcx_status mcx_run(mcx_ctx *ctx, uint64_t nphoton, uint64_t seed);
@@ -154,7 +231,9 @@ mcx_status mcx_run(mcx_ctx *ctx, uint64_t nphoton, uint64_t seed);
 /* Enqueue photons [first, first+n) with `seed` on `hip_stream` (a
  * hipStream_t; NULL = the context's own stream), accumulating into the
  * current tallies; returns without waiting.  Runs with different seeds may
- * be accumulated; the normalisation divides by the total photon count. */
+ * be accumulated; the normalisation divides by the total photon count.
+ * Runs of one context are ordered by their stream: enqueue them on one
+ * stream (or synchronise between streams). */
 mcx_status mcx_run_range(mcx_ctx *ctx, uint64_t first, uint64_t n, uint64_t seed,
                          void *hip_stream);
 

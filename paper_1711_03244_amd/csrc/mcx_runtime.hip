@@ -3,12 +3,16 @@
 // The host side of the paper's workflow (Fig. 1): take the user's domain,
 // optical properties, source, detectors and gates, validate them, derive the
 // per-medium constants the kernel needs, upload once, launch the photon
-// kernel, reduce and normalise the read-back maps.  One context owns one
-// device's buffers and one stream.
+// kernel, reduce and normalise the read-back maps.  A context owns one
+// device's buffers and one stream and holds one simulation (mcx_create) or
+// many independent ones served by a single persistent launch
+// (mcx_batch_create).  The paper's device runtime model T = a n + T0 and its
+// pilot runs drive the launch-shape autotuner (mcx_autotune).
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <string>
@@ -21,8 +25,8 @@ namespace {
 
 constexpr double kCmmPerNs = 299.792458;  // speed of light in vacuum, mm/ns
 constexpr int kDefaultChunk = 256;
-constexpr int kParamSlots = 32;  // device copies of launch parameters, used round-robin
-constexpr int kDefaultWindow = 4096;  // FP64 cells, 32 KB of LDS
+constexpr int kDefaultWindow = 4096;       // FP64 cells, 32 KB of LDS
+constexpr uint64_t kMaxLaunchPhotons = 1ull << 31;  // per simulation and launch
 
 thread_local std::string g_error;
 
@@ -44,35 +48,53 @@ mcx_status fail(mcx_status st, const char* fmt, ...) {
                   #expr, hipGetErrorString(e_));                                   \
   } while (0)
 
+#define MCX_TRY(expr)               \
+  do {                              \
+    mcx_status s_ = (expr);         \
+    if (s_ != MCX_OK) return s_;    \
+  } while (0)
+
 bool finite(float x) { return std::isfinite(x); }
+
+// Host-side description of one simulation.
+struct SimHost {
+  int nx = 0, ny = 0, nz = 0;
+  uint32_t nvox = 0;
+  float h = 1.f;
+  int nmedia = 0, ndet = 0, ngates = 0;
+  float t0 = 0.f, dt = 1.f;
+  int reflect = 0;
+  float n_out = 1.f;
+  std::vector<float4> tables;  // 3 * nmedia + ndet rows, see SimDesc::tables
+  int src_i[3] = {0, 0, 0};
+  float src_f[3] = {0, 0, 0};
+  float src_dir[3] = {0, 0, 1};
+  int src_label = 0;
+  int rec_len = 0;
+  uint64_t label_off = 0, tally_off = 0, table_off = 0;
+  uint64_t rec_off = 0;    // first record row (photon-index array)
+  uint64_t rec_foff = 0;   // first float of the records (rows differ in length)
+  uint64_t photons = 0;  // accumulated since the last reset
+  uint64_t ncells() const { return static_cast<uint64_t>(nvox) * ngates; }
+};
 
 }  // namespace
 
 struct mcx_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  int nx = 0, ny = 0, nz = 0;
-  uint32_t nvox = 0;
-  float h = 1.f;
-  int nmedia = 0, ndet = 0, ngates = 0;
-  float t0 = 0.f, dt = 1.f;
   mcx_options opt{};
-  std::vector<float4> table;  // 3 * nmedia + ndet rows, see TransportParams::media
-  int src_i[3] = {0, 0, 0};
-  float src_f[3] = {0, 0, 0};
-  int src_label = 0;
-  float src_dir[3] = {0, 0, 1};
+  std::vector<SimHost> sims;
   bool detect = false, diag = false;
-  int block = 256, grid = 0, cus = 0;
-  int win[7] = {0, 0, 0, 0, 0, 0, 0};  // x0, y0, z0, nx, ny, nz, ngates
-  int rec_len = 0;
+  int block = 256, grid = 0, cus = 0, chunk = kDefaultChunk;
+  int window_budget = 0;
+  int win[7] = {0, 0, 0, 0, 0, 0, 0};  // x0, y0, z0, nx, ny, nz, ngates (simulation 0)
+  int table_rows = 0, nmedia_max = 0;
+  uint64_t total_cells = 0, max_cells = 0;
 
   uint8_t* d_labels = nullptr;
-  float4* d_table = nullptr;
+  float4* d_tables = nullptr;
   double* d_tally = nullptr;
-  unsigned long long* d_counter = nullptr;
-  mcx::TransportParams* d_params = nullptr;  // kParamSlots slots
-  uint64_t launches = 0;
   double* d_ledger = nullptr;
   unsigned long long* d_counts = nullptr;
   unsigned long long* d_det_count = nullptr;
@@ -80,14 +102,14 @@ struct mcx_ctx {
   float* d_rec = nullptr;
   unsigned long long* d_rec_photon = nullptr;
   double* d_digest = nullptr;
+  mcx::SimDesc* d_desc = nullptr;
+  uint64_t* d_job_start = nullptr;
+  unsigned long long* d_job_counter = nullptr;
+  mcx::LaunchParams* d_launch = nullptr;
   float* d_stage32 = nullptr;
   double* d_stage64 = nullptr;
   hipEvent_t ev_begin = nullptr, ev_k0 = nullptr, ev_k1 = nullptr, ev_end = nullptr;
-
-  uint64_t photons = 0;  // photons accumulated since the last reset
   bool have_timing = false;
-
-  uint64_t ncells() const { return static_cast<uint64_t>(nvox) * ngates; }
 };
 
 extern "C" {
@@ -112,80 +134,96 @@ void mcx_default_options(mcx_options* o) {
 
 const char* mcx_last_error(void) { return g_error.c_str(); }
 
-static mcx_status validate(const mcx_volume* vol, const mcx_source* src, const mcx_detector* det,
-                           int32_t ndet, const mcx_gates* gates, const mcx_options* o) {
-  if (!vol || !src || !gates) return fail(MCX_EINVAL, "volume, source and gates are required");
+}  // extern "C"
+
+// ------------------------------------------------------------ validation
+
+static mcx_status validate_sim(const mcx_sim& sm, int index) {
+  const mcx_volume* vol = &sm.vol;
+  const mcx_source* src = &sm.src;
+  const mcx_gates* gates = &sm.gates;
+  char tag[40] = "";
+  if (index >= 0) snprintf(tag, sizeof(tag), "simulation %d: ", index);
   if (vol->nx <= 0 || vol->ny <= 0 || vol->nz <= 0)
-    return fail(MCX_EINVAL, "grid dimensions must be positive (got %d x %d x %d)", vol->nx,
-                vol->ny, vol->nz);
+    return fail(MCX_EINVAL, "%sgrid dimensions must be positive (got %d x %d x %d)", tag,
+                vol->nx, vol->ny, vol->nz);
   const uint64_t nvox = static_cast<uint64_t>(vol->nx) * vol->ny * vol->nz;
-  if (gates->ngates <= 0) return fail(MCX_EINVAL, "ngates must be positive");
+  if (gates->ngates <= 0) return fail(MCX_EINVAL, "%sngates must be positive", tag);
   if (nvox * static_cast<uint64_t>(gates->ngates) > (1ull << 31))
-    return fail(MCX_EINVAL, "ngates * voxels must be <= 2^31 (got %llu)",
+    return fail(MCX_EINVAL, "%sngates * voxels must be <= 2^31 (got %llu)", tag,
                 static_cast<unsigned long long>(nvox * gates->ngates));
   if (!(vol->voxel_mm > 0.f) || !finite(vol->voxel_mm))
-    return fail(MCX_EINVAL, "voxel size must be positive and finite");
-  if (!vol->labels || !vol->media) return fail(MCX_EINVAL, "labels and media are required");
+    return fail(MCX_EINVAL, "%svoxel size must be positive and finite", tag);
+  if (!vol->labels || !vol->media) return fail(MCX_EINVAL, "%slabels and media are required", tag);
   if (vol->nmedia < 2 || vol->nmedia > 256)
-    return fail(MCX_EINVAL, "nmedia must be in [2, 256] (row 0 is the outside)");
+    return fail(MCX_EINVAL, "%snmedia must be in [2, 256] (row 0 is the outside)", tag);
   for (int m = 1; m < vol->nmedia; ++m) {
     const mcx_medium& md = vol->media[m];
     if (!(md.mua >= 0.f) || !finite(md.mua) || !(md.mus >= 0.f) || !finite(md.mus))
-      return fail(MCX_EINVAL, "medium %d: mua and mus must be finite and >= 0", m);
-    if (!(md.g >= -1.f && md.g <= 1.f)) return fail(MCX_EINVAL, "medium %d: g must be in [-1, 1]", m);
-    if (!(md.n >= 1.f) || !finite(md.n)) return fail(MCX_EINVAL, "medium %d: n must be >= 1", m);
+      return fail(MCX_EINVAL, "%smedium %d: mua and mus must be finite and >= 0", tag, m);
+    if (!(md.g >= -1.f && md.g <= 1.f))
+      return fail(MCX_EINVAL, "%smedium %d: g must be in [-1, 1]", tag, m);
+    if (!(md.n >= 1.f) || !finite(md.n)) return fail(MCX_EINVAL, "%smedium %d: n must be >= 1", tag, m);
   }
   for (uint64_t i = 0; i < nvox; ++i)
     if (vol->labels[i] >= vol->nmedia)
-      return fail(MCX_EINVAL, "label %d at voxel %llu is >= nmedia %d", vol->labels[i],
+      return fail(MCX_EINVAL, "%slabel %d at voxel %llu is >= nmedia %d", tag, vol->labels[i],
                   static_cast<unsigned long long>(i), vol->nmedia);
   if (!(gates->dt_ns > 0.f) || !finite(gates->dt_ns) || !finite(gates->t0_ns))
-    return fail(MCX_EINVAL, "gate width must be positive and t0 finite");
+    return fail(MCX_EINVAL, "%sgate width must be positive and t0 finite", tag);
   const double dn = std::sqrt(static_cast<double>(src->dir[0]) * src->dir[0] +
                               static_cast<double>(src->dir[1]) * src->dir[1] +
                               static_cast<double>(src->dir[2]) * src->dir[2]);
-  if (!(std::fabs(dn - 1.0) <= 1e-5)) return fail(MCX_EINVAL, "source direction must be a unit vector");
+  if (!(std::fabs(dn - 1.0) <= 1e-5))
+    return fail(MCX_EINVAL, "%ssource direction must be a unit vector", tag);
   const int dim[3] = {vol->nx, vol->ny, vol->nz};
   int64_t iv[3];
   for (int a = 0; a < 3; ++a) {
     const double x = static_cast<double>(src->pos[a]) / vol->voxel_mm;
     if (!(x >= 0.0) || !(x < dim[a]))
-      return fail(MCX_EINVAL, "source position lies outside the grid (axis %d)", a);
+      return fail(MCX_EINVAL, "%ssource position lies outside the grid (axis %d)", tag, a);
     iv[a] = static_cast<int64_t>(std::floor(x));
   }
   if (vol->labels[iv[0] + vol->nx * (iv[1] + static_cast<int64_t>(vol->ny) * iv[2])] == 0)
-    return fail(MCX_EINVAL, "source voxel has label 0 (outside)");
-  if (ndet < 0 || ndet > 4096) return fail(MCX_EINVAL, "ndet must be in [0, 4096]");
-  if (ndet > 0 && !det) return fail(MCX_EINVAL, "detector array is NULL");
-  for (int d = 0; d < ndet; ++d)
-    if (!(det[d].radius > 0.f) || !finite(det[d].radius) || !finite(det[d].pos[0]) ||
-        !finite(det[d].pos[1]) || !finite(det[d].pos[2]))
-      return fail(MCX_EINVAL, "detector %d: radius must be positive and the centre finite", d);
-  if (o) {
-    if (!(o->n_outside >= 1.f) || !finite(o->n_outside))
-      return fail(MCX_EINVAL, "n_outside must be >= 1");
-    if (!(o->rr_m > 1.f) || !finite(o->rr_m)) return fail(MCX_EINVAL, "rr_m must be > 1");
-    if (!(o->rr_threshold >= 0.f) || !finite(o->rr_threshold))
-      return fail(MCX_EINVAL, "rr_threshold must be >= 0");
-    if (o->block_size != 0 && (o->block_size < 64 || o->block_size > 1024 || o->block_size % 64))
-      return fail(MCX_EINVAL, "block_size must be a multiple of 64 in [64, 1024]");
-    if (o->blocks_per_cu < 0 || o->refill_chunk < 0 || o->device < 0)
-      return fail(MCX_EINVAL, "blocks_per_cu, refill_chunk and device must be >= 0");
-    if (o->refill_chunk != 0 && o->refill_chunk < 64)
-      return fail(MCX_EINVAL, "refill_chunk must be 0 or >= 64");
-    if (o->max_events == 0 || o->max_events > 0xffffffffull)
-      return fail(MCX_EINVAL, "max_events must be in [1, 2^32-1]");
-    if (o->lds_window_cells > 8192)
-      return fail(MCX_EINVAL, "lds_window_cells must be <= 8192 (64 KB of LDS)");
-  }
+    return fail(MCX_EINVAL, "%ssource voxel has label 0 (outside)", tag);
+  if (sm.ndet < 0 || sm.ndet > 4096) return fail(MCX_EINVAL, "%sndet must be in [0, 4096]", tag);
+  if (sm.ndet > 0 && !sm.det) return fail(MCX_EINVAL, "%sdetector array is NULL", tag);
+  for (int d = 0; d < sm.ndet; ++d)
+    if (!(sm.det[d].radius > 0.f) || !finite(sm.det[d].radius) || !finite(sm.det[d].pos[0]) ||
+        !finite(sm.det[d].pos[1]) || !finite(sm.det[d].pos[2]))
+      return fail(MCX_EINVAL, "%sdetector %d: radius must be positive and the centre finite",
+                  tag, d);
+  if (!(sm.n_outside >= 1.f) || !finite(sm.n_outside))
+    return fail(MCX_EINVAL, "%sn_outside must be >= 1", tag);
   return MCX_OK;
 }
 
+static mcx_status validate_options(const mcx_options* o) {
+  if (!o) return MCX_OK;
+  if (!(o->rr_m > 1.f) || !finite(o->rr_m)) return fail(MCX_EINVAL, "rr_m must be > 1");
+  if (!(o->rr_threshold >= 0.f) || !finite(o->rr_threshold))
+    return fail(MCX_EINVAL, "rr_threshold must be >= 0");
+  if (o->block_size != 0 && (o->block_size < 64 || o->block_size > 1024 || o->block_size % 64))
+    return fail(MCX_EINVAL, "block_size must be a multiple of 64 in [64, 1024]");
+  if (o->blocks_per_cu < 0 || o->refill_chunk < 0 || o->device < 0)
+    return fail(MCX_EINVAL, "blocks_per_cu, refill_chunk and device must be >= 0");
+  if (o->refill_chunk != 0 && o->refill_chunk < 64)
+    return fail(MCX_EINVAL, "refill_chunk must be 0 or >= 64");
+  if (o->max_events == 0 || o->max_events > 0xffffffffull)
+    return fail(MCX_EINVAL, "max_events must be in [1, 2^32-1]");
+  if (o->lds_window_cells > 8192)
+    return fail(MCX_EINVAL, "lds_window_cells must be <= 8192 (64 KB of LDS)");
+  return MCX_OK;
+}
+
+// ------------------------------------------------------------- set-up
+
 static void release(mcx_ctx* c) {
   if (!c) return;
-  void* bufs[] = {c->d_labels,  c->d_table, c->d_tally, c->d_counter, c->d_params, c->d_ledger,
-                  c->d_counts,  c->d_det_count, c->d_reduce, c->d_rec, c->d_rec_photon,
-                  c->d_digest,  c->d_stage32, c->d_stage64};
+  void* bufs[] = {c->d_labels,      c->d_tables,     c->d_tally,   c->d_ledger,
+                  c->d_counts,      c->d_det_count,  c->d_reduce,  c->d_rec,
+                  c->d_rec_photon,  c->d_digest,     c->d_desc,    c->d_job_start,
+                  c->d_job_counter, c->d_launch,     c->d_stage32, c->d_stage64};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   hipEvent_t evs[] = {c->ev_begin, c->ev_k0, c->ev_k1, c->ev_end};
@@ -195,54 +233,92 @@ static void release(mcx_ctx* c) {
   delete c;
 }
 
-static mcx_status setup(mcx_ctx* c, const mcx_volume* vol) {
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
-    return fail(MCX_ENODEV, "no HIP device available");
-  if (c->device >= ndev) return fail(MCX_ENODEV, "device %d not present (%d devices)", c->device, ndev);
-  HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
-  HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-  HIP_TRY(hipEventCreate(&c->ev_begin));
-  HIP_TRY(hipEventCreate(&c->ev_k0));
-  HIP_TRY(hipEventCreate(&c->ev_k1));
-  HIP_TRY(hipEventCreate(&c->ev_end));
-
-  const uint64_t ncells = c->ncells();
-  HIP_TRY(hipMalloc(&c->d_labels, c->nvox));
-  HIP_TRY(hipMalloc(&c->d_table, c->table.size() * sizeof(float4)));
-  HIP_TRY(hipMalloc(&c->d_tally, ncells * sizeof(double)));
-  HIP_TRY(hipMalloc(&c->d_counter, sizeof(unsigned long long)));
-  HIP_TRY(hipMalloc(&c->d_params, kParamSlots * sizeof(mcx::TransportParams)));
-  HIP_TRY(hipMalloc(&c->d_ledger, mcx::kLedgerN * sizeof(double)));
-  HIP_TRY(hipMalloc(&c->d_counts, mcx::kCountN * sizeof(unsigned long long)));
-  HIP_TRY(hipMalloc(&c->d_det_count, sizeof(unsigned long long)));
-  HIP_TRY(hipMalloc(&c->d_reduce, 2 * sizeof(double)));
-  if (c->detect && c->opt.max_detected > 0) {
-    HIP_TRY(hipMalloc(&c->d_rec, c->opt.max_detected * c->rec_len * sizeof(float)));
-    HIP_TRY(hipMalloc(&c->d_rec_photon, c->opt.max_detected * sizeof(unsigned long long)));
+static void describe(SimHost& sh, const mcx_sim& sm) {
+  const mcx_volume* vol = &sm.vol;
+  sh.nx = vol->nx;
+  sh.ny = vol->ny;
+  sh.nz = vol->nz;
+  sh.nvox = static_cast<uint32_t>(static_cast<uint64_t>(vol->nx) * vol->ny * vol->nz);
+  sh.h = vol->voxel_mm;
+  sh.nmedia = vol->nmedia;
+  sh.ndet = sm.ndet;
+  sh.ngates = sm.gates.ngates;
+  sh.t0 = sm.gates.t0_ns;
+  sh.dt = sm.gates.dt_ns;
+  sh.reflect = sm.reflect ? 1 : 0;
+  sh.n_out = sm.n_outside;
+  sh.rec_len = 4 + (sh.nmedia - 1);
+  // per-medium tables: properties, derived reciprocals, HG constants
+  sh.tables.assign(3 * sh.nmedia + sh.ndet, make_float4(0.f, 0.f, 0.f, 0.f));
+  for (int m = 0; m < sh.nmedia; ++m) {
+    mcx_medium md = vol->media[m];
+    if (m == 0) md = mcx_medium{0.f, 0.f, 0.f, sh.n_out};
+    const double mua = md.mua, mus = md.mus, g = md.g, n = md.n;
+    sh.tables[m] = make_float4(md.mua, md.mus, md.g, md.n);
+    sh.tables[sh.nmedia + m] = make_float4(
+        mus > 0 ? static_cast<float>(1.0 / mus) : __builtin_huge_valf(),
+        static_cast<float>(n / kCmmPerNs), static_cast<float>(kCmmPerNs / n),
+        mua > 0 ? static_cast<float>(1.0 / mua) : 0.f);
+    sh.tables[2 * sh.nmedia + m] = make_float4(
+        static_cast<float>(1.0 - g), static_cast<float>(2.0 * g),
+        static_cast<float>(2.0 * (1.0 + g * g)), static_cast<float>((1.0 - g) * (1.0 - g)));
   }
-  if (c->diag) HIP_TRY(hipMalloc(&c->d_digest, c->opt.ndigest * mcx::kDigestN * sizeof(double)));
-  HIP_TRY(hipMemcpyAsync(c->d_labels, vol->labels, c->nvox, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->d_table, c->table.data(), c->table.size() * sizeof(float4),
-                         hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(mcx::launch_clear(c->d_tally, ncells, c->d_ledger, c->d_counts, c->d_det_count,
-                            c->d_reduce, c->stream));
-  if (c->diag)
-    HIP_TRY(hipMemsetAsync(c->d_digest, 0, c->opt.ndigest * mcx::kDigestN * sizeof(double),
-                           c->stream));
+  for (int d = 0; d < sh.ndet; ++d) {
+    const double r = sm.det[d].radius;
+    sh.tables[3 * sh.nmedia + d] = make_float4(sm.det[d].pos[0], sm.det[d].pos[1],
+                                               sm.det[d].pos[2], static_cast<float>(r * r));
+  }
+  for (int a = 0; a < 3; ++a) {
+    const double x = static_cast<double>(sm.src.pos[a]) / sh.h;
+    const double fl = std::floor(x);
+    sh.src_i[a] = static_cast<int>(fl);
+    sh.src_f[a] = static_cast<float>(x - fl);
+    sh.src_dir[a] = sm.src.dir[a];
+  }
+  sh.src_label =
+      vol->labels[sh.src_i[0] + sh.nx * (sh.src_i[1] + static_cast<int64_t>(sh.ny) * sh.src_i[2])];
+}
 
-  // Launch shape: the requested block size, or the one of the candidates
-  // that keeps the most waves resident per CU once LDS is counted.
-  const int wcells = c->win[3] * c->win[4] * c->win[5] * c->win[6];
+// LDS window of simulation 0: a box of cells centred on the source voxel
+// (shifted to stay inside the grid) over the first gate, or the first two
+// when there are several, holding at most `budget` cells.  Only used when the
+// context holds one simulation.
+static void set_window(mcx_ctx* c, int budget) {
+  for (int& v : c->win) v = 0;
+  c->window_budget = budget;
+  if (budget <= 0 || c->sims.size() != 1) return;
+  const SimHost& sh = c->sims[0];
+  const int wg = sh.ngates > 1 ? 2 : 1;
+  const int per_gate = budget / wg;
+  int side = 1;
+  while ((side + 1) * (side + 1) * (side + 1) <= per_gate) ++side;
+  const int dims[3] = {sh.nx, sh.ny, sh.nz};
+  for (int a = 0; a < 3; ++a) {
+    const int n = side < dims[a] ? side : dims[a];
+    int lo = sh.src_i[a] - n / 2;
+    if (lo > dims[a] - n) lo = dims[a] - n;
+    if (lo < 0) lo = 0;
+    c->win[a] = lo;
+    c->win[3 + a] = n;
+  }
+  c->win[6] = wg;
+}
+
+static int window_cells(const mcx_ctx* c) { return c->win[3] * c->win[4] * c->win[5] * c->win[6]; }
+
+// Launch shape: `block` threads (0 = the candidate that keeps the most waves
+// resident per CU once LDS is counted), grid = resident workgroups x CUs.
+static mcx_status set_shape(mcx_ctx* c, int block) {
   const int candidates[] = {256, 448, 512, 768, 1024};
   int best_block = 0, best_occ = 0, best_waves = -1;
   for (int b : candidates) {
-    if (c->opt.block_size > 0 && b != candidates[0]) break;
-    const int blk = c->opt.block_size > 0 ? c->opt.block_size : b;
-    const size_t smem = mcx::transport_smem_bytes(c->nmedia, c->ndet, blk, c->detect, wcells);
+    if (block > 0 && b != candidates[0]) break;
+    const int blk = block > 0 ? block : b;
+    const size_t smem =
+        mcx::transport_smem_bytes(c->table_rows, c->nmedia_max, blk, c->detect, window_cells(c));
     int occ = 0;
-    HIP_TRY(mcx::transport_occupancy(&occ, blk, smem, c->detect, c->diag, c->opt.accurate_math != 0));
+    HIP_TRY(mcx::transport_occupancy(&occ, blk, smem, c->detect, c->diag,
+                                     c->opt.accurate_math != 0));
     if (occ * blk / 64 > best_waves) {
       best_waves = occ * blk / 64;
       best_block = blk;
@@ -254,17 +330,90 @@ static mcx_status setup(mcx_ctx* c, const mcx_volume* vol) {
   const int per_cu = c->opt.blocks_per_cu > 0 && c->opt.blocks_per_cu < best_occ
                          ? c->opt.blocks_per_cu : best_occ;
   c->grid = per_cu * c->cus;
+  return MCX_OK;
+}
+
+static mcx_status clear_all(mcx_ctx* c, hipStream_t st) {
+  HIP_TRY(mcx::launch_clear(c->d_tally, c->total_cells, c->d_ledger, c->d_counts, c->d_det_count,
+                            static_cast<int>(c->sims.size()), st));
+  if (c->diag)
+    HIP_TRY(hipMemsetAsync(c->d_digest, 0,
+                           c->sims.size() * c->opt.ndigest * mcx::kDigestN * sizeof(double), st));
+  for (SimHost& sh : c->sims) sh.photons = 0;
+  c->have_timing = false;
+  return MCX_OK;
+}
+
+static mcx_status setup(mcx_ctx* c, const mcx_sim* sims) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(MCX_ENODEV, "no HIP device available");
+  if (c->device >= ndev)
+    return fail(MCX_ENODEV, "device %d not present (%d devices)", c->device, ndev);
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreate(&c->ev_begin));
+  HIP_TRY(hipEventCreate(&c->ev_k0));
+  HIP_TRY(hipEventCreate(&c->ev_k1));
+  HIP_TRY(hipEventCreate(&c->ev_end));
+
+  const size_t n = c->sims.size();
+  uint64_t labels = 0, tables = 0, recs = 0, rec_rows = 0;
+  for (SimHost& sh : c->sims) {
+    sh.label_off = labels;
+    sh.tally_off = c->total_cells;
+    sh.table_off = tables;
+    sh.rec_off = rec_rows;
+    sh.rec_foff = recs;
+    labels += sh.nvox;
+    c->total_cells += sh.ncells();
+    c->max_cells = std::max(c->max_cells, sh.ncells());
+    tables += sh.tables.size();
+    if (sh.ndet > 0) {
+      recs += c->opt.max_detected * sh.rec_len;
+      rec_rows += c->opt.max_detected;
+    }
+  }
+  HIP_TRY(hipMalloc(&c->d_labels, labels));
+  HIP_TRY(hipMalloc(&c->d_tables, tables * sizeof(float4)));
+  HIP_TRY(hipMalloc(&c->d_tally, c->total_cells * sizeof(double)));
+  HIP_TRY(hipMalloc(&c->d_ledger, n * mcx::kLedgerN * sizeof(double)));
+  HIP_TRY(hipMalloc(&c->d_counts, n * mcx::kCountN * sizeof(unsigned long long)));
+  HIP_TRY(hipMalloc(&c->d_det_count, n * sizeof(unsigned long long)));
+  HIP_TRY(hipMalloc(&c->d_reduce, n * 2 * sizeof(double)));
+  HIP_TRY(hipMalloc(&c->d_desc, n * sizeof(mcx::SimDesc)));
+  HIP_TRY(hipMalloc(&c->d_job_start, (n + 1) * sizeof(uint64_t)));
+  HIP_TRY(hipMalloc(&c->d_job_counter, sizeof(unsigned long long)));
+  HIP_TRY(hipMalloc(&c->d_launch, sizeof(mcx::LaunchParams)));
+  if (recs > 0) {
+    HIP_TRY(hipMalloc(&c->d_rec, recs * sizeof(float)));
+    HIP_TRY(hipMalloc(&c->d_rec_photon, rec_rows * sizeof(unsigned long long)));
+  }
+  if (c->diag)
+    HIP_TRY(hipMalloc(&c->d_digest, n * c->opt.ndigest * mcx::kDigestN * sizeof(double)));
+  for (size_t i = 0; i < n; ++i) {
+    const SimHost& sh = c->sims[i];
+    HIP_TRY(hipMemcpyAsync(c->d_labels + sh.label_off, sims[i].vol.labels, sh.nvox,
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->d_tables + sh.table_off, sh.tables.data(),
+                           sh.tables.size() * sizeof(float4), hipMemcpyHostToDevice, c->stream));
+  }
+  MCX_TRY(clear_all(c, c->stream));
+  set_window(c, c->opt.lds_window_cells == 0 ? kDefaultWindow : c->opt.lds_window_cells);
+  c->chunk = c->opt.refill_chunk > 0 ? c->opt.refill_chunk : kDefaultChunk;
+  MCX_TRY(set_shape(c, c->opt.block_size));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return MCX_OK;
 }
 
-mcx_status mcx_create(const mcx_volume* vol, const mcx_source* src, const mcx_detector* det,
-                      int32_t ndet, const mcx_gates* gates, const mcx_options* opt,
-                      mcx_ctx** out) {
+static mcx_status create(const mcx_sim* sims, int32_t nsims, const mcx_options* opt,
+                         mcx_ctx** out) {
   if (!out) return fail(MCX_EINVAL, "out pointer is NULL");
-  mcx_status st = validate(vol, src, det, ndet, gates, opt);
-  if (st != MCX_OK) return st;
-
+  if (!sims || nsims <= 0 || nsims > 65536)
+    return fail(MCX_EINVAL, "need 1 to 65536 simulations");
+  MCX_TRY(validate_options(opt));
+  for (int i = 0; i < nsims; ++i) MCX_TRY(validate_sim(sims[i], nsims > 1 ? i : -1));
   mcx_ctx* c = new (std::nothrow) mcx_ctx();
   if (!c) return fail(MCX_ENOMEM, "host allocation failed");
   if (opt)
@@ -272,70 +421,15 @@ mcx_status mcx_create(const mcx_volume* vol, const mcx_source* src, const mcx_de
   else
     mcx_default_options(&c->opt);
   c->device = c->opt.device;
-  c->nx = vol->nx;
-  c->ny = vol->ny;
-  c->nz = vol->nz;
-  c->nvox = static_cast<uint32_t>(static_cast<uint64_t>(vol->nx) * vol->ny * vol->nz);
-  c->h = vol->voxel_mm;
-  c->nmedia = vol->nmedia;
-  c->ndet = ndet;
-  c->ngates = gates->ngates;
-  c->t0 = gates->t0_ns;
-  c->dt = gates->dt_ns;
-  c->detect = ndet > 0;
   c->diag = c->opt.ndigest > 0;
-  c->rec_len = 4 + (c->nmedia - 1);
-
-  // per-medium tables: properties, derived reciprocals, HG constants
-  c->table.assign(3 * c->nmedia + ndet, make_float4(0.f, 0.f, 0.f, 0.f));
-  for (int m = 0; m < c->nmedia; ++m) {
-    mcx_medium md = vol->media[m];
-    if (m == 0) md = mcx_medium{0.f, 0.f, 0.f, c->opt.n_outside};
-    const double mua = md.mua, mus = md.mus, g = md.g, n = md.n;
-    c->table[m] = make_float4(md.mua, md.mus, md.g, md.n);
-    c->table[c->nmedia + m] = make_float4(
-        mus > 0 ? static_cast<float>(1.0 / mus) : __builtin_huge_valf(),
-        static_cast<float>(n / kCmmPerNs), static_cast<float>(kCmmPerNs / n),
-        mua > 0 ? static_cast<float>(1.0 / mua) : 0.f);
-    c->table[2 * c->nmedia + m] =
-        make_float4(static_cast<float>(1.0 - g), static_cast<float>(2.0 * g),
-                    static_cast<float>(2.0 * (1.0 + g * g)), static_cast<float>((1.0 - g) * (1.0 - g)));
+  c->sims.resize(nsims);
+  for (int i = 0; i < nsims; ++i) {
+    describe(c->sims[i], sims[i]);
+    c->detect = c->detect || c->sims[i].ndet > 0;
+    c->table_rows = std::max(c->table_rows, static_cast<int>(c->sims[i].tables.size()));
+    c->nmedia_max = std::max(c->nmedia_max, c->sims[i].nmedia);
   }
-  for (int d = 0; d < ndet; ++d) {
-    const double r = det[d].radius;
-    c->table[3 * c->nmedia + d] =
-        make_float4(det[d].pos[0], det[d].pos[1], det[d].pos[2], static_cast<float>(r * r));
-  }
-  for (int a = 0; a < 3; ++a) {
-    const double x = static_cast<double>(src->pos[a]) / c->h;
-    const double fl = std::floor(x);
-    c->src_i[a] = static_cast<int>(fl);
-    c->src_f[a] = static_cast<float>(x - fl);
-    c->src_dir[a] = src->dir[a];
-  }
-  c->src_label = vol->labels[c->src_i[0] + c->nx * (c->src_i[1] + static_cast<int64_t>(c->ny) * c->src_i[2])];
-
-  // LDS window: a box of cells centred on the source voxel (shifted to stay
-  // inside the grid) over the first gate, or the first two when there are
-  // several, holding at most `budget` cells.
-  const int budget = c->opt.lds_window_cells == 0 ? kDefaultWindow : c->opt.lds_window_cells;
-  if (budget > 0) {
-    const int wg = c->ngates > 1 ? 2 : 1;
-    const int per_gate = budget / wg;
-    int side = 1;
-    while ((side + 1) * (side + 1) * (side + 1) <= per_gate) ++side;
-    const int dims[3] = {c->nx, c->ny, c->nz};
-    for (int a = 0; a < 3; ++a) {
-      const int n = side < dims[a] ? side : dims[a];
-      int lo = c->src_i[a] - n / 2;
-      if (lo > dims[a] - n) lo = dims[a] - n;
-      if (lo < 0) lo = 0;
-      c->win[a] = lo;
-      c->win[3 + a] = n;
-    }
-    c->win[6] = wg;
-  }
-  st = setup(c, vol);
+  const mcx_status st = setup(c, sims);
   if (st != MCX_OK) {
     std::string keep = g_error;
     release(c);
@@ -346,6 +440,33 @@ mcx_status mcx_create(const mcx_volume* vol, const mcx_source* src, const mcx_de
   return MCX_OK;
 }
 
+extern "C" {
+
+mcx_status mcx_create(const mcx_volume* vol, const mcx_source* src, const mcx_detector* det,
+                      int32_t ndet, const mcx_gates* gates, const mcx_options* opt,
+                      mcx_ctx** out) {
+  if (!vol || !src || !gates) return fail(MCX_EINVAL, "volume, source and gates are required");
+  mcx_options o;
+  if (opt)
+    o = *opt;
+  else
+    mcx_default_options(&o);
+  mcx_sim sm;
+  sm.vol = *vol;
+  sm.src = *src;
+  sm.det = det;
+  sm.ndet = ndet;
+  sm.gates = *gates;
+  sm.reflect = o.reflect;
+  sm.n_outside = o.n_outside;
+  return create(&sm, 1, &o, out);
+}
+
+mcx_status mcx_batch_create(const mcx_sim* sims, int32_t nsims, const mcx_options* opt,
+                            mcx_ctx** out) {
+  return create(sims, nsims, opt, out);
+}
+
 void mcx_destroy(mcx_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
@@ -353,118 +474,200 @@ void mcx_destroy(mcx_ctx* c) {
   release(c);
 }
 
-uint64_t mcx_ncells(const mcx_ctx* c) { return c ? c->ncells() : 0; }
+uint64_t mcx_ncells(const mcx_ctx* c) { return c ? c->sims[0].ncells() : 0; }
+
+int32_t mcx_batch_size(const mcx_ctx* c) { return c ? static_cast<int32_t>(c->sims.size()) : 0; }
+
+uint64_t mcx_batch_ncells(const mcx_ctx* c, int32_t sim) {
+  if (!c || sim < 0 || sim >= static_cast<int32_t>(c->sims.size())) return 0;
+  return c->sims[sim].ncells();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ runs
 
 static hipStream_t pick_stream(mcx_ctx* c, void* s) {
   return s ? static_cast<hipStream_t>(s) : c->stream;
 }
 
-mcx_status mcx_reset(mcx_ctx* c, void* stream) {
-  if (!c) return fail(MCX_EINVAL, "context is NULL");
-  HIP_TRY(hipSetDevice(c->device));
-  hipStream_t st = pick_stream(c, stream);
-  HIP_TRY(mcx::launch_clear(c->d_tally, c->ncells(), c->d_ledger, c->d_counts, c->d_det_count,
-                            c->d_reduce, st));
-  if (c->diag)
-    HIP_TRY(hipMemsetAsync(c->d_digest, 0, c->opt.ndigest * mcx::kDigestN * sizeof(double), st));
-  c->photons = 0;
-  c->have_timing = false;
-  return MCX_OK;
-}
+// Enqueue one launch: photons [first[i], first[i] + n[i]) of simulation i
+// with seed seed[i], accumulating into the current tallies.
+static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
+                          const uint64_t* seed, hipStream_t st) {
+  const size_t ns = c->sims.size();
+  std::vector<mcx::SimDesc> desc(ns);
+  std::vector<uint64_t> job_start(ns + 1, 0);
+  for (size_t i = 0; i < ns; ++i) {
+    const SimHost& sh = c->sims[i];
+    mcx::SimDesc& d = desc[i];
+    memset(&d, 0, sizeof(d));
+    d.labels = c->d_labels + sh.label_off;
+    d.nx = sh.nx;
+    d.ny = sh.ny;
+    d.nz = sh.nz;
+    d.nvox = sh.nvox;
+    d.stride_y = static_cast<uint32_t>(sh.nx);
+    d.stride_z = static_cast<uint32_t>(sh.nx) * static_cast<uint32_t>(sh.ny);
+    d.h = sh.h;
+    d.inv_h = static_cast<float>(1.0 / sh.h);
+    d.tables = c->d_tables + sh.table_off;
+    d.nmedia = sh.nmedia;
+    d.ndet = sh.ndet;
+    d.src_ix = sh.src_i[0];
+    d.src_iy = sh.src_i[1];
+    d.src_iz = sh.src_i[2];
+    d.src_label = sh.src_label;
+    d.src_lin = static_cast<uint32_t>(sh.src_i[0]) + d.stride_y * sh.src_i[1] +
+                d.stride_z * sh.src_i[2];
+    d.src_fx = sh.src_f[0];
+    d.src_fy = sh.src_f[1];
+    d.src_fz = sh.src_f[2];
+    d.src_vx = sh.src_dir[0];
+    d.src_vy = sh.src_dir[1];
+    d.src_vz = sh.src_dir[2];
+    d.t0 = sh.t0;
+    d.inv_dt = static_cast<float>(1.0 / sh.dt);
+    d.t_end =
+        static_cast<float>(static_cast<double>(sh.t0) + static_cast<double>(sh.ngates) * sh.dt);
+    d.ngates = sh.ngates;
+    d.reflect = sh.reflect;
+    d.n_out = sh.n_out;
+    d.first = first[i];
+    d.nphoton = n[i];
+    d.key0 = static_cast<uint32_t>(seed[i]);
+    d.key1 = static_cast<uint32_t>(seed[i] >> 32);
+    d.tally = c->d_tally + sh.tally_off;
+    d.ledger = c->d_ledger + i * mcx::kLedgerN;
+    d.counts = c->d_counts + i * mcx::kCountN;
+    d.det_count = c->d_det_count + i;
+    if (sh.ndet > 0 && c->d_rec) {
+      d.det_rec = c->d_rec + sh.rec_foff;
+      d.det_photon = c->d_rec_photon + sh.rec_off;
+      d.det_cap = c->opt.max_detected;
+    }
+    d.rec_len = sh.rec_len;
+    if (c->diag) {
+      d.digest = c->d_digest + i * c->opt.ndigest * mcx::kDigestN;
+      d.ndigest = c->opt.ndigest;
+    }
+    job_start[i + 1] = job_start[i] + (n[i] + c->chunk - 1) / c->chunk;
+  }
+  mcx::LaunchParams lp{};
+  lp.sims = c->d_desc;
+  lp.nsims = static_cast<int32_t>(ns);
+  lp.job_start = c->d_job_start;
+  lp.njobs = job_start[ns];
+  lp.chunk = static_cast<uint32_t>(c->chunk);
+  lp.job_counter = c->d_job_counter;
+  lp.rr_threshold = c->opt.rr_threshold;
+  lp.rr_p = static_cast<float>(1.0 / c->opt.rr_m);
+  lp.rr_m = c->opt.rr_m;
+  lp.max_events = static_cast<uint32_t>(c->opt.max_events);
+  lp.table_rows = c->table_rows;
+  lp.nmedia_max = c->nmedia_max;
+  lp.wx0 = c->win[0];
+  lp.wy0 = c->win[1];
+  lp.wz0 = c->win[2];
+  lp.wnx = c->win[3];
+  lp.wny = c->win[4];
+  lp.wnz = c->win[5];
+  lp.wng = c->win[6];
 
-static mcx_status enqueue(mcx_ctx* c, uint64_t first, uint64_t n, uint64_t seed, hipStream_t st) {
-  mcx::TransportParams p{};
-  p.labels = c->d_labels;
-  p.nx = c->nx;
-  p.ny = c->ny;
-  p.nz = c->nz;
-  p.nvox = c->nvox;
-  p.h = c->h;
-  p.inv_h = static_cast<float>(1.0 / c->h);
-  p.media = c->d_table;
-  p.nmedia = c->nmedia;
-  p.ndet = c->ndet;
-  p.src_ix = c->src_i[0];
-  p.src_iy = c->src_i[1];
-  p.src_iz = c->src_i[2];
-  p.src_label = c->src_label;
-  p.src_fx = c->src_f[0];
-  p.src_fy = c->src_f[1];
-  p.src_fz = c->src_f[2];
-  p.src_vx = c->src_dir[0];
-  p.src_vy = c->src_dir[1];
-  p.src_vz = c->src_dir[2];
-  p.t0 = c->t0;
-  p.inv_dt = static_cast<float>(1.0 / c->dt);
-  p.t_end = static_cast<float>(static_cast<double>(c->t0) + static_cast<double>(c->ngates) * c->dt);
-  p.ngates = c->ngates;
-  p.reflect = c->opt.reflect ? 1 : 0;
-  p.n_out = c->opt.n_outside;
-  p.rr_threshold = c->opt.rr_threshold;
-  p.rr_p = static_cast<float>(1.0 / c->opt.rr_m);
-  p.rr_m = c->opt.rr_m;
-  p.max_events = static_cast<uint32_t>(c->opt.max_events);
-  p.first = first;
-  p.nphoton = n;
-  p.key0 = static_cast<uint32_t>(seed);
-  p.key1 = static_cast<uint32_t>(seed >> 32);
-  p.chunk = c->opt.refill_chunk > 0 ? static_cast<uint32_t>(c->opt.refill_chunk) : kDefaultChunk;
-  p.wx0 = c->win[0];
-  p.wy0 = c->win[1];
-  p.wz0 = c->win[2];
-  p.wnx = c->win[3];
-  p.wny = c->win[4];
-  p.wnz = c->win[5];
-  p.wng = c->win[6];
-  p.tally = c->d_tally;
-  p.photon_counter = c->d_counter;
-  p.ledger = c->d_ledger;
-  p.counts = c->d_counts;
-  p.det_rec = c->d_rec;
-  p.det_photon = c->d_rec_photon;
-  p.det_count = c->d_det_count;
-  p.det_cap = c->d_rec ? c->opt.max_detected : 0;
-  p.rec_len = c->rec_len;
-  p.digest = c->d_digest;
-  p.ndigest = c->diag ? c->opt.ndigest : 0;
-
-  // Each launch reads its parameters from its own device slot, so launches
-  // queued back to back (even on different streams, up to kParamSlots deep)
-  // never see each other's parameters.
-  mcx::TransportParams* slot = c->d_params + (c->launches++ % kParamSlots);
-  HIP_TRY(hipMemcpyAsync(slot, &p, sizeof(p), hipMemcpyHostToDevice, st));
-  HIP_TRY(mcx::launch_reset_counter(c->d_counter, st));
+  // Parameter blocks are copied in stream order before the launch that reads
+  // them (pageable sources are staged by the runtime before the call returns).
+  HIP_TRY(hipMemcpyAsync(c->d_desc, desc.data(), ns * sizeof(mcx::SimDesc),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->d_job_start, job_start.data(), (ns + 1) * sizeof(uint64_t),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->d_launch, &lp, sizeof(lp), hipMemcpyHostToDevice, st));
+  HIP_TRY(mcx::launch_reset_counter(c->d_job_counter, st));
   HIP_TRY(hipEventRecord(c->ev_k0, st));
-  HIP_TRY(mcx::launch_transport(p, slot, c->grid, c->block, st, c->detect, c->diag,
+  HIP_TRY(mcx::launch_transport(lp, c->d_launch, c->grid, c->block, st, c->detect, c->diag,
                                 c->opt.accurate_math != 0));
   HIP_TRY(hipEventRecord(c->ev_k1, st));
-  HIP_TRY(hipMemsetAsync(c->d_reduce, 0, 2 * sizeof(double), st));
-  HIP_TRY(mcx::launch_reduce(c->d_tally, c->d_labels, c->d_table, c->nvox, c->ngates,
-                             c->d_reduce, st));
+  HIP_TRY(hipMemsetAsync(c->d_reduce, 0, ns * 2 * sizeof(double), st));
+  for (size_t i = 0; i < ns; ++i) {
+    const SimHost& sh = c->sims[i];
+    HIP_TRY(mcx::launch_reduce(c->d_tally + sh.tally_off, c->d_labels + sh.label_off,
+                               c->d_tables + sh.table_off, sh.nvox, sh.ngates,
+                               c->d_reduce + 2 * i, st));
+  }
   HIP_TRY(hipEventRecord(c->ev_end, st));
-  c->photons += n;
+  for (size_t i = 0; i < ns; ++i) c->sims[i].photons += n[i];
   c->have_timing = true;
   return MCX_OK;
 }
 
+// Split ranges longer than one launch allows into several launches.
+static mcx_status enqueue_all(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
+                              const uint64_t* seed, hipStream_t st) {
+  const size_t ns = c->sims.size();
+  for (size_t i = 0; i < ns; ++i)
+    if (n[i] > (1ull << 62) || first[i] > (1ull << 62))
+      return fail(MCX_EINVAL, "photon range too large");
+  std::vector<uint64_t> f(first, first + ns), left(n, n + ns), part(ns);
+  for (;;) {
+    for (size_t i = 0; i < ns; ++i) part[i] = std::min(left[i], kMaxLaunchPhotons);
+    MCX_TRY(enqueue(c, f.data(), part.data(), seed, st));
+    bool done = true;
+    for (size_t i = 0; i < ns; ++i) {
+      f[i] += part[i];
+      left[i] -= part[i];
+      done = done && left[i] == 0;
+    }
+    if (done) break;
+  }
+  return MCX_OK;
+}
+
+extern "C" {
+
+mcx_status mcx_reset(mcx_ctx* c, void* stream) {
+  if (!c) return fail(MCX_EINVAL, "context is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  return clear_all(c, pick_stream(c, stream));
+}
+
 mcx_status mcx_run_range(mcx_ctx* c, uint64_t first, uint64_t n, uint64_t seed, void* stream) {
   if (!c) return fail(MCX_EINVAL, "context is NULL");
-  if (n > (1ull << 62) || first > (1ull << 62)) return fail(MCX_EINVAL, "photon range too large");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = pick_stream(c, stream);
+  const size_t ns = c->sims.size();
+  std::vector<uint64_t> f(ns, first), nn(ns, n), sd(ns, seed);
   HIP_TRY(hipEventRecord(c->ev_begin, st));
-  return enqueue(c, first, n, seed, st);
+  return enqueue_all(c, f.data(), nn.data(), sd.data(), st);
 }
 
 mcx_status mcx_run(mcx_ctx* c, uint64_t nphoton, uint64_t seed) {
   if (!c) return fail(MCX_EINVAL, "context is NULL");
-  if (nphoton > (1ull << 62)) return fail(MCX_EINVAL, "photon count too large");
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipEventRecord(c->ev_begin, c->stream));
-  mcx_status st = mcx_reset(c, c->stream);
-  if (st != MCX_OK) return st;
-  st = enqueue(c, 0, nphoton, seed, c->stream);
-  if (st != MCX_OK) return st;
+  MCX_TRY(clear_all(c, c->stream));
+  const size_t ns = c->sims.size();
+  std::vector<uint64_t> f(ns, 0), nn(ns, nphoton), sd(ns, seed);
+  MCX_TRY(enqueue_all(c, f.data(), nn.data(), sd.data(), c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MCX_OK;
+}
+
+mcx_status mcx_batch_run_range(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
+                               const uint64_t* seed, void* stream) {
+  if (!c || !n || !seed) return fail(MCX_EINVAL, "context, counts and seeds are required");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = pick_stream(c, stream);
+  std::vector<uint64_t> zero(c->sims.size(), 0);
+  HIP_TRY(hipEventRecord(c->ev_begin, st));
+  return enqueue_all(c, first ? first : zero.data(), n, seed, st);
+}
+
+mcx_status mcx_batch_run(mcx_ctx* c, const uint64_t* nphoton, const uint64_t* seed) {
+  if (!c || !nphoton || !seed) return fail(MCX_EINVAL, "context, counts and seeds are required");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipEventRecord(c->ev_begin, c->stream));
+  MCX_TRY(clear_all(c, c->stream));
+  std::vector<uint64_t> zero(c->sims.size(), 0);
+  MCX_TRY(enqueue_all(c, zero.data(), nphoton, seed, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return MCX_OK;
 }
@@ -476,102 +679,73 @@ mcx_status mcx_sync(mcx_ctx* c) {
   return MCX_OK;
 }
 
-static mcx_status scale_for(mcx_ctx* c, int32_t kind, double* scale) {
+}  // extern "C"
+
+// ------------------------------------------------------------- outputs
+
+static mcx_status check_sim(const mcx_ctx* c, int32_t sim) {
+  if (!c) return fail(MCX_EINVAL, "context is NULL");
+  if (sim < 0 || sim >= static_cast<int32_t>(c->sims.size()))
+    return fail(MCX_EINVAL, "simulation %d out of range [0, %zu)", sim, c->sims.size());
+  return MCX_OK;
+}
+
+static mcx_status scale_for(const SimHost& sh, int32_t kind, double* scale) {
   if (kind == MCX_RAW) {
     *scale = 1.0;
     return MCX_OK;
   }
   if (kind != MCX_FLUENCE && kind != MCX_FLUENCE_RATE)
     return fail(MCX_EINVAL, "kind must be 0 (raw), 1 (fluence) or 2 (fluence rate)");
-  if (c->photons == 0) return fail(MCX_ESTATE, "no photons simulated since the last reset");
-  const double hv = static_cast<double>(c->h);
-  double s = 1.0 / (static_cast<double>(c->photons) * hv * hv * hv);
-  if (kind == MCX_FLUENCE_RATE) s /= static_cast<double>(c->dt);
+  if (sh.photons == 0) return fail(MCX_ESTATE, "no photons simulated since the last reset");
+  const double hv = static_cast<double>(sh.h);
+  double s = 1.0 / (static_cast<double>(sh.photons) * hv * hv * hv);
+  if (kind == MCX_FLUENCE_RATE) s /= static_cast<double>(sh.dt);
   *scale = s;
   return MCX_OK;
 }
 
-mcx_status mcx_fluence_device(mcx_ctx* c, int32_t kind, float* dev_out, uint64_t ncells,
-                              void* stream) {
-  if (!c || !dev_out) return fail(MCX_EINVAL, "context and output are required");
-  if (ncells < c->ncells()) return fail(MCX_ERANGE, "output holds %llu cells, need %llu",
-                                        static_cast<unsigned long long>(ncells),
-                                        static_cast<unsigned long long>(c->ncells()));
+static mcx_status fluence_host(mcx_ctx* c, int32_t sim, int32_t kind, void* host_out,
+                               uint64_t ncells, bool f64) {
+  MCX_TRY(check_sim(c, sim));
+  const SimHost& sh = c->sims[sim];
+  if (!host_out) return fail(MCX_EINVAL, "output is NULL");
+  if (ncells < sh.ncells())
+    return fail(MCX_ERANGE, "output holds %llu cells, need %llu",
+                static_cast<unsigned long long>(ncells),
+                static_cast<unsigned long long>(sh.ncells()));
   double scale = 1.0;
-  mcx_status st = scale_for(c, kind, &scale);
-  if (st != MCX_OK) return st;
+  MCX_TRY(scale_for(sh, kind, &scale));
   HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(mcx::launch_normalise_f32(c->d_tally, c->ncells(), scale, dev_out,
-                                    pick_stream(c, stream)));
-  return MCX_OK;
-}
-
-mcx_status mcx_fluence(mcx_ctx* c, int32_t kind, float* host_out, uint64_t ncells) {
-  if (!c || !host_out) return fail(MCX_EINVAL, "context and output are required");
-  if (ncells < c->ncells()) return fail(MCX_ERANGE, "output holds %llu cells, need %llu",
-                                        static_cast<unsigned long long>(ncells),
-                                        static_cast<unsigned long long>(c->ncells()));
-  double scale = 1.0;
-  mcx_status st = scale_for(c, kind, &scale);
-  if (st != MCX_OK) return st;
-  HIP_TRY(hipSetDevice(c->device));
-  if (!c->d_stage32) HIP_TRY(hipMalloc(&c->d_stage32, c->ncells() * sizeof(float)));
-  HIP_TRY(mcx::launch_normalise_f32(c->d_tally, c->ncells(), scale, c->d_stage32, c->stream));
-  HIP_TRY(hipMemcpyAsync(host_out, c->d_stage32, c->ncells() * sizeof(float),
-                         hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return MCX_OK;
-}
-
-mcx_status mcx_fluence_f64(mcx_ctx* c, int32_t kind, double* host_out, uint64_t ncells) {
-  if (!c || !host_out) return fail(MCX_EINVAL, "context and output are required");
-  if (ncells < c->ncells()) return fail(MCX_ERANGE, "output holds %llu cells, need %llu",
-                                        static_cast<unsigned long long>(ncells),
-                                        static_cast<unsigned long long>(c->ncells()));
-  double scale = 1.0;
-  mcx_status st = scale_for(c, kind, &scale);
-  if (st != MCX_OK) return st;
-  HIP_TRY(hipSetDevice(c->device));
-  if (!c->d_stage64) HIP_TRY(hipMalloc(&c->d_stage64, c->ncells() * sizeof(double)));
-  HIP_TRY(mcx::launch_normalise_f64(c->d_tally, c->ncells(), scale, c->d_stage64, c->stream));
-  HIP_TRY(hipMemcpyAsync(host_out, c->d_stage64, c->ncells() * sizeof(double),
-                         hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return MCX_OK;
-}
-
-mcx_status mcx_detected(mcx_ctx* c, float* host_rec, uint64_t* host_photon, uint64_t cap,
-                        uint64_t* nrec, uint64_t* ndropped) {
-  if (!c) return fail(MCX_EINVAL, "context is NULL");
-  if (cap > 0 && !host_rec) return fail(MCX_EINVAL, "record buffer is NULL");
-  HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  unsigned long long total = 0;
-  HIP_TRY(hipMemcpy(&total, c->d_det_count, sizeof(total), hipMemcpyDeviceToHost));
-  const uint64_t stored = c->d_rec ? (total < c->opt.max_detected ? total : c->opt.max_detected) : 0;
-  const uint64_t copy = stored < cap ? stored : cap;
-  if (copy > 0) {
-    HIP_TRY(hipMemcpy(host_rec, c->d_rec, copy * c->rec_len * sizeof(float), hipMemcpyDeviceToHost));
-    if (host_photon)
-      HIP_TRY(hipMemcpy(host_photon, c->d_rec_photon, copy * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  const double* tally = c->d_tally + sh.tally_off;
+  if (f64) {
+    if (!c->d_stage64) HIP_TRY(hipMalloc(&c->d_stage64, c->max_cells * sizeof(double)));
+    HIP_TRY(mcx::launch_normalise_f64(tally, sh.ncells(), scale, c->d_stage64, c->stream));
+    HIP_TRY(hipMemcpyAsync(host_out, c->d_stage64, sh.ncells() * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  } else {
+    if (!c->d_stage32) HIP_TRY(hipMalloc(&c->d_stage32, c->max_cells * sizeof(float)));
+    HIP_TRY(mcx::launch_normalise_f32(tally, sh.ncells(), scale, c->d_stage32, c->stream));
+    HIP_TRY(hipMemcpyAsync(host_out, c->d_stage32, sh.ncells() * sizeof(float),
+                           hipMemcpyDeviceToHost, c->stream));
   }
-  if (nrec) *nrec = copy;
-  if (ndropped) *ndropped = total - stored;
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return MCX_OK;
 }
 
-mcx_status mcx_stats(mcx_ctx* c, mcx_run_stats* o) {
-  if (!c || !o) return fail(MCX_EINVAL, "context and output are required");
+static mcx_status stats_of(mcx_ctx* c, int32_t sim, mcx_run_stats* o) {
+  MCX_TRY(check_sim(c, sim));
+  if (!o) return fail(MCX_EINVAL, "output is NULL");
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipStreamSynchronize(c->stream));
   double led[mcx::kLedgerN];
   unsigned long long cnt[mcx::kCountN];
   unsigned long long det_total = 0;
   double red[2];
-  HIP_TRY(hipMemcpy(led, c->d_ledger, sizeof(led), hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(cnt, c->d_counts, sizeof(cnt), hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(&det_total, c->d_det_count, sizeof(det_total), hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(red, c->d_reduce, sizeof(red), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(led, c->d_ledger + sim * mcx::kLedgerN, sizeof(led), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(cnt, c->d_counts + sim * mcx::kCountN, sizeof(cnt), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(&det_total, c->d_det_count + sim, sizeof(det_total), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(red, c->d_reduce + 2 * sim, sizeof(red), hipMemcpyDeviceToHost));
   memset(o, 0, sizeof(*o));
   o->launched = cnt[mcx::kCntLaunched];
   o->escaped = cnt[mcx::kCntEscaped];
@@ -588,7 +762,8 @@ mcx_status mcx_stats(mcx_ctx* c, mcx_run_stats* o) {
   o->events = cnt[mcx::kCntEvents];
   o->lane_slots = cnt[mcx::kCntLaneSlots];
   o->flushes = cnt[mcx::kCntFlushes];
-  const uint64_t cap = c->d_rec ? c->opt.max_detected : 0;
+  const SimHost& sh = c->sims[sim];
+  const uint64_t cap = (sh.ndet > 0 && c->d_rec) ? c->opt.max_detected : 0;
   o->det_records = det_total < cap ? det_total : cap;
   o->det_dropped = det_total - o->det_records;
   o->w_launched = static_cast<double>(cnt[mcx::kCntLaunched]);
@@ -610,15 +785,195 @@ mcx_status mcx_stats(mcx_ctx* c, mcx_run_stats* o) {
   return MCX_OK;
 }
 
-mcx_status mcx_digest(mcx_ctx* c, double* host_out, uint64_t nrows) {
-  if (!c || !host_out) return fail(MCX_EINVAL, "context and output are required");
-  if (!c->diag) return fail(MCX_ESTATE, "context was created with ndigest = 0");
-  if (nrows > c->opt.ndigest) return fail(MCX_ERANGE, "only %llu digest rows are kept",
-                                          static_cast<unsigned long long>(c->opt.ndigest));
+extern "C" {
+
+mcx_status mcx_fluence(mcx_ctx* c, int32_t kind, float* host_out, uint64_t ncells) {
+  return fluence_host(c, 0, kind, host_out, ncells, false);
+}
+
+mcx_status mcx_fluence_f64(mcx_ctx* c, int32_t kind, double* host_out, uint64_t ncells) {
+  return fluence_host(c, 0, kind, host_out, ncells, true);
+}
+
+mcx_status mcx_batch_fluence(mcx_ctx* c, int32_t sim, int32_t kind, float* host_out,
+                             uint64_t ncells) {
+  return fluence_host(c, sim, kind, host_out, ncells, false);
+}
+
+mcx_status mcx_batch_fluence_f64(mcx_ctx* c, int32_t sim, int32_t kind, double* host_out,
+                                 uint64_t ncells) {
+  return fluence_host(c, sim, kind, host_out, ncells, true);
+}
+
+mcx_status mcx_fluence_device(mcx_ctx* c, int32_t kind, float* dev_out, uint64_t ncells,
+                              void* stream) {
+  MCX_TRY(check_sim(c, 0));
+  if (!dev_out) return fail(MCX_EINVAL, "output is NULL");
+  const SimHost& sh = c->sims[0];
+  if (ncells < sh.ncells())
+    return fail(MCX_ERANGE, "output holds %llu cells, need %llu",
+                static_cast<unsigned long long>(ncells),
+                static_cast<unsigned long long>(sh.ncells()));
+  double scale = 1.0;
+  MCX_TRY(scale_for(sh, kind, &scale));
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(mcx::launch_normalise_f32(c->d_tally + sh.tally_off, sh.ncells(), scale, dev_out,
+                                    pick_stream(c, stream)));
+  return MCX_OK;
+}
+
+}  // extern "C"
+
+static mcx_status detected_of(mcx_ctx* c, int32_t sim, float* host_rec, uint64_t* host_photon,
+                              uint64_t cap, uint64_t* nrec, uint64_t* ndropped) {
+  MCX_TRY(check_sim(c, sim));
+  if (cap > 0 && !host_rec) return fail(MCX_EINVAL, "record buffer is NULL");
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  HIP_TRY(hipMemcpy(host_out, c->d_digest, nrows * mcx::kDigestN * sizeof(double),
-                    hipMemcpyDeviceToHost));
+  const SimHost& sh = c->sims[sim];
+  unsigned long long total = 0;
+  HIP_TRY(hipMemcpy(&total, c->d_det_count + sim, sizeof(total), hipMemcpyDeviceToHost));
+  const uint64_t room = (sh.ndet > 0 && c->d_rec) ? c->opt.max_detected : 0;
+  const uint64_t stored = total < room ? total : room;
+  const uint64_t copy = stored < cap ? stored : cap;
+  if (copy > 0) {
+    HIP_TRY(hipMemcpy(host_rec, c->d_rec + sh.rec_foff,
+                      copy * sh.rec_len * sizeof(float), hipMemcpyDeviceToHost));
+    if (host_photon)
+      HIP_TRY(hipMemcpy(host_photon, c->d_rec_photon + sh.rec_off, copy * sizeof(uint64_t),
+                        hipMemcpyDeviceToHost));
+  }
+  if (nrec) *nrec = copy;
+  if (ndropped) *ndropped = total - stored;
+  return MCX_OK;
+}
+
+static mcx_status digest_of(mcx_ctx* c, int32_t sim, double* host_out, uint64_t nrows) {
+  MCX_TRY(check_sim(c, sim));
+  if (!host_out) return fail(MCX_EINVAL, "output is NULL");
+  if (!c->diag) return fail(MCX_ESTATE, "context was created with ndigest = 0");
+  if (nrows > c->opt.ndigest)
+    return fail(MCX_ERANGE, "only %llu digest rows are kept",
+                static_cast<unsigned long long>(c->opt.ndigest));
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(host_out, c->d_digest + sim * c->opt.ndigest * mcx::kDigestN,
+                    nrows * mcx::kDigestN * sizeof(double), hipMemcpyDeviceToHost));
+  return MCX_OK;
+}
+
+extern "C" {
+
+mcx_status mcx_detected(mcx_ctx* c, float* host_rec, uint64_t* host_photon, uint64_t cap,
+                        uint64_t* nrec, uint64_t* ndropped) {
+  return detected_of(c, 0, host_rec, host_photon, cap, nrec, ndropped);
+}
+
+mcx_status mcx_batch_detected(mcx_ctx* c, int32_t sim, float* host_rec, uint64_t* host_photon,
+                              uint64_t cap, uint64_t* nrec, uint64_t* ndropped) {
+  return detected_of(c, sim, host_rec, host_photon, cap, nrec, ndropped);
+}
+
+mcx_status mcx_stats(mcx_ctx* c, mcx_run_stats* o) { return stats_of(c, 0, o); }
+
+mcx_status mcx_batch_stats(mcx_ctx* c, int32_t sim, mcx_run_stats* o) {
+  return stats_of(c, sim, o);
+}
+
+mcx_status mcx_digest(mcx_ctx* c, double* host_out, uint64_t nrows) {
+  return digest_of(c, 0, host_out, nrows);
+}
+
+mcx_status mcx_batch_digest(mcx_ctx* c, int32_t sim, double* host_out, uint64_t nrows) {
+  return digest_of(c, sim, host_out, nrows);
+}
+
+mcx_status mcx_set_launch(mcx_ctx* c, int32_t block_size, int32_t refill_chunk,
+                          int32_t lds_window_cells) {
+  if (!c) return fail(MCX_EINVAL, "context is NULL");
+  if (block_size != 0 && (block_size < 64 || block_size > 1024 || block_size % 64))
+    return fail(MCX_EINVAL, "block_size must be 0 or a multiple of 64 in [64, 1024]");
+  if (refill_chunk != 0 && refill_chunk < 64)
+    return fail(MCX_EINVAL, "refill_chunk must be 0 or >= 64");
+  if (lds_window_cells > 8192) return fail(MCX_EINVAL, "lds_window_cells must be <= 8192");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  set_window(c, lds_window_cells == 0 ? kDefaultWindow : lds_window_cells);
+  c->chunk = refill_chunk > 0 ? refill_chunk : kDefaultChunk;
+  return set_shape(c, block_size);
+}
+
+// ------------------------------------------------------------- autotune
+
+// Pilot launches over block size x refill chunk x LDS window (the window only
+// for a single simulation); the fastest shape is kept.  Then the paper's
+// device model T = a n + T0 is fitted from two pilot sizes (n and n/2) with
+// that shape.  Tallies are cleared afterwards.
+mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_t* seed,
+                        mcx_tune_result* out) {
+  if (!c || !pilot_photons || !seed || !out)
+    return fail(MCX_EINVAL, "context, pilot photon counts, seeds and output are required");
+  HIP_TRY(hipSetDevice(c->device));
+  const size_t ns = c->sims.size();
+  std::vector<uint64_t> zero(ns, 0), half(ns);
+  for (size_t i = 0; i < ns; ++i) half[i] = pilot_photons[i] / 2;
+
+  auto pilot = [&](const uint64_t* n, float* ms) -> mcx_status {
+    MCX_TRY(clear_all(c, c->stream));
+    MCX_TRY(enqueue_all(c, zero.data(), n, seed, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipEventElapsedTime(ms, c->ev_k0, c->ev_k1));
+    return MCX_OK;
+  };
+
+  memset(out, 0, sizeof(*out));
+  const int blocks[] = {64, 256, 448, 512, 1024};
+  const int chunks[] = {64, 256, 1024, 4096};
+  const int windows[] = {-1, 4096, 8192};
+  const int nwin = ns == 1 ? 3 : 1;
+  // the untuned default shape first (after one warm-up launch)
+  MCX_TRY(mcx_set_launch(c, 0, 0, ns == 1 ? 0 : -1));
+  float ms = 0.f;
+  MCX_TRY(pilot(pilot_photons, &ms));
+  MCX_TRY(pilot(pilot_photons, &ms));
+  out->default_ms = ms;
+  float best = ms;
+  out->block_size = c->block;
+  out->refill_chunk = c->chunk;
+  out->lds_window_cells = ns == 1 ? kDefaultWindow : -1;
+  int nc = 1;
+  for (int wi = 0; wi < nwin; ++wi) {
+    for (int b : blocks) {
+      for (int ch : chunks) {
+        if (mcx_set_launch(c, b, ch, ns == 1 ? windows[wi] : -1) != MCX_OK) continue;
+        MCX_TRY(pilot(pilot_photons, &ms));
+        ++nc;
+        if (ms < best) {
+          best = ms;
+          out->block_size = c->block;
+          out->refill_chunk = ch;
+          out->lds_window_cells = ns == 1 ? windows[wi] : -1;
+        }
+      }
+    }
+  }
+  out->candidates = nc;
+  out->best_ms = best;
+  MCX_TRY(mcx_set_launch(c, out->block_size, out->refill_chunk, out->lds_window_cells));
+  float t_full = 0.f, t_half = 0.f;
+  MCX_TRY(pilot(pilot_photons, &t_full));
+  MCX_TRY(pilot(half.data(), &t_half));
+  uint64_t n_full = 0, n_half = 0;
+  for (size_t i = 0; i < ns; ++i) {
+    n_full += pilot_photons[i];
+    n_half += half[i];
+  }
+  if (n_full > n_half) {
+    out->ms_per_photon = (t_full - t_half) / static_cast<double>(n_full - n_half);
+    out->overhead_ms = t_full - out->ms_per_photon * static_cast<double>(n_full);
+  }
+  MCX_TRY(clear_all(c, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return MCX_OK;
 }
 

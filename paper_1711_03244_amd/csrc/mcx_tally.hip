@@ -9,17 +9,15 @@ namespace {
 
 __global__ void clear_kernel(double* tally, uint64_t ncells, double* ledger,
                              unsigned long long* counts, unsigned long long* det_count,
-                             double* reduce) {
+                             int nsims) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < ncells;
-       i += stride)
-    tally[i] = 0.0;
-  if (blockIdx.x == 0) {
-    if (threadIdx.x < kLedgerN) ledger[threadIdx.x] = 0.0;
-    if (threadIdx.x < kCountN) counts[threadIdx.x] = 0ull;
-    if (threadIdx.x == 0) *det_count = 0ull;
-    if (threadIdx.x < 2) reduce[threadIdx.x] = 0.0;
-  }
+  const uint64_t first = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (uint64_t i = first; i < ncells; i += stride) tally[i] = 0.0;
+  for (uint64_t i = first; i < static_cast<uint64_t>(nsims) * kLedgerN; i += stride)
+    ledger[i] = 0.0;
+  for (uint64_t i = first; i < static_cast<uint64_t>(nsims) * kCountN; i += stride)
+    counts[i] = 0ull;
+  for (uint64_t i = first; i < static_cast<uint64_t>(nsims); i += stride) det_count[i] = 0ull;
 }
 
 __global__ void reset_counter_kernel(unsigned long long* counter) { *counter = 0ull; }
@@ -81,9 +79,11 @@ int grid_for(uint64_t n, int block, int cap) {
 
 hipError_t launch_clear(double* tally, uint64_t ncells, double* ledger,
                         unsigned long long* counts, unsigned long long* det_count,
-                        double* reduce, hipStream_t s) {
-  clear_kernel<<<grid_for(ncells, 256, 8192), 256, 0, s>>>(tally, ncells, ledger, counts,
-                                                           det_count, reduce);
+                        int nsims, hipStream_t s) {
+  const uint64_t n = ncells > static_cast<uint64_t>(nsims) * kCountN
+                         ? ncells : static_cast<uint64_t>(nsims) * kCountN;
+  clear_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(tally, ncells, ledger, counts, det_count,
+                                                      nsims);
   return hipGetLastError();
 }
 

@@ -7,12 +7,17 @@
 // Russian roulette and detector capture.  The paper's in-workgroup dynamic
 // load balancing (a shared photon quota that threads decrement to start
 // their next photon) becomes wave-level refill: whenever lanes of a wave
-// finish, the wave hands them the next photon indices from a chunk it took
-// from a global 64-bit counter, so a wave keeps all 64 lanes busy until the
-// photon supply runs out.
+// finish, the wave hands them the next photon indices from a job (a chunk of
+// photons of one simulation) it took from a global 64-bit job counter, so a
+// wave keeps its 64 lanes busy until the supply runs out.  One launch can
+// serve many independent simulations of different grids and photon counts:
+// a wave works on one simulation at a time (its descriptor is read with
+// scalar loads) and moves to the next simulation's job once its lanes are
+// done.
 //
-// Per-lane state stays in registers; the media table, detectors, the
-// per-lane partial pathlengths and an FP64 energy ledger live in LDS.
+// Per-lane state stays in registers; each wave keeps its simulation's media
+// table and detectors, an FP64 energy ledger and rare-event counters in its
+// own slice of LDS, and the lanes' partial pathlengths in LDS.
 // Deposits made while a photon stays in one tally cell are summed in a
 // register and flushed once when it leaves the cell.  Flushes into the
 // densest cells -- a box of cells around the source, the "window" -- go to
@@ -68,6 +73,32 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
   const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), lane);
   const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), lane);
   return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Pointers read from the descriptors are generic; these casts tell the
+// compiler where they point, so that descriptor fields are read with scalar
+// loads from the constant space and labels / tallies with global (not flat)
+// instructions.
+#define MCX_CONST __attribute__((address_space(4)))
+#define MCX_GLOBAL __attribute__((address_space(1)))
+using CSim = const MCX_CONST SimDesc;
+
+template <typename T>
+__device__ __forceinline__ const MCX_CONST T* as_const(const T* p) {
+  return (const MCX_CONST T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ MCX_GLOBAL T* as_global(T* p) {
+  return (MCX_GLOBAL T*)(p);
+}
+
+// A descriptor pointer every lane holds the same value of, kept in scalar
+// registers.
+__device__ __forceinline__ CSim* uniform_sim(CSim* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return reinterpret_cast<CSim*>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 // Number of set bits of `mask` below this lane.
@@ -191,43 +222,38 @@ __device__ __forceinline__ void deposit(double* tally, double* s_win, uint32_t c
   if (slot >= 0)
     atomicAdd(s_win + slot, static_cast<double>(v));
   else
-    unsafeAtomicAdd(tally + cell, static_cast<double>(v));
+    __builtin_amdgcn_global_atomic_fadd_f64(as_global(tally) + cell, static_cast<double>(v));
 }
 
 enum : int { kEvTime = 0, kEvScat = 1, kEvCross = 2 };
 enum : int { kAlive = 0, kEndEscape = 1, kEndTime = 2, kEndRoulette = 3, kEndCapped = 4 };
 
-template <bool kDetect, bool kDiag, bool kNative>
-__global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* params) {
-  // The parameter block lives in device memory and is read where used
-  // (scalar loads that hit the scalar cache) rather than held in scalar
-  // registers for the whole persistent loop.
-  const TransportParams& P = *params;
-  extern __shared__ float4 s_tab[];
-  __shared__ double s_led[kLedgerN];
-  __shared__ unsigned long long s_cnt[kCountN];
 
-  const int ntab = 3 * P.nmedia + P.ndet;
-  const int wcells = P.wnx * P.wny * P.wnz * P.wng;
-  double* s_win = reinterpret_cast<double*>(s_tab + ntab);
-  for (int i = threadIdx.x; i < ntab; i += blockDim.x) s_tab[i] = P.media[i];
-  for (int i = threadIdx.x; i < wcells; i += blockDim.x) s_win[i] = 0.0;
-  if (threadIdx.x < kLedgerN) s_led[threadIdx.x] = 0.0;
-  if (threadIdx.x < kCountN) s_cnt[threadIdx.x] = 0ull;
-  __syncthreads();
-  const float4* s_med = s_tab;                 // (mua, mus, g, n)
-  const float4* s_der = s_tab + P.nmedia;      // (1/mus, n/c, c/n, 1/mua)
-  const float4* s_hg = s_tab + 2 * P.nmedia;   // HG constants
-  const float4* s_det = s_tab + 3 * P.nmedia;  // (x, y, z, r^2)
-  float* s_len = reinterpret_cast<float*>(s_win + wcells) + threadIdx.x;  // [m * blockDim]
-  const uint32_t bdim = blockDim.x;
+template <bool kDetect, bool kDiag, bool kNative>
+__global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* params) {
+  // Launch and simulation parameters live in device memory and are read
+  // where used (scalar loads that hit the scalar cache) rather than held in
+  // scalar registers for the whole persistent loop.
+  const LaunchParams& L = *params;
+  extern __shared__ float4 s_dyn[];
+  __shared__ double s_led[kMaxWavesPerBlock][kLedgerN];
+  __shared__ unsigned long long s_cnt[kMaxWavesPerBlock][kCountN];
 
   const uint32_t lane = __lane_id();
-  const uint32_t stride_y = static_cast<uint32_t>(P.nx);
-  const uint32_t stride_z = static_cast<uint32_t>(P.nx) * static_cast<uint32_t>(P.ny);
-  const uint32_t src_lin = P.src_ix + stride_y * P.src_iy + stride_z * P.src_iz;
-  const float src_rx = inv_speed(P.h, P.src_vx), src_ry = inv_speed(P.h, P.src_vy),
-              src_rz = inv_speed(P.h, P.src_vz);
+  const int wid = static_cast<int>(threadIdx.x >> 6);
+  const uint32_t bdim = blockDim.x;
+  const int rows = L.table_rows;
+  float4* s_tab = s_dyn + wid * rows;  // this wave's copy of its simulation's tables
+  const bool single = L.nsims == 1;
+  const int wcells = single ? L.wnx * L.wny * L.wnz * L.wng : 0;
+  double* s_win = reinterpret_cast<double*>(s_dyn + (bdim >> 6) * rows);
+  float* s_len = reinterpret_cast<float*>(s_win + wcells) + threadIdx.x;  // [m * blockDim]
+
+  for (int i = threadIdx.x; i < wcells; i += bdim) s_win[i] = 0.0;
+  if (lane < kLedgerN) s_led[wid][lane] = 0.0;
+  if (lane < kCountN) s_cnt[wid][lane] = 0ull;
+  __syncthreads();
+  const float4* s_med = s_tab;  // (mua, mus, g, n); the other tables follow at nmedia offsets
 
   // photon state
   bool alive = false;
@@ -242,65 +268,114 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
   int acc_slot = -1, old_slot = -1;
   float acc = 0.f, old_acc = 0.f;
 
-  // wave-uniform refill pool: photon offsets [pool_next, pool_end) from P.first
+  // wave-uniform state: current simulation, its photon pool [pool_next,
+  // pool_end) (offsets from its first photon), and a job taken but not yet
+  // started because the wave was still busy with another simulation
+  int cur = -1;
+  CSim* D = as_const(L.sims);
   uint64_t pool_next = 0, pool_end = 0;
-  bool dry = false;
+  bool has_pend = false, dry = false;
+  int pend_sim = 0;
+  uint64_t pend_first = 0, pend_end = 0;
   // per-wave counts of frequent events (scalar registers); rare events are
-  // counted in LDS by the lanes they happen to
+  // counted in the wave's LDS slice by the lanes they happen to
   uint32_t c_launch = 0, c_scat = 0, c_face = 0, c_fres = 0, c_ev = 0, c_slots = 0, c_flush = 0;
 
+  // add the wave's tallies of simulation `cur` to its totals and clear them
+  auto flush_wave = [&]() {
+    if (cur >= 0) {
+      if (lane == 0) {
+        unsigned long long* C = D->counts;
+        s_cnt[wid][kCntLaunched] += c_launch;
+        s_cnt[wid][kCntScatters] += c_scat;
+        s_cnt[wid][kCntFaceEvents] += c_face;
+        s_cnt[wid][kCntFresnel] += c_fres;
+        s_cnt[wid][kCntEvents] += c_ev;
+        s_cnt[wid][kCntLaneSlots] += c_slots;
+        s_cnt[wid][kCntFlushes] += c_flush;
+        for (int i = 0; i < kCountN; ++i)
+          if (s_cnt[wid][i]) atomicAdd(C + i, s_cnt[wid][i]);
+        for (int i = 0; i < kLedgerN; ++i)
+          if (s_led[wid][i] != 0.0) unsafeAtomicAdd(D->ledger + i, s_led[wid][i]);
+      }
+    }
+    if (lane < kLedgerN) s_led[wid][lane] = 0.0;
+    if (lane < kCountN) s_cnt[wid][lane] = 0ull;
+    c_launch = c_scat = c_face = c_fres = c_ev = c_slots = c_flush = 0;
+  };
+
   for (;;) {
+    // The current simulation is the same for the whole wave; say so, so that
+    // its descriptor is read with scalar loads.
+    D = uniform_sim(D);
     // ---------------------------------------------------------------- refill
     bool launched = false;
     const uint64_t dead = __ballot(!alive);
     if (dead != 0 && !dry) {
-      const uint64_t need = static_cast<uint64_t>(__popcll(dead));
-      const uint64_t rem = pool_end - pool_next;
-      uint64_t nbase = 0;
-      bool grabbed = false;
-      if (rem < need) {
+      if (pool_next == pool_end && !has_pend) {
         const int leader = __ffsll(static_cast<long long>(dead)) - 1;
         unsigned long long got = 0;
-        if (static_cast<int>(lane) == leader)
-          got = atomicAdd(P.photon_counter, static_cast<unsigned long long>(P.chunk));
-        nbase = readlane_u64(got, leader);
-        grabbed = true;
-        if (nbase >= P.nphoton) dry = true;
+        if (static_cast<int>(lane) == leader) got = atomicAdd(L.job_counter, 1ull);
+        const uint64_t j = readlane_u64(got, leader);
+        if (j >= L.njobs) {
+          dry = true;
+        } else {
+          const MCX_CONST uint64_t* js = as_const(L.job_start);
+          int lo = 0, hi = L.nsims;  // job_start[lo] <= j < job_start[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (js[mid] <= j) lo = mid; else hi = mid;
+          }
+          const uint64_t off = (j - js[lo]) * L.chunk;
+          const uint64_t n = as_const(L.sims)[lo].nphoton;
+          pend_sim = lo;
+          pend_first = off;
+          pend_end = off + L.chunk < n ? off + L.chunk : n;
+          has_pend = true;
+        }
       }
+      if (pool_next == pool_end && has_pend && (pend_sim == cur || dead == ~0ull)) {
+        if (pend_sim != cur) {
+          // every lane is idle: move the wave to the job's simulation
+          flush_wave();
+          cur = pend_sim;
+          D = uniform_sim(as_const(L.sims) + cur);
+          const int nrow = 3 * D->nmedia + D->ndet;
+          for (int i = lane; i < nrow; i += 64) s_tab[i] = D->tables[i];
+          __builtin_amdgcn_wave_barrier();
+        }
+        pool_next = pend_first;
+        pool_end = pend_end;
+        has_pend = false;
+      }
+      const uint64_t rem = pool_end - pool_next;
+      const uint64_t need = static_cast<uint64_t>(__popcll(dead));
+      const uint64_t give = rem < need ? rem : need;
       if (!alive) {
         const uint64_t rank = rank_below(dead);
-        uint64_t idx = 0;
-        bool ok = false;
-        if (rank < rem) {
-          idx = pool_next + rank;
-          ok = true;
-        } else if (grabbed && !dry) {
-          idx = nbase + (rank - rem);
-          ok = idx < P.nphoton;
-        }
-        if (ok) {
-          const uint64_t k = P.first + idx;
+        if (rank < give) {
+          const uint64_t k = D->first + pool_next + rank;
           klo = static_cast<uint32_t>(k);
           khi = static_cast<uint32_t>(k >> 32);
-          const Words r = philox4x32_10(klo, khi, 0u, 0u, P.key0, P.key1);
+          const Words r = philox4x32_10(klo, khi, 0u, 0u, D->key0, D->key1);
           s = neg_log<kNative>(unit_open(r.x));
           blk = 1;
-          ix = P.src_ix;
-          iy = P.src_iy;
-          iz = P.src_iz;
-          lin = src_lin;
-          m = P.src_label;
-          fx = P.src_fx;
-          fy = P.src_fy;
-          fz = P.src_fz;
-          vx = P.src_vx;
-          vy = P.src_vy;
-          vz = P.src_vz;
-          rx = src_rx;
-          ry = src_ry;
-          rz = src_rz;
+          ix = D->src_ix;
+          iy = D->src_iy;
+          iz = D->src_iz;
+          lin = D->src_lin;
+          m = D->src_label;
+          fx = D->src_fx;
+          fy = D->src_fy;
+          fz = D->src_fz;
+          vx = D->src_vx;
+          vy = D->src_vy;
+          vz = D->src_vz;
+          rx = inv_speed(D->h, vx);
+          ry = inv_speed(D->h, vy);
+          rz = inv_speed(D->h, vz);
           w = 1.f;
-          t = P.t0;
+          t = D->t0;
           nev = 0;
           nscat = 0;
           acc_cell = 0xffffffffu;
@@ -310,41 +385,35 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
           old_slot = -1;
           old_acc = 0.f;
           if constexpr (kDetect) {
-            for (int mm = 0; mm < P.nmedia; ++mm) s_len[mm * bdim] = 0.f;
+            for (int mm = 0; mm < L.nmedia_max; ++mm) s_len[mm * bdim] = 0.f;
           }
           alive = true;
           launched = true;
         }
       }
-      if (grabbed) {
-        if (dry) {
-          pool_next = pool_end;
-        } else {
-          const uint64_t end = nbase + P.chunk < P.nphoton ? nbase + P.chunk : P.nphoton;
-          const uint64_t nxt = nbase + (need - rem);
-          pool_next = nxt < end ? nxt : end;
-          pool_end = end;
-        }
-      } else {
-        pool_next += need;
-      }
+      pool_next += give;
     }
-    c_launch += static_cast<uint32_t>(wave_count(launched));
-    if (__ballot(alive) == 0) break;
+    c_launch += wave_count(launched);
+    if (__ballot(alive) == 0) {
+      if (dry) break;
+      continue;  // the wave's lanes just finished: take the pending job next
+    }
+    D = uniform_sim(D);
     c_slots += 64;
-    c_ev += static_cast<uint32_t>(wave_count(alive));
+    c_ev += wave_count(alive);
 
     // ----------------------------------------------------------------- event
     int end = kAlive;
     int det_hit = -1;
     bool f_scat = false, f_face = false, f_fres = false, f_flush = false, f_flush2 = false;
     if (alive) {
-      if (nev >= P.max_events) {
+      if (nev >= L.max_events) {
         end = kEndCapped;
       } else {
         ++nev;
-        const float4 md = s_med[m];  // mua, mus, g, n
-        const float4 dd = s_der[m];  // 1/mus, n/c, c/n, 1/mua
+        const int nm = D->nmedia;
+        const float4 md = s_med[m];        // mua, mus, g, n
+        const float4 dd = s_med[nm + m];   // 1/mus, n/c, c/n, 1/mua
         const float ds = md.y > 0.f ? s * dd.x : kInf;
         const float dx = face_dist(fx, vx, rx), dy = face_dist(fy, vy, ry),
                     dz = face_dist(fz, vz, rz);
@@ -360,7 +429,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
           ax = 2;
           dv = dz;
         }
-        const float dtime = fmaxf((P.t_end - t) * dd.z, 0.f);
+        const float dtime = fmaxf((D->t_end - t) * dd.z, 0.f);
         int ev;
         float l;
         if (dtime < fminf(ds, dv)) {
@@ -375,9 +444,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
         }
 
         // absorption along the segment, booked at the segment-start gate
-        int gate = static_cast<int>(floorf((t - P.t0) * P.inv_dt));
-        gate = min(max(gate, 0), P.ngates - 1);
-        const uint32_t cell = static_cast<uint32_t>(gate) * P.nvox + lin;
+        int gate = static_cast<int>(floorf((t - D->t0) * D->inv_dt));
+        gate = min(max(gate, 0), D->ngates - 1);
+        const uint32_t cell = static_cast<uint32_t>(gate) * D->nvox + lin;
         const float q = one_minus_exp<kNative>(md.x * l);  // 1 - exp(-mua l)
         const float dep = md.x > 0.f ? w * q * dd.w : w * l;
         if (cell == acc_cell) {
@@ -394,26 +463,29 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
           acc_cell = cell;
         } else {
           if (old_cell != 0xffffffffu && old_acc != 0.f) {
-            deposit(P.tally, s_win, old_cell, old_slot, old_acc);
+            deposit(D->tally, s_win, old_cell, old_slot, old_acc);
             f_flush = old_slot < 0;
           }
           old_cell = acc_cell;
           old_slot = acc_slot;
           old_acc = acc;
-          const uint32_t ux = static_cast<uint32_t>(ix - P.wx0);
-          const uint32_t uy = static_cast<uint32_t>(iy - P.wy0);
-          const uint32_t uz = static_cast<uint32_t>(iz - P.wz0);
-          const bool inwin = ux < static_cast<uint32_t>(P.wnx) &&
-                             uy < static_cast<uint32_t>(P.wny) &&
-                             uz < static_cast<uint32_t>(P.wnz) && gate < P.wng;
-          acc_slot = inwin ? static_cast<int>(((gate * P.wnz + uz) * P.wny + uy) * P.wnx + ux) : -1;
+          int slot = -1;
+          if (wcells) {
+            const uint32_t ux = static_cast<uint32_t>(ix - L.wx0);
+            const uint32_t uy = static_cast<uint32_t>(iy - L.wy0);
+            const uint32_t uz = static_cast<uint32_t>(iz - L.wz0);
+            if (ux < static_cast<uint32_t>(L.wnx) && uy < static_cast<uint32_t>(L.wny) &&
+                uz < static_cast<uint32_t>(L.wnz) && gate < L.wng)
+              slot = static_cast<int>(((gate * L.wnz + uz) * L.wny + uy) * L.wnx + ux);
+          }
+          acc_slot = slot;
           acc_cell = cell;
           acc = dep;
         }
         w = w - w * q;
 
         // move
-        const float lh = l * P.inv_h;
+        const float lh = l * D->inv_h;
         fx = __builtin_amdgcn_fmed3f(fmaf(lh, vx, fx), 0.f, 1.f);
         fy = __builtin_amdgcn_fmed3f(fmaf(lh, vy, fy), 0.f, 1.f);
         fz = __builtin_amdgcn_fmed3f(fmaf(lh, vz, fz), 0.f, 1.f);
@@ -436,13 +508,13 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
             vb2 = ax == 0 ? vz : (ax == 1 ? vx : vy);
             step = va > 0.f ? 1 : -1;
             const int qa = (ax == 0 ? ix : (ax == 1 ? iy : iz)) + step;
-            const int na = ax == 0 ? P.nx : (ax == 1 ? P.ny : P.nz);
-            const uint32_t stride = ax == 0 ? 1u : (ax == 1 ? stride_y : stride_z);
+            const int na = ax == 0 ? D->nx : (ax == 1 ? D->ny : D->nz);
+            const uint32_t stride = ax == 0 ? 1u : (ax == 1 ? D->stride_y : D->stride_z);
             qlin = step > 0 ? lin + stride : lin - stride;
-            m2 = (qa >= 0 && qa < na) ? P.labels[qlin] : 0;
+            m2 = (qa >= 0 && qa < na) ? as_global(D->labels)[qlin] : 0;
             const float n1 = md.w;
-            const float n2 = m2 != 0 ? s_med[m2].w : P.n_out;
-            fres = P.reflect && n2 != n1;
+            const float n2 = m2 != 0 ? s_med[m2].w : D->n_out;
+            fres = D->reflect && n2 != n1;
             if (fres) {
               eta = n1 * rcp(n2);
               const float st2 = eta * eta * (vb1 * vb1 + vb2 * vb2);
@@ -457,25 +529,25 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
           }
           Words r = {0u, 0u, 0u, 0u};
           if (need_rng) {
-            r = philox4x32_10(klo, khi, blk, 0u, P.key0, P.key1);
+            r = philox4x32_10(klo, khi, blk, 0u, D->key0, D->key1);
             ++blk;
           }
 
           if (ev == kEvScat) {
             f_scat = true;
             ++nscat;
-            const float ct = hg_cos(md.z, s_hg[m], unit_open(r.x));
+            const float ct = hg_cos(md.z, s_med[2 * nm + m], unit_open(r.x));
             scatter_dir<kNative>(vx, vy, vz, ct, unit_open(r.y));
-            rx = inv_speed(P.h, vx);
-            ry = inv_speed(P.h, vy);
-            rz = inv_speed(P.h, vz);
+            rx = inv_speed(D->h, vx);
+            ry = inv_speed(D->h, vy);
+            rz = inv_speed(D->h, vz);
             s = neg_log<kNative>(unit_open(r.z));
-            if (w < P.rr_threshold) {
-              atomicAdd(&s_cnt[kCntRrTests], 1ull);
-              if (unit_open(r.w) < P.rr_p) {
-                atomicAdd(&s_cnt[kCntRrSurvived], 1ull);
-                atomicAdd(&s_led[kLedRrGain], static_cast<double>((P.rr_m - 1.f) * w));
-                w *= P.rr_m;
+            if (w < L.rr_threshold) {
+              atomicAdd(&s_cnt[wid][kCntRrTests], 1ull);
+              if (unit_open(r.w) < L.rr_p) {
+                atomicAdd(&s_cnt[wid][kCntRrSurvived], 1ull);
+                atomicAdd(&s_led[wid][kLedRrGain], static_cast<double>((L.rr_m - 1.f) * w));
+                w *= L.rr_m;
               } else {
                 end = kEndRoulette;
               }
@@ -488,7 +560,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
             if (ax == 0) fx = face; else if (ax == 1) fy = face; else fz = face;
             const bool reflect = tir || (need_rng && unit_open(r.x) < refl_p);
             if (reflect) {
-              atomicAdd(&s_cnt[kCntReflections], 1ull);
+              atomicAdd(&s_cnt[wid][kCntReflections], 1ull);
               if (ax == 0) vx = -vx; else if (ax == 1) vy = -vy; else vz = -vz;
             } else if (m2 == 0) {
               end = kEndEscape;
@@ -503,9 +575,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
                 } else {
                   vx *= eta; vy *= eta; vz = na_;
                 }
-                rx = inv_speed(P.h, vx);
-                ry = inv_speed(P.h, vy);
-                rz = inv_speed(P.h, vz);
+                rx = inv_speed(D->h, vx);
+                ry = inv_speed(D->h, vy);
+                rz = inv_speed(D->h, vz);
               }
               const float enter = step > 0 ? 0.f : 1.f;
               if (ax == 0) {
@@ -524,58 +596,60 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
 
       if (end != kAlive) {
         if (acc != 0.f && acc_cell != 0xffffffffu) {
-          deposit(P.tally, s_win, acc_cell, acc_slot, acc);
+          deposit(D->tally, s_win, acc_cell, acc_slot, acc);
           f_flush = acc_slot < 0;
         }
         if (old_acc != 0.f && old_cell != 0xffffffffu) {
-          deposit(P.tally, s_win, old_cell, old_slot, old_acc);
+          deposit(D->tally, s_win, old_cell, old_slot, old_acc);
           f_flush2 = old_slot < 0;
         }
         const double wd = static_cast<double>(w);
         const int end_slot = end == kEndEscape ? kCntEscaped
                              : end == kEndTime ? kCntTimeout
                              : end == kEndRoulette ? kCntRrDead : kCntCapped;
-        atomicAdd(&s_cnt[end_slot], 1ull);
+        atomicAdd(&s_cnt[wid][end_slot], 1ull);
         if (end == kEndEscape) {
-          atomicAdd(&s_led[kLedEscaped], wd);
+          atomicAdd(&s_led[wid][kLedEscaped], wd);
           if constexpr (kDetect) {
-            const float px = P.h * (static_cast<float>(ix) + fx);
-            const float py = P.h * (static_cast<float>(iy) + fy);
-            const float pz = P.h * (static_cast<float>(iz) + fz);
-            for (int d = 0; d < P.ndet; ++d) {
-              const float4 D = s_det[d];
-              const float ex = px - D.x, ey = py - D.y, ez = pz - D.z;
-              if (ex * ex + ey * ey + ez * ez <= D.w) {
+            const float h = D->h;
+            const float px = h * (static_cast<float>(ix) + fx);
+            const float py = h * (static_cast<float>(iy) + fy);
+            const float pz = h * (static_cast<float>(iz) + fz);
+            const float4* s_det = s_med + 3 * D->nmedia;
+            for (int d = 0; d < D->ndet; ++d) {
+              const float4 Dt = s_det[d];
+              const float ex = px - Dt.x, ey = py - Dt.y, ez = pz - Dt.z;
+              if (ex * ex + ey * ey + ez * ez <= Dt.w) {
                 det_hit = d;
                 break;
               }
             }
             if (det_hit >= 0) {
-              atomicAdd(&s_cnt[kCntDetected], 1ull);
-              atomicAdd(&s_led[kLedDetected], wd);
-              const unsigned long long slot = atomicAdd(P.det_count, 1ull);
-              if (slot < P.det_cap) {
-                float* rec = P.det_rec + slot * static_cast<uint64_t>(P.rec_len);
+              atomicAdd(&s_cnt[wid][kCntDetected], 1ull);
+              atomicAdd(&s_led[wid][kLedDetected], wd);
+              const unsigned long long slot = atomicAdd(D->det_count, 1ull);
+              if (slot < D->det_cap) {
+                float* rec = D->det_rec + slot * static_cast<uint64_t>(D->rec_len);
                 rec[0] = static_cast<float>(det_hit);
                 rec[1] = static_cast<float>(nscat);
                 rec[2] = w;
                 rec[3] = t;
-                for (int mm = 1; mm < P.nmedia; ++mm) rec[3 + mm] = s_len[mm * bdim];
-                P.det_photon[slot] = (static_cast<uint64_t>(khi) << 32) | klo;
+                for (int mm = 1; mm < D->nmedia; ++mm) rec[3 + mm] = s_len[mm * bdim];
+                D->det_photon[slot] = (static_cast<uint64_t>(khi) << 32) | klo;
               }
             }
           }
         } else if (end == kEndTime) {
-          atomicAdd(&s_led[kLedTimeout], wd);
+          atomicAdd(&s_led[wid][kLedTimeout], wd);
         } else if (end == kEndRoulette) {
-          atomicAdd(&s_led[kLedRrLoss], wd);
+          atomicAdd(&s_led[wid][kLedRrLoss], wd);
         } else {
-          atomicAdd(&s_led[kLedCapped], wd);
+          atomicAdd(&s_led[wid][kLedCapped], wd);
         }
         if constexpr (kDiag) {
           const uint64_t k = (static_cast<uint64_t>(khi) << 32) | klo;
-          if (k >= P.first && k - P.first < P.ndigest) {
-            double* row = P.digest + (k - P.first) * kDigestN;
+          if (k >= D->first && k - D->first < D->ndigest) {
+            double* row = D->digest + (k - D->first) * kDigestN;
             row[0] = end;
             row[1] = nscat;
             row[2] = nev;
@@ -595,43 +669,37 @@ __global__ void __launch_bounds__(1024) transport_kernel(const TransportParams* 
     c_fres += wave_count(f_fres);
     c_flush += wave_count(f_flush) + wave_count(f_flush2);
   }
+  flush_wave();
 
-  if (lane == 0) {
-    atomicAdd(&s_cnt[kCntLaunched], static_cast<unsigned long long>(c_launch));
-    atomicAdd(&s_cnt[kCntScatters], static_cast<unsigned long long>(c_scat));
-    atomicAdd(&s_cnt[kCntFaceEvents], static_cast<unsigned long long>(c_face));
-    atomicAdd(&s_cnt[kCntFresnel], static_cast<unsigned long long>(c_fres));
-    atomicAdd(&s_cnt[kCntEvents], static_cast<unsigned long long>(c_ev));
-    atomicAdd(&s_cnt[kCntLaneSlots], static_cast<unsigned long long>(c_slots));
-    atomicAdd(&s_cnt[kCntFlushes], static_cast<unsigned long long>(c_flush));
-  }
   __syncthreads();
-  // add the workgroup's window sums to the map
-  for (int i = threadIdx.x; i < wcells; i += blockDim.x) {
-    const double v = s_win[i];
-    if (v != 0.0) {
-      int r = i;
-      const int x = r % P.wnx;
-      r /= P.wnx;
-      const int y = r % P.wny;
-      r /= P.wny;
-      const int z = r % P.wnz;
-      const int g = r / P.wnz;
-      const uint32_t cell = static_cast<uint32_t>(g) * P.nvox + (P.wx0 + x) +
-                            stride_y * (P.wy0 + y) + stride_z * (P.wz0 + z);
-      unsafeAtomicAdd(P.tally + cell, v);
+  // add the workgroup's window sums to the map of simulation 0
+  if (wcells) {
+    CSim* D0 = as_const(L.sims);
+    for (int i = threadIdx.x; i < wcells; i += bdim) {
+      const double v = s_win[i];
+      if (v != 0.0) {
+        int r = i;
+        const int x = r % L.wnx;
+        r /= L.wnx;
+        const int y = r % L.wny;
+        r /= L.wny;
+        const int z = r % L.wnz;
+        const int g = r / L.wnz;
+        const uint32_t cell = static_cast<uint32_t>(g) * D0->nvox + (L.wx0 + x) +
+                              D0->stride_y * (L.wy0 + y) + D0->stride_z * (L.wz0 + z);
+        __builtin_amdgcn_global_atomic_fadd_f64(as_global(D0->tally) + cell, v);
+      }
     }
   }
-  if (threadIdx.x < kLedgerN) unsafeAtomicAdd(P.ledger + threadIdx.x, s_led[threadIdx.x]);
-  if (threadIdx.x < kCountN) atomicAdd(P.counts + threadIdx.x, s_cnt[threadIdx.x]);
 }
 
 }  // namespace
 
-size_t transport_smem_bytes(int nmedia, int ndet, int block, bool detect, int window_cells) {
-  size_t b = static_cast<size_t>(3 * nmedia + ndet) * sizeof(float4);
+size_t transport_smem_bytes(int table_rows, int nmedia_max, int block, bool detect,
+                            int window_cells) {
+  size_t b = static_cast<size_t>(block / 64) * table_rows * sizeof(float4);
   b += static_cast<size_t>(window_cells) * sizeof(double);
-  if (detect) b += static_cast<size_t>(nmedia) * block * sizeof(float);
+  if (detect) b += static_cast<size_t>(nmedia_max) * block * sizeof(float);
   return b;
 }
 
@@ -655,12 +723,13 @@ hipError_t transport_occupancy(int* blocks_per_cu, int block, size_t smem, bool 
                                                       pick(detect, diag, accurate), block, smem);
 }
 
-hipError_t launch_transport(const TransportParams& p, TransportParams* dev_params, int grid,
+hipError_t launch_transport(const LaunchParams& host, const LaunchParams* dev, int grid,
                             int block, hipStream_t st, bool detect, bool diag, bool accurate) {
+  const int wcells = host.nsims == 1 ? host.wnx * host.wny * host.wnz * host.wng : 0;
   const size_t smem =
-      transport_smem_bytes(p.nmedia, p.ndet, block, detect, p.wnx * p.wny * p.wnz * p.wng);
+      transport_smem_bytes(host.table_rows, host.nmedia_max, block, detect, wcells);
   const void* fn = pick(detect, diag, accurate);
-  void* args[] = {const_cast<TransportParams**>(&dev_params)};
+  void* args[] = {const_cast<LaunchParams**>(&dev)};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, smem, st);
 }
 

@@ -29,7 +29,11 @@ DIGEST = ["reason", "nscat", "events", "voxel", "w", "t", "blocks", "det"]
 
 EXPORTS = ["mcx_default_options", "mcx_create", "mcx_run", "mcx_run_range", "mcx_reset",
            "mcx_sync", "mcx_ncells", "mcx_fluence", "mcx_fluence_f64", "mcx_fluence_device",
-           "mcx_detected", "mcx_stats", "mcx_digest", "mcx_last_error", "mcx_destroy"]
+           "mcx_detected", "mcx_stats", "mcx_digest", "mcx_last_error", "mcx_destroy",
+           "mcx_batch_create", "mcx_batch_size", "mcx_batch_ncells", "mcx_batch_run",
+           "mcx_batch_run_range", "mcx_batch_fluence", "mcx_batch_fluence_f64",
+           "mcx_batch_stats", "mcx_batch_detected", "mcx_batch_digest", "mcx_set_launch",
+           "mcx_autotune"]
 
 
 class McxError(RuntimeError):
@@ -57,6 +61,19 @@ class mcx_detector(C.Structure):
 
 class mcx_gates(C.Structure):
     _fields_ = [("t0_ns", C.c_float), ("dt_ns", C.c_float), ("ngates", C.c_int32)]
+
+
+class mcx_sim(C.Structure):
+    _fields_ = [("vol", mcx_volume), ("src", mcx_source), ("det", C.c_void_p),
+                ("ndet", C.c_int32), ("gates", mcx_gates), ("reflect", C.c_int32),
+                ("n_outside", C.c_float)]
+
+
+class mcx_tune_result(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("refill_chunk", C.c_int32),
+                ("lds_window_cells", C.c_int32), ("candidates", C.c_int32),
+                ("default_ms", C.c_double), ("best_ms", C.c_double),
+                ("ms_per_photon", C.c_double), ("overhead_ms", C.c_double)]
 
 
 class mcx_options(C.Structure):
@@ -116,6 +133,20 @@ def lib() -> C.CDLL:
             "mcx_digest": (C.c_int, [vp, vp, u64]),
             "mcx_last_error": (C.c_char_p, []),
             "mcx_destroy": (None, [vp]),
+            "mcx_batch_create": (C.c_int, [C.POINTER(mcx_sim), i32, C.POINTER(mcx_options),
+                                           C.POINTER(vp)]),
+            "mcx_batch_size": (i32, [vp]),
+            "mcx_batch_ncells": (u64, [vp, i32]),
+            "mcx_batch_run": (C.c_int, [vp, vp, vp]),
+            "mcx_batch_run_range": (C.c_int, [vp, vp, vp, vp, vp]),
+            "mcx_batch_fluence": (C.c_int, [vp, i32, i32, vp, u64]),
+            "mcx_batch_fluence_f64": (C.c_int, [vp, i32, i32, vp, u64]),
+            "mcx_batch_stats": (C.c_int, [vp, i32, C.POINTER(mcx_run_stats)]),
+            "mcx_batch_detected": (C.c_int, [vp, i32, vp, vp, u64, C.POINTER(u64),
+                                             C.POINTER(u64)]),
+            "mcx_batch_digest": (C.c_int, [vp, i32, vp, u64]),
+            "mcx_set_launch": (C.c_int, [vp, i32, i32, i32]),
+            "mcx_autotune": (C.c_int, [vp, vp, vp, C.POINTER(mcx_tune_result)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -158,6 +189,101 @@ class _Inputs:
         for i, d in enumerate(dets):
             self.det[i] = mcx_detector((C.c_float * 3)(*d[:3]), float(d[3]))
         self.gates = mcx_gates(p.t0, p.dt, p.ngates)
+
+
+def _options(**options) -> mcx_options:
+    o = mcx_default_options()
+    for k, v in options.items():
+        setattr(o, k, v)
+    return o
+
+
+def mcx_batch_create(problems, **options) -> C.c_void_p:
+    """One context for a list of workloads.Problem (one launch serves all).
+    Roulette settings and the event cap come from the first problem."""
+    p0 = problems[0]
+    o = mcx_default_options(rr_threshold=p0.rr_threshold, rr_m=p0.rr_m,
+                            max_events=int(p0.max_events))
+    for k, v in options.items():
+        setattr(o, k, v)
+    keep = [_Inputs(p) for p in problems]
+    sims = (mcx_sim * len(problems))()
+    for i, (p, inp) in enumerate(zip(problems, keep)):
+        sims[i] = mcx_sim(inp.vol, inp.src, C.cast(inp.det, C.c_void_p) if inp.ndet else None,
+                          inp.ndet, inp.gates, int(bool(p.reflect)), p.n_out)
+    ctx = C.c_void_p()
+    _check(lib().mcx_batch_create(sims, len(problems), C.byref(o), C.byref(ctx)))
+    return ctx
+
+
+def mcx_batch_size(ctx) -> int:
+    return int(lib().mcx_batch_size(ctx))
+
+
+def mcx_batch_ncells(ctx, sim: int) -> int:
+    return int(lib().mcx_batch_ncells(ctx, sim))
+
+
+def _u64(values):
+    return np.ascontiguousarray(np.asarray(values, dtype=np.uint64))
+
+
+def mcx_batch_run(ctx, nphoton, seed):
+    n, s = _u64(nphoton), _u64(seed)
+    _check(lib().mcx_batch_run(ctx, n.ctypes.data, s.ctypes.data))
+
+
+def mcx_batch_run_range(ctx, first, n, seed, stream=None):
+    f = _u64(first) if first is not None else None
+    nn, s = _u64(n), _u64(seed)
+    _check(lib().mcx_batch_run_range(ctx, f.ctypes.data if f is not None else None,
+                                     nn.ctypes.data, s.ctypes.data, _stream(stream)))
+
+
+def mcx_batch_fluence(ctx, sim: int, kind: int = MCX_FLUENCE) -> np.ndarray:
+    out = np.empty(mcx_batch_ncells(ctx, sim), np.float32)
+    _check(lib().mcx_batch_fluence(ctx, sim, int(kind), out.ctypes.data, out.size))
+    return out
+
+
+def mcx_batch_fluence_f64(ctx, sim: int, kind: int = MCX_FLUENCE) -> np.ndarray:
+    out = np.empty(mcx_batch_ncells(ctx, sim), np.float64)
+    _check(lib().mcx_batch_fluence_f64(ctx, sim, int(kind), out.ctypes.data, out.size))
+    return out
+
+
+def mcx_batch_detected(ctx, sim: int, cap: int, rec_len: int):
+    rec = np.zeros((cap, rec_len), np.float32)
+    ph = np.zeros(cap, np.uint64)
+    nrec, ndrop = C.c_uint64(), C.c_uint64()
+    _check(lib().mcx_batch_detected(ctx, sim, rec.ctypes.data if cap else None,
+                                    ph.ctypes.data if cap else None, cap, C.byref(nrec),
+                                    C.byref(ndrop)))
+    n = int(nrec.value)
+    return rec[:n].copy(), ph[:n].copy(), int(ndrop.value)
+
+
+def mcx_batch_digest(ctx, sim: int, nrows: int) -> np.ndarray:
+    out = np.zeros((nrows, len(DIGEST)), np.float64)
+    _check(lib().mcx_batch_digest(ctx, sim, out.ctypes.data, nrows))
+    return out
+
+
+def mcx_batch_stats(ctx, sim: int) -> dict:
+    s = mcx_run_stats()
+    _check(lib().mcx_batch_stats(ctx, sim, C.byref(s)))
+    return {name: getattr(s, name) for name, _ in mcx_run_stats._fields_}
+
+
+def mcx_set_launch(ctx, block_size: int = 0, refill_chunk: int = 0, lds_window_cells: int = 0):
+    _check(lib().mcx_set_launch(ctx, block_size, refill_chunk, lds_window_cells))
+
+
+def mcx_autotune(ctx, pilot_photons, seed) -> dict:
+    n, s = _u64(pilot_photons), _u64(seed)
+    r = mcx_tune_result()
+    _check(lib().mcx_autotune(ctx, n.ctypes.data, s.ctypes.data, C.byref(r)))
+    return {name: getattr(r, name) for name, _ in mcx_tune_result._fields_}
 
 
 def mcx_create(p, **options) -> C.c_void_p:
@@ -260,6 +386,70 @@ def _stream(s):
         return C.c_void_p(s)
     handle = getattr(s, "cuda_stream", None)  # torch.cuda.Stream
     return C.c_void_p(handle if handle is not None else int(s))
+
+
+class Batch:
+    """One context for many Problems, run by one persistent launch."""
+
+    def __init__(self, problems, **options):
+        self.problems = list(problems)
+        self.ctx = mcx_batch_create(self.problems, **options)
+        self.ndigest = int(options.get("ndigest", 0))
+
+    def __len__(self):
+        return len(self.problems)
+
+    def run(self, nphoton, seed) -> "Batch":
+        mcx_batch_run(self.ctx, nphoton, seed)
+        return self
+
+    def run_range(self, first, n, seed, stream=None) -> "Batch":
+        mcx_batch_run_range(self.ctx, first, n, seed, stream)
+        return self
+
+    def reset(self):
+        mcx_reset(self.ctx)
+
+    def sync(self):
+        mcx_sync(self.ctx)
+
+    def fluence(self, sim: int, kind: int = MCX_FLUENCE, f64: bool = False) -> np.ndarray:
+        f = (mcx_batch_fluence_f64 if f64 else mcx_batch_fluence)(self.ctx, sim, kind)
+        return f.reshape(self.problems[sim].tally_shape)
+
+    def stats(self, sim: int) -> dict:
+        return mcx_batch_stats(self.ctx, sim)
+
+    def detected(self, sim: int, cap: Optional[int] = None):
+        if cap is None:
+            cap = int(self.stats(sim)["det_records"])
+        return mcx_batch_detected(self.ctx, sim, cap, self.problems[sim].record_len)
+
+    def digest(self, sim: int, nrows: Optional[int] = None) -> np.ndarray:
+        return mcx_batch_digest(self.ctx, sim, self.ndigest if nrows is None else nrows)
+
+    def autotune(self, pilot_photons, seed) -> dict:
+        return mcx_autotune(self.ctx, pilot_photons, seed)
+
+    def set_launch(self, block_size=0, refill_chunk=0, lds_window_cells=0):
+        mcx_set_launch(self.ctx, block_size, refill_chunk, lds_window_cells)
+
+    def close(self):
+        if self.ctx:
+            mcx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Simulation:

@@ -13,6 +13,7 @@ volumes are stored x-fastest as numpy arrays of shape (nz, ny, nx).
 from __future__ import annotations
 
 import dataclasses
+import functools
 from typing import Optional
 
 import numpy as np
@@ -96,10 +97,11 @@ def _media(*rows) -> np.ndarray:
 def sphere_mask(shape, centre, radius, h=1.0) -> np.ndarray:
     """Voxels whose centre lies within `radius` (mm) of `centre` (mm)."""
     nz, ny, nx = shape
-    z, y, x = np.meshgrid((np.arange(nz) + 0.5) * h, (np.arange(ny) + 0.5) * h,
-                          (np.arange(nx) + 0.5) * h, indexing="ij")
     cx, cy, cz = centre
-    return (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= radius ** 2
+    dx2 = (((np.arange(nx) + 0.5) * h - cx) ** 2)[None, None, :]
+    dy2 = (((np.arange(ny) + 0.5) * h - cy) ** 2)[None, :, None]
+    dz2 = (((np.arange(nz) + 0.5) * h - cz) ** 2)[:, None, None]
+    return dx2 + dy2 + dz2 <= radius ** 2
 
 
 def cube_homogeneous(n: int = 60, nphoton: int = 100_000) -> Problem:
@@ -164,6 +166,182 @@ def random_small(seed: int, max_side: int = 12, nmedia: int = 4) -> Problem:
                    reflect=bool(rng.integers(0, 2)), name=f"random_small_{seed}")
 
 
+# ------------------------------------------------------------------ head
+
+HEAD_SHAPE = (181, 217, 181)                 # (nz, ny, nx) voxels of 1 mm
+HEAD_TISSUES = ("scalp", "skull", "csf", "gray", "white")
+HEAD_MEDIA = ((0.019, 7.8, 0.89, 1.37), (0.019, 7.8, 0.89, 1.37), (0.004, 0.009, 0.89, 1.37),
+              (0.02, 9.0, 0.89, 1.37), (0.08, 40.9, 0.84, 1.37))
+HEAD_SEMI_AXES = (75.0, 95.0, 80.0)          # outer scalp surface, mm (x, y, z)
+HEAD_DEPTHS = (0.0, 5.0, 12.0, 14.0, 18.0)   # outer boundary of each shell below the scalp, mm
+
+
+def _angle_field(rng, amp: float, lmax: int = 3):
+    """Seeded smooth function of direction (polar t, azimuth f) with
+    |value| <= amp: a sum of low-order cosine products."""
+    terms = []
+    for l in range(1, lmax + 1):
+        for m in range(0, lmax + 1):
+            terms.append((l, m, rng.normal(), rng.uniform(0, 2 * np.pi), rng.uniform(0, 2 * np.pi)))
+    norm = sum(abs(a) for _, _, a, _, _ in terms)
+    cache = {}
+
+    def f(t, ph):
+        # the azimuth factors are reused across calls on the same grid
+        key = id(ph)
+        if key not in cache:
+            cache.clear()
+            cache[key] = (ph, [a * np.cos(m * ph + c) for _, m, a, _, c in terms])
+        phis = cache[key][1]
+        out = np.zeros(np.broadcast(t, ph).shape)
+        for (l, _, _, b, _), cp in zip(terms, phis):
+            out += np.cos(l * t + b) * cp
+        return out * (amp / norm)
+    return f
+
+
+@functools.lru_cache(maxsize=4)
+def head_phantom(seed: int = 1) -> Problem:
+    """Synthetic layered head: five nested ellipsoidal shells (scalp, skull,
+    CSF, gray, white matter) centred in a 181 x 217 x 181 grid of 1 mm
+    voxels, each boundary scaled along every direction by 1 + a seeded
+    low-order perturbation (a shared field up to 4% plus a per-shell field up
+    to 1%, nesting kept with >= 1 mm between boundaries).  Pencil beam along
+    the inward normal of the perturbed scalp surface at a seeded point on the
+    upper half; it starts where that ray first enters a tissue voxel.  Ten
+    0.5 ns gates, Fresnel boundaries on."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = HEAD_SHAPE
+    centre = np.array([nx / 2, ny / 2, nz / 2])
+    shared = _angle_field(rng, 0.04)
+    own = [_angle_field(rng, 0.01) for _ in HEAD_DEPTHS]
+    semi = np.array(HEAD_SEMI_AXES)
+
+    def boundary_radius(k, t, ph):
+        """Radius scale of boundary k along a direction (1 = unperturbed)."""
+        return 1.0 + shared(t, ph) + own[k](t, ph)
+
+    def level(k, pts):
+        """< 1 inside boundary k, for points (..., 3) in mm."""
+        d = pts - centre
+        a = semi - HEAD_DEPTHS[k]
+        rho = np.sqrt(((d / a) ** 2).sum(-1))
+        r = np.sqrt((d ** 2).sum(-1))
+        t = np.arccos(np.clip(d[..., 2] / np.maximum(r, 1e-9), -1, 1))
+        ph = np.arctan2(d[..., 1], d[..., 0])
+        return rho / boundary_radius(k, t, ph)
+
+    labels = np.zeros(HEAD_SHAPE, np.uint8)
+    Y, X = np.meshgrid(np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    dx, dy = X - centre[0], Y - centre[1]
+    ph = np.arctan2(dy, dx)
+    for iz in range(nz):
+        dz = iz + 0.5 - centre[2]
+        r = np.sqrt(dx * dx + dy * dy + dz * dz)
+        t = np.arccos(np.clip(dz / np.maximum(r, 1e-9), -1, 1))
+        common = 1.0 + shared(t, ph)
+        lab = np.zeros((ny, nx), np.uint8)
+        for k in range(len(HEAD_DEPTHS)):
+            a = semi - HEAD_DEPTHS[k]
+            rho = np.sqrt((dx / a[0]) ** 2 + (dy / a[1]) ** 2 + (dz / a[2]) ** 2)
+            lab[rho <= common + own[k](t, ph)] = k + 1
+        labels[iz] = lab
+    # nesting: along any ray from the centre the labels never increase outward
+    # (each inner boundary lies >= 1 mm inside the one before it by
+    # construction: depths differ by >= 2 mm and perturbations by <= 1% each)
+
+    # source: seeded direction in the upper half, surface point, inward normal
+    t0 = rng.uniform(np.radians(15), np.radians(60))
+    f0 = rng.uniform(0, 2 * np.pi)
+    u = np.array([np.sin(t0) * np.cos(f0), np.sin(t0) * np.sin(f0), np.cos(t0)])
+    lo, hi = 0.0, 2.0 * semi.max()
+    for _ in range(60):  # bisection on the outer level function along the ray
+        mid = 0.5 * (lo + hi)
+        if level(0, centre + mid * u) <= 1.0:
+            lo = mid
+        else:
+            hi = mid
+    surf = centre + lo * u
+    eps = 1e-3
+    grad = np.array([(level(0, surf + eps * e) - level(0, surf - eps * e)) / (2 * eps)
+                     for e in np.eye(3)])
+    normal = grad / np.linalg.norm(grad)
+    d = (-normal).astype(np.float32)
+    d = (d / np.float32(np.sqrt((d.astype(np.float64) ** 2).sum()))).astype(np.float32)
+    # march in from outside until the first tissue voxel
+    pos = surf + 4.0 * normal
+    step = 1e-3
+    for _ in range(20000):
+        i, j, k = (int(np.floor(c)) for c in pos)
+        if 0 <= i < nx and 0 <= j < ny and 0 <= k < nz and labels[k, j, i] != 0:
+            break
+        pos = pos + step * d.astype(np.float64)
+    pos32 = tuple(float(np.float32(c)) for c in pos)
+    i, j, k = (int(np.floor(c)) for c in pos32)
+    if labels[k, j, i] == 0:
+        raise RuntimeError("head source does not start in tissue")
+    return Problem(labels=labels, media=_media(*HEAD_MEDIA), src_pos=pos32, src_dir=tuple(d),
+                   t0=0.0, dt=0.5, ngates=10, reflect=True, name=f"head_{seed}")
+
+
+# ------------------------------------------------------------------ batch
+
+BATCH_SIDES = (32, 48, 64, 96, 128)
+BATCH_MUA = (0.001, 0.05)       # 1/mm, log-uniform
+BATCH_MUS = (0.5, 20.0)         # 1/mm, log-uniform
+BATCH_G = (0.5, 0.95)           # uniform
+BATCH_PHOTONS = (1e5, 1e7)      # log-uniform
+
+
+@dataclasses.dataclass
+class BatchItem:
+    problem: Problem
+    nphoton: int
+    seed: int
+
+
+def _log_uniform(rng, lo, hi):
+    return float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+
+
+def batch_cube(rng, side: int, name: str = "") -> Problem:
+    """One cube of the batched workload: `side`^3 voxels of 1 mm, label 1
+    background with 1-3 spherical inclusions (labels 2..4, radius uniform in
+    [side/10, side/4], centre uniform where the sphere fits, later ones
+    painted over earlier ones), every label's mua / mus log-uniform and g
+    uniform in the batch ranges, n = 1.37, pencil beam along +z at the
+    voxel-centred middle of the z = 0 face, one 0-5 ns gate, Fresnel
+    boundaries on."""
+    labels = np.ones((side, side, side), np.uint8)
+    ninc = int(rng.integers(1, 4))
+    for k in range(ninc):
+        r = float(rng.uniform(side / 10, side / 4))
+        c = tuple(float(rng.uniform(r, side - r)) for _ in range(3))
+        labels[sphere_mask(labels.shape, c, r)] = 2 + k
+    rows = [(_log_uniform(rng, *BATCH_MUA), _log_uniform(rng, *BATCH_MUS),
+             float(rng.uniform(*BATCH_G)), 1.37) for _ in range(1 + ninc)]
+    c = side / 2 - 0.5
+    return Problem(labels=labels, media=_media(*rows), src_pos=(c, c, 0.0),
+                   src_dir=(0.0, 0.0, 1.0), t0=0.0, dt=5.0, ngates=1, reflect=True,
+                   name=name or f"batch_cube{side}")
+
+
+def batch_workload(nsims: int = 256, seed: int = 1, sides=BATCH_SIDES,
+                   photons=BATCH_PHOTONS, scale: float = 1.0) -> list:
+    """The batched workload: `nsims` independent cubes (`batch_cube`) with
+    sides drawn uniformly from `sides` and photon counts log-uniform in
+    `photons` (times `scale`, at least 1), each with its own seed, all drawn
+    from one numpy PCG64 stream seeded with `seed`."""
+    rng = np.random.default_rng(seed)
+    items = []
+    for i in range(nsims):
+        side = int(rng.choice(np.asarray(sides)))
+        prob = batch_cube(rng, side, name=f"batch{seed}_{i}_cube{side}")
+        n = max(1, int(round(_log_uniform(rng, *photons) * scale)))
+        items.append(BatchItem(prob, n, int(rng.integers(1, 2 ** 32))))
+    return items
+
+
 def with_medium(p: Problem, row: int, values) -> Problem:
     media = p.media.copy()
     media[row] = values
@@ -172,7 +350,8 @@ def with_medium(p: Problem, row: int, values) -> Problem:
 
 def photons_and_seed(name: str) -> tuple:
     """Photon count and seed each named workload is quoted at."""
-    return {"cube60_homogeneous": (100_000, 1), "cube60_sphere": (100_000_000, 1)}[name]
+    return {"cube60_homogeneous": (100_000, 1), "cube60_sphere": (100_000_000, 1),
+            "head_1": (100_000_000, 1)}[name]
 
 
 def describe(p: Problem, nphoton: Optional[int] = None) -> dict:

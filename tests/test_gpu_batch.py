@@ -1,0 +1,267 @@
+"""Batched launches: many independent simulations served by one launch.
+
+A simulation's random numbers are keyed by its seed and the photon index, so
+inside a batch it follows the same photon histories as when it runs alone:
+the batch must reproduce each simulation's single run -- identical event
+counts, per-photon digests and detector records, tallies and ledgers equal
+up to the order of FP64 additions.  The single runs are held to the oracle
+by the parity tests; generated batch cubes are also compared with the oracle
+directly, and the full 256-simulation workload is checked by properties that
+hold at any size and by sampled photons.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_03244_amd import mcx, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+COUNT_KEYS = ["launched", "escaped", "detected", "timeout", "rr_dead", "capped", "scatters",
+              "face_events", "fresnel_draws", "reflections", "rr_tests", "rr_survived",
+              "events"]
+LEDGER_KEYS = ["w_escaped", "w_detected", "w_timeout", "w_rr_gain", "w_rr_loss", "w_capped",
+               "tally_sum", "absorbed_grid"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def terminated(st):
+    return st["escaped"] + st["timeout"] + st["rr_dead"] + st["capped"]
+
+
+def energy_residual(st):
+    n = st["launched"]
+    return (n + st["w_rr_gain"] - st["absorbed_grid"] - st["w_escaped"] - st["w_timeout"]
+            - st["w_rr_loss"] - st["w_capped"]) / max(n, 1)
+
+
+def mixed_batch():
+    c30 = W.cube_sphere(n=30, ngates=5, dt=1.0).replace(name="cube30_sphere")
+    c20 = W.cube_homogeneous(n=20).replace(src_pos=(9.5, 9.5, 0.0), name="cube20")
+    probs = [W.random_small(0), c30, W.random_small(1), W.slab_column(nz=12), c20,
+             W.random_small(2), W.random_small(3)]
+    n = [3000, 20000, 1, 0, 5000, 4999, 777]
+    seeds = [11, 3, 5, 7, 2 ** 40 + 9, 13, 1]
+    return probs, n, seeds
+
+
+def test_batch_reproduces_each_single_run():
+    probs, n, seeds = mixed_batch()
+    nd = max(n)
+    say(f"[gpu] mixed batch of {len(probs)} N={n}")
+    with mcx.Batch(probs, ndigest=nd) as b:
+        b.run(n, seeds)
+        got = []
+        for i, p in enumerate(probs):
+            r = {"stats": b.stats(i), "raw": b.fluence(i, mcx.MCX_RAW, f64=True),
+                 "digest": b.digest(i)}
+            if p.ndet:
+                r["rec"], r["ph"], r["drop"] = b.detected(i)
+            got.append(r)
+    for i, (p, N, sd) in enumerate(zip(probs, n, seeds)):
+        say(f"[gpu] single {p.name} N={N} seed={sd}")
+        with mcx.Simulation(p, ndigest=nd) as s:
+            s.run(N, sd)
+            st = s.stats()
+            raw = s.fluence(mcx.MCX_RAW, f64=True)
+            dig = s.digest()
+            if p.ndet:
+                rec, ph, drop = s.detected()
+        g = got[i]
+        for k in COUNT_KEYS:
+            assert g["stats"][k] == st[k], (p.name, k)
+        assert g["stats"]["launched"] == N and terminated(g["stats"]) == N
+        for k in LEDGER_KEYS:
+            assert g["stats"][k] == pytest.approx(st[k], rel=1e-10, abs=1e-12), (p.name, k)
+        scale = max(1e-300, float(np.abs(raw).max()))
+        assert np.allclose(g["raw"], raw, rtol=1e-10, atol=1e-13 * scale), p.name
+        assert np.array_equal(g["digest"][:N], dig[:N]), p.name
+        if p.ndet:
+            assert g["drop"] == drop == 0
+            o1, o2 = np.argsort(g["ph"]), np.argsort(ph)
+            assert np.array_equal(g["ph"][o1], ph[o2])
+            assert np.array_equal(g["rec"][o1], rec[o2])
+            assert len(ph) > 0
+    # the empty simulation
+    assert got[3]["stats"]["launched"] == 0 and not got[3]["raw"].any()
+
+
+def test_batch_empty_simulation_cannot_be_normalised():
+    probs, n, seeds = mixed_batch()
+    with mcx.Batch(probs[:4]) as b:
+        b.run(n[:4], seeds[:4])
+        b.fluence(0)
+        with pytest.raises(mcx.McxError) as e:
+            b.fluence(3)
+        assert e.value.status == mcx.MCX_ESTATE
+        with pytest.raises(mcx.McxError) as e:
+            b.stats(4)
+        assert e.value.status == mcx.MCX_EINVAL
+
+
+def test_batch_ranges_accumulate():
+    probs, n, seeds = mixed_batch()
+    nd = [x // 2 for x in n]
+    with mcx.Batch(probs) as b:
+        b.run(n, seeds)
+        whole = [b.fluence(i, mcx.MCX_RAW, f64=True) for i in range(len(probs))]
+        s1 = [b.stats(i) for i in range(len(probs))]
+        b.reset()
+        b.run_range(None, nd, seeds)
+        b.run_range(nd, [a - c for a, c in zip(n, nd)], seeds)
+        b.sync()
+        for i in range(len(probs)):
+            st = b.stats(i)
+            for k in COUNT_KEYS:
+                assert st[k] == s1[i][k], (i, k)
+            raw = b.fluence(i, mcx.MCX_RAW, f64=True)
+            scale = max(1e-300, float(np.abs(whole[i]).max()))
+            assert np.allclose(raw, whole[i], rtol=1e-10, atol=1e-13 * scale)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, -1), (1024, 4096, -1), (256, 256, -1)])
+def test_batch_launch_shape_does_not_change_results(shape):
+    probs, n, seeds = mixed_batch()
+    with mcx.Batch(probs) as b:
+        b.run(n, seeds)
+        base = [b.stats(i) for i in range(len(probs))]
+        b.set_launch(*shape)
+        b.run(n, seeds)
+        for i in range(len(probs)):
+            st = b.stats(i)
+            assert st["block_size"] == shape[0]
+            for k in COUNT_KEYS:
+                assert st[k] == base[i][k], (shape, i, k)
+            assert st["absorbed_grid"] == pytest.approx(base[i]["absorbed_grid"], rel=1e-10)
+
+
+def test_generated_batch_cubes_against_oracle():
+    items = W.batch_workload(nsims=8, seed=7, sides=(16, 24, 32), photons=(500, 4000))
+    probs = [it.problem for it in items]
+    n = [it.nphoton for it in items]
+    seeds = [it.seed for it in items]
+    nd = max(n)
+    say(f"[gpu] generated batch N={n}")
+    with mcx.Batch(probs, ndigest=nd) as b:
+        b.run(n, seeds)
+        res = [(b.stats(i), b.digest(i)) for i in range(len(probs))]
+    for (st, dig), p, N, sd in zip(res, probs, n, seeds):
+        o = oracle.run(p, N, sd, nthreads=16, ndigest=N)
+        assert st["launched"] == N and terminated(st) == N
+        assert abs(energy_residual(st)) < 1e-5
+        same = np.all(dig[:N, [0, 1, 3]] == o["digest"][:, [0, 1, 3]], axis=1)
+        mua = np.asarray(p.media, np.float64)[:, 0][p.labels]
+        a_o = float((o["tally"].sum(axis=0) * mua).sum()) / N
+        a_g = st["absorbed_grid"] / N
+        d = dig[:N, 4] - o["digest"][:, 4]
+        se = math.sqrt(st["w_rr_gain"] / N + np.mean(d * d)) / math.sqrt(N) + 1e-12
+        say(p.name, "coupled", same.mean(), "absorbed", a_g, a_o, "se", se)
+        assert same.mean() >= 0.8
+        if same.all():
+            assert abs(a_g - a_o) <= 1e-4 * a_o + 1e-9
+        else:
+            assert abs(a_g - a_o) <= max(1e-4 * a_o, 5 * se)
+
+
+def test_autotune_keeps_results_and_reports_model():
+    probs, n, seeds = mixed_batch()
+    with mcx.Batch(probs) as b:
+        b.run(n, seeds)
+        base = [b.stats(i) for i in range(len(probs))]
+        r = b.autotune([max(2, x // 4) for x in n], seeds)
+        say("[gpu] autotune", r)
+        assert r["candidates"] == 1 + 5 * 4
+        assert r["block_size"] in (64, 256, 448, 512, 1024)
+        assert r["refill_chunk"] in (64, 256, 1024, 4096)
+        assert r["lds_window_cells"] == -1
+        assert 0 < r["best_ms"] <= r["default_ms"]
+        assert r["ms_per_photon"] == r["ms_per_photon"]  # finite
+        assert b.stats(0)["launched"] == 0  # cleared on return
+        b.run(n, seeds)
+        for i in range(len(probs)):
+            st = b.stats(i)
+            assert st["block_size"] == r["block_size"]
+            for k in COUNT_KEYS:
+                assert st[k] == base[i][k], (i, k)
+
+
+def test_autotune_single_simulation_tries_windows():
+    p = W.cube_sphere(n=30, ngates=5, dt=1.0).replace(name="cube30_sphere")
+    with mcx.Simulation(p) as s:
+        s.run(20000, 3)
+        base = s.stats()
+        r = mcx.mcx_autotune(s.ctx, [20000], [3])
+        say("[gpu] autotune single", r)
+        assert r["candidates"] == 1 + 3 * 5 * 4
+        assert r["lds_window_cells"] in (-1, 4096, 8192)
+        s.run(20000, 3)
+        st = s.stats()
+        for k in COUNT_KEYS:
+            assert st[k] == base[k], k
+
+
+# ------------------------------------------------ the full batched workload
+
+@pytest.fixture(scope="module")
+def full_batch():
+    items = W.batch_workload()
+    probs = [it.problem for it in items]
+    n = [it.nphoton for it in items]
+    seeds = [it.seed for it in items]
+    say(f"[gpu] full batch: {len(items)} simulations, {sum(n)} photons")
+    b = mcx.Batch(probs)
+    b.run(n, seeds)
+    stats = [b.stats(i) for i in range(len(items))]
+    say(f"[gpu] full batch kernel {stats[0]['kernel_ms']:.1f} ms")
+    yield items, b, stats
+    b.close()
+
+
+def test_full_batch_conserves_photons_and_energy(full_batch):
+    items, b, stats = full_batch
+    for it, st in zip(items, stats):
+        assert st["launched"] == it.nphoton and terminated(st) == it.nphoton, it.problem.name
+        assert abs(energy_residual(st)) < 1e-6, it.problem.name
+        assert st["tally_sum"] > 0
+
+
+def test_full_batch_samples_match_single_runs(full_batch):
+    items, b, stats = full_batch
+    # three simulations of different sizes, rerun alone with the same seed
+    order = np.argsort([it.nphoton for it in items])
+    for i in [int(order[0]), int(order[len(order) // 2]), int(order[-1])]:
+        it = items[i]
+        say(f"[gpu] single {it.problem.name} N={it.nphoton}")
+        with mcx.Simulation(it.problem) as s:
+            s.run(it.nphoton, it.seed)
+            st = s.stats()
+        for k in COUNT_KEYS:
+            assert stats[i][k] == st[k], (it.problem.name, k)
+        assert stats[i]["absorbed_grid"] == pytest.approx(st["absorbed_grid"], rel=1e-9)
+
+
+def test_full_batch_sampled_photons_against_oracle():
+    # photons 0..1999 of two simulations of the full workload, by digest
+    items = W.batch_workload()
+    pick = [0, 1]
+    nd = 2000
+    with mcx.Batch([it.problem for it in items], ndigest=nd) as b:
+        b.run([it.nphoton for it in items], [it.seed for it in items])
+        digs = [b.digest(i) for i in pick]
+    for i, dig in zip(pick, digs):
+        it = items[i]
+        o = oracle.run(it.problem, nd, it.seed, nthreads=16, ndigest=nd)
+        # coupled: same end, scattering count, last voxel and final weight (a
+        # photon near the roulette threshold may take the test on one side
+        # only and end with ten times the weight on otherwise equal terms)
+        same = (np.all(dig[:, [0, 1, 3]] == o["digest"][:, [0, 1, 3]], axis=1)
+                & np.isclose(dig[:, 4], o["digest"][:, 4], rtol=1e-3, atol=1e-7))
+        say(it.problem.name, "coupled", same.mean())
+        assert same.mean() >= 0.8
