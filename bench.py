@@ -17,7 +17,13 @@ normalisation of the map into a device tensor.  Problem creation and upload
 Prints one JSON line.  `roofline` is the transport kernel's algorithmic VALU
 work over its HIP-event time; `atomic_roofline` its memory-side atomic rate;
 `cpu_baseline` the FP64 oracle on the host cores over a prefix of the same
-photons.
+photons.  Two further workloads are reported beside the main one, each
+timed once after a warm-up launch: `head_volume` (the seeded 181 x 217 x
+181 layered head phantom, 10 gates of 0.5 ns, 1e8 photons) and `batched`
+(256 generated cubes of 32-128 mm with 1-3 inclusions and 1e5-1e7 photons
+each, 5.4e8 photons in one launch, with the fixed launch shape -- 64-thread
+workgroups, one photon per lane per job, direct atomics -- and with the
+shape the autotuner picks from pilot launches of 1/50 of the photons).
 """
 import argparse
 import json
@@ -40,6 +46,9 @@ def main():
     ap.add_argument("--cpu-photons", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--head-photons", type=int, default=100_000_000)
+    ap.add_argument("--no-head", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the transport on a single "
@@ -85,6 +94,9 @@ def main():
     atom = roofline.atomic_roofline(last, ksec)
     sim.close()
 
+    head = None if args.no_head else head_leg(mcx, roofline, W, args.head_photons, args.seed)
+    batched = None if args.no_batch else batch_leg(mcx, W)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -111,8 +123,52 @@ def main():
         "roofline": roof,
         "atomic_roofline": atom,
         "cpu_baseline": cpu,
+        "head_volume": head,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
+
+
+def head_leg(mcx, roofline, W, N, seed):
+    p = W.head_phantom(1)
+    with mcx.Simulation(p) as sim:
+        sim.run(N // 100, seed + 1000)  # warm-up
+        sim.run(N, seed)
+        st = sim.stats()
+    ksec = st["kernel_ms"] / 1e3
+    return {"workload": "head_1", "grid": [181, 217, 181], "gates": 10, "gate_ns": 0.5,
+            "photons": N, "photons_per_ms": N / st["run_ms"], "kernel_ms": st["kernel_ms"],
+            "run_ms": st["run_ms"], "events_per_photon": st["events"] / N,
+            "valu_frac": roofline.valu_roofline(st, ksec)["frac"],
+            "atomic_frac": roofline.atomic_roofline(st, ksec)["frac"]}
+
+
+def batch_leg(mcx, W):
+    items = W.batch_workload()
+    n = [it.nphoton for it in items]
+    seeds = [it.seed for it in items]
+    total = sum(n)
+    out = {"workload": "batch_256_cubes", "simulations": len(items), "photons": total,
+           "sides": list(W.BATCH_SIDES), "seed": 1}
+    with mcx.Batch([it.problem for it in items]) as b:
+        def timed(label):
+            b.run([max(1, x // 100) for x in n], [s + 1 for s in seeds])  # warm-up
+            b.run(n, seeds)
+            st = b.stats(0)
+            out[label] = {"photons_per_ms": total / st["run_ms"], "run_ms": st["run_ms"],
+                          "kernel_ms": st["kernel_ms"], "block_size": st["block_size"],
+                          "grid_blocks": st["grid_blocks"]}
+        b.set_launch(64, 64, -1)
+        timed("fixed")
+        out["fixed"]["refill_chunk"] = 64
+        t0 = time.perf_counter()
+        tune = b.autotune([max(1000, x // 50) for x in n], seeds)
+        out["autotune_s"] = time.perf_counter() - t0
+        timed("autotuned")
+        out["autotuned"]["refill_chunk"] = tune["refill_chunk"]
+        out["autotune"] = tune
+    out["speedup"] = out["autotuned"]["photons_per_ms"] / out["fixed"]["photons_per_ms"]
+    return out
 
 
 if __name__ == "__main__":

@@ -61,15 +61,18 @@ struct SimDesc {
 };
 
 // One launch over `nsims` simulations.  Photons are handed out in jobs of
-// `chunk` photons of one simulation; job j belongs to the last simulation s
-// with job_start[s] <= j.
+// `chunk` photons of one simulation: simulation s has jobs
+// job_start[s+1] - job_start[s], taken in order through its own counter.
+// Each wave starts on a home simulation (waves are spread over simulations
+// in proportion to their job counts) and moves on to the following
+// simulations once its home has no jobs left.
 struct LaunchParams {
   const SimDesc* sims;
   int32_t nsims;
-  const uint64_t* job_start;     // nsims + 1 entries
+  const uint64_t* job_start;     // nsims + 1 entries, prefix sums of job counts
   uint64_t njobs;
   uint32_t chunk;
-  unsigned long long* job_counter;
+  unsigned long long* job_counters;  // nsims entries, zero at launch
   float rr_threshold, rr_p, rr_m;
   uint32_t max_events;
   int32_t table_rows;            // LDS rows per wave for the current simulation's tables
@@ -92,7 +95,7 @@ hipError_t launch_transport(const LaunchParams& host, const LaunchParams* dev, i
 hipError_t launch_clear(double* tally, uint64_t ncells, double* ledger,
                         unsigned long long* counts, unsigned long long* det_count,
                         int nsims, hipStream_t s);
-hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s);
+hipError_t launch_reset_counters(unsigned long long* counters, int n, hipStream_t s);
 hipError_t launch_reduce(const double* tally, const uint8_t* labels, const float4* media,
                          uint32_t nvox, int ngates, double* out2, hipStream_t s);
 hipError_t launch_normalise_f32(const double* tally, uint64_t ncells, double scale, float* out,

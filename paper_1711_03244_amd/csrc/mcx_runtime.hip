@@ -104,7 +104,7 @@ struct mcx_ctx {
   double* d_digest = nullptr;
   mcx::SimDesc* d_desc = nullptr;
   uint64_t* d_job_start = nullptr;
-  unsigned long long* d_job_counter = nullptr;
+  unsigned long long* d_job_counter = nullptr;  // one per simulation
   mcx::LaunchParams* d_launch = nullptr;
   float* d_stage32 = nullptr;
   double* d_stage64 = nullptr;
@@ -384,7 +384,7 @@ static mcx_status setup(mcx_ctx* c, const mcx_sim* sims) {
   HIP_TRY(hipMalloc(&c->d_reduce, n * 2 * sizeof(double)));
   HIP_TRY(hipMalloc(&c->d_desc, n * sizeof(mcx::SimDesc)));
   HIP_TRY(hipMalloc(&c->d_job_start, (n + 1) * sizeof(uint64_t)));
-  HIP_TRY(hipMalloc(&c->d_job_counter, sizeof(unsigned long long)));
+  HIP_TRY(hipMalloc(&c->d_job_counter, n * sizeof(unsigned long long)));
   HIP_TRY(hipMalloc(&c->d_launch, sizeof(mcx::LaunchParams)));
   if (recs > 0) {
     HIP_TRY(hipMalloc(&c->d_rec, recs * sizeof(float)));
@@ -559,7 +559,7 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
   lp.job_start = c->d_job_start;
   lp.njobs = job_start[ns];
   lp.chunk = static_cast<uint32_t>(c->chunk);
-  lp.job_counter = c->d_job_counter;
+  lp.job_counters = c->d_job_counter;
   lp.rr_threshold = c->opt.rr_threshold;
   lp.rr_p = static_cast<float>(1.0 / c->opt.rr_m);
   lp.rr_m = c->opt.rr_m;
@@ -581,7 +581,7 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
   HIP_TRY(hipMemcpyAsync(c->d_job_start, job_start.data(), (ns + 1) * sizeof(uint64_t),
                          hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(c->d_launch, &lp, sizeof(lp), hipMemcpyHostToDevice, st));
-  HIP_TRY(mcx::launch_reset_counter(c->d_job_counter, st));
+  HIP_TRY(mcx::launch_reset_counters(c->d_job_counter, static_cast<int>(ns), st));
   HIP_TRY(hipEventRecord(c->ev_k0, st));
   HIP_TRY(mcx::launch_transport(lp, c->d_launch, c->grid, c->block, st, c->detect, c->diag,
                                 c->opt.accurate_math != 0));

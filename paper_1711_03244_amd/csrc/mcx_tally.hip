@@ -20,7 +20,10 @@ __global__ void clear_kernel(double* tally, uint64_t ncells, double* ledger,
   for (uint64_t i = first; i < static_cast<uint64_t>(nsims); i += stride) det_count[i] = 0ull;
 }
 
-__global__ void reset_counter_kernel(unsigned long long* counter) { *counter = 0ull; }
+__global__ void reset_counters_kernel(unsigned long long* counters, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    counters[i] = 0ull;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -87,8 +90,8 @@ hipError_t launch_clear(double* tally, uint64_t ncells, double* ledger,
   return hipGetLastError();
 }
 
-hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s) {
-  reset_counter_kernel<<<1, 1, 0, s>>>(counter);
+hipError_t launch_reset_counters(unsigned long long* counters, int n, hipStream_t s) {
+  reset_counters_kernel<<<(n + 255) / 256, 256, 0, s>>>(counters, n);
   return hipGetLastError();
 }
 

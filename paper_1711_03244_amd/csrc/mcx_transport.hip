@@ -8,12 +8,14 @@
 // load balancing (a shared photon quota that threads decrement to start
 // their next photon) becomes wave-level refill: whenever lanes of a wave
 // finish, the wave hands them the next photon indices from a job (a chunk of
-// photons of one simulation) it took from a global 64-bit job counter, so a
-// wave keeps its 64 lanes busy until the supply runs out.  One launch can
-// serve many independent simulations of different grids and photon counts:
-// a wave works on one simulation at a time (its descriptor is read with
-// scalar loads) and moves to the next simulation's job once its lanes are
-// done.
+// photons of one simulation) it took from that simulation's 64-bit job
+// counter, so a wave keeps its 64 lanes busy until the supply runs out.  One
+// launch can serve many independent simulations of different grids and
+// photon counts: a wave works on one simulation at a time (its descriptor is
+// read with scalar loads), starting on a home simulation chosen so that
+// waves are spread over simulations in proportion to their work, and moves
+// on to the next simulation with jobs left -- after its lanes have finished
+// -- only when the current one is exhausted.
 //
 // Per-lane state stays in registers; each wave keeps its simulation's media
 // table and detectors, an FP64 energy ledger and rare-event counters in its
@@ -240,7 +242,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   __shared__ unsigned long long s_cnt[kMaxWavesPerBlock][kCountN];
 
   const uint32_t lane = __lane_id();
-  const int wid = static_cast<int>(threadIdx.x >> 6);
+  const int wid = static_cast<int>(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));  // wave-uniform
   const uint32_t bdim = blockDim.x;
   const int rows = L.table_rows;
   float4* s_tab = s_dyn + wid * rows;  // this wave's copy of its simulation's tables
@@ -277,22 +279,48 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   bool has_pend = false, dry = false;
   int pend_sim = 0;
   uint64_t pend_first = 0, pend_end = 0;
+  const MCX_CONST uint64_t* js = as_const(L.job_start);
+  // Home simulation: the one holding job ((2 v + 1) / 2) * njobs / nwaves,
+  // where v numbers the waves so that the workgroups of one XCD (dispatched
+  // round-robin over the 8 XCDs) are consecutive; the waves of a simulation
+  // then share an XCD and its L2 as far as the counts allow.
+  int scan = 0;  // simulation the wave takes its jobs from
+  {
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t vb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
+    const uint64_t wpb = bdim >> 6;
+    const uint64_t v = vb * wpb + static_cast<uint64_t>(wid);
+    const uint64_t target = ((2 * v + 1) * L.njobs) / (2 * nb * wpb);
+    int lo = 0, hi = L.nsims;  // job_start[lo] <= target < job_start[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (js[mid] <= target) lo = mid; else hi = mid;
+    }
+    scan = lo;
+  }
   // per-wave counts of frequent events (scalar registers); rare events are
   // counted in the wave's LDS slice by the lanes they happen to
   uint32_t c_launch = 0, c_scat = 0, c_face = 0, c_fres = 0, c_ev = 0, c_slots = 0, c_flush = 0;
 
   // add the wave's tallies of simulation `cur` to its totals and clear them
+  // move the 32-bit register counts to the wave's 64-bit LDS counters
+  auto spill_counts = [&]() {
+    if (lane == 0) {
+      s_cnt[wid][kCntLaunched] += c_launch;
+      s_cnt[wid][kCntScatters] += c_scat;
+      s_cnt[wid][kCntFaceEvents] += c_face;
+      s_cnt[wid][kCntFresnel] += c_fres;
+      s_cnt[wid][kCntEvents] += c_ev;
+      s_cnt[wid][kCntLaneSlots] += c_slots;
+      s_cnt[wid][kCntFlushes] += c_flush;
+    }
+    c_launch = c_scat = c_face = c_fres = c_ev = c_slots = c_flush = 0;
+  };
   auto flush_wave = [&]() {
+    spill_counts();
     if (cur >= 0) {
       if (lane == 0) {
         unsigned long long* C = D->counts;
-        s_cnt[wid][kCntLaunched] += c_launch;
-        s_cnt[wid][kCntScatters] += c_scat;
-        s_cnt[wid][kCntFaceEvents] += c_face;
-        s_cnt[wid][kCntFresnel] += c_fres;
-        s_cnt[wid][kCntEvents] += c_ev;
-        s_cnt[wid][kCntLaneSlots] += c_slots;
-        s_cnt[wid][kCntFlushes] += c_flush;
         for (int i = 0; i < kCountN; ++i)
           if (s_cnt[wid][i]) atomicAdd(C + i, s_cnt[wid][i]);
         for (int i = 0; i < kLedgerN; ++i)
@@ -301,7 +329,6 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
     }
     if (lane < kLedgerN) s_led[wid][lane] = 0.0;
     if (lane < kCountN) s_cnt[wid][lane] = 0ull;
-    c_launch = c_scat = c_face = c_fres = c_ev = c_slots = c_flush = 0;
   };
 
   for (;;) {
@@ -313,25 +340,33 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
     const uint64_t dead = __ballot(!alive);
     if (dead != 0 && !dry) {
       if (pool_next == pool_end && !has_pend) {
+        // next job of simulation `scan`; when it has none left, try the
+        // following simulations (cyclically) until one has, or all are done
         const int leader = __ffsll(static_cast<long long>(dead)) - 1;
-        unsigned long long got = 0;
-        if (static_cast<int>(lane) == leader) got = atomicAdd(L.job_counter, 1ull);
-        const uint64_t j = readlane_u64(got, leader);
-        if (j >= L.njobs) {
-          dry = true;
-        } else {
-          const MCX_CONST uint64_t* js = as_const(L.job_start);
-          int lo = 0, hi = L.nsims;  // job_start[lo] <= j < job_start[hi]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (js[mid] <= j) lo = mid; else hi = mid;
+        for (int tried = 0;; ++tried) {
+          if (tried >= L.nsims) {
+            dry = true;
+            break;
           }
-          const uint64_t off = (j - js[lo]) * L.chunk;
-          const uint64_t n = as_const(L.sims)[lo].nphoton;
-          pend_sim = lo;
-          pend_first = off;
-          pend_end = off + L.chunk < n ? off + L.chunk : n;
-          has_pend = true;
+          const uint64_t njob = js[scan + 1] - js[scan];
+          unsigned long long* ctr = L.job_counters + scan;
+          unsigned long long got = njob;
+          if (static_cast<int>(lane) == leader) {
+            // a relaxed read first, so that finished simulations cost no atomic
+            got = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (got < njob) got = atomicAdd(ctr, 1ull);
+          }
+          const uint64_t j = readlane_u64(got, leader);
+          if (j < njob) {
+            const uint64_t off = j * L.chunk;
+            const uint64_t n = as_const(L.sims)[scan].nphoton;
+            pend_sim = scan;
+            pend_first = off;
+            pend_end = off + L.chunk < n ? off + L.chunk : n;
+            has_pend = true;
+            break;
+          }
+          scan = scan + 1 == L.nsims ? 0 : scan + 1;
         }
       }
       if (pool_next == pool_end && has_pend && (pend_sim == cur || dead == ~0ull)) {
@@ -399,6 +434,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
       continue;  // the wave's lanes just finished: take the pending job next
     }
     D = uniform_sim(D);
+    if (c_slots >= (1u << 30)) spill_counts();  // keeps every 32-bit count from wrapping
     c_slots += 64;
     c_ev += wave_count(alive);
 
