@@ -342,6 +342,47 @@ def batch_workload(nsims: int = 256, seed: int = 1, sides=BATCH_SIDES,
     return items
 
 
+# ------------------------------------------------------------------ denoiser
+
+DENOISER_CHANNELS = (32, 64, 128, 256)
+
+
+def denoiser_layer_shapes(channels=DENOISER_CHANNELS) -> list:
+    """(kind, taps, cin, cout) of the denoiser's layers in forward order:
+    input conv, level-0 conv, then per deeper level a stride-2 down conv and
+    a conv, one more conv at the bottom, then per level back up a stride-2
+    transposed conv and a conv, and the one-channel output conv."""
+    c = list(channels)
+    out = [("conv3", 27, 1, c[0]), ("conv3", 27, c[0], c[0])]
+    for l in range(1, len(c)):
+        out += [("down", 8, c[l - 1], c[l]), ("conv3", 27, c[l], c[l])]
+    out.append(("conv3", 27, c[-1], c[-1]))
+    for l in range(len(c) - 2, -1, -1):
+        out += [("up", 8, c[l + 1], c[l]), ("conv3", 27, c[l], c[l])]
+    out.append(("conv3", 27, c[0], 1))
+    return out
+
+
+def denoiser_weights(channels=DENOISER_CHANNELS, seed: int = 1, zero_output: bool = True,
+                     bias_scale: float = 0.0) -> list:
+    """Seeded initial weights: He-normal (std sqrt(2 / (taps * cin))) float32
+    weights [taps][cin][cout] and biases (zero, or normal with std
+    `bias_scale`), in forward layer order, from numpy PCG64 `seed`.  With
+    `zero_output` the output layer starts at zero, so an untrained network
+    returns its input."""
+    rng = np.random.default_rng(seed)
+    shapes = denoiser_layer_shapes(channels)
+    out = []
+    for i, (kind, taps, ci, co) in enumerate(shapes):
+        w = rng.normal(0.0, np.sqrt(2.0 / (taps * ci)), size=(taps, ci, co)).astype(np.float32)
+        b = (rng.normal(0.0, bias_scale, size=co) if bias_scale else np.zeros(co)).astype(np.float32)
+        if zero_output and i == len(shapes) - 1:
+            w[...] = 0.0
+            b[...] = 0.0
+        out.append((w, b))
+    return out
+
+
 def with_medium(p: Problem, row: int, values) -> Problem:
     media = p.media.copy()
     media[row] = values
