@@ -49,6 +49,12 @@ def main():
     ap.add_argument("--head-photons", type=int, default=100_000_000)
     ap.add_argument("--no-head", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-denoise", action="store_true")
+    ap.add_argument("--dn-train", type=int, default=64, help="denoiser training volumes")
+    ap.add_argument("--dn-steps", type=int, default=1500, help="denoiser training steps")
+    ap.add_argument("--dn-eval", type=int, default=2, help="held-out volumes")
+    ap.add_argument("--dn-plain", type=float, default=1e9, help="plain-run photons")
+    ap.add_argument("--dn-ref-runs", type=int, default=2, help="reference runs per volume")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the transport on a single "
@@ -96,6 +102,7 @@ def main():
 
     head = None if args.no_head else head_leg(mcx, roofline, W, args.head_photons, args.seed)
     batched = None if args.no_batch else batch_leg(mcx, W)
+    denoised = None if args.no_denoise else denoise_leg(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -125,6 +132,7 @@ def main():
         "cpu_baseline": cpu,
         "head_volume": head,
         "batched": batched,
+        "denoiser": denoised,
     }
     print(json.dumps(line), flush=True)
 
@@ -169,6 +177,29 @@ def batch_leg(mcx, W):
         out["autotune"] = tune
     out["speedup"] = out["autotuned"]["photons_per_ms"] / out["fixed"]["photons_per_ms"]
     return out
+
+
+def denoise_leg(args):
+    """Train the denoiser on simulator pairs, then time-to-equal-error on
+    held-out volumes against the plain run."""
+    from paper_1711_03244_amd import denoise, nn, workloads as W
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    side = 64
+    ch = W.DENOISER_CHANNELS
+    t0 = time.perf_counter()
+    ds = denoise.make_dataset(range(1, args.dn_train + 1), side, [1e5, 1e6], 1e7, say=log)
+    data_s = time.perf_counter() - t0
+    with nn.Denoiser(ch, (side, side, side)) as d:
+        d.set_params(W.denoiser_weights(ch, seed=1))
+        tr = denoise.train(d, ds, args.dn_steps, lr=1e-3, log_every=max(1, args.dn_steps // 5),
+                           say=log)
+        ev = denoise.evaluate(d, range(900001, 900001 + args.dn_eval), side, args.dn_plain,
+                              args.dn_ref_runs, [1e5, 1e6, 1e7], say=log)
+    del ds
+    return {"workload": "denoise_64cubes", "channels": list(ch), "side": side,
+            "train_volumes": args.dn_train, "train_inputs": [1e5, 1e6], "train_target": 1e7,
+            "data_s": data_s, "train_steps": tr["steps"], "train_s": tr["seconds"],
+            "final_loss": tr["losses"][-1][1] if tr["losses"] else None, **ev}
 
 
 if __name__ == "__main__":

@@ -1,0 +1,121 @@
+/* mcx_nn.h -- C ABI of the fluence denoiser in libmcx (gfx950).
+ *
+ * The paper's method (its per-thread photon loop, Fig. 1) produces noisy
+ * Monte Carlo fluence maps whose noise falls as 1/sqrt(photons).  The
+ * denoiser is an addition on top of that output: a 3-D residual U-Net that
+ * maps a low-photon fluence map (one gate, per launched photon, as returned
+ * by mcx_fluence kind MCX_FLUENCE) to an estimate of the high-photon map,
+ * trained on pairs of maps the simulator itself produces.  It works in log
+ * space, u = (ln max(phi, 1e-12) - (-16)) / 4, and adds its output to u
+ * (a global residual), so an untrained network (zero output layer) returns
+ * its input.
+ *
+ * Network with channels c[0..L-1] on an nz x ny x nx grid (each side a
+ * multiple of 2^(L-1)); every convolution has a bias per output channel:
+ *   level 0:  relu(conv3 1 -> c0), relu(conv3 c0 -> c0)            = skip 0
+ *   level l:  relu(down c[l-1] -> c[l]), relu(conv3 c[l] -> c[l])   = skip l
+ *   bottom:   relu(conv3 c[L-1] -> c[L-1])
+ *   up to l:  relu(up c[l+1] -> c[l] + skip l), relu(conv3 c[l] -> c[l])
+ *   output:   u + conv3 c0 -> 1
+ * conv3 = 3x3x3 convolution, stride 1, zero padding; down = 2x2x2
+ * convolution, stride 2; up = 2x2x2 transposed convolution, stride 2.
+ * Weights are BF16 on the matrix cores with FP32 accumulation; activations
+ * and back-propagated activation gradients are stored as BF16; master
+ * weights, weight gradients, the loss and Adam state are FP32.
+ *
+ * Parameters, as one FP32 array in layer order (the order above): for each
+ * layer its weights w[taps][cin][cout] (taps 27 for conv3 with tap
+ * t = (dz+1)*9 + (dy+1)*3 + (dx+1) reading x[z+dz][y+dy][x+dx]; taps 8 for
+ * down / up with t = 4a + 2b + c for the offset (a, b, c) in {0,1}^3) and
+ * then its biases b[cout].
+ *
+ * Loss: mean squared error between the output and the target's u over the
+ * voxels whose target fluence is at least 1e-8 of the target's maximum.
+ * Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ *
+ * All volume arguments are device pointers of nx*ny*nz floats, x fastest,
+ * read (or written) on `hip_stream` (a hipStream_t; NULL = the null
+ * stream, as for HIP calls).  Parameter and gradient copies wait for the
+ * whole device.  Calls on one network must not overlap in time (they share
+ * its activation buffers): keep them on one stream.  Errors as in mcx.h
+ * (mcx_last_error has the message).
+ */
+#ifndef MCX_NN_H
+#define MCX_NN_H
+
+#include <stdint.h>
+
+#include "mcx.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcx_nn mcx_nn;
+
+/* Layer kinds of the single-layer calls. */
+enum { MCX_NN_CONV3 = 0, MCX_NN_DOWN = 1, MCX_NN_UP = 2 };
+
+/* Network with nlevels (1..6) levels of channels[i] (1..1024, increasing
+ * not required) for volumes of nx x ny x nz voxels (each a multiple of
+ * 2^(nlevels-1)); parameters start at zero (set them with
+ * mcx_nn_set_params).  Allocates all activation, gradient and optimiser
+ * buffers on `device`.  MCX_EINVAL / MCX_ENODEV / MCX_ENOMEM. */
+mcx_status mcx_nn_create(const int32_t *channels, int32_t nlevels, int32_t nx, int32_t ny,
+                         int32_t nz, int32_t device, mcx_nn **out);
+void mcx_nn_destroy(mcx_nn *nn);
+
+/* Number of FP32 parameters (weights and biases of every layer). */
+uint64_t mcx_nn_param_count(const mcx_nn *nn);
+
+/* Copy all parameters in (host array of mcx_nn_param_count floats; also
+ * clears the Adam moments and step count) or out; copy out the gradients
+ * of the last mcx_nn_loss_grad / mcx_nn_train_step.  MCX_ERANGE when n
+ * differs from mcx_nn_param_count.  Blocking (waits for the device). */
+mcx_status mcx_nn_set_params(mcx_nn *nn, const float *host, uint64_t n);
+mcx_status mcx_nn_get_params(mcx_nn *nn, float *host, uint64_t n);
+mcx_status mcx_nn_get_grads(mcx_nn *nn, float *host, uint64_t n);
+
+/* Denoise phi_in into phi_out (fluence, may be NULL) and/or u_out (the
+ * network output in u space, may be NULL).  Async. */
+mcx_status mcx_nn_forward(mcx_nn *nn, const float *phi_in, float *phi_out, float *u_out,
+                          void *hip_stream);
+
+/* Forward pass on phi_in, loss against phi_target and backward pass: the
+ * gradients of every parameter (mcx_nn_get_grads).  *loss (may be NULL)
+ * receives the loss, which makes the call wait for the stream; with
+ * loss == NULL it is async. */
+mcx_status mcx_nn_loss_grad(mcx_nn *nn, const float *phi_in, const float *phi_target,
+                            double *loss, void *hip_stream);
+
+/* One Adam step with learning rate lr on the current gradients.  Async. */
+mcx_status mcx_nn_adam(mcx_nn *nn, float lr, void *hip_stream);
+
+/* mcx_nn_loss_grad followed by mcx_nn_adam. */
+mcx_status mcx_nn_train_step(mcx_nn *nn, const float *phi_in, const float *phi_target, float lr,
+                             double *loss, void *hip_stream);
+
+/* Single layers on device buffers (the network's kernels, for tests and
+ * for callers building other graphs).  (nx, ny, nz) is the layer's input
+ * grid; the output grid is the same (conv3), half (down) or twice (up) per
+ * axis.  x: BF16 bits [input voxel][cin]; w: FP32 [taps][cin][cout];
+ * b: FP32 [cout] (may be NULL in forward); skip: BF16 bits [output
+ * voxel][cout] added before the ReLU (may be NULL); y: [output
+ * voxel][cout], FP32 when y_f32 else BF16 bits.  Backward takes the BF16
+ * gradient gy of the layer output (after any ReLU mask) and overwrites gx
+ * (FP32 [input voxel][cin], may be NULL), gw and gb (may be NULL).
+ * Temporary weight packs are allocated per call; both wait for the stream
+ * before returning. */
+mcx_status mcx_nn_layer_forward(int32_t kind, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
+                                int32_t cout, const uint16_t *x, const float *w, const float *b,
+                                const uint16_t *skip, int32_t relu, int32_t y_f32, void *y,
+                                void *hip_stream);
+mcx_status mcx_nn_layer_backward(int32_t kind, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
+                                 int32_t cout, const uint16_t *x, const float *w,
+                                 const uint16_t *gy, float *gx, float *gw, float *gb,
+                                 void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCX_NN_H */

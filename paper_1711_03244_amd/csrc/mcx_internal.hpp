@@ -4,7 +4,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mcx.h"
+
 namespace mcx {
+
+// Set the calling thread's mcx_last_error message; returns st.
+mcx_status report(mcx_status st, const char* message);
 
 // Ledger slots (FP64 weight sums) and counter slots accumulated per simulation.
 enum LedgerSlot {

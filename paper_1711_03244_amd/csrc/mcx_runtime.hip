@@ -40,6 +40,16 @@ mcx_status fail(mcx_status st, const char* fmt, ...) {
   return st;
 }
 
+}  // namespace
+
+// Shared with the denoiser runtime: record a message for mcx_last_error.
+mcx_status mcx::report(mcx_status st, const char* message) {
+  g_error = message;
+  return st;
+}
+
+namespace {
+
 #define HIP_TRY(expr)                                                              \
   do {                                                                             \
     hipError_t e_ = (expr);                                                        \

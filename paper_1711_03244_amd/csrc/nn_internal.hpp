@@ -1,0 +1,72 @@
+// Internal interfaces of the denoiser kernels (nn_kernels.hip) used by the
+// denoiser runtime (nn_runtime.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcx {
+namespace nn {
+
+// log-space input transform u = (ln max(phi, kEps) - kLogShift) / kLogScale
+constexpr float kEps = 1e-12f;
+constexpr float kLogShift = -16.f;
+constexpr float kLogScale = 4.f;
+
+enum Geometry : int32_t { kConv3 = 0, kConv3T = 1, kDown = 2, kUp = 3 };
+
+// One implicit-GEMM convolution.  Rows m run over the d x h x w grid
+// (kConv3/kConv3T: the output grid = input grid; kDown: the output grid;
+// kUp: the input grid, the output being twice as large per axis).
+struct ConvArgs {
+  int32_t geo;
+  int32_t d, h, w;            // grid of rows
+  int32_t in_d, in_h, in_w;   // grid of x (for bounds of kConv3/kConv3T)
+  int32_t cin, cout;          // channels of x and of y
+  int32_t k;                  // reduction length: taps * cin (kUp: cin)
+  int32_t kpad;               // row length of bt
+  const uint16_t* x;          // BF16 [voxel][cin]
+  const uint16_t* bt;         // BF16 [>= cout rounded to 64][kpad]
+  const float* bias;          // [cout] or null
+  const uint16_t* skip;       // BF16 [out voxel][cout] added before ReLU, or null
+  void* y;                    // BF16 or FP32 [out voxel][cout]
+  int32_t y_f32, relu;
+};
+
+// Weight gradient gw[t][ci][n] += sum_m A(m, t, ci) gy(m, n) (FP32 atomics).
+struct WgradArgs {
+  int32_t geo;                // kConv3, kDown or kUp (the layer's forward geometry)
+  int32_t d, h, w;            // grid of m: the output grid (kConv3, kDown), the input grid (kUp)
+  int32_t taps, cin, cout;
+  int64_t m_per_block;        // voxels per workgroup (multiple of 32)
+  ConvArgs g;                 // geometry fields for the gather (geo, in_d, in_h, in_w)
+  const uint16_t* x;          // BF16 [voxel][cin], the layer input
+  const uint16_t* gy;         // BF16 [voxel][cout], gradient of the layer output
+  float* gw;                  // FP32 [taps][cin][cout], accumulated
+};
+
+hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
+hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s);
+// pack w[taps][cin][cout] (FP32) into BF16 rows: forward Bt[n][t * cin + ci]
+// (rows >= cout) or transposed Bt[ci][t * cout + n] (rows >= cin); the
+// rows x kpad buffer is cleared first
+hipError_t launch_pack(const float* w, int taps, int cin, int cout, int rows, int kpad,
+                       bool transposed, uint16_t* bt, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_to_log(const float* phi, int64_t n, float* u, uint16_t* u16, hipStream_t s);
+hipError_t launch_from_log(const float* r, const float* u, int64_t n, float* out_u, float* phi,
+                           hipStream_t s);
+hipError_t launch_relu_grad(const float* g, const uint16_t* skip16, const uint16_t* y16, int64_t n,
+                            uint16_t* g16, hipStream_t s);
+// masked MSE in u space; target voxels with phi >= rel_floor * max(phi)
+// count; grad = 2 (out - t) / count there.  acc[0] = sum of squares,
+// acc[1] = count (FP64); phi_max: one float of scratch
+hipError_t launch_mse(const float* out, const float* target_u, const float* target_phi,
+                      float rel_floor, int64_t n, float* grad, double* acc, float* phi_max,
+                      hipStream_t s);
+hipError_t launch_bias_grad(const uint16_t* gy, int64_t m, int cout, float* gb, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, int step,
+                       hipStream_t s);
+
+}  // namespace nn
+}  // namespace mcx

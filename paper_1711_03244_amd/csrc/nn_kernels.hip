@@ -1,0 +1,553 @@
+// gfx950 kernels of the fluence denoiser: BF16 MFMA convolutions with FP32
+// accumulation (forward, input gradient, weight gradient) and the
+// element-wise steps around them.
+//
+// Activations are channels-last BF16 arrays [voxel][channel], voxels
+// x-fastest.  A convolution is an implicit GEMM: rows m are the voxels of
+// the grid the kernel iterates, columns n the output channels, and the
+// reduction index k = tap * Cin + ci walks the input channels of every tap.
+// The A operand is gathered from the activation array on the fly (zero
+// outside the volume), the B operand is the weight matrix packed as BF16
+// rows Bt[n][k] (k contiguous, padded with zeros to the tile sizes).
+// Four gather geometries cover the forward pass and the input gradient of
+// all three layer kinds:
+//   kConv3   y[v] += x[v + d(t)] W[t]        (3x3x3, stride 1, zero pad)
+//   kConv3T  y[v] += x[v - d(t)] W[t]        (its input gradient)
+//   kDown    y[v] += x[2v + e(t)] W[t]       (2x2x2, stride 2)
+//   kUp      y[2v + e(c)] = x[v] W[c]        (2x2x2 transposed, one parity
+//                                             class c per grid z-slice)
+// The down layer's input gradient is a kUp product and the up layer's a
+// kDown product, each with transposed weights.
+//
+// MFMA v_mfma_f32_16x16x32_bf16: lane l supplies A[l % 16][8(l / 16) + j]
+// and B[8(l / 16) + j][l % 16] (j = 0..7) and receives
+// D[4(l / 16) + i][l % 16] (i = 0..3).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#include "nn_internal.hpp"
+
+namespace mcx {
+namespace nn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBM = 64;   // rows per workgroup tile (4 waves x 16)
+constexpr int kBK = 32;   // reduction step
+constexpr int kPadK = 8;  // LDS row padding (bf16 elements)
+
+// float -> bf16 bits, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// voxel index of the A operand for row m (grid coordinates z, y, x) and
+// tap t, or -1 when it lies outside the input volume
+__device__ __forceinline__ int64_t gather_at(const ConvArgs& a, int z, int y, int x, int t) {
+  int iz, iy, ix;
+  if (a.geo == kConv3 || a.geo == kConv3T) {
+    const int s = a.geo == kConv3 ? 1 : -1;
+    iz = z + s * (t / 9 - 1);
+    iy = y + s * ((t / 3) % 3 - 1);
+    ix = x + s * (t % 3 - 1);
+    if (iz < 0 || iy < 0 || ix < 0 || iz >= a.in_d || iy >= a.in_h || ix >= a.in_w) return -1;
+  } else if (a.geo == kDown) {
+    iz = 2 * z + (t >> 2);
+    iy = 2 * y + ((t >> 1) & 1);
+    ix = 2 * x + (t & 1);
+  } else {
+    iz = z;
+    iy = y;
+    ix = x;
+  }
+  return (static_cast<int64_t>(iz) * a.in_h + iy) * a.in_w + ix;
+}
+
+// ------------------------------------------------------------ forward GEMM
+// One workgroup: 64 rows x 16*NB columns; wave w owns rows 16w..16w+15.
+template <int NB, bool kVec>
+__global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
+  __shared__ uint16_t sA[kBM][kBK + kPadK];
+  __shared__ uint16_t sB[16 * NB][kBK + kPadK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * kBM;
+  const int n0 = blockIdx.y * 16 * NB;
+  const int cls = blockIdx.z;  // parity class of kUp, else 0
+  const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
+  const int koff = a.geo == kUp ? cls * a.cin : 0;
+
+  // this thread's A row and 8-wide k chunk for the loads
+  const int lr = tid >> 2, lc = (tid & 3) * 8;
+  const int64_t lm = m0 + lr;
+  int lz = 0, ly = 0, lx = 0;
+  if (lm < M) {
+    lx = static_cast<int>(lm % a.w);
+    ly = static_cast<int>((lm / a.w) % a.h);
+    lz = static_cast<int>(lm / (static_cast<int64_t>(a.w) * a.h));
+  }
+
+  floatx4 acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < a.k; k0 += kBK) {
+    // A tile: 64 rows x 32 k
+    {
+      const int k = k0 + lc;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (lm < M) {
+        if constexpr (kVec) {
+          if (k < a.k) {
+            const int t = k / a.cin, ci = k - t * a.cin;
+            const int64_t src = gather_at(a, lz, ly, lx, t);
+            if (src >= 0) v = *reinterpret_cast<const uint4*>(a.x + src * a.cin + ci);
+          }
+        } else {
+          uint16_t e[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            e[j] = 0;
+            const int kk = k + j;
+            if (kk < a.k) {
+              const int t = kk / a.cin, ci = kk - t * a.cin;
+              const int64_t src = gather_at(a, lz, ly, lx, t);
+              if (src >= 0) e[j] = a.x[src * a.cin + ci];
+            }
+          }
+          v = make_uint4(e[0] | (uint32_t(e[1]) << 16), e[2] | (uint32_t(e[3]) << 16),
+                         e[4] | (uint32_t(e[5]) << 16), e[6] | (uint32_t(e[7]) << 16));
+        }
+      }
+      *reinterpret_cast<uint4*>(&sA[lr][lc]) = v;
+    }
+    // B tile: 16*NB rows (output channels) x 32 k from Bt[n][koff + k]
+    for (int i = tid; i < 16 * NB * 4; i += 256) {
+      const int r = i >> 2, c = (i & 3) * 8;
+      const int k = k0 + c;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      const uint16_t* row = a.bt + static_cast<int64_t>(n0 + r) * a.kpad + koff;
+      if (k + 8 <= a.k && (koff & 7) == 0) {
+        v = *reinterpret_cast<const uint4*>(row + k);
+      } else {
+        uint16_t e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) e[j] = (k + j < a.k) ? row[k + j] : 0;
+        v = make_uint4(e[0] | (uint32_t(e[1]) << 16), e[2] | (uint32_t(e[3]) << 16),
+                       e[4] | (uint32_t(e[5]) << 16), e[6] | (uint32_t(e[7]) << 16));
+      }
+      *reinterpret_cast<uint4*>(&sB[r][c]) = v;
+    }
+    __syncthreads();
+    const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sA[wave * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const bf16x8 bf = *reinterpret_cast<const bf16x8*>(&sB[j * 16 + (lane & 15)][(lane >> 4) * 8]);
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: bias, skip, ReLU, store
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int n = n0 + j * 16 + (lane & 15);
+    if (n >= a.cout) continue;
+    const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t m = m0 + wave * 16 + (lane >> 4) * 4 + i;
+      if (m >= M) continue;
+      int64_t o = m;
+      if (a.geo == kUp) {
+        const int x = static_cast<int>(m % a.w);
+        const int y = static_cast<int>((m / a.w) % a.h);
+        const int z = static_cast<int>(m / (static_cast<int64_t>(a.w) * a.h));
+        o = (static_cast<int64_t>(2 * z + (cls >> 2)) * (2 * a.h) + 2 * y + ((cls >> 1) & 1)) *
+                (2 * a.w) + 2 * x + (cls & 1);
+      }
+      float v = acc[j][i] + bias;
+      if (a.skip) v += from_bf16(a.skip[o * a.cout + n]);
+      if (a.relu) v = fmaxf(v, 0.f);
+      if (a.y_f32)
+        static_cast<float*>(a.y)[o * a.cout + n] = v;
+      else
+        static_cast<uint16_t*>(a.y)[o * a.cout + n] = to_bf16(v);
+    }
+  }
+}
+
+// ------------------------------------------------------------ weight GEMM
+// gw[p][n] += sum over the workgroup's voxels of A(m, p) gy(m, n), with
+// p = t * cin + ci.  kConv3 / kDown: m runs over the output grid, A is x
+// gathered at the tap; kUp: m runs over the input grid, A = x[m] and gy is
+// read at the parity-class position of tap t (all rows of a tile share t).
+template <int NB, bool kVec>
+__global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
+  __shared__ uint16_t sA[kBM][kBK + kPadK];       // [p][m]
+  __shared__ uint16_t sB[16 * NB][kBK + kPadK];   // [n][m]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
+  const int64_t mb = static_cast<int64_t>(blockIdx.x) * a.m_per_block;
+  const int64_t me = mb + a.m_per_block < M ? mb + a.m_per_block : M;
+  const int n0 = blockIdx.z * 16 * NB;
+  const int P = a.taps * a.cin;
+  // rows of this tile
+  int p0, t_up = 0, prow_lim;
+  if (a.geo == kUp) {
+    const int tiles = (a.cin + kBM - 1) / kBM;
+    t_up = blockIdx.y / tiles;
+    p0 = t_up * a.cin + (blockIdx.y % tiles) * kBM;
+    prow_lim = t_up * a.cin + a.cin;
+  } else {
+    p0 = blockIdx.y * kBM;
+    prow_lim = P;
+  }
+
+  floatx4 acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t m0 = mb; m0 < me; m0 += kBK) {
+    // A: 64 rows (p) x 32 voxels, loaded 8 rows of one voxel per thread
+    {
+      const int mm = tid >> 3, rc = (tid & 7) * 8;
+      const int64_t m = m0 + mm;
+      uint16_t e[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) e[j] = 0;
+      if (m < me) {
+        const int x = static_cast<int>(m % a.w);
+        const int y = static_cast<int>((m / a.w) % a.h);
+        const int z = static_cast<int>(m / (static_cast<int64_t>(a.w) * a.h));
+        const int p = p0 + rc;
+        if constexpr (kVec) {
+          if (p < prow_lim) {
+            const int t = p / a.cin, ci = p - t * a.cin;
+            const int64_t src = a.geo == kUp ? m : gather_at(a.g, z, y, x, t);
+            if (src >= 0) {
+              const uint4 v = *reinterpret_cast<const uint4*>(a.x + src * a.cin + ci);
+              e[0] = v.x & 0xffff; e[1] = v.x >> 16; e[2] = v.y & 0xffff; e[3] = v.y >> 16;
+              e[4] = v.z & 0xffff; e[5] = v.z >> 16; e[6] = v.w & 0xffff; e[7] = v.w >> 16;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int pj = p + j;
+            if (pj < prow_lim) {
+              const int t = pj / a.cin, ci = pj - t * a.cin;
+              const int64_t src = a.geo == kUp ? m : gather_at(a.g, z, y, x, t);
+              if (src >= 0) e[j] = a.x[src * a.cin + ci];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sA[rc + j][mm] = e[j];
+    }
+    // B: 16*NB channels x 32 voxels of gy
+    for (int i = tid; i < 2 * NB * kBK; i += 256) {
+      const int nc = (i % (2 * NB)) * 8, mm = i / (2 * NB);
+      const int64_t m = m0 + mm;
+      uint16_t e[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) e[j] = 0;
+      if (m < me) {
+        int64_t gi = m;
+        if (a.geo == kUp) {
+          const int x = static_cast<int>(m % a.w);
+          const int y = static_cast<int>((m / a.w) % a.h);
+          const int z = static_cast<int>(m / (static_cast<int64_t>(a.w) * a.h));
+          gi = (static_cast<int64_t>(2 * z + (t_up >> 2)) * (2 * a.h) + 2 * y + ((t_up >> 1) & 1)) *
+                   (2 * a.w) + 2 * x + (t_up & 1);
+        }
+        const uint16_t* row = a.gy + gi * a.cout + n0 + nc;
+        if (a.cout % 8 == 0 && n0 + nc + 8 <= a.cout) {
+          const uint4 v = *reinterpret_cast<const uint4*>(row);
+          e[0] = v.x & 0xffff; e[1] = v.x >> 16; e[2] = v.y & 0xffff; e[3] = v.y >> 16;
+          e[4] = v.z & 0xffff; e[5] = v.z >> 16; e[6] = v.w & 0xffff; e[7] = v.w >> 16;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) e[j] = (n0 + nc + j < a.cout) ? row[j] : 0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sB[nc + j][mm] = e[j];
+    }
+    __syncthreads();
+    const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sA[wave * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const bf16x8 bf = *reinterpret_cast<const bf16x8*>(&sB[j * 16 + (lane & 15)][(lane >> 4) * 8]);
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int n = n0 + j * 16 + (lane & 15);
+    if (n >= a.cout) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = p0 + wave * 16 + (lane >> 4) * 4 + i;
+      if (p < prow_lim && acc[j][i] != 0.f)
+        unsafeAtomicAdd(a.gw + static_cast<int64_t>(p) * a.cout + n, acc[j][i]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ element-wise
+
+// Bt[n][koff(t) + ci] from w[t][ci][n] (forward packing) or
+// Bt[ci][t * cout + n] from w[t][ci][n] (transposed packing); rows and
+// columns beyond the matrix stay zero (the buffer is cleared first).
+__global__ void pack_kernel(const float* w, int taps, int cin, int cout, int kpad, int transposed,
+                            uint16_t* bt) {
+  const int64_t total = static_cast<int64_t>(taps) * cin * cout;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int n = static_cast<int>(i % cout);
+    const int ci = static_cast<int>((i / cout) % cin);
+    const int t = static_cast<int>(i / (static_cast<int64_t>(cout) * cin));
+    const uint16_t v = to_bf16(w[i]);
+    if (transposed)
+      bt[static_cast<int64_t>(ci) * kpad + t * cout + n] = v;
+    else
+      bt[static_cast<int64_t>(n) * kpad + t * cin + ci] = v;
+  }
+}
+
+__global__ void fill_u16_kernel(uint16_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
+
+__global__ void zero2_kernel(double* acc, float* fmax) {
+  acc[0] = 0.0;
+  acc[1] = 0.0;
+  fmax[0] = 0.f;
+}
+
+__global__ void fill_f32_kernel(float* p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// u = (ln max(phi, eps) - shift) / scale, in FP32 and as BF16
+__global__ void to_log_kernel(const float* phi, int64_t n, float eps, float shift, float inv_scale,
+                              float* u, uint16_t* u16) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float v = (logf(fmaxf(phi[i], eps)) - shift) * inv_scale;
+    if (u) u[i] = v;
+    if (u16) u16[i] = to_bf16(v);
+  }
+}
+
+// phi_out = exp((r + u) * scale + shift): output of the residual network
+__global__ void from_log_kernel(const float* r, const float* u, int64_t n, float scale, float shift,
+                                float* out_u, float* phi) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float v = r[i] + u[i];
+    if (out_u) out_u[i] = v;
+    if (phi) phi[i] = expf(v * scale + shift);
+  }
+}
+
+// g16 = bf16((g + skip16) * (y16 > 0)); g may be FP32 or absent (skip only)
+__global__ void relu_grad_kernel(const float* g, const uint16_t* skip16, const uint16_t* y16,
+                                 int64_t n, uint16_t* g16) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float v = g ? g[i] : 0.f;
+    if (skip16) v += from_bf16(skip16[i]);
+    if (y16 && !(from_bf16(y16[i]) > 0.f)) v = 0.f;
+    g16[i] = to_bf16(v);
+  }
+}
+
+// masked squared error of out against target (both in u space): sum and
+// count into acc[0..1] (FP64), and the unnormalised gradient 2 (out - t)
+// per masked voxel (zero elsewhere)
+__global__ void mse_kernel(const float* out, const float* target_u, const float* target_phi,
+                           float rel_floor, const float* phi_max, int64_t n, float* grad,
+                           double* acc) {
+  double s = 0.0, c = 0.0;
+  const float thr = rel_floor * phi_max[0];
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const bool on = target_phi[i] >= thr;
+    const float d = on ? out[i] - target_u[i] : 0.f;
+    grad[i] = 2.f * d;
+    s += static_cast<double>(d) * d;
+    c += on ? 1.0 : 0.0;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_down(s, off, 64);
+    c += __shfl_down(c, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    unsafeAtomicAdd(acc, s);
+    unsafeAtomicAdd(acc + 1, c);
+  }
+}
+
+__global__ void max_kernel(const float* x, int64_t n, float* out) {
+  float m = 0.f;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    m = fmaxf(m, x[i]);
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<int*>(out), __float_as_int(m));
+}
+
+// grad *= 1 / count (count from acc[1])
+__global__ void scale_grad_kernel(float* g, int64_t n, const double* acc) {
+  const float s = acc[1] > 0.0 ? static_cast<float>(1.0 / acc[1]) : 0.f;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    g[i] *= s;
+}
+
+// gb[n] += sum over voxels of gy[m][n]
+__global__ void bias_grad_kernel(const uint16_t* gy, int64_t m, int cout, float* gb) {
+  for (int n = threadIdx.x; n < cout; n += blockDim.x) {
+    float s = 0.f;
+    for (int64_t i = blockIdx.x; i < m; i += gridDim.x) s += from_bf16(gy[i * cout + n]);
+    unsafeAtomicAdd(gb + n, s);
+  }
+}
+
+// Adam with bias-corrected moments
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+int blocks_for(int64_t n, int per = 256, int cap = 8192) {
+  const int64_t b = (n + per - 1) / per;
+  return static_cast<int>(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- launchers
+
+hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
+  const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
+  const int nb = a.cout > 32 ? 4 : (a.cout > 16 ? 2 : 1);
+  const dim3 grid(static_cast<unsigned>((M + kBM - 1) / kBM),
+                  static_cast<unsigned>((a.cout + 16 * nb - 1) / (16 * nb)), a.geo == kUp ? 8 : 1);
+  const bool vec = a.cin % 8 == 0;
+#define MCX_CONV(NB)                                                   \
+  if (vec)                                                             \
+    conv_kernel<NB, true><<<grid, 256, 0, s>>>(a);                     \
+  else                                                                 \
+    conv_kernel<NB, false><<<grid, 256, 0, s>>>(a);
+  if (nb == 4) { MCX_CONV(4) } else if (nb == 2) { MCX_CONV(2) } else { MCX_CONV(1) }
+#undef MCX_CONV
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
+  const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
+  const int nb = a.cout > 32 ? 4 : (a.cout > 16 ? 2 : 1);
+  const int P = a.taps * a.cin;
+  const int ptiles = a.geo == kUp ? a.taps * ((a.cin + kBM - 1) / kBM) : (P + kBM - 1) / kBM;
+  const dim3 grid(static_cast<unsigned>((M + a.m_per_block - 1) / a.m_per_block),
+                  static_cast<unsigned>(ptiles),
+                  static_cast<unsigned>((a.cout + 16 * nb - 1) / (16 * nb)));
+  const bool vec = a.cin % 8 == 0;
+#define MCX_WG(NB)                                                     \
+  if (vec)                                                             \
+    wgrad_kernel<NB, true><<<grid, 256, 0, s>>>(a);                    \
+  else                                                                 \
+    wgrad_kernel<NB, false><<<grid, 256, 0, s>>>(a);
+  if (nb == 4) { MCX_WG(4) } else if (nb == 2) { MCX_WG(2) } else { MCX_WG(1) }
+#undef MCX_WG
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* w, int taps, int cin, int cout, int rows, int kpad,
+                       bool transposed, uint16_t* bt, hipStream_t s) {
+  fill_u16_kernel<<<blocks_for(static_cast<int64_t>(rows) * kpad), 256, 0, s>>>(
+      bt, static_cast<int64_t>(rows) * kpad);
+  pack_kernel<<<blocks_for(static_cast<int64_t>(taps) * cin * cout), 256, 0, s>>>(
+      w, taps, cin, cout, kpad, transposed ? 1 : 0, bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
+  fill_f32_kernel<<<blocks_for(n), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_log(const float* phi, int64_t n, float* u, uint16_t* u16, hipStream_t s) {
+  to_log_kernel<<<blocks_for(n), 256, 0, s>>>(phi, n, kEps, kLogShift, 1.f / kLogScale, u, u16);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_log(const float* r, const float* u, int64_t n, float* out_u, float* phi,
+                           hipStream_t s) {
+  from_log_kernel<<<blocks_for(n), 256, 0, s>>>(r, u, n, kLogScale, kLogShift, out_u, phi);
+  return hipGetLastError();
+}
+
+hipError_t launch_relu_grad(const float* g, const uint16_t* skip16, const uint16_t* y16, int64_t n,
+                            uint16_t* g16, hipStream_t s) {
+  relu_grad_kernel<<<blocks_for(n), 256, 0, s>>>(g, skip16, y16, n, g16);
+  return hipGetLastError();
+}
+
+hipError_t launch_mse(const float* out, const float* target_u, const float* target_phi,
+                      float rel_floor, int64_t n, float* grad, double* acc, float* phi_max,
+                      hipStream_t s) {
+  zero2_kernel<<<1, 1, 0, s>>>(acc, phi_max);
+  max_kernel<<<blocks_for(n, 256, 1024), 256, 0, s>>>(target_phi, n, phi_max);
+  mse_kernel<<<blocks_for(n, 256, 1024), 256, 0, s>>>(out, target_u, target_phi, rel_floor,
+                                                     phi_max, n, grad, acc);
+  scale_grad_kernel<<<blocks_for(n), 256, 0, s>>>(grad, n, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_grad(const uint16_t* gy, int64_t m, int cout, float* gb, hipStream_t s) {
+  const int blocks = static_cast<int>(m < 1024 ? m : 1024);
+  bias_grad_kernel<<<blocks < 1 ? 1 : blocks, 256, 0, s>>>(gy, m, cout, gb);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, int step,
+                       hipStream_t s) {
+  const double c1 = 1.0 - std::pow(0.9, step), c2 = 1.0 - std::pow(0.999, step);
+  adam_kernel<<<blocks_for(n), 256, 0, s>>>(p, g, m, v, n, lr, 0.9f, 0.999f, 1e-8f,
+                                            static_cast<float>(c1), static_cast<float>(c2));
+  return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace mcx

@@ -1,0 +1,191 @@
+"""Training data, training loop and time-to-equal-error evaluation of the
+fluence denoiser (include/mcx_nn.h), all on one GPU.
+
+Data: seeded random heterogeneous volumes (workloads.denoiser_volume), each
+simulated by the library's batched transport at a low photon count (the
+network input; several counts per volume) and a high one (the target),
+with independent seeds.  Maps are fluence per launched photon of the single
+gate.  Training: Adam with a cosine learning-rate decay over the
+(input, target) pairs in a seeded random order, one volume per step.
+
+Evaluation on held-out volumes: the reference map is the mean of K
+independent runs at the plain photon count; the error of a map is the RMS,
+over the medium voxels where the reference is at least 1e-8 of its
+maximum, of ln max(phi, 1e-12) - ln max(phi_ref, 1e-12).  The reference's
+own noise inflates every measured error; its share, estimated from the
+spread of the K runs (variance of the log map / K), is reported and
+subtracted in quadrature.  Times: the plain run's and each low-photon run's
+HIP-event time (clear + transport + reductions) plus the network's
+inference time (HIP events on the inference stream).
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import mcx, nn, workloads as W
+
+EPS = 1e-12
+MASK_FLOOR = 1e-8
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def simulate(problems, nphoton, seeds):
+    """Fluence maps (per launched photon, gate 0) of every problem, one
+    batched launch; returns (maps as float32 arrays, launch run_ms)."""
+    n = [int(nphoton)] * len(problems) if np.isscalar(nphoton) else [int(v) for v in nphoton]
+    with mcx.Batch(problems) as b:
+        b.run(n, [int(s) for s in seeds])
+        maps = [b.fluence(i, mcx.MCX_FLUENCE)[0].copy() for i in range(len(problems))]
+        run_ms = b.stats(0)["run_ms"]
+    return maps, run_ms
+
+
+def simulate_one(problem, nphoton, seed):
+    """One simulation in its own context; returns (map, run_ms)."""
+    with mcx.Simulation(problem) as s:
+        s.run(int(nphoton), int(seed))
+        return s.fluence(mcx.MCX_FLUENCE)[0].copy(), s.stats()["run_ms"]
+
+
+def error_mask(ref, labels):
+    return (labels != 0) & (ref >= MASK_FLOOR * ref.max())
+
+
+def log_rms(phi, ref, mask) -> float:
+    d = np.log(np.maximum(phi, EPS)) - np.log(np.maximum(ref, EPS))
+    return float(np.sqrt(np.mean(d[mask] ** 2)))
+
+
+@dataclass
+class DataSet:
+    volumes: list
+    inputs: list = field(default_factory=list)    # (volume index, photons, torch map)
+    targets: list = field(default_factory=list)   # torch map per volume
+    sim_ms: float = 0.0
+
+
+def make_dataset(seeds, side, input_photons, target_photons, seed_base=1_000_000, say=print):
+    """Simulate every volume at each input photon count and at the target
+    count (independent seeds)."""
+    t = _torch()
+    vols = [W.denoiser_volume(int(s), side) for s in seeds]
+    ds = DataSet(vols)
+    for j, n_in in enumerate(input_photons):
+        maps, ms = simulate(vols, n_in, [seed_base * (j + 1) + int(s) for s in seeds])
+        ds.sim_ms += ms
+        for i, m in enumerate(maps):
+            ds.inputs.append((i, int(n_in), t.as_tensor(m).cuda()))
+        say(f"[data] {len(vols)} volumes x {n_in:.0e} photons: {ms:.0f} ms")
+    maps, ms = simulate(vols, target_photons, [seed_base * 97 + int(s) for s in seeds])
+    ds.sim_ms += ms
+    ds.targets = [t.as_tensor(m).cuda() for m in maps]
+    say(f"[data] {len(vols)} volumes x {target_photons:.0e} photons (targets): {ms:.0f} ms")
+    return ds
+
+
+def train(den: nn.Denoiser, ds: DataSet, steps: int, lr: float = 1e-3, lr_min: float = 1e-5,
+          seed: int = 1, log_every: int = 0, say=print) -> dict:
+    """Adam steps over the pairs in a seeded random order, cosine-decayed
+    learning rate; returns losses and wall time."""
+    t = _torch()
+    rng = np.random.default_rng(seed)
+    order = []
+    losses = []
+    t.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if not order:
+            order = list(rng.permutation(len(ds.inputs)))
+        i = order.pop()
+        vi, _, x = ds.inputs[i]
+        rate = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * k / max(1, steps)))
+        want = log_every and (k % log_every == 0 or k == steps - 1)
+        loss = den.train_step(x, ds.targets[vi], rate, want_loss=bool(want))
+        if want:
+            losses.append((k, loss))
+            say(f"[train] step {k} lr {rate:.2e} loss {loss:.5f}")
+    t.cuda.synchronize()
+    return {"steps": steps, "seconds": time.perf_counter() - t0, "losses": losses}
+
+
+def infer_timed(den: nn.Denoiser, phi):
+    """Denoise one map; returns (map as numpy, inference ms by HIP events)."""
+    t = _torch()
+    x = t.as_tensor(phi).cuda()
+    out = t.empty_like(x)
+    s = t.cuda.current_stream()
+    e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+    e0.record(s)
+    den.forward(x, phi_out=out, stream=s)
+    e1.record(s)
+    e1.synchronize()
+    return out.cpu().numpy(), e0.elapsed_time(e1)
+
+
+def evaluate(den: nn.Denoiser, seeds, side, plain_photons, ref_runs, input_photons,
+             seed_base=5_000_000, say=print) -> dict:
+    """Time-to-equal-error on held-out volumes (see the module docstring)."""
+    rows = []
+    for s in seeds:
+        p = W.denoiser_volume(int(s), side)
+        refs = []
+        for k in range(ref_runs):
+            m, _ = simulate_one(p, plain_photons, seed_base + 1000 * int(s) + 11 + k)
+            refs.append(m.astype(np.float64))
+        ref = np.mean(refs, axis=0)
+        mask = error_mask(ref, p.labels)
+        logs = np.log(np.maximum(np.stack(refs), EPS))
+        ref_err = float(np.sqrt(np.mean(np.var(logs, axis=0, ddof=1)[mask]) / ref_runs))
+        plain, plain_ms = simulate_one(p, plain_photons, seed_base + 1000 * int(s) + 1)
+        row = {"seed": int(s), "mask_voxels": int(mask.sum()), "ref_err": ref_err,
+               "plain_err": log_rms(plain, ref, mask), "plain_ms": plain_ms, "inputs": []}
+        for j, n in enumerate(input_photons):
+            lo, lo_ms = simulate_one(p, n, seed_base + 1000 * int(s) + 100 + j)
+            dn, inf_ms = infer_timed(den, lo)
+            infer_timed(den, lo)  # the first call includes weight packing; time a second
+            dn, inf_ms = infer_timed(den, lo)
+            row["inputs"].append({"photons": int(n), "sim_ms": lo_ms, "infer_ms": inf_ms,
+                                  "noisy_err": log_rms(lo, ref, mask),
+                                  "denoised_err": log_rms(dn, ref, mask)})
+        rows.append(row)
+        say(f"[eval] volume {s}: plain {plain_photons:.0e} err {row['plain_err']:.4f} "
+            f"(ref share {ref_err:.4f}), " + ", ".join(
+                f"{r['photons']:.0e}: noisy {r['noisy_err']:.4f} denoised {r['denoised_err']:.4f}"
+                for r in row["inputs"]))
+    return summarise(rows, plain_photons, input_photons)
+
+
+def _debias(e, r):
+    return math.sqrt(max(e * e - r * r, 0.0))
+
+
+def summarise(rows, plain_photons, input_photons) -> dict:
+    ref = float(np.sqrt(np.mean([r["ref_err"] ** 2 for r in rows])))
+    plain = float(np.sqrt(np.mean([r["plain_err"] ** 2 for r in rows])))
+    plain_ms = float(np.mean([r["plain_ms"] for r in rows]))
+    per_n = []
+    for j, n in enumerate(input_photons):
+        den = float(np.sqrt(np.mean([r["inputs"][j]["denoised_err"] ** 2 for r in rows])))
+        noisy = float(np.sqrt(np.mean([r["inputs"][j]["noisy_err"] ** 2 for r in rows])))
+        ms = float(np.mean([r["inputs"][j]["sim_ms"] + r["inputs"][j]["infer_ms"] for r in rows]))
+        per_n.append({"photons": int(n), "noisy_err": noisy, "denoised_err": den,
+                      "noisy_err_debiased": _debias(noisy, ref),
+                      "denoised_err_debiased": _debias(den, ref), "sim_plus_infer_ms": ms,
+                      "infer_ms": float(np.mean([r["inputs"][j]["infer_ms"] for r in rows]))})
+    out = {"volumes": len(rows), "plain_photons": int(plain_photons), "plain_err": plain,
+           "plain_err_debiased": _debias(plain, ref), "ref_err": ref, "plain_ms": plain_ms,
+           "per_input": per_n, "equal_error_photons": None, "time_ratio": None}
+    for r in per_n:
+        if r["denoised_err_debiased"] <= out["plain_err_debiased"]:
+            out["equal_error_photons"] = r["photons"]
+            out["time_ratio"] = plain_ms / r["sim_plus_infer_ms"]
+            break
+    return out

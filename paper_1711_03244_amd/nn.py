@@ -1,0 +1,202 @@
+"""ctypes binding of the denoiser's C ABI (include/mcx_nn.h).
+
+Argument marshalling only: every step runs in libmcx's HIP kernels.  Volume
+arguments are torch CUDA tensors (device memory and streams are all torch
+is used for); parameters move as numpy float32 arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import mcx
+
+EXPORTS = ["mcx_nn_create", "mcx_nn_destroy", "mcx_nn_param_count", "mcx_nn_set_params",
+           "mcx_nn_get_params", "mcx_nn_get_grads", "mcx_nn_forward", "mcx_nn_loss_grad",
+           "mcx_nn_adam", "mcx_nn_train_step", "mcx_nn_layer_forward", "mcx_nn_layer_backward"]
+
+MCX_NN_CONV3, MCX_NN_DOWN, MCX_NN_UP = 0, 1, 2
+
+_bound = False
+
+
+def lib() -> C.CDLL:
+    global _bound
+    L = mcx.lib()
+    if not _bound:
+        vp, i32, u64, f32 = C.c_void_p, C.c_int32, C.c_uint64, C.c_float
+        sig = {
+            "mcx_nn_create": (C.c_int, [vp, i32, i32, i32, i32, i32, C.POINTER(vp)]),
+            "mcx_nn_destroy": (None, [vp]),
+            "mcx_nn_param_count": (u64, [vp]),
+            "mcx_nn_set_params": (C.c_int, [vp, vp, u64]),
+            "mcx_nn_get_params": (C.c_int, [vp, vp, u64]),
+            "mcx_nn_get_grads": (C.c_int, [vp, vp, u64]),
+            "mcx_nn_forward": (C.c_int, [vp, vp, vp, vp, vp]),
+            "mcx_nn_loss_grad": (C.c_int, [vp, vp, vp, C.POINTER(C.c_double), vp]),
+            "mcx_nn_adam": (C.c_int, [vp, f32, vp]),
+            "mcx_nn_train_step": (C.c_int, [vp, vp, vp, f32, C.POINTER(C.c_double), vp]),
+            "mcx_nn_layer_forward": (C.c_int, [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp,
+                                               i32, i32, vp, vp]),
+            "mcx_nn_layer_backward": (C.c_int, [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp,
+                                                vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _bound = True
+    return L
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(s):
+    import torch
+    if s is None:
+        s = torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check_volume(t, numel):
+    import torch
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == numel
+
+
+def mcx_nn_create(channels: Sequence[int], shape, device: int = 0) -> C.c_void_p:
+    nz, ny, nx = shape
+    ch = (C.c_int32 * len(channels))(*channels)
+    out = C.c_void_p()
+    mcx._check(lib().mcx_nn_create(ch, len(channels), nx, ny, nz, device, C.byref(out)))
+    return out
+
+
+def mcx_nn_destroy(h):
+    if h:
+        lib().mcx_nn_destroy(h)
+
+
+def mcx_nn_param_count(h) -> int:
+    return int(lib().mcx_nn_param_count(h))
+
+
+def mcx_nn_set_params(h, values: np.ndarray):
+    v = np.ascontiguousarray(values, np.float32)
+    mcx._check(lib().mcx_nn_set_params(h, v.ctypes.data, v.size))
+
+
+def mcx_nn_get_params(h) -> np.ndarray:
+    out = np.empty(mcx_nn_param_count(h), np.float32)
+    mcx._check(lib().mcx_nn_get_params(h, out.ctypes.data, out.size))
+    return out
+
+
+def mcx_nn_get_grads(h) -> np.ndarray:
+    out = np.empty(mcx_nn_param_count(h), np.float32)
+    mcx._check(lib().mcx_nn_get_grads(h, out.ctypes.data, out.size))
+    return out
+
+
+def mcx_nn_forward(h, phi_in, phi_out=None, u_out=None, stream=None):
+    mcx._check(lib().mcx_nn_forward(h, _ptr(phi_in), _ptr(phi_out), _ptr(u_out), _stream(stream)))
+
+
+def mcx_nn_loss_grad(h, phi_in, phi_target, want_loss=True, stream=None) -> Optional[float]:
+    loss = C.c_double()
+    mcx._check(lib().mcx_nn_loss_grad(h, _ptr(phi_in), _ptr(phi_target),
+                                      C.byref(loss) if want_loss else None, _stream(stream)))
+    return loss.value if want_loss else None
+
+
+def mcx_nn_adam(h, lr: float, stream=None):
+    mcx._check(lib().mcx_nn_adam(h, float(lr), _stream(stream)))
+
+
+def mcx_nn_train_step(h, phi_in, phi_target, lr: float, want_loss=False, stream=None):
+    loss = C.c_double()
+    mcx._check(lib().mcx_nn_train_step(h, _ptr(phi_in), _ptr(phi_target), float(lr),
+                                       C.byref(loss) if want_loss else None, _stream(stream)))
+    return loss.value if want_loss else None
+
+
+def mcx_nn_layer_forward(kind, shape, cin, cout, x, w, b=None, skip=None, relu=True, y=None,
+                         y_f32=False, stream=None):
+    nz, ny, nx = shape
+    mcx._check(lib().mcx_nn_layer_forward(kind, nx, ny, nz, cin, cout, _ptr(x), _ptr(w), _ptr(b),
+                                          _ptr(skip), int(bool(relu)), int(bool(y_f32)), _ptr(y),
+                                          _stream(stream)))
+    return y
+
+
+def mcx_nn_layer_backward(kind, shape, cin, cout, x, w, gy, gx=None, gw=None, gb=None,
+                          stream=None):
+    nz, ny, nx = shape
+    mcx._check(lib().mcx_nn_layer_backward(kind, nx, ny, nz, cin, cout, _ptr(x), _ptr(w), _ptr(gy),
+                                           _ptr(gx), _ptr(gw), _ptr(gb), _stream(stream)))
+
+
+class Denoiser:
+    """The U-Net of include/mcx_nn.h on one volume shape."""
+
+    def __init__(self, channels: Sequence[int], shape, device: int = 0):
+        self.channels = tuple(int(c) for c in channels)
+        self.shape = tuple(int(s) for s in shape)  # (nz, ny, nx)
+        self.h = mcx_nn_create(self.channels, self.shape, device)
+
+    @property
+    def nparam(self) -> int:
+        return mcx_nn_param_count(self.h)
+
+    def set_params(self, values):
+        if isinstance(values, (list, tuple)):  # [(w, b), ...] in layer order
+            values = np.concatenate([np.concatenate([np.ravel(w), np.ravel(b)]) for w, b in values])
+        mcx_nn_set_params(self.h, values)
+
+    def params(self) -> np.ndarray:
+        return mcx_nn_get_params(self.h)
+
+    def grads(self) -> np.ndarray:
+        return mcx_nn_get_grads(self.h)
+
+    def _vol(self, t):
+        _check_volume(t, int(np.prod(self.shape)))
+        return t
+
+    def forward(self, phi_in, phi_out=None, u_out=None, stream=None):
+        import torch
+        self._vol(phi_in)
+        if phi_out is None and u_out is None:
+            phi_out = torch.empty_like(phi_in)
+        mcx_nn_forward(self.h, phi_in, phi_out, u_out, stream)
+        return phi_out if phi_out is not None else u_out
+
+    def loss_grad(self, phi_in, phi_target, want_loss=True, stream=None):
+        return mcx_nn_loss_grad(self.h, self._vol(phi_in), self._vol(phi_target), want_loss, stream)
+
+    def adam(self, lr, stream=None):
+        mcx_nn_adam(self.h, lr, stream)
+
+    def train_step(self, phi_in, phi_target, lr, want_loss=False, stream=None):
+        return mcx_nn_train_step(self.h, self._vol(phi_in), self._vol(phi_target), lr, want_loss,
+                                 stream)
+
+    def close(self):
+        if self.h:
+            mcx_nn_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -383,6 +383,35 @@ def denoiser_weights(channels=DENOISER_CHANNELS, seed: int = 1, zero_output: boo
     return out
 
 
+def denoiser_volume(seed: int, side: int = 64) -> Problem:
+    """One volume of the denoiser's data set: `side`^3 voxels of 1 mm, label 1
+    background with 1-5 randomly oriented ellipsoidal inclusions (labels
+    2..6, semi-axes uniform in [side/10, side/4], centres uniform where the
+    largest semi-axis fits, later ones painted over earlier ones), every
+    label's mua / mus log-uniform and g uniform in the batched workload's
+    ranges, n = 1.37; pencil beam along +z at the voxel-centred middle of the
+    z = 0 face, one 0-5 ns gate, Fresnel boundaries on.  numpy PCG64 `seed`."""
+    rng = np.random.default_rng(seed)
+    labels = np.ones((side, side, side), np.uint8)
+    ninc = int(rng.integers(1, 6))
+    c1 = np.arange(side) + 0.5
+    z, y, x = np.meshgrid(c1, c1, c1, indexing="ij")
+    pts = np.stack([x, y, z], axis=-1)
+    for k in range(ninc):
+        axes = rng.uniform(side / 10, side / 4, size=3)
+        rmax = float(axes.max())
+        centre = rng.uniform(rmax, side - rmax, size=3)
+        q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        d = (pts - centre) @ q          # coordinates along the ellipsoid's axes
+        labels[((d / axes) ** 2).sum(-1) <= 1.0] = 2 + k
+    rows = [(_log_uniform(rng, *BATCH_MUA), _log_uniform(rng, *BATCH_MUS),
+             float(rng.uniform(*BATCH_G)), 1.37) for _ in range(1 + ninc)]
+    c = side / 2 - 0.5
+    return Problem(labels=labels, media=_media(*rows), src_pos=(c, c, 0.0),
+                   src_dir=(0.0, 0.0, 1.0), t0=0.0, dt=5.0, ngates=1, reflect=True,
+                   name=f"denoise_{seed}")
+
+
 def with_medium(p: Problem, row: int, values) -> Problem:
     media = p.media.copy()
     media[row] = values

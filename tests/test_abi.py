@@ -7,13 +7,13 @@ import re
 import numpy as np
 import pytest
 
-from paper_1711_03244_amd import mcx, workloads as W
+from paper_1711_03244_amd import mcx, nn, workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    text = open(os.path.join(ROOT, "include", "mcx.h")).read()
+def declared_functions(header="mcx.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(mcx_[a-z0-9_]+)\s*\(", text)))
 
@@ -30,6 +30,9 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert set(declared_functions()) == set(mcx.EXPORTS)
+    for n in declared_functions("mcx_nn.h"):
+        assert hasattr(lib, n), n
+    assert set(declared_functions("mcx_nn.h")) == set(nn.EXPORTS)
 
 
 def test_default_options():
@@ -126,3 +129,29 @@ def test_null_context_calls_fail_cleanly():
     assert lib.mcx_sync(None) == mcx.MCX_EINVAL
     assert lib.mcx_ncells(None) == 0
     lib.mcx_destroy(None)
+
+
+def test_denoiser_arguments_checked_before_the_gpu():
+    L = nn.lib()
+    out = C.c_void_p()
+    ch = (C.c_int32 * 3)(8, 16, 32)
+    assert L.mcx_nn_create(ch, 0, 16, 16, 16, 0, C.byref(out)) == mcx.MCX_EINVAL
+    assert L.mcx_nn_create(ch, 3, 16, 16, 10, 0, C.byref(out)) == mcx.MCX_EINVAL  # not a multiple of 4
+    assert "multiples of 4" in mcx.mcx_last_error()
+    bad = (C.c_int32 * 3)(8, 0, 32)
+    assert L.mcx_nn_create(bad, 3, 16, 16, 16, 0, C.byref(out)) == mcx.MCX_EINVAL
+    assert L.mcx_nn_layer_forward(7, 4, 4, 4, 1, 1, None, None, None, None, 0, 0, None,
+                                  None) == mcx.MCX_EINVAL
+    assert L.mcx_nn_layer_forward(nn.MCX_NN_DOWN, 3, 4, 4, 1, 1, None, None, None, None, 0, 0,
+                                  None, None) == mcx.MCX_EINVAL
+    assert "even" in mcx.mcx_last_error()
+    assert L.mcx_nn_param_count(None) == 0
+
+
+def test_denoiser_reports_no_device_without_gpu():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    out = C.c_void_p()
+    ch = (C.c_int32 * 2)(8, 16)
+    assert nn.lib().mcx_nn_create(ch, 2, 8, 8, 8, 0, C.byref(out)) == mcx.MCX_ENODEV

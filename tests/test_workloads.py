@@ -87,3 +87,37 @@ def test_random_small_is_seeded():
     assert np.array_equal(a.labels, b.labels) and a.src_pos == b.src_pos
     i, j, k = (int(np.floor(v)) for v in a.src_pos)
     assert a.labels[k, j, i] != 0
+
+
+def test_batch_workload_recipe():
+    items = W.batch_workload()
+    assert len(items) == 256
+    sides = {it.problem.shape[0] for it in items}
+    assert sides == set(W.BATCH_SIDES)
+    n = np.array([it.nphoton for it in items])
+    assert n.min() >= 1e5 and n.max() <= 1e7
+    assert 4.5e8 < n.sum() < 6.5e8            # mean of log-uniform [1e5, 1e7] ~ 2.15e6 each
+    for it in items[:40]:
+        p = it.problem
+        s = p.shape[0]
+        assert p.shape == (s, s, s) and p.reflect and p.ngates == 1 and p.dt == 5.0
+        assert p.src_pos == (s / 2 - 0.5, s / 2 - 0.5, 0.0)
+        k = p.nmedia - 2                         # inclusions
+        assert 1 <= k <= 3 and set(np.unique(p.labels)) <= set(range(1, 2 + k))
+        mua, mus, g, nn = p.media[1:].T
+        assert (mua >= 0.001 - 1e-9).all() and (mua <= 0.05 + 1e-9).all()
+        assert (mus >= 0.5 - 1e-6).all() and (mus <= 20 + 1e-5).all()
+        assert (g >= 0.5).all() and (g <= 0.95).all() and (nn == np.float32(1.37)).all()
+    # seeded and independent of other draws
+    again = W.batch_workload(nsims=3)
+    for a, b in zip(items[:3], again):
+        assert np.array_equal(a.problem.labels, b.problem.labels) and a.seed == b.seed
+
+
+def test_denoiser_volume_recipe():
+    a, b = W.denoiser_volume(5), W.denoiser_volume(5)
+    assert np.array_equal(a.labels, b.labels) and np.array_equal(a.media, b.media)
+    assert a.shape == (64, 64, 64) and a.src_pos == (31.5, 31.5, 0.0) and a.reflect
+    counts = [W.denoiser_volume(s, 32).nmedia - 2 for s in range(1, 30)]
+    assert min(counts) >= 1 and max(counts) <= 5 and len(set(counts)) >= 3
+    assert not np.array_equal(W.denoiser_volume(6).labels, a.labels)
