@@ -102,54 +102,60 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
 #pragma unroll
   for (int j = 0; j < NB; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < a.k; k0 += kBK) {
-    // A tile: 64 rows x 32 k
-    {
-      const int k = k0 + lc;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (lm < M) {
-        if constexpr (kVec) {
-          if (k < a.k) {
-            const int t = k / a.cin, ci = k - t * a.cin;
-            const int64_t src = gather_at(a, lz, ly, lx, t);
-            if (src >= 0) v = *reinterpret_cast<const uint4*>(a.x + src * a.cin + ci);
-          }
-        } else {
-          uint16_t e[8];
+  // this thread's 8 k of row lr of the A tile at reduction step k0
+  auto load_a = [&](int k0) -> uint4 {
+    const int k = k0 + lc;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (lm >= M) return v;
+    if constexpr (kVec) {
+      if (k < a.k) {
+        const int t = k / a.cin, ci = k - t * a.cin;
+        const int64_t src = gather_at(a, lz, ly, lx, t);
+        if (src >= 0) v = *reinterpret_cast<const uint4*>(a.x + src * a.cin + ci);
+      }
+    } else {
+      uint16_t e[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            e[j] = 0;
-            const int kk = k + j;
-            if (kk < a.k) {
-              const int t = kk / a.cin, ci = kk - t * a.cin;
-              const int64_t src = gather_at(a, lz, ly, lx, t);
-              if (src >= 0) e[j] = a.x[src * a.cin + ci];
-            }
-          }
-          v = make_uint4(e[0] | (uint32_t(e[1]) << 16), e[2] | (uint32_t(e[3]) << 16),
-                         e[4] | (uint32_t(e[5]) << 16), e[6] | (uint32_t(e[7]) << 16));
+      for (int j = 0; j < 8; ++j) {
+        e[j] = 0;
+        const int kk = k + j;
+        if (kk < a.k) {
+          const int t = kk / a.cin, ci = kk - t * a.cin;
+          const int64_t src = gather_at(a, lz, ly, lx, t);
+          if (src >= 0) e[j] = a.x[src * a.cin + ci];
         }
       }
-      *reinterpret_cast<uint4*>(&sA[lr][lc]) = v;
+      v = make_uint4(e[0] | (uint32_t(e[1]) << 16), e[2] | (uint32_t(e[3]) << 16),
+                     e[4] | (uint32_t(e[5]) << 16), e[6] | (uint32_t(e[7]) << 16));
     }
-    // B tile: 16*NB rows (output channels) x 32 k from Bt[n][koff + k]
-    for (int i = tid; i < 16 * NB * 4; i += 256) {
-      const int r = i >> 2, c = (i & 3) * 8;
-      const int k = k0 + c;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      const uint16_t* row = a.bt + static_cast<int64_t>(n0 + r) * a.kpad + koff;
-      if (k + 8 <= a.k && (koff & 7) == 0) {
-        v = *reinterpret_cast<const uint4*>(row + k);
-      } else {
-        uint16_t e[8];
+    return v;
+  };
+  // this thread's 8 k of one B row (threads 0 .. 64*NB-1), Bt[n][koff + k]
+  const bool has_b = tid < 16 * NB * 4;
+  const int br = tid >> 2, bc = (tid & 3) * 8;
+  const uint16_t* brow = a.bt + static_cast<int64_t>(n0 + br) * a.kpad + koff;
+  auto load_b = [&](int k0) -> uint4 {
+    const int k = k0 + bc;
+    if (k + 8 <= a.k && (koff & 7) == 0) return *reinterpret_cast<const uint4*>(brow + k);
+    uint16_t e[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) e[j] = (k + j < a.k) ? row[k + j] : 0;
-        v = make_uint4(e[0] | (uint32_t(e[1]) << 16), e[2] | (uint32_t(e[3]) << 16),
-                       e[4] | (uint32_t(e[5]) << 16), e[6] | (uint32_t(e[7]) << 16));
-      }
-      *reinterpret_cast<uint4*>(&sB[r][c]) = v;
-    }
+    for (int j = 0; j < 8; ++j) e[j] = (k + j < a.k) ? brow[k + j] : 0;
+    return make_uint4(e[0] | (uint32_t(e[1]) << 16), e[2] | (uint32_t(e[3]) << 16),
+                      e[4] | (uint32_t(e[5]) << 16), e[6] | (uint32_t(e[7]) << 16));
+  };
+
+  // software pipeline: the next step's global loads are in flight while
+  // the matrix cores work on the current step's tiles
+  uint4 va = load_a(0);
+  uint4 vb = has_b ? load_b(0) : make_uint4(0u, 0u, 0u, 0u);
+  for (int k0 = 0; k0 < a.k; k0 += kBK) {
+    *reinterpret_cast<uint4*>(&sA[lr][lc]) = va;
+    if (has_b) *reinterpret_cast<uint4*>(&sB[br][bc]) = vb;
     __syncthreads();
+    if (k0 + kBK < a.k) {
+      va = load_a(k0 + kBK);
+      if (has_b) vb = load_b(k0 + kBK);
+    }
     const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sA[wave * 16 + (lane & 15)][(lane >> 4) * 8]);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {

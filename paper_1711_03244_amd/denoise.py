@@ -167,22 +167,64 @@ def _debias(e, r):
     return math.sqrt(max(e * e - r * r, 0.0))
 
 
+def _equivalent_photons(n_err, err):
+    """Photon count at which plain runs reach `err`: log-log interpolation
+    between the two measured plain points that bracket it (extrapolation
+    from the two nearest ones outside the measured range).  n_err:
+    [(photons, error), ...]; None when the curve cannot be used."""
+    pts = sorted((n, e) for n, e in n_err if e > 0)
+    if len(pts) < 2 or err <= 0:
+        return None
+    if err >= pts[0][1]:
+        pair = pts[0], pts[1]
+    elif err <= pts[-1][1]:
+        pair = pts[-2], pts[-1]
+    else:
+        pair = next((p, q) for p, q in zip(pts, pts[1:]) if p[1] >= err >= q[1])
+    (n0, e0), (n1, e1) = pair
+    if e0 == e1:
+        return None
+    slope = math.log(e1 / e0) / math.log(n1 / n0)
+    return n0 * (err / e0) ** (1.0 / slope)
+
+
 def summarise(rows, plain_photons, input_photons) -> dict:
+    """Errors (reference share removed in quadrature), the plain runs'
+    error curve and time model T = a n + T0 over all plain photon counts
+    (the low-photon runs are plain runs too), and for every input count the
+    plain photon count of equal error and the time ratio of that plain run
+    to the low-photon run plus inference."""
     ref = float(np.sqrt(np.mean([r["ref_err"] ** 2 for r in rows])))
     plain = float(np.sqrt(np.mean([r["plain_err"] ** 2 for r in rows])))
     plain_ms = float(np.mean([r["plain_ms"] for r in rows]))
+    curve = [(float(plain_photons), _debias(plain, ref))]
+    times = [(float(plain_photons), plain_ms)]
     per_n = []
     for j, n in enumerate(input_photons):
         den = float(np.sqrt(np.mean([r["inputs"][j]["denoised_err"] ** 2 for r in rows])))
         noisy = float(np.sqrt(np.mean([r["inputs"][j]["noisy_err"] ** 2 for r in rows])))
-        ms = float(np.mean([r["inputs"][j]["sim_ms"] + r["inputs"][j]["infer_ms"] for r in rows]))
+        sim_ms = float(np.mean([r["inputs"][j]["sim_ms"] for r in rows]))
+        inf_ms = float(np.mean([r["inputs"][j]["infer_ms"] for r in rows]))
+        curve.append((float(n), _debias(noisy, ref)))
+        times.append((float(n), sim_ms))
         per_n.append({"photons": int(n), "noisy_err": noisy, "denoised_err": den,
                       "noisy_err_debiased": _debias(noisy, ref),
-                      "denoised_err_debiased": _debias(den, ref), "sim_plus_infer_ms": ms,
-                      "infer_ms": float(np.mean([r["inputs"][j]["infer_ms"] for r in rows]))})
+                      "denoised_err_debiased": _debias(den, ref), "sim_ms": sim_ms,
+                      "infer_ms": inf_ms, "sim_plus_infer_ms": sim_ms + inf_ms})
+    ns = np.array([t[0] for t in times])
+    ts = np.array([t[1] for t in times])
+    a, t0 = np.polyfit(ns, ts, 1)
+    for r in per_n:
+        neq = _equivalent_photons(curve, r["denoised_err_debiased"])
+        r["equal_error_plain_photons"] = neq
+        r["time_ratio"] = (a * neq + t0) / r["sim_plus_infer_ms"] if neq else None
     out = {"volumes": len(rows), "plain_photons": int(plain_photons), "plain_err": plain,
            "plain_err_debiased": _debias(plain, ref), "ref_err": ref, "plain_ms": plain_ms,
-           "per_input": per_n, "equal_error_photons": None, "time_ratio": None}
+           "plain_time_model": {"ms_per_photon": float(a), "overhead_ms": float(t0)},
+           "plain_error_curve": curve, "per_input": per_n, "equal_error_photons": None,
+           "time_ratio": None, "best_time_ratio": None}
+    ratios = [r["time_ratio"] for r in per_n if r["time_ratio"]]
+    out["best_time_ratio"] = max(ratios) if ratios else None
     for r in per_n:
         if r["denoised_err_debiased"] <= out["plain_err_debiased"]:
             out["equal_error_photons"] = r["photons"]

@@ -171,11 +171,20 @@ def test_network_forward_matches_oracle(channels, shape):
         got = host(uo)
     assert np.allclose(u32, u, atol=3e-6)
     err = np.abs(got - ref)
-    print("max |gpu - oracle|", err.max(), "median", np.median(err), flush=True)
-    # accumulation-order differences flip an occasional BF16 rounding; they
-    # stay at the level of one BF16 unit of the activations
-    assert np.median(err) < 2e-3
-    assert err.max() < 5e-2
+    # The bf16 model is sensitive to the last FP32 bits of its sums: a sum
+    # that lands next to a BF16 rounding midpoint rounds either way, and the
+    # flip propagates.  The bar is the spread the oracle itself shows when
+    # its pre-rounding sums move by 1e-6 (the FP32 accumulation error of
+    # these sums): the GPU may differ from the oracle by no more than twice
+    # that spread.
+    rng = np.random.default_rng(0)
+    nudged = {k: (w, b + rng.normal(size=b.shape) * 1e-6) for k, (w, b) in params.items()}
+    alt, _ = O.forward(nudged, u32, channels, precision="bf16")
+    spread = np.abs(alt - ref)
+    print("gpu - oracle: median", np.median(err), "max", err.max(), "| oracle spread: median",
+          np.median(spread), "max", spread.max(), flush=True)
+    assert np.median(err) <= 2 * max(np.median(spread), 1e-6)
+    assert err.max() <= 2 * max(spread.max(), 1e-5)
 
 
 def test_network_gradients_match_oracle():
@@ -264,3 +273,22 @@ def test_training_reduces_the_loss():
         last = np.mean([d.loss_grad(a, b) for a, b in dev])
     print("loss", first, "->", last, flush=True)
     assert last < 0.5 * first
+
+
+def test_denoiser_gain_on_held_out_volumes():
+    """Trained on simulator pairs, the network brings low-photon maps of
+    volumes it has not seen closer to the reference than they were."""
+    from paper_1711_03244_amd import denoise
+    channels, side = (16, 32, 64), 32
+    ds = denoise.make_dataset(range(1, 33), side, [5e4, 5e5], 1e7, say=print)
+    with nn.Denoiser(channels, (side,) * 3) as d:
+        d.set_params(W.denoiser_weights(channels, seed=1))
+        mean_loss = lambda: np.mean([d.loss_grad(x, ds.targets[v]) for v, _, x in ds.inputs])
+        before = mean_loss()
+        denoise.train(d, ds, 1500, lr=1e-3, log_every=500, say=print)
+        after = mean_loss()
+        ev = denoise.evaluate(d, [700001, 700002, 700003], side, 1e7, 2, [5e4, 5e5], say=print)
+    print("mean training loss", before, "->", after, ev, flush=True)
+    assert after < 0.5 * before
+    for r in ev["per_input"]:
+        assert r["denoised_err"] < 0.8 * r["noisy_err"], r
