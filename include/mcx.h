@@ -108,7 +108,8 @@ typedef struct {
   int32_t refill_chunk;   /* photons a wave takes per refill grab; 0 = library default */
   uint64_t ndigest;       /* per-photon digest rows kept for photons [first, first+ndigest) */
   int32_t lds_window_cells; /* cells around the source summed per workgroup in LDS before they
-                               reach the map; 0 = library default (4096), < 0 = none */
+                               reach the map; 0 = library default (8192), < 0 = none,
+                               at most 16384 (128 KB) */
   int32_t accurate_math;  /* 0: hardware transcendentals (~1 ulp); 1: device math library */
 } mcx_options;
 
@@ -208,14 +209,15 @@ mcx_status mcx_batch_digest(mcx_ctx *ctx, int32_t sim, double *host_out, uint64_
 
 /* Launch shape: threads per workgroup (0 = the size that keeps the most waves
  * resident), photons per job (0 = default 256), LDS window cells (0 = default
- * 4096, < 0 = none; single-simulation contexts only).  Waits for the stream. */
+ * 8192, < 0 = none, at most 16384; single-simulation contexts only).  Waits
+ * for the stream. */
 mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk,
                           int32_t lds_window_cells);
 
 /* Autotuner: times pilot launches of pilot_photons[i] photons (seed[i]) per
  * simulation over block sizes {64, 256, 448, 512, 1024} x jobs of {64, 256,
  * 1024, 4096} photons (1 to 64 photons per lane) x deposit schemes {direct
- * global atomics, LDS window of 4096 or 8192 cells} (windows only for one
+ * global atomics, LDS window of 4096, 8192 or 16384 cells} (windows only for one
  * simulation), keeps the fastest shape, and fits the linear device runtime
  * model T = a n + T0 of the paper's device-level load balancing (the study
  * of Fig. 3(b)) from pilots of n and n/2 photons.  Results do not depend on the shape (the

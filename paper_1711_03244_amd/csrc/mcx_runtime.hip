@@ -25,7 +25,8 @@ namespace {
 
 constexpr double kCmmPerNs = 299.792458;  // speed of light in vacuum, mm/ns
 constexpr int kDefaultChunk = 256;
-constexpr int kDefaultWindow = 4096;       // FP64 cells, 32 KB of LDS
+constexpr int kDefaultWindow = 8192;       // FP64 cells, 64 KB of LDS
+constexpr int kMaxWindow = 16384;          // 128 KB of the 160 KB of LDS per CU
 constexpr uint64_t kMaxLaunchPhotons = 1ull << 31;  // per simulation and launch
 
 thread_local std::string g_error;
@@ -221,8 +222,8 @@ static mcx_status validate_options(const mcx_options* o) {
     return fail(MCX_EINVAL, "refill_chunk must be 0 or >= 64");
   if (o->max_events == 0 || o->max_events > 0xffffffffull)
     return fail(MCX_EINVAL, "max_events must be in [1, 2^32-1]");
-  if (o->lds_window_cells > 8192)
-    return fail(MCX_EINVAL, "lds_window_cells must be <= 8192 (64 KB of LDS)");
+  if (o->lds_window_cells > kMaxWindow)
+    return fail(MCX_EINVAL, "lds_window_cells must be <= %d (128 KB of LDS)", kMaxWindow);
   return MCX_OK;
 }
 
@@ -905,7 +906,8 @@ mcx_status mcx_set_launch(mcx_ctx* c, int32_t block_size, int32_t refill_chunk,
     return fail(MCX_EINVAL, "block_size must be 0 or a multiple of 64 in [64, 1024]");
   if (refill_chunk != 0 && refill_chunk < 64)
     return fail(MCX_EINVAL, "refill_chunk must be 0 or >= 64");
-  if (lds_window_cells > 8192) return fail(MCX_EINVAL, "lds_window_cells must be <= 8192");
+  if (lds_window_cells > kMaxWindow)
+    return fail(MCX_EINVAL, "lds_window_cells must be <= %d", kMaxWindow);
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipStreamSynchronize(c->stream));
   set_window(c, lds_window_cells == 0 ? kDefaultWindow : lds_window_cells);
@@ -939,8 +941,8 @@ mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_
   memset(out, 0, sizeof(*out));
   const int blocks[] = {64, 256, 448, 512, 1024};
   const int chunks[] = {64, 256, 1024, 4096};
-  const int windows[] = {-1, 4096, 8192};
-  const int nwin = ns == 1 ? 3 : 1;
+  const int windows[] = {-1, 4096, 8192, 16384};
+  const int nwin = ns == 1 ? 4 : 1;
   // the untuned default shape first (after one warm-up launch)
   MCX_TRY(mcx_set_launch(c, 0, 0, ns == 1 ? 0 : -1));
   float ms = 0.f;

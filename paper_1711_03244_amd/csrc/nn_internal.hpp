@@ -48,16 +48,21 @@ struct WgradArgs {
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s);
 // pack w[taps][cin][cout] (FP32) into BF16 rows: forward Bt[n][t * cin + ci]
-// (rows >= cout) or transposed Bt[ci][t * cout + n] (rows >= cin); the
-// rows x kpad buffer is cleared first
+// (rows >= cout) or transposed Bt[ci][t * cout + n] (rows >= cin); with
+// `clear` the rows x kpad buffer is zeroed first (the padding outside the
+// weights never changes, so later packs of the same buffer skip it)
 hipError_t launch_pack(const float* w, int taps, int cin, int cout, int rows, int kpad,
-                       bool transposed, uint16_t* bt, hipStream_t s);
+                       bool transposed, uint16_t* bt, hipStream_t s, bool clear = true);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_to_log(const float* phi, int64_t n, float* u, uint16_t* u16, hipStream_t s);
 hipError_t launch_from_log(const float* r, const float* u, int64_t n, float* out_u, float* phi,
                            hipStream_t s);
+// g16 = bf16((g + skip16) * (y16 > 0)) over n = voxels * cout values;
+// with gb set, also gb[c] += sum over voxels of g16[.][c] (through
+// `partial`, kBiasBlocks * cout floats of scratch)
+constexpr int kBiasBlocks = 2048;
 hipError_t launch_relu_grad(const float* g, const uint16_t* skip16, const uint16_t* y16, int64_t n,
-                            uint16_t* g16, hipStream_t s);
+                            int cout, uint16_t* g16, float* gb, float* partial, hipStream_t s);
 // masked MSE in u space; target voxels with phi >= rel_floor * max(phi)
 // count; grad = 2 (out - t) / count there.  acc[0] = sum of squares,
 // acc[1] = count (FP64); phi_max: one float of scratch

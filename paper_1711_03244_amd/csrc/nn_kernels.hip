@@ -377,24 +377,68 @@ __global__ void from_log_kernel(const float* r, const float* u, int64_t n, float
   }
 }
 
-// g16 = bf16((g + skip16) * (y16 > 0)); g may be FP32 or absent (skip only)
-__global__ void relu_grad_kernel(const float* g, const uint16_t* skip16, const uint16_t* y16,
-                                 int64_t n, uint16_t* g16) {
+// g16 = bf16((g + skip16) * (y16 > 0)); g may be FP32 or absent (skip
+// only).  With `partial` set (and 256 a multiple of cout, so that a thread
+// sees one channel in every grid-stride step) each block also writes its
+// per-channel sums of g16 to partial[block][cout] for bias_sum_kernel.
+__global__ void __launch_bounds__(256) relu_grad_kernel(const float* g, const uint16_t* skip16,
+                                                        const uint16_t* y16, int64_t n, int cout,
+                                                        uint16_t* g16, float* partial) {
+  __shared__ float sh[256];
+  float s = 0.f;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     float v = g ? g[i] : 0.f;
     if (skip16) v += from_bf16(skip16[i]);
     if (y16 && !(from_bf16(y16[i]) > 0.f)) v = 0.f;
-    g16[i] = to_bf16(v);
+    const uint16_t h = to_bf16(v);
+    g16[i] = h;
+    s += from_bf16(h);
+  }
+  if (!partial) return;
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (static_cast<int>(threadIdx.x) < cout) {
+    float t = 0.f;
+    for (int j = threadIdx.x; j < 256; j += cout) t += sh[j];
+    partial[static_cast<int64_t>(blockIdx.x) * cout + threadIdx.x] = t;
   }
 }
 
+// gb[c] += sum over blocks of partial[block][c]; one workgroup per channel
+__global__ void __launch_bounds__(256) bias_sum_kernel(const float* partial, int blocks, int cout,
+                                                       float* gb) {
+  __shared__ float sh[4];
+  const int c = blockIdx.x;
+  float t = 0.f;
+  for (int b = threadIdx.x; b < blocks; b += blockDim.x)
+    t += partial[static_cast<int64_t>(b) * cout + c];
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) gb[c] += sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// block-wide sum of one double per thread (256 threads), returned to thread 0
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
 // masked squared error of out against target (both in u space): sum and
-// count into acc[0..1] (FP64), and the unnormalised gradient 2 (out - t)
-// per masked voxel (zero elsewhere)
-__global__ void mse_kernel(const float* out, const float* target_u, const float* target_phi,
-                           float rel_floor, const float* phi_max, int64_t n, float* grad,
-                           double* acc) {
+// count into acc[0..1] (FP64, one atomic per block), and the unnormalised
+// gradient 2 (out - t) per masked voxel (zero elsewhere)
+__global__ void __launch_bounds__(256) mse_kernel(const float* out, const float* target_u,
+                                                  const float* target_phi, float rel_floor,
+                                                  const float* phi_max, int64_t n, float* grad,
+                                                  double* acc) {
+  __shared__ double sh[4];
   double s = 0.0, c = 0.0;
   const float thr = rel_floor * phi_max[0];
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -405,23 +449,27 @@ __global__ void mse_kernel(const float* out, const float* target_u, const float*
     s += static_cast<double>(d) * d;
     c += on ? 1.0 : 0.0;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    s += __shfl_down(s, off, 64);
-    c += __shfl_down(c, off, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
+  s = block_sum(s, sh);
+  c = block_sum(c, sh);
+  if (threadIdx.x == 0) {
     unsafeAtomicAdd(acc, s);
     unsafeAtomicAdd(acc + 1, c);
   }
 }
 
-__global__ void max_kernel(const float* x, int64_t n, float* out) {
+__global__ void __launch_bounds__(256) max_kernel(const float* x, int64_t n, float* out) {
+  __shared__ float sh[4];
   float m = 0.f;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     m = fmaxf(m, x[i]);
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<int*>(out), __float_as_int(m));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w) m = fmaxf(m, sh[w]);
+    atomicMax(reinterpret_cast<int*>(out), __float_as_int(m));  // m >= 0
+  }
 }
 
 // grad *= 1 / count (count from acc[1])
@@ -432,12 +480,30 @@ __global__ void scale_grad_kernel(float* g, int64_t n, const double* acc) {
     g[i] *= s;
 }
 
-// gb[n] += sum over voxels of gy[m][n]
-__global__ void bias_grad_kernel(const uint16_t* gy, int64_t m, int cout, float* gb) {
-  for (int n = threadIdx.x; n < cout; n += blockDim.x) {
+// gb[n] += sum over voxels of gy[m][n]: each block sums a range of rows,
+// its threads split as (channel, row phase), then one atomic per channel
+__global__ void __launch_bounds__(256) bias_grad_kernel(const uint16_t* gy, int64_t m, int cout,
+                                                        int64_t rows_per_block, float* gb) {
+  __shared__ float sh[256];
+  const int lanes_c = cout < 256 ? cout : 256;       // threads per row
+  const int phases = 256 / lanes_c;                  // rows in flight
+  const int tid = threadIdx.x;
+  const int64_t r0 = blockIdx.x * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < m ? r0 + rows_per_block : m;
+  for (int c0 = 0; c0 < cout; c0 += lanes_c) {
     float s = 0.f;
-    for (int64_t i = blockIdx.x; i < m; i += gridDim.x) s += from_bf16(gy[i * cout + n]);
-    unsafeAtomicAdd(gb + n, s);
+    const int c = c0 + tid % lanes_c;
+    const int ph = tid / lanes_c;
+    if (ph < phases && c < cout)
+      for (int64_t r = r0 + ph; r < r1; r += phases) s += from_bf16(gy[r * cout + c]);
+    sh[tid] = s;
+    __syncthreads();
+    if (tid < lanes_c && c0 + tid < cout) {
+      float t = 0.f;
+      for (int p = 0; p < phases; ++p) t += sh[p * lanes_c + tid];
+      unsafeAtomicAdd(gb + c0 + tid, t);
+    }
+    __syncthreads();
   }
 }
 
@@ -500,9 +566,10 @@ hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_pack(const float* w, int taps, int cin, int cout, int rows, int kpad,
-                       bool transposed, uint16_t* bt, hipStream_t s) {
-  fill_u16_kernel<<<blocks_for(static_cast<int64_t>(rows) * kpad), 256, 0, s>>>(
-      bt, static_cast<int64_t>(rows) * kpad);
+                       bool transposed, uint16_t* bt, hipStream_t s, bool clear) {
+  if (clear)
+    fill_u16_kernel<<<blocks_for(static_cast<int64_t>(rows) * kpad), 256, 0, s>>>(
+        bt, static_cast<int64_t>(rows) * kpad);
   pack_kernel<<<blocks_for(static_cast<int64_t>(taps) * cin * cout), 256, 0, s>>>(
       w, taps, cin, cout, kpad, transposed ? 1 : 0, bt);
   return hipGetLastError();
@@ -524,12 +591,6 @@ hipError_t launch_from_log(const float* r, const float* u, int64_t n, float* out
   return hipGetLastError();
 }
 
-hipError_t launch_relu_grad(const float* g, const uint16_t* skip16, const uint16_t* y16, int64_t n,
-                            uint16_t* g16, hipStream_t s) {
-  relu_grad_kernel<<<blocks_for(n), 256, 0, s>>>(g, skip16, y16, n, g16);
-  return hipGetLastError();
-}
-
 hipError_t launch_mse(const float* out, const float* target_u, const float* target_phi,
                       float rel_floor, int64_t n, float* grad, double* acc, float* phi_max,
                       hipStream_t s) {
@@ -542,8 +603,23 @@ hipError_t launch_mse(const float* out, const float* target_u, const float* targ
 }
 
 hipError_t launch_bias_grad(const uint16_t* gy, int64_t m, int cout, float* gb, hipStream_t s) {
-  const int blocks = static_cast<int>(m < 1024 ? m : 1024);
-  bias_grad_kernel<<<blocks < 1 ? 1 : blocks, 256, 0, s>>>(gy, m, cout, gb);
+  const int64_t blocks = m < 512 ? 1 : (m / 256 < 1024 ? m / 256 : 1024);
+  const int64_t per = (m + blocks - 1) / blocks;
+  bias_grad_kernel<<<static_cast<int>(blocks), 256, 0, s>>>(gy, m, cout, per, gb);
+  return hipGetLastError();
+}
+
+hipError_t launch_relu_grad(const float* g, const uint16_t* skip16, const uint16_t* y16, int64_t n,
+                            int cout, uint16_t* g16, float* gb, float* partial, hipStream_t s) {
+  const int blocks = blocks_for(n, 256, kBiasBlocks);
+  const bool fused = gb && partial && cout <= 256 && 256 % cout == 0;
+  relu_grad_kernel<<<blocks, 256, 0, s>>>(g, skip16, y16, n, cout, g16,
+                                          fused ? partial : nullptr);
+  if (fused) {
+    bias_sum_kernel<<<cout, 256, 0, s>>>(partial, blocks, cout, gb);
+    return hipGetLastError();
+  }
+  if (gb) return launch_bias_grad(g16, n / cout, cout, gb, s);
   return hipGetLastError();
 }
 

@@ -212,7 +212,8 @@ struct mcx_nn {
   float* adam_m = nullptr;
   float* adam_v = nullptr;
   int step = 0;
-  bool packed = false;
+  bool packed = false;       // packs hold the current parameters
+  bool pads_clear = false;   // pack padding has been zeroed once
   float* u = nullptr;        // input in u space (FP32)
   uint16_t* u16 = nullptr;   // and as BF16
   float* r = nullptr;        // output layer result (FP32)
@@ -224,6 +225,7 @@ struct mcx_nn {
   std::vector<uint16_t*> skip_grad;  // per level 0..L-2
   double* acc = nullptr;
   float* phimax = nullptr;
+  float* bias_partial = nullptr;  // per-block channel sums of the bias gradients
   std::vector<void*> owned;
 };
 
@@ -254,11 +256,12 @@ mcx_status pack_all(mcx_nn* nn, hipStream_t s) {
   if (nn->packed) return MCX_OK;
   for (Layer& L : nn->layers) {
     NN_HIP(launch_pack(nn->params + L.woff, L.taps, L.cin, L.cout, L.fwd_rows, L.fwd_kpad, false,
-                       L.fwd, s));
+                       L.fwd, s, !nn->pads_clear));
     NN_HIP(launch_pack(nn->params + L.woff, L.taps, L.cin, L.cout, L.bwd_rows, L.bwd_kpad, true,
-                       L.bwd, s));
+                       L.bwd, s, !nn->pads_clear));
   }
   nn->packed = true;
+  nn->pads_clear = true;
   return MCX_OK;
 }
 
@@ -299,9 +302,9 @@ mcx_status run_backward(mcx_nn* nn, hipStream_t s) {
     if (L.kind == MCX_NN_UP) gy = nn->skip_grad[L.up_level];  // also the skip's gradient
     const uint16_t* skip = (L.skip_level >= 0 && L.skip_level < nn->L - 1)
                                ? nn->skip_grad[L.skip_level] : nullptr;
-    NN_HIP(launch_relu_grad(g, skip, i == last ? nullptr : L.act, nout, gy, s));
+    NN_HIP(launch_relu_grad(g, skip, i == last ? nullptr : L.act, nout, L.cout, gy,
+                            nn->grads + L.boff, nn->bias_partial, s));
     NN_HIP(launch_wgrad(wgrad_args(L, layer_input(nn, i), gy, nn->grads + L.woff), s));
-    NN_HIP(launch_bias_grad(gy, L.out.vox(), L.cout, nn->grads + L.boff, s));
     if (i > 0) {
       NN_HIP(launch_conv(dgrad_args(L, gy, nn->gx), s));
       g = nn->gx;
@@ -394,6 +397,9 @@ mcx_status mcx_nn_create(const int32_t* channels, int32_t nlevels, int32_t nx, i
     for (int l = 0; l + 1 < L; ++l)
       NN_TRY(nn_alloc(nn, &nn->skip_grad[l], static_cast<size_t>(level(l).vox() * c[l])));
     NN_TRY(nn_alloc(nn, &nn->acc, 2));
+    int max_c = 1;
+    for (const Layer& Ly : nn->layers) max_c = std::max(max_c, Ly.cout);
+    NN_TRY(nn_alloc(nn, &nn->bias_partial, static_cast<size_t>(kBiasBlocks) * max_c));
     NN_TRY(nn_alloc(nn, &nn->phimax, 1));
     NN_HIP(launch_fill(nn->params, static_cast<int64_t>(nn->nparam), 0.f, nn->stream));
     NN_HIP(launch_fill(nn->adam_m, static_cast<int64_t>(nn->nparam), 0.f, nn->stream));

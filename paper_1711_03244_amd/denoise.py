@@ -231,3 +231,47 @@ def summarise(rows, plain_photons, input_photons) -> dict:
             out["time_ratio"] = plain_ms / r["sim_plus_infer_ms"]
             break
     return out
+
+
+def main(argv=None) -> dict:
+    """Command line: simulate a training set, train, evaluate; prints JSON.
+
+        python -m paper_1711_03244_amd.denoise [--train 64] [--steps 4000]
+            [--side 64] [--inputs 1e5,1e6,1e7] [--target 1e8] [--eval 2]
+            [--plain 1e9] [--ref-runs 2] [--lr 1e-3]
+    """
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(prog="python -m paper_1711_03244_amd.denoise")
+    ap.add_argument("--train", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--side", type=int, default=64)
+    ap.add_argument("--inputs", default="1e5,1e6,1e7")
+    ap.add_argument("--target", type=float, default=1e8)
+    ap.add_argument("--eval", type=int, default=2)
+    ap.add_argument("--plain", type=float, default=1e9)
+    ap.add_argument("--ref-runs", type=int, default=2)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    a = ap.parse_args(argv)
+    log = lambda *m: print(*m, file=sys.stderr, flush=True)
+    inputs = [float(v) for v in a.inputs.split(",")]
+    ch = W.DENOISER_CHANNELS
+    t0 = time.perf_counter()
+    ds = make_dataset(range(1, a.train + 1), a.side, inputs, a.target, say=log)
+    data_s = time.perf_counter() - t0
+    with nn.Denoiser(ch, (a.side,) * 3) as d:
+        d.set_params(W.denoiser_weights(ch, seed=1))
+        tr = train(d, ds, a.steps, lr=a.lr, log_every=max(1, a.steps // 5), say=log)
+        ev = evaluate(d, range(900001, 900001 + a.eval), a.side, a.plain, a.ref_runs, inputs,
+                      say=log) if a.eval > 0 else None
+    out = {"channels": list(ch), "side": a.side, "train_volumes": a.train, "inputs": inputs,
+           "target": a.target, "data_s": data_s, "train_steps": a.steps,
+           "train_s": tr["seconds"], "losses": tr["losses"], "evaluation": ev}
+    print(json.dumps(out), flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    main()

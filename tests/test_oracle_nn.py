@@ -14,7 +14,6 @@ import torch.nn.functional as F
 from oracle import nn as O
 from paper_1711_03244_amd import workloads as W
 
-torch.set_default_dtype(torch.float64)
 
 
 def t_conv3(x, w, b):
