@@ -55,7 +55,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-denoise", action="store_true")
     ap.add_argument("--dn-train", type=int, default=64, help="denoiser training volumes")
-    ap.add_argument("--dn-steps", type=int, default=4000, help="denoiser training steps")
+    ap.add_argument("--dn-steps", type=int, default=3000, help="denoiser training steps")
+    ap.add_argument("--dn-batch", type=int, default=4, help="volumes per training step")
+    ap.add_argument("--dn-clip", type=float, default=0.1, help="gradient-norm clip")
     ap.add_argument("--dn-target", type=float, default=1e8, help="target photons per volume")
     ap.add_argument("--dn-eval", type=int, default=2, help="held-out volumes")
     ap.add_argument("--dn-plain", type=float, default=1e9, help="plain-run photons")
@@ -105,11 +107,12 @@ def main():
     atom = roofline.atomic_roofline(last, ksec)
     sim.close()
 
+    cube1 = None if args.no_head else cube1_leg(mcx, W)
     head = None if args.no_head else head_leg(mcx, roofline, W, args.head_photons, args.seed)
     batched = None if args.no_batch else batch_leg(mcx, W)
     denoised = None if args.no_denoise else denoise_leg(args)
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu_baseline:
         import oracle
         nthreads = min(os.cpu_count() or 1, 16)
@@ -118,7 +121,12 @@ def main():
                "cores": nthreads, "kind": "oracle",
                "sample": f"photons 0..{args.cpu_photons - 1} of the same workload and seed "
                          f"({r['wall_s']:.1f} s, FP64, {nthreads} threads)"}
+        n1 = max(1, args.cpu_photons // 16)
+        r1 = oracle.run(p, n1, args.seed, nthreads=1)
+        cpu1 = {"value": n1 / (r1["wall_s"] * 1e3), "unit": "photons/ms", "cores": 1,
+                "kind": "oracle", "sample": f"photons 0..{n1 - 1}, one thread ({r1['wall_s']:.1f} s)"}
 
+    ks = sorted(kernel_ms)
     line = {
         "metric": METRIC, "value": value, "unit": "photons/ms", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -129,12 +137,16 @@ def main():
                    "reflect": True, "seed": args.seed, "tally": "fp64"},
         "kernel_ms_per_step": sum(kernel_ms) / len(kernel_ms),
         "kernel_photons_per_ms": N / (sum(kernel_ms) / len(kernel_ms)),
+        "kernel_photons_per_ms_best": N / ks[0],
+        "kernel_photons_per_ms_median": N / ks[len(ks) // 2],
         "create_ms": create_ms,
         "events_per_photon": last["events"] / N,
         "lane_utilisation": last["events"] / max(1, last["lane_slots"]),
         "roofline": roof,
         "atomic_roofline": atom,
         "cpu_baseline": cpu,
+        "cpu_single_thread": cpu1,
+        "homogeneous_cube": cube1,
         "head_volume": head,
         "batched": batched,
         "denoiser": denoised,
@@ -142,15 +154,49 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def best_median(mcx, sim, N, seeds):
+    """Kernel-time photons/ms of one run per seed: best and median (the
+    paper reports the best of three runs)."""
+    rates, stats = [], []
+    for sd in seeds:
+        sim.run(N, sd)
+        st = sim.stats()
+        stats.append(st)
+        rates.append(N / st["kernel_ms"])
+    r = sorted(rates)
+    return r[-1], r[len(r) // 2], stats
+
+
+def cube1_leg(mcx, W):
+    """The homogeneous 60^3 cube at 1e8 photons, seeds 1-3; plus, for
+    context, 1e7 photons with the paper's baseline launch of 2^14 threads
+    in 64-thread workgroups."""
+    p = W.cube_homogeneous()
+    N = 100_000_000
+    with mcx.Simulation(p) as sim:
+        sim.run(N // 100, 99)
+        best, med, st = best_median(mcx, sim, N, [1, 2, 3])
+    with mcx.Simulation(p, block_size=64, blocks_per_cu=1, lds_window_cells=-1) as sim:
+        sim.run(100_000, 99)
+        sim.run(N // 10, 1)
+        base = sim.stats()
+    return {"workload": "cube60_homogeneous", "photons": N, "photons_per_ms_best": best,
+            "photons_per_ms_median": med, "events_per_photon": st[-1]["events"] / N,
+            "paper_baseline_launch": {"threads": base["grid_blocks"] * base["block_size"],
+                                      "block_size": base["block_size"], "photons": N // 10,
+                                      "photons_per_ms": (N // 10) / base["kernel_ms"]}}
+
+
 def head_leg(mcx, roofline, W, N, seed):
     p = W.head_phantom(1)
     with mcx.Simulation(p) as sim:
         sim.run(N // 100, seed + 1000)  # warm-up
-        sim.run(N, seed)
-        st = sim.stats()
+        best, med, runs = best_median(mcx, sim, N, [seed, seed + 1, seed + 2])
+        st = runs[0]
     ksec = st["kernel_ms"] / 1e3
     return {"workload": "head_1", "grid": [181, 217, 181], "gates": 10, "gate_ns": 0.5,
-            "photons": N, "photons_per_ms": N / st["run_ms"], "kernel_ms": st["kernel_ms"],
+            "photons": N, "photons_per_ms": N / st["run_ms"], "photons_per_ms_best": best,
+            "photons_per_ms_median": med, "kernel_ms": st["kernel_ms"],
             "run_ms": st["run_ms"], "events_per_photon": st["events"] / N,
             "valu_frac": roofline.valu_roofline(st, ksec)["frac"],
             "atomic_frac": roofline.atomic_roofline(st, ksec)["frac"]}
@@ -198,13 +244,14 @@ def denoise_leg(args):
     with nn.Denoiser(ch, (side, side, side)) as d:
         d.set_params(W.denoiser_weights(ch, seed=1))
         tr = denoise.train(d, ds, args.dn_steps, lr=1e-3, log_every=max(1, args.dn_steps // 5),
-                           say=log)
+                           batch=args.dn_batch, max_norm=args.dn_clip, say=log)
         ev = denoise.evaluate(d, range(900001, 900001 + args.dn_eval), side, args.dn_plain,
                               args.dn_ref_runs, inputs, say=log)
     del ds
     return {"workload": "denoise_64cubes", "channels": list(ch), "side": side,
             "train_volumes": args.dn_train, "train_inputs": inputs, "train_target": args.dn_target,
-            "data_s": data_s, "train_steps": tr["steps"], "train_s": tr["seconds"],
+            "data_s": data_s, "train_steps": tr["steps"], "train_batch": tr["batch"],
+            "train_clip": tr["max_norm"], "train_s": tr["seconds"],
             "final_loss": tr["losses"][-1][1] if tr["losses"] else None, **ev}
 
 

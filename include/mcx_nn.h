@@ -82,16 +82,20 @@ mcx_status mcx_nn_forward(mcx_nn *nn, const float *phi_in, float *phi_out, float
                           void *hip_stream);
 
 /* Forward pass on phi_in, loss against phi_target and backward pass: the
- * gradients of every parameter (mcx_nn_get_grads).  *loss (may be NULL)
- * receives the loss, which makes the call wait for the stream; with
- * loss == NULL it is async. */
+ * gradients of every parameter (mcx_nn_get_grads), replacing the current
+ * gradients, or added to them when accumulate != 0 (for steps over several
+ * volumes).  *loss (may be NULL) receives this volume's loss, which makes
+ * the call wait for the stream; with loss == NULL it is async. */
 mcx_status mcx_nn_loss_grad(mcx_nn *nn, const float *phi_in, const float *phi_target,
-                            double *loss, void *hip_stream);
+                            int32_t accumulate, double *loss, void *hip_stream);
 
-/* One Adam step with learning rate lr on the current gradients.  Async. */
-mcx_status mcx_nn_adam(mcx_nn *nn, float lr, void *hip_stream);
+/* One Adam step with learning rate lr on g = grad_scale * (current
+ * gradients), with g scaled down to global L2 norm max_norm when its norm
+ * is larger (max_norm <= 0: no clipping).  Async. */
+mcx_status mcx_nn_adam(mcx_nn *nn, float lr, float grad_scale, float max_norm, void *hip_stream);
 
-/* mcx_nn_loss_grad followed by mcx_nn_adam. */
+/* mcx_nn_loss_grad (replacing the gradients) followed by mcx_nn_adam with
+ * grad_scale 1 and no clipping. */
 mcx_status mcx_nn_train_step(mcx_nn *nn, const float *phi_in, const float *phi_target, float lr,
                              double *loss, void *hip_stream);
 

@@ -25,7 +25,8 @@ frozen design:
 * Loss: mean squared error of out against the target's u over a mask of
   voxels (the medium voxels where the target fluence is at least 1e-8 of
   its maximum); Adam (beta1 0.9, beta2 0.999, eps 1e-8) on every weight
-  and bias.
+  and bias, on the gradients averaged over the volumes of a step and
+  optionally clipped to a global L2 norm (`clip_scale`).
 
 Weight layouts (shared with the library's C interface): conv3 w[27][Cin][Cout]
 with tap t = (dz+1)*9 + (dy+1)*3 + (dx+1) reading x[z+dz][y+dy][x+dx];
@@ -263,6 +264,16 @@ def loss_and_grad(out, target_u, mask):
     n = int(mask.sum())
     d = np.where(mask, out - target_u, 0.0)
     return float((d * d).sum() / n), 2.0 * d / n
+
+
+def clip_scale(grads, grad_scale: float = 1.0, max_norm: float = 0.0) -> float:
+    """Factor applied to every gradient before Adam: grad_scale (1/B when B
+    volumes' gradients were summed), shrunk so that the global L2 norm of
+    all scaled gradients is at most max_norm when max_norm > 0."""
+    norm = grad_scale * float(np.sqrt(sum(float(np.sum(np.square(g))) for g in grads)))
+    if max_norm > 0 and norm > max_norm:
+        return grad_scale * max_norm / norm
+    return grad_scale
 
 
 def adam(param, grad, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):

@@ -70,8 +70,11 @@ hipError_t launch_mse(const float* out, const float* target_u, const float* targ
                       float rel_floor, int64_t n, float* grad, double* acc, float* phi_max,
                       hipStream_t s);
 hipError_t launch_bias_grad(const uint16_t* gy, int64_t m, int cout, float* gb, hipStream_t s);
+// Adam step on grad_scale * g, clipped to global norm max_norm (> 0);
+// partial: kNormBlocks doubles of scratch
+constexpr int kNormBlocks = 1024;
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, int step,
-                       hipStream_t s);
+                       float grad_scale, float max_norm, double* partial, hipStream_t s);
 
 }  // namespace nn
 }  // namespace mcx

@@ -507,12 +507,39 @@ __global__ void __launch_bounds__(256) bias_grad_kernel(const uint16_t* gy, int6
   }
 }
 
-// Adam with bias-corrected moments
+// per-block sums of squares of g (for the global gradient norm)
+__global__ void __launch_bounds__(256) sumsq_kernel(const float* g, int64_t n, double* partial) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    s += static_cast<double>(g[i]) * g[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Adam with bias-corrected moments on g * scale, where scale also clips
+// the global norm: scale = gs * min(1, max_norm / (gs * |g|)) when
+// max_norm > 0 (|g|^2 = sum of the `blocks` partial sums)
 __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr,
-                            float b1, float b2, float eps, float c1, float c2) {
+                            float b1, float b2, float eps, float c1, float c2, float gs,
+                            float max_norm, const double* partial, int blocks) {
+  __shared__ float s_scale;
+  if (threadIdx.x == 0) {
+    float sc = gs;
+    if (max_norm > 0.f) {
+      double ss = 0.0;
+      for (int b = 0; b < blocks; ++b) ss += partial[b];
+      const double norm = gs * sqrt(ss);
+      if (norm > max_norm) sc = static_cast<float>(gs * (max_norm / norm));
+    }
+    s_scale = sc;
+  }
+  __syncthreads();
+  const float scale = s_scale;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const float gi = g[i];
+    const float gi = g[i] * scale;
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
@@ -624,10 +651,16 @@ hipError_t launch_relu_grad(const float* g, const uint16_t* skip16, const uint16
 }
 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, int step,
-                       hipStream_t s) {
+                       float grad_scale, float max_norm, double* partial, hipStream_t s) {
   const double c1 = 1.0 - std::pow(0.9, step), c2 = 1.0 - std::pow(0.999, step);
+  int blocks = 0;
+  if (max_norm > 0.f) {
+    blocks = blocks_for(n, 256, kNormBlocks);
+    sumsq_kernel<<<blocks, 256, 0, s>>>(g, n, partial);
+  }
   adam_kernel<<<blocks_for(n), 256, 0, s>>>(p, g, m, v, n, lr, 0.9f, 0.999f, 1e-8f,
-                                            static_cast<float>(c1), static_cast<float>(c2));
+                                            static_cast<float>(c1), static_cast<float>(c2),
+                                            grad_scale, max_norm, partial, blocks);
   return hipGetLastError();
 }
 

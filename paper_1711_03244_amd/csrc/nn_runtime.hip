@@ -226,6 +226,7 @@ struct mcx_nn {
   double* acc = nullptr;
   float* phimax = nullptr;
   float* bias_partial = nullptr;  // per-block channel sums of the bias gradients
+  double* norm_partial = nullptr; // per-block sums of squares of the gradients
   std::vector<void*> owned;
 };
 
@@ -289,9 +290,9 @@ mcx_status run_forward(mcx_nn* nn, const float* phi_in, hipStream_t s) {
   return MCX_OK;
 }
 
-mcx_status run_backward(mcx_nn* nn, hipStream_t s) {
+mcx_status run_backward(mcx_nn* nn, bool accumulate, hipStream_t s) {
   const size_t last = nn->layers.size() - 1;
-  NN_HIP(launch_fill(nn->grads, static_cast<int64_t>(nn->nparam), 0.f, s));
+  if (!accumulate) NN_HIP(launch_fill(nn->grads, static_cast<int64_t>(nn->nparam), 0.f, s));
   const float* g = nn->gout;
   for (size_t k = 0; k <= last; ++k) {
     const size_t i = last - k;
@@ -400,6 +401,7 @@ mcx_status mcx_nn_create(const int32_t* channels, int32_t nlevels, int32_t nx, i
     int max_c = 1;
     for (const Layer& Ly : nn->layers) max_c = std::max(max_c, Ly.cout);
     NN_TRY(nn_alloc(nn, &nn->bias_partial, static_cast<size_t>(kBiasBlocks) * max_c));
+    NN_TRY(nn_alloc(nn, &nn->norm_partial, static_cast<size_t>(kNormBlocks)));
     NN_TRY(nn_alloc(nn, &nn->phimax, 1));
     NN_HIP(launch_fill(nn->params, static_cast<int64_t>(nn->nparam), 0.f, nn->stream));
     NN_HIP(launch_fill(nn->adam_m, static_cast<int64_t>(nn->nparam), 0.f, nn->stream));
@@ -464,7 +466,7 @@ mcx_status mcx_nn_forward(mcx_nn* nn, const float* phi_in, float* phi_out, float
 }
 
 mcx_status mcx_nn_loss_grad(mcx_nn* nn, const float* phi_in, const float* phi_target,
-                            double* loss, void* stream) {
+                            int32_t accumulate, double* loss, void* stream) {
   if (!nn || !phi_in || !phi_target)
     return nfail(MCX_EINVAL, "network, input and target are required");
   NN_HIP(hipSetDevice(nn->device));
@@ -475,7 +477,7 @@ mcx_status mcx_nn_loss_grad(mcx_nn* nn, const float* phi_in, const float* phi_ta
   NN_HIP(launch_to_log(phi_target, n0, nn->tgt_u, nullptr, s));
   NN_HIP(launch_mse(nn->out_u, nn->tgt_u, phi_target, kMaskFloor, n0, nn->gout, nn->acc,
                     nn->phimax, s));
-  NN_TRY(run_backward(nn, s));
+  NN_TRY(run_backward(nn, accumulate != 0, s));
   if (loss) {
     double acc[2];
     NN_HIP(hipMemcpyAsync(acc, nn->acc, sizeof(acc), hipMemcpyDeviceToHost, s));
@@ -485,21 +487,24 @@ mcx_status mcx_nn_loss_grad(mcx_nn* nn, const float* phi_in, const float* phi_ta
   return MCX_OK;
 }
 
-mcx_status mcx_nn_adam(mcx_nn* nn, float lr, void* stream) {
+mcx_status mcx_nn_adam(mcx_nn* nn, float lr, float grad_scale, float max_norm, void* stream) {
   if (!nn) return nfail(MCX_EINVAL, "network is NULL");
   if (!(lr >= 0.f)) return nfail(MCX_EINVAL, "learning rate must be >= 0");
+  if (!(grad_scale > 0.f)) return nfail(MCX_EINVAL, "grad_scale must be > 0");
+  if (!(max_norm == max_norm)) return nfail(MCX_EINVAL, "max_norm is NaN");
   NN_HIP(hipSetDevice(nn->device));
   nn->step += 1;
   NN_HIP(launch_adam(nn->params, nn->grads, nn->adam_m, nn->adam_v,
-                     static_cast<int64_t>(nn->nparam), lr, nn->step, pick(nn, stream)));
+                     static_cast<int64_t>(nn->nparam), lr, nn->step, grad_scale, max_norm,
+                     nn->norm_partial, pick(nn, stream)));
   nn->packed = false;
   return MCX_OK;
 }
 
 mcx_status mcx_nn_train_step(mcx_nn* nn, const float* phi_in, const float* phi_target, float lr,
                              double* loss, void* stream) {
-  NN_TRY(mcx_nn_loss_grad(nn, phi_in, phi_target, loss, stream));
-  return mcx_nn_adam(nn, lr, stream);
+  NN_TRY(mcx_nn_loss_grad(nn, phi_in, phi_target, 0, loss, stream));
+  return mcx_nn_adam(nn, lr, 1.f, 0.f, stream);
 }
 
 mcx_status mcx_nn_layer_forward(int32_t kind, int32_t nx, int32_t ny, int32_t nz, int32_t cin,

@@ -6,7 +6,8 @@ simulated by the library's batched transport at a low photon count (the
 network input; several counts per volume) and a high one (the target),
 with independent seeds.  Maps are fluence per launched photon of the single
 gate.  Training: Adam with a cosine learning-rate decay over the
-(input, target) pairs in a seeded random order, one volume per step.
+(input, target) pairs in a seeded random order, on the mean gradient of a
+few volumes per step, clipped to a global norm.
 
 Evaluation on held-out volumes: the reference map is the mean of K
 independent runs at the plain photon count; the error of a map is the RMS,
@@ -92,9 +93,11 @@ def make_dataset(seeds, side, input_photons, target_photons, seed_base=1_000_000
 
 
 def train(den: nn.Denoiser, ds: DataSet, steps: int, lr: float = 1e-3, lr_min: float = 1e-5,
-          seed: int = 1, log_every: int = 0, say=print) -> dict:
-    """Adam steps over the pairs in a seeded random order, cosine-decayed
-    learning rate; returns losses and wall time."""
+          seed: int = 1, log_every: int = 0, batch: int = 1, max_norm: float = 0.0,
+          say=print) -> dict:
+    """Adam steps over the pairs in a seeded random order, each on the mean
+    gradient of `batch` pairs, clipped to global norm `max_norm` (> 0), with
+    a cosine-decayed learning rate; returns losses and wall time."""
     t = _torch()
     rng = np.random.default_rng(seed)
     order = []
@@ -102,18 +105,22 @@ def train(den: nn.Denoiser, ds: DataSet, steps: int, lr: float = 1e-3, lr_min: f
     t.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        if not order:
-            order = list(rng.permutation(len(ds.inputs)))
-        i = order.pop()
-        vi, _, x = ds.inputs[i]
         rate = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * k / max(1, steps)))
-        want = log_every and (k % log_every == 0 or k == steps - 1)
-        loss = den.train_step(x, ds.targets[vi], rate, want_loss=bool(want))
+        want = bool(log_every) and (k % log_every == 0 or k == steps - 1)
+        step_loss = []
+        for b in range(batch):
+            if not order:
+                order = list(rng.permutation(len(ds.inputs)))
+            vi, _, x = ds.inputs[order.pop()]
+            step_loss.append(den.loss_grad(x, ds.targets[vi], want_loss=want, accumulate=b > 0))
+        den.adam(rate, 1.0 / batch, max_norm)
         if want:
+            loss = float(np.mean(step_loss))
             losses.append((k, loss))
             say(f"[train] step {k} lr {rate:.2e} loss {loss:.5f}")
     t.cuda.synchronize()
-    return {"steps": steps, "seconds": time.perf_counter() - t0, "losses": losses}
+    return {"steps": steps, "batch": batch, "max_norm": max_norm,
+            "seconds": time.perf_counter() - t0, "losses": losses}
 
 
 def infer_timed(den: nn.Denoiser, phi):
@@ -236,9 +243,9 @@ def summarise(rows, plain_photons, input_photons) -> dict:
 def main(argv=None) -> dict:
     """Command line: simulate a training set, train, evaluate; prints JSON.
 
-        python -m paper_1711_03244_amd.denoise [--train 64] [--steps 4000]
+        python -m paper_1711_03244_amd.denoise [--train 64] [--steps 3000]
             [--side 64] [--inputs 1e5,1e6,1e7] [--target 1e8] [--eval 2]
-            [--plain 1e9] [--ref-runs 2] [--lr 1e-3]
+            [--plain 1e9] [--ref-runs 2] [--lr 1e-3] [--batch 4] [--max-norm 0.1]
     """
     import argparse
     import json
@@ -246,7 +253,7 @@ def main(argv=None) -> dict:
 
     ap = argparse.ArgumentParser(prog="python -m paper_1711_03244_amd.denoise")
     ap.add_argument("--train", type=int, default=64)
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--side", type=int, default=64)
     ap.add_argument("--inputs", default="1e5,1e6,1e7")
     ap.add_argument("--target", type=float, default=1e8)
@@ -254,6 +261,8 @@ def main(argv=None) -> dict:
     ap.add_argument("--plain", type=float, default=1e9)
     ap.add_argument("--ref-runs", type=int, default=2)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--max-norm", type=float, default=0.1)
     a = ap.parse_args(argv)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
     inputs = [float(v) for v in a.inputs.split(",")]
@@ -263,7 +272,8 @@ def main(argv=None) -> dict:
     data_s = time.perf_counter() - t0
     with nn.Denoiser(ch, (a.side,) * 3) as d:
         d.set_params(W.denoiser_weights(ch, seed=1))
-        tr = train(d, ds, a.steps, lr=a.lr, log_every=max(1, a.steps // 5), say=log)
+        tr = train(d, ds, a.steps, lr=a.lr, log_every=max(1, a.steps // 5), batch=a.batch,
+                   max_norm=a.max_norm, say=log)
         ev = evaluate(d, range(900001, 900001 + a.eval), a.side, a.plain, a.ref_runs, inputs,
                       say=log) if a.eval > 0 else None
     out = {"channels": list(ch), "side": a.side, "train_volumes": a.train, "inputs": inputs,

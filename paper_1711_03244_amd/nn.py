@@ -35,8 +35,8 @@ def lib() -> C.CDLL:
             "mcx_nn_get_params": (C.c_int, [vp, vp, u64]),
             "mcx_nn_get_grads": (C.c_int, [vp, vp, u64]),
             "mcx_nn_forward": (C.c_int, [vp, vp, vp, vp, vp]),
-            "mcx_nn_loss_grad": (C.c_int, [vp, vp, vp, C.POINTER(C.c_double), vp]),
-            "mcx_nn_adam": (C.c_int, [vp, f32, vp]),
+            "mcx_nn_loss_grad": (C.c_int, [vp, vp, vp, i32, C.POINTER(C.c_double), vp]),
+            "mcx_nn_adam": (C.c_int, [vp, f32, f32, f32, vp]),
             "mcx_nn_train_step": (C.c_int, [vp, vp, vp, f32, C.POINTER(C.c_double), vp]),
             "mcx_nn_layer_forward": (C.c_int, [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp,
                                                i32, i32, vp, vp]),
@@ -105,15 +105,17 @@ def mcx_nn_forward(h, phi_in, phi_out=None, u_out=None, stream=None):
     mcx._check(lib().mcx_nn_forward(h, _ptr(phi_in), _ptr(phi_out), _ptr(u_out), _stream(stream)))
 
 
-def mcx_nn_loss_grad(h, phi_in, phi_target, want_loss=True, stream=None) -> Optional[float]:
+def mcx_nn_loss_grad(h, phi_in, phi_target, want_loss=True, stream=None,
+                     accumulate=False) -> Optional[float]:
     loss = C.c_double()
-    mcx._check(lib().mcx_nn_loss_grad(h, _ptr(phi_in), _ptr(phi_target),
+    mcx._check(lib().mcx_nn_loss_grad(h, _ptr(phi_in), _ptr(phi_target), int(bool(accumulate)),
                                       C.byref(loss) if want_loss else None, _stream(stream)))
     return loss.value if want_loss else None
 
 
-def mcx_nn_adam(h, lr: float, stream=None):
-    mcx._check(lib().mcx_nn_adam(h, float(lr), _stream(stream)))
+def mcx_nn_adam(h, lr: float, grad_scale: float = 1.0, max_norm: float = 0.0, stream=None):
+    mcx._check(lib().mcx_nn_adam(h, float(lr), float(grad_scale), float(max_norm),
+                                 _stream(stream)))
 
 
 def mcx_nn_train_step(h, phi_in, phi_target, lr: float, want_loss=False, stream=None):
@@ -174,11 +176,12 @@ class Denoiser:
         mcx_nn_forward(self.h, phi_in, phi_out, u_out, stream)
         return phi_out if phi_out is not None else u_out
 
-    def loss_grad(self, phi_in, phi_target, want_loss=True, stream=None):
-        return mcx_nn_loss_grad(self.h, self._vol(phi_in), self._vol(phi_target), want_loss, stream)
+    def loss_grad(self, phi_in, phi_target, want_loss=True, stream=None, accumulate=False):
+        return mcx_nn_loss_grad(self.h, self._vol(phi_in), self._vol(phi_target), want_loss, stream,
+                                accumulate)
 
-    def adam(self, lr, stream=None):
-        mcx_nn_adam(self.h, lr, stream)
+    def adam(self, lr, grad_scale=1.0, max_norm=0.0, stream=None):
+        mcx_nn_adam(self.h, lr, grad_scale, max_norm, stream)
 
     def train_step(self, phi_in, phi_target, lr, want_loss=False, stream=None):
         return mcx_nn_train_step(self.h, self._vol(phi_in), self._vol(phi_target), lr, want_loss,

@@ -226,21 +226,33 @@ def test_adam_step_matches_oracle():
     channels, shape = (4, 8), (8, 8, 8)
     ws, flat = make_net(channels, shape, 9)
     noisy, clean = fluence_pair(shape, 10)
+    noisy2, clean2 = fluence_pair(shape, 11)
     with nn.Denoiser(channels, shape) as d:
         d.set_params(flat)
         d.loss_grad(dev_f32(noisy), dev_f32(clean))
         g1 = d.grads().astype(np.float64)
         d.adam(1e-3)
         p1 = d.params().astype(np.float64)
+        # a step on the mean gradient of two volumes, clipped to a norm below
+        # the gradient's own
         d.loss_grad(dev_f32(noisy), dev_f32(clean))
+        ga = d.grads().astype(np.float64)
+        d.loss_grad(dev_f32(noisy2), dev_f32(clean2))
+        gb = d.grads().astype(np.float64)
+        d.loss_grad(dev_f32(noisy), dev_f32(clean))
+        d.loss_grad(dev_f32(noisy2), dev_f32(clean2), accumulate=True)
         g2 = d.grads().astype(np.float64)
-        d.adam(1e-3)
+        max_norm = 0.25 * float(np.linalg.norm(0.5 * g2))
+        d.adam(1e-3, grad_scale=0.5, max_norm=max_norm)
         p2 = d.params().astype(np.float64)
+    assert np.allclose(g2, ga + gb, rtol=1e-5, atol=1e-7 * np.abs(g2).max())
     p = flat.astype(np.float64)
     m = np.zeros_like(p)
     v = np.zeros_like(p)
     q1, m, v = O.adam(p, g1, m, v, 1, 1e-3)
-    q2, m, v = O.adam(p1, g2, m, v, 2, 1e-3)
+    scale = O.clip_scale([g2], 0.5, max_norm)
+    assert scale == pytest.approx(0.125, rel=1e-9)
+    q2, m, v = O.adam(p1, scale * g2, m, v, 2, 1e-3)
     assert np.allclose(p1, q1, rtol=1e-6, atol=1e-7)
     assert np.allclose(p2, q2, rtol=1e-6, atol=1e-7)
 
@@ -285,7 +297,7 @@ def test_denoiser_gain_on_held_out_volumes():
         d.set_params(W.denoiser_weights(channels, seed=1))
         mean_loss = lambda: np.mean([d.loss_grad(x, ds.targets[v]) for v, _, x in ds.inputs])
         before = mean_loss()
-        denoise.train(d, ds, 1500, lr=1e-3, log_every=500, say=print)
+        denoise.train(d, ds, 500, lr=1e-3, log_every=100, batch=4, max_norm=0.1, say=print)
         after = mean_loss()
         ev = denoise.evaluate(d, [700001, 700002, 700003], side, 1e7, 2, [5e4, 5e5], say=print)
     print("mean training loss", before, "->", after, ev, flush=True)

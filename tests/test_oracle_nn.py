@@ -256,3 +256,17 @@ def test_log_transform_round_trip_and_floor():
     assert np.allclose(O.from_log(u[2:]), phi[2:], rtol=1e-12)
     m = O.loss_mask(np.array([1.0, 1e-9, 2e-8, 0.5]))
     assert list(m) == [True, False, True, True]
+
+
+def test_gradient_clipping_matches_library():
+    rng = np.random.default_rng(5)
+    gs = [rng.normal(size=(3, 4)), rng.normal(size=7)]
+    for scale, max_norm in [(1.0, 0.0), (0.5, 100.0), (0.25, 0.3), (1.0, 1.0)]:
+        ts = [torch.tensor(g * scale, requires_grad=True) for g in gs]
+        for tt in ts:
+            tt.grad = tt.detach().clone()
+        if max_norm > 0:
+            torch.nn.utils.clip_grad_norm_(ts, max_norm)
+        got = O.clip_scale(gs, scale, max_norm)
+        for g, tt in zip(gs, ts):
+            assert np.allclose(got * g, tt.grad.numpy(), rtol=1e-6, atol=1e-12)
