@@ -209,20 +209,20 @@ mcx_status mcx_batch_digest(mcx_ctx *ctx, int32_t sim, double *host_out, uint64_
 
 /* Launch shape: threads per workgroup (0 = the size that keeps the most waves
  * resident), photons per job (0 = default 256), LDS window cells (0 = default
- * 8192, < 0 = none, at most 16384; single-simulation contexts only).  Waits
- * for the stream. */
+ * 8192, < 0 = none, at most 16384; in a batch each workgroup keeps the window
+ * of the simulation its first wave starts on).  Waits for the stream. */
 mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk,
                           int32_t lds_window_cells);
 
 /* Autotuner: times pilot launches of pilot_photons[i] photons (seed[i]) per
- * simulation over block sizes {64, 256, 448, 512, 1024} x jobs of {64, 256,
- * 1024, 4096} photons (1 to 64 photons per lane) x deposit schemes {direct
- * global atomics, LDS window of 4096, 8192 or 16384 cells} (windows only for one
- * simulation), keeps the fastest shape, and fits the linear device runtime
- * model T = a n + T0 of the paper's device-level load balancing (the study
- * of Fig. 3(b)) from pilots of n and n/2 photons.  Results do not depend on the shape (the
- * random numbers are keyed by photon index); tallies are cleared on return.
- * Blocking. */
+ * simulation over block sizes {64, 256, 448, 512, 768, 1024} x jobs of {64,
+ * 256, 1024} photons (1 to 16 photons per lane) x deposit schemes {direct
+ * global atomics, LDS window of 4096, 8192 or 16384 cells} (shapes that do
+ * not fit on a compute unit are skipped), keeps the fastest shape, and fits
+ * the linear device runtime model T = a n + T0 of the paper's device-level
+ * load balancing (the study of Fig. 3(b)) from pilots of n and n/2 photons.
+ * Results do not depend on the shape (the random numbers are keyed by photon
+ * index); tallies are cleared on return.  Blocking. */
 mcx_status mcx_autotune(mcx_ctx *ctx, const uint64_t *pilot_photons, const uint64_t *seed,
                         mcx_tune_result *out);
 

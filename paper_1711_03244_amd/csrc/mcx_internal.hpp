@@ -63,6 +63,9 @@ struct SimDesc {
   int32_t rec_len;
   double* digest;
   uint64_t ndigest;
+  // LDS window of this simulation: cells [wx0, wx0 + wnx) x [wy0, ...) x
+  // [wz0, ...) of gates [0, wng) (all zero: none)
+  int32_t wx0, wy0, wz0, wnx, wny, wnz, wng;
 };
 
 // One launch over `nsims` simulations.  Photons are handed out in jobs of
@@ -82,9 +85,10 @@ struct LaunchParams {
   uint32_t max_events;
   int32_t table_rows;            // LDS rows per wave for the current simulation's tables
   int32_t nmedia_max;            // for the per-lane pathlength array (detectors)
-  // LDS window of simulation 0, used only when nsims == 1: cells
-  // [wx0, wx0 + wnx) x [wy0, ...) x [wz0, ...) of gates [0, wng)
-  int32_t wx0, wy0, wz0, wnx, wny, wnz, wng;
+  // LDS window capacity in cells (0: no window).  Each workgroup keeps the
+  // window of one simulation -- the home simulation of its first wave -- and
+  // its waves use it while they work on that simulation.
+  int32_t window_cells;
 };
 
 size_t transport_smem_bytes(int table_rows, int nmedia_max, int block, bool detect,

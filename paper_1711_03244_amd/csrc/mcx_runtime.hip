@@ -85,6 +85,7 @@ struct SimHost {
   uint64_t label_off = 0, tally_off = 0, table_off = 0;
   uint64_t rec_off = 0;    // first record row (photon-index array)
   uint64_t rec_foff = 0;   // first float of the records (rows differ in length)
+  int win[7] = {0, 0, 0, 0, 0, 0, 0};  // LDS window: x0, y0, z0, nx, ny, nz, ngates
   uint64_t photons = 0;  // accumulated since the last reset
   uint64_t ncells() const { return static_cast<uint64_t>(nvox) * ngates; }
 };
@@ -99,7 +100,7 @@ struct mcx_ctx {
   bool detect = false, diag = false;
   int block = 256, grid = 0, cus = 0, chunk = kDefaultChunk;
   int window_budget = 0;
-  int win[7] = {0, 0, 0, 0, 0, 0, 0};  // x0, y0, z0, nx, ny, nz, ngates (simulation 0)
+  int win_cells = 0;  // LDS window capacity: the largest window of any simulation
   int table_rows = 0, nmedia_max = 0;
   uint64_t total_cells = 0, max_cells = 0;
 
@@ -290,32 +291,34 @@ static void describe(SimHost& sh, const mcx_sim& sm) {
       vol->labels[sh.src_i[0] + sh.nx * (sh.src_i[1] + static_cast<int64_t>(sh.ny) * sh.src_i[2])];
 }
 
-// LDS window of simulation 0: a box of cells centred on the source voxel
-// (shifted to stay inside the grid) over the first gate, or the first two
-// when there are several, holding at most `budget` cells.  Only used when the
-// context holds one simulation.
+// LDS window of every simulation: a box of cells centred on the source
+// voxel (shifted to stay inside the grid) over the first gate, or the first
+// two when there are several, holding at most `budget` cells.
 static void set_window(mcx_ctx* c, int budget) {
-  for (int& v : c->win) v = 0;
   c->window_budget = budget;
-  if (budget <= 0 || c->sims.size() != 1) return;
-  const SimHost& sh = c->sims[0];
-  const int wg = sh.ngates > 1 ? 2 : 1;
-  const int per_gate = budget / wg;
-  int side = 1;
-  while ((side + 1) * (side + 1) * (side + 1) <= per_gate) ++side;
-  const int dims[3] = {sh.nx, sh.ny, sh.nz};
-  for (int a = 0; a < 3; ++a) {
-    const int n = side < dims[a] ? side : dims[a];
-    int lo = sh.src_i[a] - n / 2;
-    if (lo > dims[a] - n) lo = dims[a] - n;
-    if (lo < 0) lo = 0;
-    c->win[a] = lo;
-    c->win[3 + a] = n;
+  c->win_cells = 0;
+  for (SimHost& sh : c->sims) {
+    for (int& v : sh.win) v = 0;
+    if (budget <= 0) continue;
+    const int wg = sh.ngates > 1 ? 2 : 1;
+    const int per_gate = budget / wg;
+    int side = 1;
+    while ((side + 1) * (side + 1) * (side + 1) <= per_gate) ++side;
+    const int dims[3] = {sh.nx, sh.ny, sh.nz};
+    for (int a = 0; a < 3; ++a) {
+      const int n = side < dims[a] ? side : dims[a];
+      int lo = sh.src_i[a] - n / 2;
+      if (lo > dims[a] - n) lo = dims[a] - n;
+      if (lo < 0) lo = 0;
+      sh.win[a] = lo;
+      sh.win[3 + a] = n;
+    }
+    sh.win[6] = wg;
+    c->win_cells = std::max(c->win_cells, sh.win[3] * sh.win[4] * sh.win[5] * sh.win[6]);
   }
-  c->win[6] = wg;
 }
 
-static int window_cells(const mcx_ctx* c) { return c->win[3] * c->win[4] * c->win[5] * c->win[6]; }
+static int window_cells(const mcx_ctx* c) { return c->win_cells; }
 
 // Launch shape: `block` threads (0 = the candidate that keeps the most waves
 // resident per CU once LDS is counted), grid = resident workgroups x CUs.
@@ -562,6 +565,13 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
       d.digest = c->d_digest + i * c->opt.ndigest * mcx::kDigestN;
       d.ndigest = c->opt.ndigest;
     }
+    d.wx0 = sh.win[0];
+    d.wy0 = sh.win[1];
+    d.wz0 = sh.win[2];
+    d.wnx = sh.win[3];
+    d.wny = sh.win[4];
+    d.wnz = sh.win[5];
+    d.wng = sh.win[6];
     job_start[i + 1] = job_start[i] + (n[i] + c->chunk - 1) / c->chunk;
   }
   mcx::LaunchParams lp{};
@@ -577,13 +587,7 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
   lp.max_events = static_cast<uint32_t>(c->opt.max_events);
   lp.table_rows = c->table_rows;
   lp.nmedia_max = c->nmedia_max;
-  lp.wx0 = c->win[0];
-  lp.wy0 = c->win[1];
-  lp.wz0 = c->win[2];
-  lp.wnx = c->win[3];
-  lp.wny = c->win[4];
-  lp.wnz = c->win[5];
-  lp.wng = c->win[6];
+  lp.window_cells = c->win_cells;
 
   // Parameter blocks are copied in stream order before the launch that reads
   // them (pageable sources are staged by the runtime before the call returns).
@@ -917,8 +921,8 @@ mcx_status mcx_set_launch(mcx_ctx* c, int32_t block_size, int32_t refill_chunk,
 
 // ------------------------------------------------------------- autotune
 
-// Pilot launches over block size x refill chunk x LDS window (the window only
-// for a single simulation); the fastest shape is kept.  Then the paper's
+// Pilot launches over block size x refill chunk x LDS window; the fastest
+// shape is kept.  Then the paper's
 // device model T = a n + T0 is fitted from two pilot sizes (n and n/2) with
 // that shape.  Tallies are cleared afterwards.
 mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_t* seed,
@@ -939,12 +943,12 @@ mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_
   };
 
   memset(out, 0, sizeof(*out));
-  const int blocks[] = {64, 256, 448, 512, 1024};
-  const int chunks[] = {64, 256, 1024, 4096};
+  const int blocks[] = {64, 256, 448, 512, 768, 1024};
+  const int chunks[] = {64, 256, 1024};
   const int windows[] = {-1, 4096, 8192, 16384};
-  const int nwin = ns == 1 ? 4 : 1;
+  const int nwin = 4;
   // the untuned default shape first (after one warm-up launch)
-  MCX_TRY(mcx_set_launch(c, 0, 0, ns == 1 ? 0 : -1));
+  MCX_TRY(mcx_set_launch(c, 0, 0, 0));
   float ms = 0.f;
   MCX_TRY(pilot(pilot_photons, &ms));
   MCX_TRY(pilot(pilot_photons, &ms));
@@ -952,19 +956,19 @@ mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_
   float best = ms;
   out->block_size = c->block;
   out->refill_chunk = c->chunk;
-  out->lds_window_cells = ns == 1 ? kDefaultWindow : -1;
+  out->lds_window_cells = kDefaultWindow;
   int nc = 1;
   for (int wi = 0; wi < nwin; ++wi) {
     for (int b : blocks) {
       for (int ch : chunks) {
-        if (mcx_set_launch(c, b, ch, ns == 1 ? windows[wi] : -1) != MCX_OK) continue;
+        if (mcx_set_launch(c, b, ch, windows[wi]) != MCX_OK) continue;
         MCX_TRY(pilot(pilot_photons, &ms));
         ++nc;
         if (ms < best) {
           best = ms;
           out->block_size = c->block;
           out->refill_chunk = ch;
-          out->lds_window_cells = ns == 1 ? windows[wi] : -1;
+          out->lds_window_cells = windows[wi];
         }
       }
     }

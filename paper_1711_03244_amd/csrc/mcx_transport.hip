@@ -22,9 +22,10 @@
 // own slice of LDS, and the lanes' partial pathlengths in LDS.
 // Deposits made while a photon stays in one tally cell are summed in a
 // register and flushed once when it leaves the cell.  Flushes into the
-// densest cells -- a box of cells around the source, the "window" -- go to
-// an FP64 copy of those cells in LDS, summed per workgroup and added to the
-// map once when the workgroup finishes; all other flushes are one
+// densest cells -- a box of cells around the source of the workgroup's
+// window simulation (the home simulation of its first wave), the "window"
+// -- go to an FP64 copy of those cells in LDS, summed per workgroup and
+// added to the map once when the workgroup finishes; all other flushes are one
 // non-returning FP64 atomic add on the map.  Device-memory atomics on
 // gfx950 execute at the memory side at a fixed rate per address, so the
 // window is what keeps the cells next to a pencil beam, which every photon
@@ -246,8 +247,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   const uint32_t bdim = blockDim.x;
   const int rows = L.table_rows;
   float4* s_tab = s_dyn + wid * rows;  // this wave's copy of its simulation's tables
-  const bool single = L.nsims == 1;
-  const int wcells = single ? L.wnx * L.wny * L.wnz * L.wng : 0;
+  const int wcells = L.window_cells;
   double* s_win = reinterpret_cast<double*>(s_dyn + (bdim >> 6) * rows);
   float* s_len = reinterpret_cast<float*>(s_win + wcells) + threadIdx.x;  // [m * blockDim]
 
@@ -284,20 +284,22 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   // where v numbers the waves so that the workgroups of one XCD (dispatched
   // round-robin over the 8 XCDs) are consecutive; the waves of a simulation
   // then share an XCD and its L2 as far as the counts allow.
-  int scan = 0;  // simulation the wave takes its jobs from
-  {
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
-    const uint32_t vb = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
-    const uint64_t wpb = bdim >> 6;
-    const uint64_t v = vb * wpb + static_cast<uint64_t>(wid);
+  const uint32_t nb = gridDim.x;
+  const uint32_t vb = (nb % 8u == 0u) ? (blockIdx.x % 8u) * (nb / 8u) + blockIdx.x / 8u
+                                      : blockIdx.x;
+  const uint64_t wpb = bdim >> 6;
+  auto home_of = [&](uint64_t v) -> int {
     const uint64_t target = ((2 * v + 1) * L.njobs) / (2 * nb * wpb);
     int lo = 0, hi = L.nsims;  // job_start[lo] <= target < job_start[hi]
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (js[mid] <= target) lo = mid; else hi = mid;
     }
-    scan = lo;
-  }
+    return lo;
+  };
+  int scan = home_of(vb * wpb + static_cast<uint64_t>(wid));  // where the wave takes jobs
+  // the workgroup's window belongs to the home simulation of its first wave
+  const int wsim = home_of(vb * wpb);
   // per-wave counts of frequent events (scalar registers); rare events are
   // counted in the wave's LDS slice by the lanes they happen to
   uint32_t c_launch = 0, c_scat = 0, c_face = 0, c_fres = 0, c_ev = 0, c_slots = 0, c_flush = 0;
@@ -506,13 +508,13 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
           old_slot = acc_slot;
           old_acc = acc;
           int slot = -1;
-          if (wcells) {
-            const uint32_t ux = static_cast<uint32_t>(ix - L.wx0);
-            const uint32_t uy = static_cast<uint32_t>(iy - L.wy0);
-            const uint32_t uz = static_cast<uint32_t>(iz - L.wz0);
-            if (ux < static_cast<uint32_t>(L.wnx) && uy < static_cast<uint32_t>(L.wny) &&
-                uz < static_cast<uint32_t>(L.wnz) && gate < L.wng)
-              slot = static_cast<int>(((gate * L.wnz + uz) * L.wny + uy) * L.wnx + ux);
+          if (wcells && cur == wsim) {
+            const uint32_t ux = static_cast<uint32_t>(ix - D->wx0);
+            const uint32_t uy = static_cast<uint32_t>(iy - D->wy0);
+            const uint32_t uz = static_cast<uint32_t>(iz - D->wz0);
+            if (ux < static_cast<uint32_t>(D->wnx) && uy < static_cast<uint32_t>(D->wny) &&
+                uz < static_cast<uint32_t>(D->wnz) && gate < D->wng)
+              slot = static_cast<int>(((gate * D->wnz + uz) * D->wny + uy) * D->wnx + ux);
           }
           acc_slot = slot;
           acc_cell = cell;
@@ -708,22 +710,24 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   flush_wave();
 
   __syncthreads();
-  // add the workgroup's window sums to the map of simulation 0
+  // add the workgroup's window sums to the map of its window's simulation
   if (wcells) {
-    CSim* D0 = as_const(L.sims);
-    for (int i = threadIdx.x; i < wcells; i += bdim) {
+    CSim* DW = uniform_sim(as_const(L.sims) + wsim);
+    const int nwx = DW->wnx, nwy = DW->wny, nwz = DW->wnz;
+    const int dcells = nwx * nwy * nwz * DW->wng;
+    for (int i = threadIdx.x; i < dcells; i += bdim) {
       const double v = s_win[i];
       if (v != 0.0) {
         int r = i;
-        const int x = r % L.wnx;
-        r /= L.wnx;
-        const int y = r % L.wny;
-        r /= L.wny;
-        const int z = r % L.wnz;
-        const int g = r / L.wnz;
-        const uint32_t cell = static_cast<uint32_t>(g) * D0->nvox + (L.wx0 + x) +
-                              D0->stride_y * (L.wy0 + y) + D0->stride_z * (L.wz0 + z);
-        __builtin_amdgcn_global_atomic_fadd_f64(as_global(D0->tally) + cell, v);
+        const int x = r % nwx;
+        r /= nwx;
+        const int y = r % nwy;
+        r /= nwy;
+        const int z = r % nwz;
+        const int g = r / nwz;
+        const uint32_t cell = static_cast<uint32_t>(g) * DW->nvox + (DW->wx0 + x) +
+                              DW->stride_y * (DW->wy0 + y) + DW->stride_z * (DW->wz0 + z);
+        __builtin_amdgcn_global_atomic_fadd_f64(as_global(DW->tally) + cell, v);
       }
     }
   }
@@ -761,7 +765,7 @@ hipError_t transport_occupancy(int* blocks_per_cu, int block, size_t smem, bool 
 
 hipError_t launch_transport(const LaunchParams& host, const LaunchParams* dev, int grid,
                             int block, hipStream_t st, bool detect, bool diag, bool accurate) {
-  const int wcells = host.nsims == 1 ? host.wnx * host.wny * host.wnz * host.wng : 0;
+  const int wcells = host.window_cells;
   const size_t smem =
       transport_smem_bytes(host.table_rows, host.nmedia_max, block, detect, wcells);
   const void* fn = pick(detect, diag, accurate);

@@ -177,10 +177,10 @@ def test_autotune_keeps_results_and_reports_model():
         base = [b.stats(i) for i in range(len(probs))]
         r = b.autotune([max(2, x // 4) for x in n], seeds)
         say("[gpu] autotune", r)
-        assert r["candidates"] == 1 + 5 * 4
-        assert r["block_size"] in (64, 256, 448, 512, 1024)
-        assert r["refill_chunk"] in (64, 256, 1024, 4096)
-        assert r["lds_window_cells"] == -1
+        assert 1 + 6 * 3 <= r["candidates"] <= 1 + 6 * 3 * 4
+        assert r["block_size"] in (64, 256, 448, 512, 768, 1024)
+        assert r["refill_chunk"] in (64, 256, 1024)
+        assert r["lds_window_cells"] in (-1, 4096, 8192, 16384)
         assert 0 < r["best_ms"] <= r["default_ms"]
         assert r["ms_per_photon"] == r["ms_per_photon"]  # finite
         assert b.stats(0)["launched"] == 0  # cleared on return
@@ -199,7 +199,7 @@ def test_autotune_single_simulation_tries_windows():
         base = s.stats()
         r = mcx.mcx_autotune(s.ctx, [20000], [3])
         say("[gpu] autotune single", r)
-        assert r["candidates"] <= 1 + 4 * 5 * 4
+        assert 1 + 6 * 3 <= r["candidates"] <= 1 + 6 * 3 * 4
         assert r["lds_window_cells"] in (-1, 4096, 8192, 16384)
         s.run(20000, 3)
         st = s.stats()
