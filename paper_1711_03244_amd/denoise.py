@@ -73,22 +73,39 @@ class DataSet:
     sim_ms: float = 0.0
 
 
+def simulate_groups(vols, nphoton, seeds, max_photons=5e9):
+    """`simulate` in batches of at most max_photons photons per launch."""
+    per = max(1, int(max_photons // max(1.0, float(nphoton))))
+    maps, ms = [], 0.0
+    for g in range(0, len(vols), per):
+        m, t = simulate(vols[g:g + per], nphoton, seeds[g:g + per])
+        maps += m
+        ms += t
+    return maps, ms
+
+
 def make_dataset(seeds, side, input_photons, target_photons, seed_base=1_000_000, say=print):
     """Simulate every volume at each input photon count and at the target
     count (independent seeds)."""
     t = _torch()
-    vols = [W.denoiser_volume(int(s), side) for s in seeds]
+    seeds = [int(s) for s in seeds]
+    vols = [W.denoiser_volume(s, side) for s in seeds]
     ds = DataSet(vols)
     for j, n_in in enumerate(input_photons):
-        maps, ms = simulate(vols, n_in, [seed_base * (j + 1) + int(s) for s in seeds])
+        maps, ms = simulate_groups(vols, n_in, [seed_base * (j + 1) + s for s in seeds])
         ds.sim_ms += ms
         for i, m in enumerate(maps):
             ds.inputs.append((i, int(n_in), t.as_tensor(m).cuda()))
         say(f"[data] {len(vols)} volumes x {n_in:.0e} photons: {ms:.0f} ms")
-    maps, ms = simulate(vols, target_photons, [seed_base * 97 + int(s) for s in seeds])
-    ds.sim_ms += ms
+    maps = []
+    per = max(1, int(5e9 // float(target_photons)))
+    for g in range(0, len(vols), per):
+        m, ms = simulate(vols[g:g + per], target_photons,
+                         [seed_base * 97 + s for s in seeds[g:g + per]])
+        maps += m
+        ds.sim_ms += ms
+        say(f"[data] targets {g + len(m)}/{len(vols)} x {target_photons:.0e} photons: {ms:.0f} ms")
     ds.targets = [t.as_tensor(m).cuda() for m in maps]
-    say(f"[data] {len(vols)} volumes x {target_photons:.0e} photons (targets): {ms:.0f} ms")
     return ds
 
 
