@@ -155,3 +155,22 @@ def test_denoiser_reports_no_device_without_gpu():
     out = C.c_void_p()
     ch = (C.c_int32 * 2)(8, 16)
     assert nn.lib().mcx_nn_create(ch, 2, 8, 8, 8, 0, C.byref(out)) == mcx.MCX_ENODEV
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # a fresh interpreter pointed at a package copy without libmcx.so must
+    # raise instead of computing anything another way
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_1711_03244_amd"
+    pkg.mkdir()
+    src = os.path.join(ROOT, "paper_1711_03244_amd")
+    for f in ["__init__.py", "mcx.py", "nn.py", "workloads.py"]:
+        shutil.copy(os.path.join(src, f), pkg / f)
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1711_03244_amd import mcx\n"
+            "try:\n    mcx.lib()\nexcept RuntimeError as e:\n    print('RAISED', e)\n"
+            % str(tmp_path))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert "RAISED" in r.stdout and "missing" in r.stdout, r.stdout + r.stderr

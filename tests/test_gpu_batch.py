@@ -265,3 +265,34 @@ def test_full_batch_sampled_photons_against_oracle():
                 & np.isclose(dig[:, 4], o["digest"][:, 4], rtol=1e-3, atol=1e-7))
         say(it.problem.name, "coupled", same.mean())
         assert same.mean() >= 0.8
+
+
+def test_batch_detector_records_of_several_simulations():
+    # detector records of simulations with different numbers of media (so
+    # different record lengths) live side by side in one buffer
+    c30 = W.cube_sphere(n=30, ngates=2, dt=2.0).replace(name="cube30_sphere")
+    d = c30.detectors.copy()
+    d[:, 3] = 4.0
+    c30 = c30.replace(detectors=d)
+    c24 = W.cube_homogeneous(n=24).replace(src_pos=(11.5, 11.5, 0.0), name="cube24")
+    c24 = c24.replace(detectors=np.array([(5.5, 11.5, 0.0, 3.0), (17.5, 11.5, 0.0, 3.0)],
+                                         np.float32), reflect=True)
+    r3 = W.random_small(4)
+    r3 = r3.replace(detectors=np.array([(0.0, 0.0, 0.0, 50.0)], np.float32))
+    probs = [c30, c24, r3]
+    n = [20000, 15000, 3000]
+    seeds = [5, 6, 7]
+    assert len({p.record_len for p in probs}) == 3
+    with mcx.Batch(probs) as b:
+        b.run(n, seeds)
+        got = [b.detected(i) for i in range(len(probs))]
+        stats = [b.stats(i) for i in range(len(probs))]
+    for p, N, sd, (rec, ph, drop), st in zip(probs, n, seeds, got, stats):
+        with mcx.Simulation(p) as s:
+            s.run(N, sd)
+            rec1, ph1, drop1 = s.detected()
+        assert drop == drop1 == 0 and len(ph) == st["detected"] > 0, p.name
+        assert rec.shape[1] == p.record_len
+        o1, o2 = np.argsort(ph), np.argsort(ph1)
+        assert np.array_equal(ph[o1], ph1[o2]), p.name
+        assert np.array_equal(rec[o1], rec1[o2]), p.name
