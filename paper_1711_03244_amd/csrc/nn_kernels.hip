@@ -194,6 +194,95 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
   }
 }
 
+// ------------------------------------------------- 3x3x3 conv from an LDS brick
+// kConv3 / kConv3T with cin a multiple of 32: a workgroup owns a 4 x 4 x 4
+// tile of output voxels (wave w: the z-slice w, one 16-row MFMA block) and
+// 16 NB output channels.  Per chunk of 32 input channels it stages the 6 x 6
+// x 6 input brick (tile plus halo, zero outside the volume) in LDS once and
+// runs all 27 taps from it -- A fragments read from LDS, B fragments
+// (weights) from global memory one tap ahead -- with no barrier between taps.
+template <int NB>
+__global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
+  __shared__ uint16_t sBr[216][kBK + kPadK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tx_n = (a.w + 3) >> 2, ty_n = (a.h + 3) >> 2;
+  const int tile = blockIdx.x;
+  const int bx = (tile % tx_n) * 4;
+  const int by = ((tile / tx_n) % ty_n) * 4;
+  const int bz = (tile / (tx_n * ty_n)) * 4;
+  const int n0 = blockIdx.y * 16 * NB;
+  const int sgn = a.geo == kConv3 ? 1 : -1;
+  const int r = lane & 15;            // A row of this lane: voxel (r & 3, r >> 2, wave)
+  const int ox = r & 3, oy = r >> 2, oz = wave;
+  const int kq = (lane >> 4) * 8;     // this lane's 8 reduction (channel) positions
+
+  floatx4 acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  auto load_b = [&](int t, int c0, int j) -> bf16x8 {
+    const uint16_t* p = a.bt + static_cast<int64_t>(n0 + 16 * j + r) * a.kpad + t * a.cin + c0 + kq;
+    return *reinterpret_cast<const bf16x8*>(p);
+  };
+
+  for (int c0 = 0; c0 < a.cin; c0 += kBK) {
+    for (int i = tid; i < 216 * 4; i += 256) {
+      const int v = i >> 2, cc = (i & 3) * 8;
+      const int vx = v % 6, vy = (v / 6) % 6, vz = v / 36;
+      const int gx = bx + vx - 1, gy = by + vy - 1, gz = bz + vz - 1;
+      uint4 val = make_uint4(0u, 0u, 0u, 0u);
+      if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.in_w && gy < a.in_h && gz < a.in_d)
+        val = *reinterpret_cast<const uint4*>(
+            a.x + ((static_cast<int64_t>(gz) * a.in_h + gy) * a.in_w + gx) * a.cin + c0 + cc);
+      *reinterpret_cast<uint4*>(&sBr[v][cc]) = val;
+    }
+    bf16x8 bn[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) bn[j] = load_b(0, c0, j);
+    __syncthreads();
+    for (int t = 0; t < 27; ++t) {
+      bf16x8 bc[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) bc[j] = bn[j];
+      if (t + 1 < 27) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) bn[j] = load_b(t + 1, c0, j);
+      }
+      const int dz = sgn * (t / 9 - 1), dy = sgn * ((t / 3) % 3 - 1), dx = sgn * (t % 3 - 1);
+      const int v = ((oz + 1 + dz) * 6 + (oy + 1 + dy)) * 6 + (ox + 1 + dx);
+      const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sBr[v][kq]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bc[j], acc[j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: rows 4 (lane >> 4) + e of the wave's slice
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int n = n0 + j * 16 + (lane & 15);
+    if (n >= a.cout) continue;
+    const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int rr = (lane >> 4) * 4 + e;
+      const int x = bx + (rr & 3), y = by + (rr >> 2), z = bz + oz;
+      if (x >= a.w || y >= a.h || z >= a.d) continue;
+      const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
+      float v = acc[j][e] + bias;
+      if (a.skip) v += from_bf16(a.skip[o * a.cout + n]);
+      if (a.relu) v = fmaxf(v, 0.f);
+      if (a.y_f32)
+        static_cast<float*>(a.y)[o * a.cout + n] = v;
+      else
+        static_cast<uint16_t*>(a.y)[o * a.cout + n] = to_bf16(v);
+    }
+  }
+}
+
 // ------------------------------------------------------------ weight GEMM
 // gw[p][n] += sum over the workgroup's voxels of A(m, p) gy(m, n), with
 // p = t * cin + ci.  kConv3 / kDown: m runs over the output grid, A is x
@@ -560,6 +649,18 @@ int blocks_for(int64_t n, int per = 256, int cap = 8192) {
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
   const int nb = a.cout > 32 ? 4 : (a.cout > 16 ? 2 : 1);
+  if ((a.geo == kConv3 || a.geo == kConv3T) && a.cin % kBK == 0) {
+    const int64_t tiles = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 3) / 4);
+    const dim3 grid(static_cast<unsigned>(tiles),
+                    static_cast<unsigned>((a.cout + 16 * nb - 1) / (16 * nb)), 1);
+    if (nb == 4)
+      conv3_brick_kernel<4><<<grid, 256, 0, s>>>(a);
+    else if (nb == 2)
+      conv3_brick_kernel<2><<<grid, 256, 0, s>>>(a);
+    else
+      conv3_brick_kernel<1><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+  }
   const dim3 grid(static_cast<unsigned>((M + kBM - 1) / kBM),
                   static_cast<unsigned>((a.cout + 16 * nb - 1) / (16 * nb)), a.geo == kUp ? 8 : 1);
   const bool vec = a.cin % 8 == 0;
