@@ -306,3 +306,32 @@ def test_denoiser_gain_on_held_out_volumes():
     # photons): there the network must remove a large part of it
     low = ev["per_input"][0]
     assert low["denoised_err"] < 0.7 * low["noisy_err"], low
+
+
+def test_network_forward_full_size():
+    """The (32, 64, 128, 256) network on a 64^3 map of the denoiser's data
+    set, against the oracle's bf16 mode, with the bar derived from the
+    oracle's own spread as in test_network_forward_matches_oracle."""
+    from paper_1711_03244_amd import denoise
+    t = torch()
+    channels, shape = W.DENOISER_CHANNELS, (64, 64, 64)
+    ws, flat = make_net(channels, shape, 21)
+    params = O.params_from_list(channels, [(w.astype(np.float64), b.astype(np.float64)) for w, b in ws])
+    maps, _ = denoise.simulate([W.denoiser_volume(3)], 100_000, [5])
+    phi = maps[0]
+    u32 = ((np.log(np.maximum(phi, np.float32(1e-12))).astype(np.float32) + np.float32(16))
+           * np.float32(0.25)).astype(np.float64)
+    with nn.Denoiser(channels, shape) as d:
+        d.set_params(flat)
+        uo = t.empty(shape, dtype=t.float32, device="cuda")
+        d.forward(dev_f32(phi), u_out=uo)
+        got = host(uo)
+    ref, _ = O.forward(params, u32, channels, precision="bf16")
+    rng = np.random.default_rng(0)
+    nudged = {k: (w, b + rng.normal(size=b.shape) * 1e-6) for k, (w, b) in params.items()}
+    alt, _ = O.forward(nudged, u32, channels, precision="bf16")
+    err, spread = np.abs(got - ref), np.abs(alt - ref)
+    print("64^3: gpu - oracle median", np.median(err), "max", err.max(), "| oracle spread median",
+          np.median(spread), "max", spread.max(), flush=True)
+    assert np.median(err) <= 2 * max(np.median(spread), 1e-6)
+    assert err.max() <= 2 * max(spread.max(), 1e-5)
