@@ -1,7 +1,9 @@
 """Throughput benchmark of the photon-transport hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--photons N]
-                    [--no-cpu-baseline] [--head-photons M]
+                    [--launch BLOCK,CHUNK,WINDOW] [--head-launch BLOCK,CHUNK,WINDOW]
+                    [--no-cpu-baseline] [--head-photons M] [--no-head] [--no-batch]
+                    [--no-denoise]
 
 Workload: the paper's heterogeneous cube benchmark as configured here -- a
 60 x 60 x 60 grid of 1 mm voxels, background mua 0.005/mm, mus 1.0/mm,
@@ -17,7 +19,9 @@ normalisation of the map into a device tensor.  Problem creation and upload
 Prints one JSON line.  `roofline` is the transport kernel's algorithmic VALU
 work over its HIP-event time; `atomic_roofline` its memory-side atomic rate;
 `cpu_baseline` the FP64 oracle on the host cores over a prefix of the same
-photons.  Two further workloads are reported beside the main one, each
+photons.  The launch shape of the timed steps is the one the library's
+autotuner picks (before the timed region) from pilot launches of 1/50 of the
+photons; the rate of the default shape is reported beside it.  Two further workloads are reported beside the main one, each
 timed once after a warm-up launch: `head_volume` (the seeded 181 x 217 x
 181 layered head phantom, 10 gates of 0.5 ns, 1e8 photons) and `batched`
 (256 generated cubes of 32-128 mm with 1-3 inclusions and 1e5-1e7 photons
@@ -48,6 +52,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--photons", type=int, default=100_000_000)
     ap.add_argument("--cpu-photons", type=int, default=3_000_000)
+    ap.add_argument("--launch", default=None, metavar="BLOCK,CHUNK,WINDOW",
+                    help="fix the transport launch shape (skips the autotuner and the "
+                         "default-shape context run, e.g. for profiling)")
+    ap.add_argument("--head-launch", default=None, metavar="BLOCK,CHUNK,WINDOW",
+                    help="the same for the head-volume leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--head-photons", type=int, default=100_000_000)
@@ -64,9 +73,9 @@ def main():
     ap.add_argument("--dn-ref-runs", type=int, default=2, help="reference runs per volume")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the transport on a single "
-              "MI355X (photons shard across GPUs by index range, which is not run here); "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the transport runs on a single MI355X "
+              "(photons would shard across GPUs by index range; no multi-GPU launch is "
+              "provided); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -79,6 +88,22 @@ def main():
     create_ms = (time.perf_counter() - t_create) * 1e3
     out = torch.empty(p.tally_shape, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
+    if args.launch:
+        blk, chunk, win = (int(v) for v in args.launch.split(","))
+        sim.set_launch(blk, chunk, win)
+        default_rate = None
+        tune = {"refill_chunk": chunk, "lds_window_cells": win}
+        chosen_by = "--launch"
+    else:
+        # the library's default launch shape, for context, then the shape the
+        # autotuner picks from pilot launches of N/50 photons (kept for the steps)
+        sim.run(N // 100, args.seed + 2000)
+        sim.run(N, args.seed + 2001)
+        default_rate = N / sim.stats()["kernel_ms"]
+        t_tune = time.perf_counter()
+        tune = sim.autotune(max(1000, N // 50), args.seed + 3000)
+        chosen_by = (f"autotuner, {tune['candidates']} shapes, pilots of {N // 50} photons, "
+                     f"{time.perf_counter() - t_tune:.1f} s before the timed steps")
 
     def step(i):
         mcx.mcx_reset(sim.ctx)
@@ -103,12 +128,13 @@ def main():
     last = stats[-1]
     ksec = sum(kernel_ms) / len(kernel_ms) / 1e3
     roof = roofline.valu_roofline(last, ksec)
-    roof["traffic"] = roofline.measured_traffic(N)
+    roof["traffic"] = roofline.measured_traffic(N, tune["lds_window_cells"])
     atom = roofline.atomic_roofline(last, ksec)
     sim.close()
 
     cube1 = None if args.no_head else cube1_leg(mcx, W)
-    head = None if args.no_head else head_leg(mcx, roofline, W, args.head_photons, args.seed)
+    head = None if args.no_head else head_leg(mcx, roofline, W, args.head_photons, args.seed,
+                                              args.head_launch)
     batched = None if args.no_batch else batch_leg(mcx, W)
     denoised = None if args.no_denoise else denoise_leg(args)
 
@@ -139,6 +165,11 @@ def main():
         "kernel_photons_per_ms": N / (sum(kernel_ms) / len(kernel_ms)),
         "kernel_photons_per_ms_best": N / ks[0],
         "kernel_photons_per_ms_median": N / ks[len(ks) // 2],
+        "kernel_photons_per_ms_default_launch": default_rate,
+        "launch": {"block_size": last["block_size"], "grid_blocks": last["grid_blocks"],
+                   "refill_chunk": tune["refill_chunk"],
+                   "lds_window_cells": tune["lds_window_cells"],
+                   "chosen_by": chosen_by},
         "create_ms": create_ms,
         "events_per_photon": last["events"] / N,
         "lane_utilisation": last["events"] / max(1, last["lane_slots"]),
@@ -187,16 +218,27 @@ def cube1_leg(mcx, W):
                                       "photons_per_ms": (N // 10) / base["kernel_ms"]}}
 
 
-def head_leg(mcx, roofline, W, N, seed):
+def head_leg(mcx, roofline, W, N, seed, launch=None):
     p = W.head_phantom(1)
     with mcx.Simulation(p) as sim:
-        sim.run(N // 100, seed + 1000)  # warm-up
+        if launch:
+            blk, chunk, win = (int(v) for v in launch.split(","))
+            sim.set_launch(blk, chunk, win)
+            default_med, tune = None, {"refill_chunk": chunk, "lds_window_cells": win}
+            sim.run(N // 100, seed + 1000)  # warm-up
+        else:
+            sim.run(N // 100, seed + 1000)  # warm-up
+            _, default_med, _ = best_median(mcx, sim, N, [seed, seed + 1, seed + 2])
+            tune = sim.autotune(max(1000, N // 50), seed + 3000)
         best, med, runs = best_median(mcx, sim, N, [seed, seed + 1, seed + 2])
         st = runs[0]
     ksec = st["kernel_ms"] / 1e3
     return {"workload": "head_1", "grid": [181, 217, 181], "gates": 10, "gate_ns": 0.5,
             "photons": N, "photons_per_ms": N / st["run_ms"], "photons_per_ms_best": best,
-            "photons_per_ms_median": med, "kernel_ms": st["kernel_ms"],
+            "photons_per_ms_median": med, "photons_per_ms_median_default_launch": default_med,
+            "launch": {"block_size": st["block_size"], "refill_chunk": tune["refill_chunk"],
+                       "lds_window_cells": tune["lds_window_cells"]},
+            "kernel_ms": st["kernel_ms"],
             "run_ms": st["run_ms"], "events_per_photon": st["events"] / N,
             "valu_frac": roofline.valu_roofline(st, ksec)["frac"],
             "atomic_frac": roofline.atomic_roofline(st, ksec)["frac"]}

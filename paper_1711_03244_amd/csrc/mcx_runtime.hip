@@ -292,15 +292,22 @@ static void describe(SimHost& sh, const mcx_sim& sm) {
 }
 
 // LDS window of every simulation: a box of cells centred on the source
-// voxel (shifted to stay inside the grid) over the first gate, or the first
-// two when there are several, holding at most `budget` cells.
+// voxel (shifted to stay inside the grid) over the gates of about the first
+// kWindowNs after t0 (at least one, at most kWindowGates), holding at most
+// `budget` cells.  Early in a photon's life its deposits crowd round the
+// source whatever the gate width, so narrow gates get more of them in the
+// window and a smaller box; wide gates get one gate and the largest box.
+constexpr double kWindowNs = 0.5;
+constexpr int kWindowGates = 8;
 static void set_window(mcx_ctx* c, int budget) {
   c->window_budget = budget;
   c->win_cells = 0;
   for (SimHost& sh : c->sims) {
     for (int& v : sh.win) v = 0;
     if (budget <= 0) continue;
-    const int wg = sh.ngates > 1 ? 2 : 1;
+    const double span = kWindowNs / static_cast<double>(sh.dt);
+    int wg = span >= kWindowGates ? kWindowGates : static_cast<int>(std::lround(span));
+    wg = std::max(1, std::min(wg, std::min(sh.ngates, kWindowGates)));
     const int per_gate = budget / wg;
     int side = 1;
     while ((side + 1) * (side + 1) * (side + 1) <= per_gate) ++side;

@@ -489,6 +489,12 @@ class Simulation:
     def digest(self, nrows: Optional[int] = None) -> np.ndarray:
         return mcx_digest(self.ctx, self.ndigest if nrows is None else nrows)
 
+    def autotune(self, pilot_photons: int, seed: int) -> dict:
+        return mcx_autotune(self.ctx, [pilot_photons], [seed])
+
+    def set_launch(self, block_size=0, refill_chunk=0, lds_window_cells=0):
+        mcx_set_launch(self.ctx, block_size, refill_chunk, lds_window_cells)
+
     def close(self):
         if self.ctx:
             mcx_destroy(self.ctx)

@@ -73,24 +73,29 @@ COUNTERS = os.path.join(os.path.dirname(HERE), "profiles", "transport_cube60_sph
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 of the transport kernel's sources (kernel + internal header)."""
+    """SHA-256 of the transport kernel's sources (kernel, internal header and
+    the host code that lays out its launch and LDS window)."""
     h = hashlib.sha256()
-    for f in ["mcx_transport.hip", "mcx_internal.hpp"]:
+    for f in ["mcx_transport.hip", "mcx_internal.hpp", "mcx_runtime.hip"]:
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(photons: int):
+def measured_traffic(photons: int, lds_window_cells: int):
     """HBM-side bytes per transport launch from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE counters, scaled by the copy-kernel calibration
-    and by photons; None when the counters were taken on other kernel source."""
+    and by photons; None when the counters were taken on other kernel source
+    or with another LDS window (the window decides how many deposits reach
+    memory as atomics)."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
     if c.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if c.get("launch", {}).get("lds_window_cells") != lds_window_cells:
         return None
     per_photon = (c["fetch_kib"] * c["fetch_factor"] + c["write_kib"] * c["write_factor"]) * 1024.0 \
         / c["photons"]

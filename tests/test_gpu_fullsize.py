@@ -1,5 +1,6 @@
 """The benchmark workloads at full size (1e8 photons), in the launch
-configuration bench.py times (library defaults, no digests).
+configuration bench.py times (the shape the autotuner picks from pilots of
+1/50 of the photons, no digests).
 
 At this size the oracle cannot follow every photon, so the checks are
 properties that hold at any size -- every photon launched and terminated
@@ -37,8 +38,12 @@ def energy_residual(st):
             - st["w_rr_loss"] - st["w_capped"]) / max(n, 1)
 
 
-def whole_and_split(p, N, seed):
+def whole_and_split(p, N, seed, tune=False):
     with mcx.Simulation(p) as sim:
+        if tune:
+            t = sim.autotune(max(1000, N // 50), seed + 3000)
+            say("autotuned shape: block", t["block_size"], "chunk", t["refill_chunk"],
+                "window", t["lds_window_cells"])
         sim.run(N, seed)
         st = sim.stats()
         raw = sim.fluence(mcx.MCX_RAW, f64=True)
@@ -66,8 +71,17 @@ def test_sphere_benchmark_full_size():
     p = W.cube_sphere()
     N = 100_000_000
     say(f"[gpu] {p.name} N={N} (bench launch configuration)")
-    st, raw, (rec, ph, drop), st2, raw2 = whole_and_split(p, N, 1)
+    st, raw, (rec, ph, drop), st2, raw2 = whole_and_split(p, N, 1, tune=True)
     check_properties(st, raw, st2, raw2, N)
+    # the default launch shape follows the same photons: same counts, same map
+    with mcx.Simulation(p) as sim:
+        sim.run(N, 1)
+        st3 = sim.stats()
+        raw3 = sim.fluence(mcx.MCX_RAW, f64=True)
+    for k in COUNT_KEYS:
+        assert st3[k] == st[k], k
+    big = raw > 1e-6 * raw.max()
+    assert np.allclose(raw3[big], raw[big], rtol=1e-9)
     # detector records: one per detected photon, mirror pairs agree
     assert drop == 0 and len(rec) == st["detected"] > 1000
     det = rec[:, 0].astype(int)
@@ -113,7 +127,7 @@ def test_head_phantom_full_size():
     p = W.head_phantom(1)
     N = 100_000_000
     say(f"[gpu] {p.name} N={N}")
-    st, raw, _, st2, raw2 = whole_and_split(p, N, 1)
+    st, raw, _, st2, raw2 = whole_and_split(p, N, 1, tune=True)
     check_properties(st, raw, st2, raw2, N)
     assert st["rr_tests"] > 0 and st["timeout"] > 0
     M = 100_000
