@@ -31,7 +31,8 @@ shape the autotuner picks from pilot launches of 1/50 of the photons).
 `denoiser` trains the 3-D U-Net on simulator pairs of 64^3 volumes (inputs
 at 1e5, 1e6 and 1e7 photons, targets at 1e8) and reports, on held-out
 volumes, the error of the denoised and the plain maps against a reference
-and the time-to-equal-error against plain runs (see denoise.py).
+and the time-to-equal-error against plain runs, with every run in its own
+launch and with 32 volumes per batched launch (see denoise.py).
 """
 import argparse
 import json
@@ -71,6 +72,10 @@ def main():
     ap.add_argument("--dn-eval", type=int, default=2, help="held-out volumes")
     ap.add_argument("--dn-plain", type=float, default=1e9, help="plain-run photons")
     ap.add_argument("--dn-ref-runs", type=int, default=2, help="reference runs per volume")
+    ap.add_argument("--dn-augment", type=int, default=1,
+                    help="1: random x-y symmetries of the training pairs")
+    ap.add_argument("--dn-batch-volumes", type=int, default=32,
+                    help="volumes per batched launch in the denoiser's batched timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transport runs on a single MI355X "
@@ -286,14 +291,16 @@ def denoise_leg(args):
     with nn.Denoiser(ch, (side, side, side)) as d:
         d.set_params(W.denoiser_weights(ch, seed=1))
         tr = denoise.train(d, ds, args.dn_steps, lr=1e-3, log_every=max(1, args.dn_steps // 5),
-                           batch=args.dn_batch, max_norm=args.dn_clip, say=log)
+                           batch=args.dn_batch, max_norm=args.dn_clip,
+                           augment=bool(args.dn_augment), say=log)
         ev = denoise.evaluate(d, range(900001, 900001 + args.dn_eval), side, args.dn_plain,
-                              args.dn_ref_runs, inputs, say=log)
+                              args.dn_ref_runs, inputs, say=log,
+                              batch_seeds=range(800001, 800001 + args.dn_batch_volumes))
     del ds
     return {"workload": "denoise_64cubes", "channels": list(ch), "side": side,
             "train_volumes": args.dn_train, "train_inputs": inputs, "train_target": args.dn_target,
             "data_s": data_s, "train_steps": tr["steps"], "train_batch": tr["batch"],
-            "train_clip": tr["max_norm"], "train_s": tr["seconds"],
+            "train_clip": tr["max_norm"], "train_augment": tr["augment"], "train_s": tr["seconds"],
             "final_loss": tr["losses"][-1][1] if tr["losses"] else None, **ev}
 
 

@@ -99,6 +99,19 @@ mcx_status mcx_nn_adam(mcx_nn *nn, float lr, float grad_scale, float max_norm, v
 mcx_status mcx_nn_train_step(mcx_nn *nn, const float *phi_in, const float *phi_target, float lr,
                              double *loss, void *hip_stream);
 
+/* Training-data augmentation: out[z][y][x] = in[z][y'][x'] for one of the
+ * eight symmetries of the square x-y cross-section, op in 0..7:
+ * (x', y') = (y, x) when op & 4, else (x, y); then x' -> nx-1-x' when op & 1
+ * and y' -> ny-1-y' when op & 2.  For a problem whose source sits on the
+ * cross-section's centre line and points along z, a symmetry maps an
+ * (input, target) pair of fluence maps to the pair of the mirrored volume
+ * (with the source moved to the mirrored voxel).  in, out: FP32 device
+ * buffers [nz][ny][nx], distinct.  MCX_EINVAL for NULL or equal buffers,
+ * non-positive sizes, op outside 0..7, or a swap with nx != ny (checked
+ * before any HIP call).  Async on hip_stream (NULL = the null stream). */
+mcx_status mcx_nn_mirror_xy(const float *in, float *out, int32_t nx, int32_t ny, int32_t nz,
+                            int32_t op, void *hip_stream);
+
 /* Single layers on device buffers (the network's kernels, for tests and
  * for callers building other graphs).  (nx, ny, nz) is the layer's input
  * grid; the output grid is the same (conv3), half (down) or twice (up) per

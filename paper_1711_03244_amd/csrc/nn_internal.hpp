@@ -55,6 +55,8 @@ hipError_t launch_pack(const float* w, int taps, int cin, int cout, int rows, in
                        bool transposed, uint16_t* bt, hipStream_t s, bool clear = true);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_to_log(const float* phi, int64_t n, float* u, uint16_t* u16, hipStream_t s);
+hipError_t launch_mirror_xy(const float* in, float* out, int nx, int ny, int nz, int op,
+                            hipStream_t s);
 hipError_t launch_from_log(const float* r, const float* u, int64_t n, float* out_u, float* phi,
                            hipStream_t s);
 // g16 = bf16((g + skip16) * (y16 > 0)) over n = voxels * cout values;

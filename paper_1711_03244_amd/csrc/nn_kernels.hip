@@ -455,6 +455,24 @@ __global__ void to_log_kernel(const float* phi, int64_t n, float eps, float shif
   }
 }
 
+// out[z][y][x] = in[z][y'][x'], (x', y') = (op & 4 ? (y, x) : (x, y)) with
+// x' mirrored when op & 1 and y' when op & 2: the eight symmetries of a
+// square cross-section (the swap needs nx == ny)
+__global__ void mirror_xy_kernel(const float* in, float* out, int nx, int ny, int64_t n, int op) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int x = static_cast<int>(i % nx);
+    const int64_t r = i / nx;
+    const int y = static_cast<int>(r % ny);
+    const int64_t z = r / ny;
+    int sx = (op & 4) ? y : x;
+    int sy = (op & 4) ? x : y;
+    if (op & 1) sx = nx - 1 - sx;
+    if (op & 2) sy = ny - 1 - sy;
+    out[i] = in[(z * ny + sy) * nx + sx];
+  }
+}
+
 // phi_out = exp((r + u) * scale + shift): output of the residual network
 __global__ void from_log_kernel(const float* r, const float* u, int64_t n, float scale, float shift,
                                 float* out_u, float* phi) {
@@ -710,6 +728,13 @@ hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
 
 hipError_t launch_to_log(const float* phi, int64_t n, float* u, uint16_t* u16, hipStream_t s) {
   to_log_kernel<<<blocks_for(n), 256, 0, s>>>(phi, n, kEps, kLogShift, 1.f / kLogScale, u, u16);
+  return hipGetLastError();
+}
+
+hipError_t launch_mirror_xy(const float* in, float* out, int nx, int ny, int nz, int op,
+                            hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(nx) * ny * nz;
+  mirror_xy_kernel<<<blocks_for(n), 256, 0, s>>>(in, out, nx, ny, n, op);
   return hipGetLastError();
 }
 

@@ -507,6 +507,16 @@ mcx_status mcx_nn_train_step(mcx_nn* nn, const float* phi_in, const float* phi_t
   return mcx_nn_adam(nn, lr, 1.f, 0.f, stream);
 }
 
+mcx_status mcx_nn_mirror_xy(const float* in, float* out, int32_t nx, int32_t ny, int32_t nz,
+                            int32_t op, void* stream) {
+  if (!in || !out || in == out) return nfail(MCX_EINVAL, "in and out are required and distinct");
+  if (nx <= 0 || ny <= 0 || nz <= 0) return nfail(MCX_EINVAL, "grid sizes must be positive");
+  if (op < 0 || op > 7) return nfail(MCX_EINVAL, "op must be in 0..7");
+  if ((op & 4) && nx != ny) return nfail(MCX_EINVAL, "swapping x and y needs nx == ny");
+  NN_HIP(launch_mirror_xy(in, out, nx, ny, nz, op, static_cast<hipStream_t>(stream)));
+  return MCX_OK;
+}
+
 mcx_status mcx_nn_layer_forward(int32_t kind, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
                                 int32_t cout, const uint16_t* x, const float* w, const float* b,
                                 const uint16_t* skip, int32_t relu, int32_t y_f32, void* y,

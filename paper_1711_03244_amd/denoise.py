@@ -18,6 +18,14 @@ spread of the K runs (variance of the log map / K), is reported and
 subtracted in quadrature.  Times: the plain run's and each low-photon run's
 HIP-event time (clear + transport + reductions) plus the network's
 inference time (HIP events on the inference stream).
+
+Two timings are reported.  Single volume: each run in its own launch, so a
+low-photon run pays the whole latency of its longest photons (tens of ms in
+these media).  Batched: K volumes share one launch of the batched transport
+at each photon count; the per-volume time is the launch time / K, and the
+plain runs' per-volume time model T = a n + T0 is fitted over the same
+batched launches.  Batching changes no result (a batched simulation
+reproduces its single run photon for photon), only the time.
 """
 from __future__ import annotations
 
@@ -111,14 +119,19 @@ def make_dataset(seeds, side, input_photons, target_photons, seed_base=1_000_000
 
 def train(den: nn.Denoiser, ds: DataSet, steps: int, lr: float = 1e-3, lr_min: float = 1e-5,
           seed: int = 1, log_every: int = 0, batch: int = 1, max_norm: float = 0.0,
-          say=print) -> dict:
+          augment: bool = False, say=print) -> dict:
     """Adam steps over the pairs in a seeded random order, each on the mean
     gradient of `batch` pairs, clipped to global norm `max_norm` (> 0), with
-    a cosine-decayed learning rate; returns losses and wall time."""
+    a cosine-decayed learning rate; with `augment`, every pair passes
+    through one of the eight x-y symmetries (seeded draw) first.  Returns
+    losses and wall time."""
     t = _torch()
     rng = np.random.default_rng(seed)
     order = []
     losses = []
+    if augment:
+        xa = t.empty_like(ds.targets[0])
+        ta = t.empty_like(ds.targets[0])
     t.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -129,14 +142,18 @@ def train(den: nn.Denoiser, ds: DataSet, steps: int, lr: float = 1e-3, lr_min: f
             if not order:
                 order = list(rng.permutation(len(ds.inputs)))
             vi, _, x = ds.inputs[order.pop()]
-            step_loss.append(den.loss_grad(x, ds.targets[vi], want_loss=want, accumulate=b > 0))
+            y = ds.targets[vi]
+            if augment:
+                op = int(rng.integers(8))
+                x, y = nn.mcx_nn_mirror_xy(x, op, xa), nn.mcx_nn_mirror_xy(y, op, ta)
+            step_loss.append(den.loss_grad(x, y, want_loss=want, accumulate=b > 0))
         den.adam(rate, 1.0 / batch, max_norm)
         if want:
             loss = float(np.mean(step_loss))
             losses.append((k, loss))
             say(f"[train] step {k} lr {rate:.2e} loss {loss:.5f}")
     t.cuda.synchronize()
-    return {"steps": steps, "batch": batch, "max_norm": max_norm,
+    return {"steps": steps, "batch": batch, "max_norm": max_norm, "augment": augment,
             "seconds": time.perf_counter() - t0, "losses": losses}
 
 
@@ -155,8 +172,14 @@ def infer_timed(den: nn.Denoiser, phi):
 
 
 def evaluate(den: nn.Denoiser, seeds, side, plain_photons, ref_runs, input_photons,
-             seed_base=5_000_000, say=print) -> dict:
-    """Time-to-equal-error on held-out volumes (see the module docstring)."""
+             seed_base=5_000_000, say=print, batch_seeds=(), batch_extra=(3e7,)) -> dict:
+    """Time-to-equal-error on held-out volumes (see the module docstring);
+    with `batch_seeds`, also per-volume times of those volumes in batched
+    launches at the input counts and at `batch_extra` counts."""
+    batched = None
+    if len(batch_seeds):
+        counts = sorted(set(float(n) for n in list(input_photons) + list(batch_extra)))
+        batched = batch_timing(side, batch_seeds, counts, say=say)
     rows = []
     for s in seeds:
         p = W.denoiser_volume(int(s), side)
@@ -184,7 +207,25 @@ def evaluate(den: nn.Denoiser, seeds, side, plain_photons, ref_runs, input_photo
             f"(ref share {ref_err:.4f}), " + ", ".join(
                 f"{r['photons']:.0e}: noisy {r['noisy_err']:.4f} denoised {r['denoised_err']:.4f}"
                 for r in row["inputs"]))
-    return summarise(rows, plain_photons, input_photons)
+    return summarise(rows, plain_photons, input_photons, batched)
+
+
+def batch_timing(side, seeds, photon_counts, seed_base=7_000_000, say=print) -> list:
+    """Per-volume time of plain runs when the volumes `seeds` share one
+    batched launch, at every photon count: [(photons, launch run_ms / K)]
+    (HIP events: clear + launch + per-simulation reductions), after a
+    warm-up launch."""
+    vols = [W.denoiser_volume(int(s), side) for s in seeds]
+    K = len(vols)
+    out = []
+    with mcx.Batch(vols) as b:
+        b.run([1000] * K, [seed_base + int(s) for s in seeds])
+        for j, n in enumerate(photon_counts):
+            b.run([int(n)] * K, [seed_base + 1000 * (j + 1) + int(s) for s in seeds])
+            ms = b.stats(0)["run_ms"]
+            out.append((float(n), ms / K))
+            say(f"[batch] {K} volumes x {n:.0e} photons: {ms:.1f} ms, {ms / K:.2f} ms per volume")
+    return out
 
 
 def _debias(e, r):
@@ -212,12 +253,14 @@ def _equivalent_photons(n_err, err):
     return n0 * (err / e0) ** (1.0 / slope)
 
 
-def summarise(rows, plain_photons, input_photons) -> dict:
+def summarise(rows, plain_photons, input_photons, batched=None) -> dict:
     """Errors (reference share removed in quadrature), the plain runs'
     error curve and time model T = a n + T0 over all plain photon counts
     (the low-photon runs are plain runs too), and for every input count the
     plain photon count of equal error and the time ratio of that plain run
-    to the low-photon run plus inference."""
+    to the low-photon run plus inference.  `batched` (from batch_timing,
+    covering every input count) adds the same ratios with per-volume times
+    of batched launches."""
     ref = float(np.sqrt(np.mean([r["ref_err"] ** 2 for r in rows])))
     plain = float(np.sqrt(np.mean([r["plain_err"] ** 2 for r in rows])))
     plain_ms = float(np.mean([r["plain_ms"] for r in rows]))
@@ -249,6 +292,20 @@ def summarise(rows, plain_photons, input_photons) -> dict:
            "time_ratio": None, "best_time_ratio": None}
     ratios = [r["time_ratio"] for r in per_n if r["time_ratio"]]
     out["best_time_ratio"] = max(ratios) if ratios else None
+    if batched:
+        bn = np.array([b[0] for b in batched])
+        bt = np.array([b[1] for b in batched])
+        ab, t0b = np.polyfit(bn, bt, 1)
+        per_vol = dict(batched)
+        for r in per_n:
+            lo = per_vol[float(r["photons"])]
+            neq = r["equal_error_plain_photons"]
+            r["batched_sim_ms"] = lo
+            r["batched_time_ratio"] = (ab * neq + t0b) / (lo + r["infer_ms"]) if neq else None
+        br = [r["batched_time_ratio"] for r in per_n if r["batched_time_ratio"]]
+        out["batched"] = {"per_volume_ms": [list(b) for b in batched],
+                          "time_model": {"ms_per_photon": float(ab), "overhead_ms": float(t0b)},
+                          "best_time_ratio": max(br) if br else None}
     for r in per_n:
         if r["denoised_err_debiased"] <= out["plain_err_debiased"]:
             out["equal_error_photons"] = r["photons"]
@@ -263,6 +320,7 @@ def main(argv=None) -> dict:
         python -m paper_1711_03244_amd.denoise [--train 64] [--steps 3000]
             [--side 64] [--inputs 1e5,1e6,1e7] [--target 1e8] [--eval 2]
             [--plain 1e9] [--ref-runs 2] [--lr 1e-3] [--batch 4] [--max-norm 0.1]
+            [--augment 1] [--batch-volumes 32]
     """
     import argparse
     import json
@@ -280,6 +338,10 @@ def main(argv=None) -> dict:
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--max-norm", type=float, default=0.1)
+    ap.add_argument("--augment", type=int, default=1,
+                    help="1: pass training pairs through random x-y symmetries")
+    ap.add_argument("--batch-volumes", type=int, default=32,
+                    help="volumes per batched launch in the batched timing (0 = none)")
     a = ap.parse_args(argv)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
     inputs = [float(v) for v in a.inputs.split(",")]
@@ -290,11 +352,12 @@ def main(argv=None) -> dict:
     with nn.Denoiser(ch, (a.side,) * 3) as d:
         d.set_params(W.denoiser_weights(ch, seed=1))
         tr = train(d, ds, a.steps, lr=a.lr, log_every=max(1, a.steps // 5), batch=a.batch,
-                   max_norm=a.max_norm, say=log)
+                   max_norm=a.max_norm, augment=bool(a.augment), say=log)
         ev = evaluate(d, range(900001, 900001 + a.eval), a.side, a.plain, a.ref_runs, inputs,
-                      say=log) if a.eval > 0 else None
+                      say=log, batch_seeds=range(800001, 800001 + a.batch_volumes)) \
+            if a.eval > 0 else None
     out = {"channels": list(ch), "side": a.side, "train_volumes": a.train, "inputs": inputs,
-           "target": a.target, "data_s": data_s, "train_steps": a.steps,
+           "target": a.target, "data_s": data_s, "train_steps": a.steps, "augment": bool(a.augment),
            "train_s": tr["seconds"], "losses": tr["losses"], "evaluation": ev}
     print(json.dumps(out), flush=True)
     return out

@@ -15,7 +15,8 @@ from . import mcx
 
 EXPORTS = ["mcx_nn_create", "mcx_nn_destroy", "mcx_nn_param_count", "mcx_nn_set_params",
            "mcx_nn_get_params", "mcx_nn_get_grads", "mcx_nn_forward", "mcx_nn_loss_grad",
-           "mcx_nn_adam", "mcx_nn_train_step", "mcx_nn_layer_forward", "mcx_nn_layer_backward"]
+           "mcx_nn_adam", "mcx_nn_train_step", "mcx_nn_mirror_xy", "mcx_nn_layer_forward",
+           "mcx_nn_layer_backward"]
 
 MCX_NN_CONV3, MCX_NN_DOWN, MCX_NN_UP = 0, 1, 2
 
@@ -38,6 +39,7 @@ def lib() -> C.CDLL:
             "mcx_nn_loss_grad": (C.c_int, [vp, vp, vp, i32, C.POINTER(C.c_double), vp]),
             "mcx_nn_adam": (C.c_int, [vp, f32, f32, f32, vp]),
             "mcx_nn_train_step": (C.c_int, [vp, vp, vp, f32, C.POINTER(C.c_double), vp]),
+            "mcx_nn_mirror_xy": (C.c_int, [vp, vp, i32, i32, i32, i32, vp]),
             "mcx_nn_layer_forward": (C.c_int, [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp,
                                                i32, i32, vp, vp]),
             "mcx_nn_layer_backward": (C.c_int, [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp,
@@ -123,6 +125,17 @@ def mcx_nn_train_step(h, phi_in, phi_target, lr: float, want_loss=False, stream=
     mcx._check(lib().mcx_nn_train_step(h, _ptr(phi_in), _ptr(phi_target), float(lr),
                                        C.byref(loss) if want_loss else None, _stream(stream)))
     return loss.value if want_loss else None
+
+
+def mcx_nn_mirror_xy(x, op: int, out=None, stream=None):
+    """One of the eight x-y symmetries of a (nz, ny, nx) float32 CUDA tensor
+    (op bits: 1 mirror x, 2 mirror y, 4 swap x and y first)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(x)
+    nz, ny, nx = x.shape
+    mcx._check(lib().mcx_nn_mirror_xy(_ptr(x), _ptr(out), nx, ny, nz, int(op), _stream(stream)))
+    return out
 
 
 def mcx_nn_layer_forward(kind, shape, cin, cout, x, w, b=None, skip=None, relu=True, y=None,

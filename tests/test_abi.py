@@ -146,6 +146,14 @@ def test_denoiser_arguments_checked_before_the_gpu():
                                   None, None) == mcx.MCX_EINVAL
     assert "even" in mcx.mcx_last_error()
     assert L.mcx_nn_param_count(None) == 0
+    # augmentation op (fake addresses: the checks run before any HIP call)
+    a, b = C.c_void_p(4096), C.c_void_p(8192)
+    assert L.mcx_nn_mirror_xy(a, a, 4, 4, 4, 1, None) == mcx.MCX_EINVAL
+    assert L.mcx_nn_mirror_xy(None, b, 4, 4, 4, 1, None) == mcx.MCX_EINVAL
+    assert L.mcx_nn_mirror_xy(a, b, 4, 4, 4, 8, None) == mcx.MCX_EINVAL
+    assert L.mcx_nn_mirror_xy(a, b, 4, 4, 0, 1, None) == mcx.MCX_EINVAL
+    assert L.mcx_nn_mirror_xy(a, b, 4, 5, 4, 4, None) == mcx.MCX_EINVAL
+    assert "nx == ny" in mcx.mcx_last_error()
 
 
 def test_denoiser_reports_no_device_without_gpu():

@@ -257,6 +257,28 @@ def test_adam_step_matches_oracle():
     assert np.allclose(p2, q2, rtol=1e-6, atol=1e-7)
 
 
+@pytest.mark.parametrize("shape", [(3, 5, 6), (3, 8, 8)])
+def test_mirror_xy_is_the_symmetry(shape):
+    """Each of the eight x-y symmetries against numpy's flips and transpose
+    (bit-exact: a pure permutation)."""
+    rng = np.random.default_rng(31)
+    a = rng.normal(size=shape).astype(np.float32)
+    x = dev_f32(a)
+    for op in range(8):
+        if (op & 4) and shape[1] != shape[2]:
+            continue
+        e = a
+        if op & 1:
+            e = e[:, :, ::-1]
+        if op & 2:
+            e = e[:, ::-1, :]
+        if op & 4:
+            e = e.transpose(0, 2, 1)
+        got = nn.mcx_nn_mirror_xy(x, op).cpu().numpy()
+        torch().cuda.synchronize()
+        assert np.array_equal(got, e), op
+
+
 def test_untrained_network_returns_its_input():
     t = torch()
     channels, shape = (8, 16), (8, 8, 8)
