@@ -121,8 +121,9 @@ mcx_status mcx_nn_mirror_xy(const float *in, float *out, int32_t nx, int32_t ny,
  * voxel][cout], FP32 when y_f32 else BF16 bits.  Backward takes the BF16
  * gradient gy of the layer output (after any ReLU mask) and overwrites gx
  * (FP32 [input voxel][cin], may be NULL), gw and gb (may be NULL).
- * Temporary weight packs are allocated per call; both wait for the stream
- * before returning. */
+ * Temporary weight packs (and, for 3x3x3 layers whose reductions are
+ * split over workgroups, FP32 workspaces of partial sums) are allocated
+ * per call; both wait for the stream before returning. */
 mcx_status mcx_nn_layer_forward(int32_t kind, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
                                 int32_t cout, const uint16_t *x, const float *w, const float *b,
                                 const uint16_t *skip, int32_t relu, int32_t y_f32, void *y,

@@ -31,6 +31,8 @@ struct ConvArgs {
   const uint16_t* skip;       // BF16 [out voxel][cout] added before ReLU, or null
   void* y;                    // BF16 or FP32 [out voxel][cout]
   int32_t y_f32, relu;
+  float* part;                // FP32 workspace for split reductions, or null (no split)
+  int64_t part_cap;           // its size in floats
 };
 
 // Weight gradient gw[t][ci][n] += sum_m A(m, t, ci) gy(m, n) (FP32 atomics).
@@ -43,10 +45,17 @@ struct WgradArgs {
   const uint16_t* x;          // BF16 [voxel][cin], the layer input
   const uint16_t* gy;         // BF16 [voxel][cout], gradient of the layer output
   float* gw;                  // FP32 [taps][cin][cout], accumulated
+  float* part;                // FP32 workspace for per-workgroup partial sums, or null
+  int64_t part_cap;           // its size in floats
 };
 
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
+// floats of split-reduction workspace launch_conv would use for `a` given an
+// unlimited workspace (0: it does not split this product)
+int64_t conv_workspace_floats(const ConvArgs& a);
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s);
+// floats of workspace launch_wgrad uses for `a` (0: it needs none)
+int64_t wgrad_workspace_floats(const WgradArgs& a);
 // pack w[taps][cin][cout] (FP32) into BF16 rows: forward Bt[n][t * cin + ci]
 // (rows >= cout) or transposed Bt[ci][t * cout + n] (rows >= cin); with
 // `clear` the rows x kpad buffer is zeroed first (the padding outside the

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "nn_internal.hpp"
@@ -201,6 +202,9 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
 // x 6 input brick (tile plus halo, zero outside the volume) in LDS once and
 // runs all 27 taps from it -- A fragments read from LDS, B fragments
 // (weights) from global memory one tap ahead -- with no barrier between taps.
+// With gridDim.z = S > 1 the chunks are split into S equal ranges, one per
+// grid z index, and each workgroup stores its raw sums to the workspace
+// part[z][out voxel][cout] for split_reduce_kernel to finish.
 template <int NB>
 __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
   __shared__ uint16_t sBr[216][kBK + kPadK];
@@ -227,7 +231,9 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
     return *reinterpret_cast<const bf16x8*>(p);
   };
 
-  for (int c0 = 0; c0 < a.cin; c0 += kBK) {
+  const int split_len = a.cin / static_cast<int>(gridDim.z);  // a multiple of kBK
+  const int c_begin = static_cast<int>(blockIdx.z) * split_len;
+  for (int c0 = c_begin; c0 < c_begin + split_len; c0 += kBK) {
     for (int i = tid; i < 216 * 4; i += 256) {
       const int v = i >> 2, cc = (i & 3) * 8;
       const int vx = v % 6, vy = (v / 6) % 6, vz = v / 36;
@@ -261,6 +267,9 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
   }
 
   // epilogue: rows 4 (lane >> 4) + e of the wave's slice
+  const bool split = gridDim.z > 1;
+  float* part = split ? a.part + static_cast<int64_t>(blockIdx.z) * a.d * a.h * a.w * a.cout
+                      : nullptr;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int n = n0 + j * 16 + (lane & 15);
@@ -272,6 +281,10 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
       const int x = bx + (rr & 3), y = by + (rr >> 2), z = bz + oz;
       if (x >= a.w || y >= a.h || z >= a.d) continue;
       const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
+      if (split) {
+        part[o * a.cout + n] = acc[j][e];
+        continue;
+      }
       float v = acc[j][e] + bias;
       if (a.skip) v += from_bf16(a.skip[o * a.cout + n]);
       if (a.relu) v = fmaxf(v, 0.f);
@@ -280,6 +293,25 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
       else
         static_cast<uint16_t*>(a.y)[o * a.cout + n] = to_bf16(v);
     }
+  }
+}
+
+// Finish a split product: y[o][n] = [relu](sum over splits of part[s][o][n]
+// + bias[n] [+ skip[o][n]]), splits summed in order.
+__global__ void __launch_bounds__(256) split_reduce_kernel(ConvArgs a, int nsplit) {
+  const int64_t n_out = static_cast<int64_t>(a.d) * a.h * a.w * a.cout;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n_out;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int n = static_cast<int>(i % a.cout);
+    float v = a.part[i];
+    for (int sp = 1; sp < nsplit; ++sp) v += a.part[sp * n_out + i];
+    v += a.bias ? a.bias[n] : 0.f;
+    if (a.skip) v += from_bf16(a.skip[i]);
+    if (a.relu) v = fmaxf(v, 0.f);
+    if (a.y_f32)
+      static_cast<float*>(a.y)[i] = v;
+    else
+      static_cast<uint16_t*>(a.y)[i] = to_bf16(v);
   }
 }
 
@@ -402,6 +434,156 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
       if (p < prow_lim && acc[j][i] != 0.f)
         unsafeAtomicAdd(a.gw + static_cast<int64_t>(p) * a.cout + n, acc[j][i]);
     }
+  }
+}
+
+// ---------------------------------------- 3x3x3 weight gradient from a slab
+// kConv3 layers with cin a multiple of 32.  A workgroup owns one chunk of 32
+// input channels (blockIdx.y % chunks), one plane dz = blockIdx.y / chunks
+// of taps (the 9 taps t = 9 dz + 3 dy + dx) and 32 NBW output channels
+// (blockIdx.z), and walks the 4 x 4 x 4 voxel tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ...  Per tile it stages the 4 x 6 x 6 slab of x
+// the plane's taps read (channels-last, zero outside the volume) and the
+// tile's gy transposed to [n][m]; wave w then accumulates the 16 input
+// channels 16 (w & 1).. and 16 NBW output channels of its half (w >> 1)
+// for all 9 taps, with the tile's 64 voxels on the MFMA's reduction axis
+// (two steps of 32).  The sums are stored to part[blockIdx.x][t][ci][n]
+// and wgrad_reduce_kernel adds them to gw in a fixed order.
+template <int NBW>
+__global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
+  __shared__ uint16_t sX[144][kBK + kPadK];          // slab voxel, channel of the chunk
+  __shared__ uint16_t sG[32 * NBW][64 + kPadK];      // output channel, tile voxel
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int chunks = a.cin / kBK;
+  const int c0 = static_cast<int>(blockIdx.y % chunks) * kBK;
+  const int dz = static_cast<int>(blockIdx.y / chunks);
+  const int n0 = static_cast<int>(blockIdx.z) * 32 * NBW;
+  const int cb = wave & 1;
+  const int nw = (wave >> 1) * 16 * NBW;  // this wave's first channel within the group
+  const int tx_n = (a.w + 3) >> 2, ty_n = (a.h + 3) >> 2, tz_n = (a.d + 3) >> 2;
+  const int tiles = tx_n * ty_n * tz_n;
+  const int P = a.taps * a.cin;
+
+  floatx4 acc[9][NBW];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int j = 0; j < NBW; ++j) acc[t][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int bx = (tile % tx_n) * 4;
+    const int by = ((tile / tx_n) % ty_n) * 4;
+    const int bz = (tile / (tx_n * ty_n)) * 4;
+    __syncthreads();  // the previous tile's fragments have been read
+    for (int i = tid; i < 144 * 4; i += 256) {
+      const int v = i >> 2, cc = (i & 3) * 8;
+      const int xx = v % 6, yy = (v / 6) % 6, zz = v / 36;
+      const int gx = bx + xx - 1, gy = by + yy - 1, gz = bz + zz + dz - 1;
+      uint4 val = make_uint4(0u, 0u, 0u, 0u);
+      if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.g.in_w && gy < a.g.in_h && gz < a.g.in_d)
+        val = *reinterpret_cast<const uint4*>(
+            a.x + ((static_cast<int64_t>(gz) * a.g.in_h + gy) * a.g.in_w + gx) * a.cin + c0 + cc);
+      *reinterpret_cast<uint4*>(&sX[v][cc]) = val;
+    }
+    for (int i = tid; i < 64 * 4 * NBW; i += 256) {
+      const int m = i / (4 * NBW), nc = (i % (4 * NBW)) * 8;
+      const int x = bx + (m & 3), y = by + ((m >> 2) & 3), z = bz + (m >> 4);
+      uint16_t e[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) e[j] = 0;
+      if (x < a.w && y < a.h && z < a.d) {
+        const uint16_t* row =
+            a.gy + ((static_cast<int64_t>(z) * a.h + y) * a.w + x) * a.cout + n0 + nc;
+        if (a.cout % 8 == 0 && n0 + nc + 8 <= a.cout) {
+          const uint4 q = *reinterpret_cast<const uint4*>(row);
+          e[0] = q.x & 0xffff; e[1] = q.x >> 16; e[2] = q.y & 0xffff; e[3] = q.y >> 16;
+          e[4] = q.z & 0xffff; e[5] = q.z >> 16; e[6] = q.w & 0xffff; e[7] = q.w >> 16;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) e[j] = (n0 + nc + j < a.cout) ? row[j] : 0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sG[nc + j][m] = e[j];
+    }
+    __syncthreads();
+    // B fragments: voxels 32 ks + 8 g .. + 7 of output channel nw + 16 j + r
+    bf16x8 bf[2][NBW];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+      for (int j = 0; j < NBW; ++j)
+        bf[ks][j] = *reinterpret_cast<const bf16x8*>(&sG[nw + 16 * j + r][32 * ks + 8 * g]);
+    // A fragments: channel 16 cb + r of the slab at voxel m + tap offset,
+    // m = 32 ks + 8 g + j: x = j & 3, y = 2 (g & 1) + (j >> 2), z = 2 ks + (g >> 1)
+    const int ci = cb * 16 + r;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int zz = 2 * ks + (g >> 1);
+      const int y0 = 2 * (g & 1);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3, dx = t % 3;
+        const int base0 = (zz * 6 + y0 + dy) * 6 + dx;  // row y0: x = 0..3
+        bf16x8 af;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          af[j] = __builtin_bit_cast(__bf16, sX[base0 + j][ci]);
+          af[4 + j] = __builtin_bit_cast(__bf16, sX[base0 + 6 + j][ci]);
+        }
+#pragma unroll
+        for (int j = 0; j < NBW; ++j)
+          acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[ks][j], acc[t][j], 0, 0, 0);
+      }
+    }
+  }
+  // lane (r, g) holds D[4 g + i][r]: input channel c0 + 16 cb + 4 g + i, output channel
+  float* out = a.part + static_cast<int64_t>(blockIdx.x) * P * a.cout;
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int j = 0; j < NBW; ++j) {
+      const int n = n0 + nw + 16 * j + r;
+      if (n >= a.cout) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int p = (9 * dz + t) * a.cin + c0 + 16 * cb + 4 * g + i;
+        out[static_cast<int64_t>(p) * a.cout + n] = acc[t][j][i];
+      }
+    }
+}
+
+// the same for fewer than 8 workgroups: one thread per i
+__global__ void wgrad_reduce_few_kernel(const float* part, int groups, int64_t n, float* gw) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float v = part[i];
+    for (int k = 1; k < groups; ++k) v += part[k * n + i];
+    gw[i] += v;
+  }
+}
+
+// gw[i] += sum over the workgroups k < groups of part[k][i]: a workgroup
+// takes 32 consecutive i; thread (q, il) sums k = q, q + 8, ... for i =
+// 32 blockIdx.x + il, and the eight sums of each i are added in q order
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* part, int groups,
+                                                           int64_t n, float* gw) {
+  __shared__ float sh[8][33];
+  const int il = threadIdx.x & 31, q = threadIdx.x >> 5;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 32 + il;
+  float v = 0.f;
+  if (i < n)
+    for (int k = q; k < groups; k += 8) v += part[k * n + i];
+  sh[q][il] = v;
+  __syncthreads();
+  if (q == 0 && i < n) {
+    float t = sh[0][il];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) t += sh[k][il];
+    gw[i] += t;
   }
 }
 
@@ -664,19 +846,57 @@ int blocks_for(int64_t n, int per = 256, int cap = 8192) {
 
 // --------------------------------------------------------------- launchers
 
+namespace {
+
+constexpr int64_t kSplitTargetGroups = 1024;  // about four workgroups per CU
+constexpr int64_t kSplitBelowGroups = 512;    // split only launches smaller than this
+
+int conv_nb(const ConvArgs& a) { return a.cout > 32 ? 4 : (a.cout > 16 ? 2 : 1); }
+
+bool uses_brick(const ConvArgs& a) {
+  return (a.geo == kConv3 || a.geo == kConv3T) && a.cin % kBK == 0;
+}
+
+// splits of the brick kernel's input-channel chunks: for launches of fewer
+// than two workgroups per CU, enough to fill the chip, a divisor of the
+// chunk count, within `cap` floats (measured: on 8^3 and 16^3 grids the
+// split runs 6x and 1.8x faster; at 512 workgroups it gains nothing)
+int brick_splits(const ConvArgs& a, int64_t cap) {
+  const int nb = conv_nb(a);
+  const int64_t tiles = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 3) / 4);
+  const int64_t groups = tiles * ((a.cout + 16 * nb - 1) / (16 * nb));
+  if (groups >= kSplitBelowGroups) return 1;
+  const int chunks = a.cin / kBK;
+  int sp = static_cast<int>(std::min<int64_t>(chunks, (kSplitTargetGroups + groups - 1) / groups));
+  const int64_t per = static_cast<int64_t>(a.d) * a.h * a.w * a.cout;
+  while (sp > 1 && (chunks % sp != 0 || sp * per > cap)) --sp;
+  return sp < 1 ? 1 : sp;
+}
+
+}  // namespace
+
+int64_t conv_workspace_floats(const ConvArgs& a) {
+  if (!uses_brick(a)) return 0;
+  const int sp = brick_splits(a, INT64_MAX);
+  return sp > 1 ? sp * static_cast<int64_t>(a.d) * a.h * a.w * a.cout : 0;
+}
+
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
-  const int nb = a.cout > 32 ? 4 : (a.cout > 16 ? 2 : 1);
-  if ((a.geo == kConv3 || a.geo == kConv3T) && a.cin % kBK == 0) {
+  const int nb = conv_nb(a);
+  if (uses_brick(a)) {
     const int64_t tiles = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 3) / 4);
+    const int sp = a.part ? brick_splits(a, a.part_cap) : 1;
     const dim3 grid(static_cast<unsigned>(tiles),
-                    static_cast<unsigned>((a.cout + 16 * nb - 1) / (16 * nb)), 1);
+                    static_cast<unsigned>((a.cout + 16 * nb - 1) / (16 * nb)),
+                    static_cast<unsigned>(sp));
     if (nb == 4)
       conv3_brick_kernel<4><<<grid, 256, 0, s>>>(a);
     else if (nb == 2)
       conv3_brick_kernel<2><<<grid, 256, 0, s>>>(a);
     else
       conv3_brick_kernel<1><<<grid, 256, 0, s>>>(a);
+    if (sp > 1) split_reduce_kernel<<<blocks_for(M * a.cout), 256, 0, s>>>(a, sp);
     return hipGetLastError();
   }
   const dim3 grid(static_cast<unsigned>((M + kBM - 1) / kBM),
@@ -692,7 +912,53 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+
+constexpr int64_t kSlabTargetGroups = 512;
+constexpr int64_t kSlabMaxPart = int64_t(8) << 20;  // floats of partial sums at most
+
+bool uses_slab(const WgradArgs& a) { return a.geo == kConv3 && a.cin % kBK == 0; }
+int slab_nbw(const WgradArgs& a) { return a.cout > 32 ? 2 : 1; }
+
+// workgroups along the voxel tiles: about kSlabTargetGroups in all, at most
+// one per tile, with the partial sums within `cap` floats
+int slab_groups(const WgradArgs& a, int64_t cap) {
+  const int64_t tiles = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 3) / 4);
+  const int nbw = slab_nbw(a);
+  const int64_t other = static_cast<int64_t>(a.cin / kBK) * 3 * ((a.cout + 32 * nbw - 1) / (32 * nbw));
+  int64_t G = std::min<int64_t>(tiles, (kSlabTargetGroups + other - 1) / other);
+  const int64_t per = static_cast<int64_t>(a.taps) * a.cin * a.cout;
+  while (G > 1 && G * per > cap) G = (G + 1) / 2;
+  return static_cast<int>(G < 1 ? 1 : G);
+}
+
+}  // namespace
+
+int64_t wgrad_workspace_floats(const WgradArgs& a) {
+  if (!uses_slab(a)) return 0;
+  return slab_groups(a, kSlabMaxPart) * static_cast<int64_t>(a.taps) * a.cin * a.cout;
+}
+
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
+  if (uses_slab(a) && a.part) {
+    const int64_t per = static_cast<int64_t>(a.taps) * a.cin * a.cout;
+    const int G = slab_groups(a, a.part_cap);
+    if (static_cast<int64_t>(G) * per <= a.part_cap) {
+      const int nbw = slab_nbw(a);
+      const dim3 grid(static_cast<unsigned>(G), static_cast<unsigned>(a.cin / kBK * 3),
+                      static_cast<unsigned>((a.cout + 32 * nbw - 1) / (32 * nbw)));
+      if (nbw == 2)
+        wgrad_slab_kernel<2><<<grid, 256, 0, s>>>(a);
+      else
+        wgrad_slab_kernel<1><<<grid, 256, 0, s>>>(a);
+      if (G < 8)
+        wgrad_reduce_few_kernel<<<blocks_for(per), 256, 0, s>>>(a.part, G, per, a.gw);
+      else
+        wgrad_reduce_kernel<<<static_cast<unsigned>((per + 31) / 32), 256, 0, s>>>(a.part, G, per,
+                                                                                   a.gw);
+      return hipGetLastError();
+    }
+  }
   const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
   const int nb = a.cout > 32 ? 4 : (a.cout > 16 ? 2 : 1);
   const int P = a.taps * a.cin;

@@ -227,6 +227,8 @@ struct mcx_nn {
   float* phimax = nullptr;
   float* bias_partial = nullptr;  // per-block channel sums of the bias gradients
   double* norm_partial = nullptr; // per-block sums of squares of the gradients
+  float* part = nullptr;          // split-reduction workspace of the convolutions
+  int64_t part_cap = 0;           // its size in floats
   std::vector<void*> owned;
 };
 
@@ -283,8 +285,10 @@ mcx_status run_forward(mcx_nn* nn, const float* phi_in, hipStream_t s) {
         if (S.skip_level == L.up_level) skip = S.act;
     }
     const bool out = i == last;
-    const ConvArgs a = forward_args(L, layer_input(nn, i), nn->params + L.boff, skip, !out, out,
-                                    out ? static_cast<void*>(nn->r) : static_cast<void*>(L.act));
+    ConvArgs a = forward_args(L, layer_input(nn, i), nn->params + L.boff, skip, !out, out,
+                              out ? static_cast<void*>(nn->r) : static_cast<void*>(L.act));
+    a.part = nn->part;
+    a.part_cap = nn->part_cap;
     NN_HIP(launch_conv(a, s));
   }
   return MCX_OK;
@@ -305,9 +309,15 @@ mcx_status run_backward(mcx_nn* nn, bool accumulate, hipStream_t s) {
                                ? nn->skip_grad[L.skip_level] : nullptr;
     NN_HIP(launch_relu_grad(g, skip, i == last ? nullptr : L.act, nout, L.cout, gy,
                             nn->grads + L.boff, nn->bias_partial, s));
-    NN_HIP(launch_wgrad(wgrad_args(L, layer_input(nn, i), gy, nn->grads + L.woff), s));
+    WgradArgs wa = wgrad_args(L, layer_input(nn, i), gy, nn->grads + L.woff);
+    wa.part = nn->part;
+    wa.part_cap = nn->part_cap;
+    NN_HIP(launch_wgrad(wa, s));
     if (i > 0) {
-      NN_HIP(launch_conv(dgrad_args(L, gy, nn->gx), s));
+      ConvArgs a = dgrad_args(L, gy, nn->gx);
+      a.part = nn->part;
+      a.part_cap = nn->part_cap;
+      NN_HIP(launch_conv(a, s));
       g = nn->gx;
     }
   }
@@ -403,6 +413,15 @@ mcx_status mcx_nn_create(const int32_t* channels, int32_t nlevels, int32_t nx, i
     NN_TRY(nn_alloc(nn, &nn->bias_partial, static_cast<size_t>(kBiasBlocks) * max_c));
     NN_TRY(nn_alloc(nn, &nn->norm_partial, static_cast<size_t>(kNormBlocks)));
     NN_TRY(nn_alloc(nn, &nn->phimax, 1));
+    for (const Layer& Ly : nn->layers) {
+      nn->part_cap = std::max(nn->part_cap, conv_workspace_floats(
+                                                forward_args(Ly, nullptr, nullptr, nullptr, false,
+                                                             false, nullptr)));
+      nn->part_cap = std::max(nn->part_cap, conv_workspace_floats(dgrad_args(Ly, nullptr, nullptr)));
+      nn->part_cap =
+          std::max(nn->part_cap, wgrad_workspace_floats(wgrad_args(Ly, nullptr, nullptr, nullptr)));
+    }
+    if (nn->part_cap > 0) NN_TRY(nn_alloc(nn, &nn->part, static_cast<size_t>(nn->part_cap)));
     NN_HIP(launch_fill(nn->params, static_cast<int64_t>(nn->nparam), 0.f, nn->stream));
     NN_HIP(launch_fill(nn->adam_m, static_cast<int64_t>(nn->nparam), 0.f, nn->stream));
     NN_HIP(launch_fill(nn->adam_v, static_cast<int64_t>(nn->nparam), 0.f, nn->stream));
@@ -527,12 +546,18 @@ mcx_status mcx_nn_layer_forward(int32_t kind, int32_t nx, int32_t ny, int32_t nz
   describe_layer(L, kind, cin, cout, Grid{nz, ny, nx});
   hipStream_t s = static_cast<hipStream_t>(stream);
   NN_HIP(hipMalloc(&L.fwd, static_cast<size_t>(L.fwd_rows) * L.fwd_kpad * sizeof(uint16_t)));
+  ConvArgs a = forward_args(L, x, b, skip, relu != 0, y_f32 != 0, y);
+  a.part_cap = conv_workspace_floats(a);
+  hipError_t e = hipSuccess;
+  if (a.part_cap > 0) e = hipMalloc(&a.part, static_cast<size_t>(a.part_cap) * sizeof(float));
   mcx_status st = MCX_OK;
-  hipError_t e = launch_pack(w, L.taps, cin, cout, L.fwd_rows, L.fwd_kpad, false, L.fwd, s);
-  if (e == hipSuccess) e = launch_conv(forward_args(L, x, b, skip, relu != 0, y_f32 != 0, y), s);
+  if (e == hipSuccess)
+    e = launch_pack(w, L.taps, cin, cout, L.fwd_rows, L.fwd_kpad, false, L.fwd, s);
+  if (e == hipSuccess) e = launch_conv(a, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) st = nfail(MCX_EDEVICE, "layer forward: %s", hipGetErrorString(e));
   (void)hipFree(L.fwd);
+  if (a.part) (void)hipFree(a.part);
   return st;
 }
 
@@ -549,14 +574,24 @@ mcx_status mcx_nn_layer_backward(int32_t kind, int32_t nx, int32_t ny, int32_t n
   mcx_status st = MCX_OK;
   hipError_t e = launch_fill(gw, static_cast<int64_t>(L.taps) * cin * cout, 0.f, s);
   if (e == hipSuccess && gb) e = launch_fill(gb, cout, 0.f, s);
-  if (e == hipSuccess) e = launch_wgrad(wgrad_args(L, x, gy, gw), s);
+  WgradArgs wa = wgrad_args(L, x, gy, gw);
+  wa.part_cap = wgrad_workspace_floats(wa);
+  if (e == hipSuccess && wa.part_cap > 0)
+    e = hipMalloc(&wa.part, static_cast<size_t>(wa.part_cap) * sizeof(float));
+  if (e == hipSuccess) e = launch_wgrad(wa, s);
   if (e == hipSuccess && gb) e = launch_bias_grad(gy, L.out.vox(), cout, gb, s);
   if (e == hipSuccess && gx)
     e = launch_pack(w, L.taps, cin, cout, L.bwd_rows, L.bwd_kpad, true, L.bwd, s);
-  if (e == hipSuccess && gx) e = launch_conv(dgrad_args(L, gy, gx), s);
+  ConvArgs da = dgrad_args(L, gy, gx);
+  da.part_cap = gx ? conv_workspace_floats(da) : 0;
+  if (e == hipSuccess && da.part_cap > 0)
+    e = hipMalloc(&da.part, static_cast<size_t>(da.part_cap) * sizeof(float));
+  if (e == hipSuccess && gx) e = launch_conv(da, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) st = nfail(MCX_EDEVICE, "layer backward: %s", hipGetErrorString(e));
   (void)hipFree(L.bwd);
+  if (da.part) (void)hipFree(da.part);
+  if (wa.part) (void)hipFree(wa.part);
   return st;
 }
 

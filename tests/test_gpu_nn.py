@@ -67,7 +67,11 @@ CASES = [("conv3", (6, 5, 7), 1, 32), ("conv3", (4, 6, 5), 8, 16), ("conv3", (5,
          ("conv3", (4, 4, 4), 64, 64), ("conv3", (3, 5, 4), 3, 5), ("conv3", (4, 4, 4), 32, 1),
          ("conv3", (2, 2, 2), 256, 256), ("down", (6, 4, 8), 32, 64), ("down", (4, 4, 2), 3, 7),
          ("down", (8, 8, 8), 64, 128), ("up", (3, 2, 4), 64, 32), ("up", (2, 3, 2), 5, 3),
-         ("up", (4, 4, 4), 256, 128)]
+         ("up", (4, 4, 4), 256, 128),
+         # many tiles on ragged grids: weight-gradient partial sums of >= 8
+         # workgroups, and a forward split over input-channel chunks
+         ("conv3", (15, 13, 18), 32, 32), ("conv3", (9, 10, 11), 64, 64),
+         ("conv3", (10, 9, 12), 32, 1)]
 
 
 @pytest.mark.parametrize("kind,shape,ci,co", CASES)
