@@ -196,18 +196,23 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
 }
 
 // ------------------------------------------------- 3x3x3 conv from an LDS brick
-// kConv3 / kConv3T with cin a multiple of 32: a workgroup owns a 4 x 4 x 4
-// tile of output voxels (wave w: the z-slice w, one 16-row MFMA block) and
-// 16 NB output channels.  Per chunk of 32 input channels it stages the 6 x 6
-// x 6 input brick (tile plus halo, zero outside the volume) in LDS once and
-// runs all 27 taps from it -- A fragments read from LDS, B fragments
-// (weights) from global memory one tap ahead -- with no barrier between taps.
+// kConv3 / kConv3T with cin a multiple of 32: a workgroup owns a 4 x 4 x 4MZ
+// tile of output voxels (wave w: the z-slices MZ w .. MZ w + MZ - 1, one
+// 16-row MFMA block each) and 16 NB output channels.  Per chunk of 32 input
+// channels it stages the 6 x 6 x (4MZ + 2) input brick (tile plus halo, zero
+// outside the volume) in LDS once, and per plane of 9 taps the weights of
+// those taps for its channels; every tap then reads its A fragments from
+// the brick and its B fragments from the staged weights, so each weight
+// fragment feeds MZ NB matrix instructions.
 // With gridDim.z = S > 1 the chunks are split into S equal ranges, one per
 // grid z index, and each workgroup stores its raw sums to the workspace
 // part[z][out voxel][cout] for split_reduce_kernel to finish.
-template <int NB>
+template <int NB, int MZ>
 __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
-  __shared__ uint16_t sBr[216][kBK + kPadK];
+  constexpr int BZ = 4 * MZ + 2;
+  constexpr int BV = 36 * BZ;
+  __shared__ uint16_t sBr[BV][kBK + kPadK];
+  __shared__ uint16_t sW[9][16 * NB][kBK + kPadK];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -215,26 +220,24 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
   const int tile = blockIdx.x;
   const int bx = (tile % tx_n) * 4;
   const int by = ((tile / tx_n) % ty_n) * 4;
-  const int bz = (tile / (tx_n * ty_n)) * 4;
+  const int bz = (tile / (tx_n * ty_n)) * (4 * MZ);
   const int n0 = blockIdx.y * 16 * NB;
   const int sgn = a.geo == kConv3 ? 1 : -1;
-  const int r = lane & 15;            // A row of this lane: voxel (r & 3, r >> 2, wave)
-  const int ox = r & 3, oy = r >> 2, oz = wave;
+  const int r = lane & 15;            // A row of this lane: voxel (r & 3, r >> 2) of a slice
+  const int ox = r & 3, oy = r >> 2;
   const int kq = (lane >> 4) * 8;     // this lane's 8 reduction (channel) positions
 
-  floatx4 acc[NB];
+  floatx4 acc[MZ][NB];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  auto load_b = [&](int t, int c0, int j) -> bf16x8 {
-    const uint16_t* p = a.bt + static_cast<int64_t>(n0 + 16 * j + r) * a.kpad + t * a.cin + c0 + kq;
-    return *reinterpret_cast<const bf16x8*>(p);
-  };
+  for (int q = 0; q < MZ; ++q)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[q][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   const int split_len = a.cin / static_cast<int>(gridDim.z);  // a multiple of kBK
   const int c_begin = static_cast<int>(blockIdx.z) * split_len;
   for (int c0 = c_begin; c0 < c_begin + split_len; c0 += kBK) {
-    for (int i = tid; i < 216 * 4; i += 256) {
+    __syncthreads();  // the previous chunk's fragments have been read
+    for (int i = tid; i < BV * 4; i += 256) {
       const int v = i >> 2, cc = (i & 3) * 8;
       const int vx = v % 6, vy = (v / 6) % 6, vz = v / 36;
       const int gx = bx + vx - 1, gy = by + vy - 1, gz = bz + vz - 1;
@@ -244,56 +247,68 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
             a.x + ((static_cast<int64_t>(gz) * a.in_h + gy) * a.in_w + gx) * a.cin + c0 + cc);
       *reinterpret_cast<uint4*>(&sBr[v][cc]) = val;
     }
-    bf16x8 bn[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) bn[j] = load_b(0, c0, j);
-    __syncthreads();
-    for (int t = 0; t < 27; ++t) {
-      bf16x8 bc[NB];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) bc[j] = bn[j];
-      if (t + 1 < 27) {
-#pragma unroll
-        for (int j = 0; j < NB; ++j) bn[j] = load_b(t + 1, c0, j);
+    for (int pz = 0; pz < 3; ++pz) {
+      if (pz > 0) __syncthreads();  // the previous plane's weights have been read
+      // weights of taps 9 pz .. 9 pz + 8: rows n0 .. n0 + 16 NB - 1 of bt (the
+      // packed rows extend to a multiple of 64 >= n0 + 16 NB), 32 columns each
+      for (int i = tid; i < 9 * 16 * NB * 4; i += 256) {
+        const int tt = i / (16 * NB * 4), rem = i % (16 * NB * 4);
+        const int row = rem >> 2, cc = (rem & 3) * 8;
+        *reinterpret_cast<uint4*>(&sW[tt][row][cc]) = *reinterpret_cast<const uint4*>(
+            a.bt + static_cast<int64_t>(n0 + row) * a.kpad + (9 * pz + tt) * a.cin + c0 + cc);
       }
-      const int dz = sgn * (t / 9 - 1), dy = sgn * ((t / 3) % 3 - 1), dx = sgn * (t % 3 - 1);
-      const int v = ((oz + 1 + dz) * 6 + (oy + 1 + dy)) * 6 + (ox + 1 + dx);
-      const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sBr[v][kq]);
+      __syncthreads();
+      const int dz = sgn * (pz - 1);
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bc[j], acc[j], 0, 0, 0);
+      for (int tt = 0; tt < 9; ++tt) {
+        const int dy = sgn * (tt / 3 - 1), dx = sgn * (tt % 3 - 1);
+        bf16x8 bc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          bc[j] = *reinterpret_cast<const bf16x8*>(&sW[tt][16 * j + r][kq]);
+#pragma unroll
+        for (int q = 0; q < MZ; ++q) {
+          const int oz = wave * MZ + q;
+          const int v = ((oz + 1 + dz) * 6 + (oy + 1 + dy)) * 6 + (ox + 1 + dx);
+          const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sBr[v][kq]);
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bc[j], acc[q][j], 0, 0, 0);
+        }
+      }
     }
-    __syncthreads();
   }
 
-  // epilogue: rows 4 (lane >> 4) + e of the wave's slice
+  // epilogue: rows 4 (lane >> 4) + e of each of the wave's slices
   const bool split = gridDim.z > 1;
   float* part = split ? a.part + static_cast<int64_t>(blockIdx.z) * a.d * a.h * a.w * a.cout
                       : nullptr;
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int n = n0 + j * 16 + (lane & 15);
-    if (n >= a.cout) continue;
-    const float bias = a.bias ? a.bias[n] : 0.f;
+  for (int q = 0; q < MZ; ++q)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int rr = (lane >> 4) * 4 + e;
-      const int x = bx + (rr & 3), y = by + (rr >> 2), z = bz + oz;
-      if (x >= a.w || y >= a.h || z >= a.d) continue;
-      const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
-      if (split) {
-        part[o * a.cout + n] = acc[j][e];
-        continue;
+    for (int j = 0; j < NB; ++j) {
+      const int n = n0 + j * 16 + (lane & 15);
+      if (n >= a.cout) continue;
+      const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rr = (lane >> 4) * 4 + e;
+        const int x = bx + (rr & 3), y = by + (rr >> 2), z = bz + wave * MZ + q;
+        if (x >= a.w || y >= a.h || z >= a.d) continue;
+        const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
+        if (split) {
+          part[o * a.cout + n] = acc[q][j][e];
+          continue;
+        }
+        float v = acc[q][j][e] + bias;
+        if (a.skip) v += from_bf16(a.skip[o * a.cout + n]);
+        if (a.relu) v = fmaxf(v, 0.f);
+        if (a.y_f32)
+          static_cast<float*>(a.y)[o * a.cout + n] = v;
+        else
+          static_cast<uint16_t*>(a.y)[o * a.cout + n] = to_bf16(v);
       }
-      float v = acc[j][e] + bias;
-      if (a.skip) v += from_bf16(a.skip[o * a.cout + n]);
-      if (a.relu) v = fmaxf(v, 0.f);
-      if (a.y_f32)
-        static_cast<float*>(a.y)[o * a.cout + n] = v;
-      else
-        static_cast<uint16_t*>(a.y)[o * a.cout + n] = to_bf16(v);
     }
-  }
 }
 
 // Finish a split product: y[o][n] = [relu](sum over splits of part[s][o][n]
@@ -850,6 +865,7 @@ namespace {
 
 constexpr int64_t kSplitTargetGroups = 1024;  // about four workgroups per CU
 constexpr int64_t kSplitBelowGroups = 512;    // split only launches smaller than this
+constexpr int64_t kDeepTileGroups = 1024;     // 4 x 4 x 8 tiles when at least this many
 
 int conv_nb(const ConvArgs& a) { return a.cout > 32 ? 4 : (a.cout > 16 ? 2 : 1); }
 
@@ -857,14 +873,27 @@ bool uses_brick(const ConvArgs& a) {
   return (a.geo == kConv3 || a.geo == kConv3T) && a.cin % kBK == 0;
 }
 
+int64_t brick_tiles(const ConvArgs& a, int mz) {
+  return static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 4 * mz - 1) / (4 * mz));
+}
+
+int64_t brick_ngroups(const ConvArgs& a) {
+  const int nb = conv_nb(a);
+  return (a.cout + 16 * nb - 1) / (16 * nb);
+}
+
+// z-slices per wave: two when the launch keeps at least kDeepTileGroups
+// workgroups with them
+int brick_mz(const ConvArgs& a) {
+  return brick_tiles(a, 2) * brick_ngroups(a) >= kDeepTileGroups ? 2 : 1;
+}
+
 // splits of the brick kernel's input-channel chunks: for launches of fewer
 // than two workgroups per CU, enough to fill the chip, a divisor of the
 // chunk count, within `cap` floats (measured: on 8^3 and 16^3 grids the
 // split runs 6x and 1.8x faster; at 512 workgroups it gains nothing)
 int brick_splits(const ConvArgs& a, int64_t cap) {
-  const int nb = conv_nb(a);
-  const int64_t tiles = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 3) / 4);
-  const int64_t groups = tiles * ((a.cout + 16 * nb - 1) / (16 * nb));
+  const int64_t groups = brick_tiles(a, brick_mz(a)) * brick_ngroups(a);
   if (groups >= kSplitBelowGroups) return 1;
   const int chunks = a.cin / kBK;
   int sp = static_cast<int>(std::min<int64_t>(chunks, (kSplitTargetGroups + groups - 1) / groups));
@@ -885,17 +914,17 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
   const int nb = conv_nb(a);
   if (uses_brick(a)) {
-    const int64_t tiles = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 3) / 4);
+    const int mz = brick_mz(a);
     const int sp = a.part ? brick_splits(a, a.part_cap) : 1;
-    const dim3 grid(static_cast<unsigned>(tiles),
-                    static_cast<unsigned>((a.cout + 16 * nb - 1) / (16 * nb)),
-                    static_cast<unsigned>(sp));
-    if (nb == 4)
-      conv3_brick_kernel<4><<<grid, 256, 0, s>>>(a);
-    else if (nb == 2)
-      conv3_brick_kernel<2><<<grid, 256, 0, s>>>(a);
-    else
-      conv3_brick_kernel<1><<<grid, 256, 0, s>>>(a);
+    const dim3 grid(static_cast<unsigned>(brick_tiles(a, mz)),
+                    static_cast<unsigned>(brick_ngroups(a)), static_cast<unsigned>(sp));
+#define MCX_BRICK(NB)                                                  \
+  if (mz == 2)                                                         \
+    conv3_brick_kernel<NB, 2><<<grid, 256, 0, s>>>(a);                 \
+  else                                                                 \
+    conv3_brick_kernel<NB, 1><<<grid, 256, 0, s>>>(a);
+    if (nb == 4) { MCX_BRICK(4) } else if (nb == 2) { MCX_BRICK(2) } else { MCX_BRICK(1) }
+#undef MCX_BRICK
     if (sp > 1) split_reduce_kernel<<<blocks_for(M * a.cout), 256, 0, s>>>(a, sp);
     return hipGetLastError();
   }
