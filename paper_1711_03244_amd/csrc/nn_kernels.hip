@@ -311,6 +311,79 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
     }
 }
 
+// ------------------------------------------ 3x3x3 conv with one gathered channel
+// kConv3 / kConv3T with cin == 1 (the input layer's forward pass, the output
+// layer's input gradient): the 27 taps are the reduction axis (one MFMA
+// step, taps 27..31 zero).  A workgroup owns a 4 x 4 x 4 tile (wave w: the
+// z-slice w) and 16 NB output channels; the tile's 6 x 6 x 6 input brick is
+// staged in LDS and the B fragments Bt[n][t] are read once from the packed
+// weights (kpad >= 32, zero beyond tap 26).
+template <int NB>
+__global__ void __launch_bounds__(256) conv3_scalar_kernel(ConvArgs a) {
+  __shared__ uint16_t sB[216];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tx_n = (a.w + 3) >> 2, ty_n = (a.h + 3) >> 2;
+  const int tile = blockIdx.x;
+  const int bx = (tile % tx_n) * 4;
+  const int by = ((tile / tx_n) % ty_n) * 4;
+  const int bz = (tile / (tx_n * ty_n)) * 4;
+  const int n0 = blockIdx.y * 16 * NB;
+  const int sgn = a.geo == kConv3 ? 1 : -1;
+  const int r = lane & 15, g = lane >> 4;
+  for (int v = tid; v < 216; v += 256) {
+    const int gx = bx + v % 6 - 1, gy = by + (v / 6) % 6 - 1, gz = bz + v / 36 - 1;
+    uint16_t val = 0;
+    if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.in_w && gy < a.in_h && gz < a.in_d)
+      val = a.x[(static_cast<int64_t>(gz) * a.in_h + gy) * a.in_w + gx];
+    sB[v] = val;
+  }
+  bf16x8 bf[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    bf[j] = *reinterpret_cast<const bf16x8*>(a.bt + static_cast<int64_t>(n0 + 16 * j + r) * a.kpad +
+                                            8 * g);
+  __syncthreads();
+  // A row r = voxel (r & 3, r >> 2, wave) of the tile; k = tap 8 g + j
+  bf16x8 af;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int t = 8 * g + j;
+    uint16_t e = 0;
+    if (t < 27) {
+      const int dz = sgn * (t / 9 - 1), dy = sgn * ((t / 3) % 3 - 1), dx = sgn * (t % 3 - 1);
+      e = sB[((wave + 1 + dz) * 6 + ((r >> 2) + 1 + dy)) * 6 + ((r & 3) + 1 + dx)];
+    }
+    af[j] = __builtin_bit_cast(__bf16, e);
+  }
+  floatx4 acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[j], floatx4{0.f, 0.f, 0.f, 0.f}, 0,
+                                                     0, 0);
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int n = n0 + j * 16 + r;
+    if (n >= a.cout) continue;
+    const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int rr = 4 * g + e;
+      const int x = bx + (rr & 3), y = by + (rr >> 2), z = bz + wave;
+      if (x >= a.w || y >= a.h || z >= a.d) continue;
+      const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
+      float v = acc[j][e] + bias;
+      if (a.skip) v += from_bf16(a.skip[o * a.cout + n]);
+      if (a.relu) v = fmaxf(v, 0.f);
+      if (a.y_f32)
+        static_cast<float*>(a.y)[o * a.cout + n] = v;
+      else
+        static_cast<uint16_t*>(a.y)[o * a.cout + n] = to_bf16(v);
+    }
+  }
+}
+
 // Finish a split product: y[o][n] = [relu](sum over splits of part[s][o][n]
 // + bias[n] [+ skip[o][n]]), splits summed in order.
 __global__ void __launch_bounds__(256) split_reduce_kernel(ConvArgs a, int nsplit) {
@@ -571,6 +644,97 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
     }
 }
 
+// ------------------------------------- 3x3x3 weight gradients with one channel
+// Taps as a matrix axis (27 of 32 used).  kConv3 layers with cin == 1:
+// gw[t][n] = sum_m x[m + d(t)] gy[m][n], rows t, columns n; with cout == 1:
+// gw[t][ci] = sum_m x[m][ci] gy[m - d(t)], rows ci, columns t (the same sum
+// with m shifted; x and gy are zero outside the volume).  A workgroup
+// walks 4 x 4 x 4 tiles blockIdx.x, + gridDim.x, ... and owns 32 columns
+// (cin == 1: output channels 32 blockIdx.z ..) or 32 rows (cout == 1: input
+// channels 32 blockIdx.z ..); wave w computes the 16 x 16 block (w & 1,
+// w >> 1).  Per tile the single-channel side is staged as a 6 x 6 x 6
+// brick and the other side transposed to [channel][voxel]; sums go to
+// part[blockIdx.x][t][ci][n] for wgrad_reduce_kernel.
+template <bool kCin1>
+__global__ void __launch_bounds__(256) wgrad_onechannel_kernel(WgradArgs a) {
+  __shared__ uint16_t sB[216];                 // brick of the one-channel side
+  __shared__ uint16_t sT[32][64 + kPadK];      // [channel][tile voxel] of the other side
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int rb = wave & 1, cb = wave >> 1;     // row block, column block
+  const int c0 = static_cast<int>(blockIdx.z) * 32;  // first channel of the many-channel side
+  const int cmany = kCin1 ? a.cout : a.cin;
+  const int tx_n = (a.w + 3) >> 2, ty_n = (a.h + 3) >> 2, tz_n = (a.d + 3) >> 2;
+  const int tiles = tx_n * ty_n * tz_n;
+  const int sgn = kCin1 ? 1 : -1;  // brick offset of tap t: x at m + d(t), or gy at m - d(t)
+  floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int bx = (tile % tx_n) * 4;
+    const int by = ((tile / tx_n) % ty_n) * 4;
+    const int bz = (tile / (tx_n * ty_n)) * 4;
+    __syncthreads();
+    if (tid < 216) {
+      const int v = tid;
+      const int gx = bx + v % 6 - 1, gy = by + (v / 6) % 6 - 1, gz = bz + v / 36 - 1;
+      uint16_t val = 0;
+      if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.w && gy < a.h && gz < a.d) {
+        const int64_t o = (static_cast<int64_t>(gz) * a.h + gy) * a.w + gx;
+        val = kCin1 ? a.x[o] : a.gy[o];
+      }
+      sB[v] = val;
+    }
+    for (int i = tid; i < 64 * 4; i += 256) {
+      const int m = i >> 2, cc = (i & 3) * 8;
+      const int x = bx + (m & 3), y = by + ((m >> 2) & 3), z = bz + (m >> 4);
+      uint16_t e[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) e[j] = 0;
+      if (x < a.w && y < a.h && z < a.d) {
+        const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
+        const uint16_t* row = (kCin1 ? a.gy : a.x) + o * cmany + c0 + cc;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) e[j] = (c0 + cc + j < cmany) ? row[j] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sT[cc + j][m] = e[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      // voxels m = 32 ks + 8 g + j: x = j & 3, y = 2 (g & 1) + (j >> 2), z = 2 ks + (g >> 1)
+      const int zz = 2 * ks + (g >> 1), y0 = 2 * (g & 1);
+      // brick side: tap t = 16 (kCin1 ? rb : cb) + r at the 8 voxels
+      const int t = 16 * (kCin1 ? rb : cb) + r;
+      bf16x8 br;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        uint16_t e = 0;
+        if (t < 27) {
+          const int dz = sgn * (t / 9 - 1), dy = sgn * ((t / 3) % 3 - 1), dx = sgn * (t % 3 - 1);
+          e = sB[((zz + 1 + dz) * 6 + (y0 + (j >> 2) + 1 + dy)) * 6 + ((j & 3) + 1 + dx)];
+        }
+        br[j] = __builtin_bit_cast(__bf16, e);
+      }
+      // channel side: channel 16 (kCin1 ? cb : rb) + r at the 8 voxels
+      const bf16x8 ch = *reinterpret_cast<const bf16x8*>(
+          &sT[16 * (kCin1 ? cb : rb) + r][32 * ks + 8 * g]);
+      acc = kCin1 ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(br, ch, acc, 0, 0, 0)
+                  : __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, br, acc, 0, 0, 0);
+    }
+  }
+  // lane (r, g) holds D[4 g + i][r] of block (rb, cb)
+  float* out = a.part + static_cast<int64_t>(blockIdx.x) * 27 * a.cin * a.cout;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = 16 * rb + 4 * g + i, col = 16 * cb + r;
+    const int t = kCin1 ? row : col;
+    const int c = c0 + (kCin1 ? col : row);
+    if (t < 27 && c < cmany) out[static_cast<int64_t>(t) * cmany + c] = acc[i];
+  }
+}
+
 // the same for fewer than 8 workgroups: one thread per i
 __global__ void wgrad_reduce_few_kernel(const float* part, int groups, int64_t n, float* gw) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -582,22 +746,24 @@ __global__ void wgrad_reduce_few_kernel(const float* part, int groups, int64_t n
 }
 
 // gw[i] += sum over the workgroups k < groups of part[k][i]: a workgroup
-// takes 32 consecutive i; thread (q, il) sums k = q, q + 8, ... for i =
-// 32 blockIdx.x + il, and the eight sums of each i are added in q order
+// takes E = 256 / KL consecutive i; thread (q, il) sums k = q, q + KL, ...
+// for i = E blockIdx.x + il, and the KL sums of each i are added in q order
+template <int KL>
 __global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* part, int groups,
                                                            int64_t n, float* gw) {
-  __shared__ float sh[8][33];
-  const int il = threadIdx.x & 31, q = threadIdx.x >> 5;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 32 + il;
+  constexpr int E = 256 / KL;
+  __shared__ float sh[KL][E + 1];
+  const int il = threadIdx.x % E, q = threadIdx.x / E;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * E + il;
   float v = 0.f;
   if (i < n)
-    for (int k = q; k < groups; k += 8) v += part[k * n + i];
+    for (int k = q; k < groups; k += KL) v += part[k * n + i];
   sh[q][il] = v;
   __syncthreads();
   if (q == 0 && i < n) {
     float t = sh[0][il];
 #pragma unroll
-    for (int k = 1; k < 8; ++k) t += sh[k][il];
+    for (int k = 1; k < KL; ++k) t += sh[k][il];
     gw[i] += t;
   }
 }
@@ -913,6 +1079,17 @@ int64_t conv_workspace_floats(const ConvArgs& a) {
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
   const int nb = conv_nb(a);
+  if ((a.geo == kConv3 || a.geo == kConv3T) && a.cin == 1) {
+    const dim3 grid(static_cast<unsigned>(brick_tiles(a, 1)),
+                    static_cast<unsigned>(brick_ngroups(a)), 1);
+    if (nb == 4)
+      conv3_scalar_kernel<4><<<grid, 256, 0, s>>>(a);
+    else if (nb == 2)
+      conv3_scalar_kernel<2><<<grid, 256, 0, s>>>(a);
+    else
+      conv3_scalar_kernel<1><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+  }
   if (uses_brick(a)) {
     const int mz = brick_mz(a);
     const int sp = a.part ? brick_splits(a, a.part_cap) : 1;
@@ -946,7 +1123,23 @@ namespace {
 constexpr int64_t kSlabTargetGroups = 512;
 constexpr int64_t kSlabMaxPart = int64_t(8) << 20;  // floats of partial sums at most
 
-bool uses_slab(const WgradArgs& a) { return a.geo == kConv3 && a.cin % kBK == 0; }
+bool uses_onechannel(const WgradArgs& a) {
+  return a.geo == kConv3 && (a.cin == 1 || (a.cout == 1 && a.cin > 1));
+}
+bool uses_slab(const WgradArgs& a) {
+  return a.geo == kConv3 && a.cin % kBK == 0 && !uses_onechannel(a);
+}
+
+// tile groups of the one-channel kernels: about kSlabTargetGroups in all
+int onechannel_groups(const WgradArgs& a, int64_t cap) {
+  const int64_t tiles = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 3) / 4);
+  const int cmany = a.cin == 1 ? a.cout : a.cin;
+  const int64_t other = (cmany + 31) / 32;
+  int64_t G = std::min<int64_t>(tiles, (kSlabTargetGroups + other - 1) / other);
+  const int64_t per = static_cast<int64_t>(a.taps) * a.cin * a.cout;
+  while (G > 1 && G * per > cap) G = (G + 1) / 2;
+  return static_cast<int>(G < 1 ? 1 : G);
+}
 int slab_nbw(const WgradArgs& a) { return a.cout > 32 ? 2 : 1; }
 
 // workgroups along the voxel tiles: about kSlabTargetGroups in all, at most
@@ -963,12 +1156,42 @@ int slab_groups(const WgradArgs& a, int64_t cap) {
 
 }  // namespace
 
+namespace {
+
+// the reduction of G partial sums of n floats into gw
+hipError_t launch_wgrad_reduce(const float* part, int G, int64_t n, float* gw, hipStream_t s) {
+  if (G < 8)
+    wgrad_reduce_few_kernel<<<blocks_for(n), 256, 0, s>>>(part, G, n, gw);
+  else if (G >= 64 && n < 8192)  // fewer than 256 workgroups with 8 lanes per i
+    wgrad_reduce_kernel<32><<<static_cast<unsigned>((n + 7) / 8), 256, 0, s>>>(part, G, n, gw);
+  else
+    wgrad_reduce_kernel<8><<<static_cast<unsigned>((n + 31) / 32), 256, 0, s>>>(part, G, n, gw);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 int64_t wgrad_workspace_floats(const WgradArgs& a) {
+  if (uses_onechannel(a))
+    return onechannel_groups(a, kSlabMaxPart) * static_cast<int64_t>(a.taps) * a.cin * a.cout;
   if (!uses_slab(a)) return 0;
   return slab_groups(a, kSlabMaxPart) * static_cast<int64_t>(a.taps) * a.cin * a.cout;
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
+  if (uses_onechannel(a) && a.part) {
+    const int64_t per = static_cast<int64_t>(a.taps) * a.cin * a.cout;
+    const int G = onechannel_groups(a, a.part_cap);
+    if (static_cast<int64_t>(G) * per <= a.part_cap) {
+      const int cmany = a.cin == 1 ? a.cout : a.cin;
+      const dim3 grid(static_cast<unsigned>(G), 1, static_cast<unsigned>((cmany + 31) / 32));
+      if (a.cin == 1)
+        wgrad_onechannel_kernel<true><<<grid, 256, 0, s>>>(a);
+      else
+        wgrad_onechannel_kernel<false><<<grid, 256, 0, s>>>(a);
+      return launch_wgrad_reduce(a.part, G, per, a.gw, s);
+    }
+  }
   if (uses_slab(a) && a.part) {
     const int64_t per = static_cast<int64_t>(a.taps) * a.cin * a.cout;
     const int G = slab_groups(a, a.part_cap);
@@ -980,12 +1203,7 @@ hipError_t launch_wgrad(const WgradArgs& a, hipStream_t s) {
         wgrad_slab_kernel<2><<<grid, 256, 0, s>>>(a);
       else
         wgrad_slab_kernel<1><<<grid, 256, 0, s>>>(a);
-      if (G < 8)
-        wgrad_reduce_few_kernel<<<blocks_for(per), 256, 0, s>>>(a.part, G, per, a.gw);
-      else
-        wgrad_reduce_kernel<<<static_cast<unsigned>((per + 31) / 32), 256, 0, s>>>(a.part, G, per,
-                                                                                   a.gw);
-      return hipGetLastError();
+      return launch_wgrad_reduce(a.part, G, per, a.gw, s);
     }
   }
   const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;

@@ -71,7 +71,9 @@ CASES = [("conv3", (6, 5, 7), 1, 32), ("conv3", (4, 6, 5), 8, 16), ("conv3", (5,
          # many tiles on ragged grids: weight-gradient partial sums of >= 8
          # workgroups, and a forward split over input-channel chunks
          ("conv3", (15, 13, 18), 32, 32), ("conv3", (9, 10, 11), 64, 64),
-         ("conv3", (10, 9, 12), 32, 1)]
+         ("conv3", (10, 9, 12), 32, 1),
+         # one-channel weight gradients summed over >= 64 workgroups
+         ("conv3", (20, 17, 24), 32, 1), ("conv3", (16, 20, 18), 1, 32)]
 
 
 @pytest.mark.parametrize("kind,shape,ci,co", CASES)
