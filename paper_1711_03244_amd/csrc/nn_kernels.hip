@@ -76,10 +76,11 @@ __device__ __forceinline__ int64_t gather_at(const ConvArgs& a, int z, int y, in
 
 // ------------------------------------------------------------ forward GEMM
 // One workgroup: 64 rows x 16*NB columns; wave w owns rows 16w..16w+15.
-template <int NB, bool kVec>
+// KS reduction steps of 32 are staged per pair of barriers.
+template <int NB, bool kVec, int KS>
 __global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
-  __shared__ uint16_t sA[kBM][kBK + kPadK];
-  __shared__ uint16_t sB[16 * NB][kBK + kPadK];
+  __shared__ uint16_t sA[kBM][KS * kBK + kPadK];
+  __shared__ uint16_t sB[16 * NB][KS * kBK + kPadK];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -145,46 +146,82 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
                       e[4] | (uint32_t(e[5]) << 16), e[6] | (uint32_t(e[7]) << 16));
   };
 
-  // software pipeline: the next step's global loads are in flight while
-  // the matrix cores work on the current step's tiles
-  uint4 va = load_a(0);
-  uint4 vb = has_b ? load_b(0) : make_uint4(0u, 0u, 0u, 0u);
-  for (int k0 = 0; k0 < a.k; k0 += kBK) {
-    *reinterpret_cast<uint4*>(&sA[lr][lc]) = va;
-    if (has_b) *reinterpret_cast<uint4*>(&sB[br][bc]) = vb;
-    __syncthreads();
-    if (k0 + kBK < a.k) {
-      va = load_a(k0 + kBK);
-      if (has_b) vb = load_b(k0 + kBK);
-    }
-    const bf16x8 af = *reinterpret_cast<const bf16x8*>(&sA[wave * 16 + (lane & 15)][(lane >> 4) * 8]);
+  // software pipeline: the next stage's global loads are in flight while
+  // the matrix cores work on the current stage's tiles
+  constexpr int kStage = KS * kBK;
+  // kDown with gridDim.z = S > 1: this workgroup's reduction range (a
+  // multiple of kStage; the last range ends at a.k)
+  int k_begin = 0, k_end = a.k;
+  if (a.geo != kUp && gridDim.z > 1) {
+    const int len = (a.k / static_cast<int>(gridDim.z) + kStage - 1) / kStage * kStage;
+    k_begin = static_cast<int>(blockIdx.z) * len;
+    k_end = min(a.k, k_begin + len);
+  }
+  uint4 va[KS], vb[KS];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const bf16x8 bf = *reinterpret_cast<const bf16x8*>(&sB[j * 16 + (lane & 15)][(lane >> 4) * 8]);
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[j], 0, 0, 0);
+  for (int q = 0; q < KS; ++q) {
+    va[q] = k_begin + q * kBK < k_end ? load_a(k_begin + q * kBK) : make_uint4(0u, 0u, 0u, 0u);
+    vb[q] = has_b && k_begin + q * kBK < k_end ? load_b(k_begin + q * kBK)
+                                               : make_uint4(0u, 0u, 0u, 0u);
+  }
+  for (int k0 = k_begin; k0 < k_end; k0 += kStage) {
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      *reinterpret_cast<uint4*>(&sA[lr][q * kBK + lc]) = va[q];
+      if (has_b) *reinterpret_cast<uint4*>(&sB[br][q * kBK + bc]) = vb[q];
+    }
+    __syncthreads();
+    if (k0 + kStage < k_end) {
+#pragma unroll
+      for (int q = 0; q < KS; ++q) {
+        const int kn = k0 + kStage + q * kBK;
+        va[q] = kn < k_end ? load_a(kn) : make_uint4(0u, 0u, 0u, 0u);
+        if (has_b) vb[q] = kn < k_end ? load_b(kn) : make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      if (k0 + q * kBK >= k_end) break;
+      const bf16x8 af =
+          *reinterpret_cast<const bf16x8*>(&sA[wave * 16 + (lane & 15)][q * kBK + (lane >> 4) * 8]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const bf16x8 bf =
+            *reinterpret_cast<const bf16x8*>(&sB[j * 16 + (lane & 15)][q * kBK + (lane >> 4) * 8]);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[j], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
 
-  // epilogue: bias, skip, ReLU, store
+  // epilogue: bias, skip, ReLU, store; with gridDim.z = S > 1 (kDown only)
+  // the raw sums of this reduction range go to part[z][m][cout] instead
+  const bool split = a.geo != kUp && gridDim.z > 1;
+  float* part = split ? a.part + static_cast<int64_t>(blockIdx.z) * M * a.cout : nullptr;
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int n = n0 + j * 16 + (lane & 15);
-    if (n >= a.cout) continue;
-    const float bias = a.bias ? a.bias[n] : 0.f;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t m = m0 + wave * 16 + (lane >> 4) * 4 + i;
+    if (m >= M) continue;
+    int64_t o = m;
+    if (a.geo == kUp) {
+      // grids hold at most 2^30 voxels: 32-bit arithmetic
+      const uint32_t mm = static_cast<uint32_t>(m);
+      const uint32_t x = mm % static_cast<uint32_t>(a.w);
+      const uint32_t rest = mm / static_cast<uint32_t>(a.w);
+      const uint32_t y = rest % static_cast<uint32_t>(a.h);
+      const uint32_t z = rest / static_cast<uint32_t>(a.h);
+      o = (static_cast<int64_t>(2 * z + (cls >> 2)) * (2 * a.h) + 2 * y + ((cls >> 1) & 1)) *
+              (2 * a.w) + 2 * x + (cls & 1);
+    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t m = m0 + wave * 16 + (lane >> 4) * 4 + i;
-      if (m >= M) continue;
-      int64_t o = m;
-      if (a.geo == kUp) {
-        const int x = static_cast<int>(m % a.w);
-        const int y = static_cast<int>((m / a.w) % a.h);
-        const int z = static_cast<int>(m / (static_cast<int64_t>(a.w) * a.h));
-        o = (static_cast<int64_t>(2 * z + (cls >> 2)) * (2 * a.h) + 2 * y + ((cls >> 1) & 1)) *
-                (2 * a.w) + 2 * x + (cls & 1);
+    for (int j = 0; j < NB; ++j) {
+      const int n = n0 + j * 16 + (lane & 15);
+      if (n >= a.cout) continue;
+      if (split) {
+        part[o * a.cout + n] = acc[j][i];
+        continue;
       }
-      float v = acc[j][i] + bias;
+      float v = acc[j][i] + (a.bias ? a.bias[n] : 0.f);
       if (a.skip) v += from_bf16(a.skip[o * a.cout + n]);
       if (a.relu) v = fmaxf(v, 0.f);
       if (a.y_f32)
@@ -1070,10 +1107,28 @@ int brick_splits(const ConvArgs& a, int64_t cap) {
 
 }  // namespace
 
+// splits of the generic kernel's reduction for kDown products (the other
+// geometries are not split): for launches of fewer than two workgroups per
+// CU, enough to fill the chip, at least one stage of 128 per split, within
+// `cap` floats
+int generic_splits(const ConvArgs& a, int64_t cap) {
+  if (a.geo != kDown || a.cin % 8 != 0) return 1;
+  const int64_t M = static_cast<int64_t>(a.d) * a.h * a.w;
+  const int64_t groups = (M + kBM - 1) / kBM * ((a.cout + 16 * conv_nb(a) - 1) / (16 * conv_nb(a)));
+  if (groups >= kSplitBelowGroups) return 1;
+  int sp = static_cast<int>(std::min<int64_t>(a.k / (4 * kBK), (kSplitTargetGroups + groups - 1) / groups));
+  while (sp > 1 && sp * M * a.cout > cap) --sp;
+  return sp < 1 ? 1 : sp;
+}
+
 int64_t conv_workspace_floats(const ConvArgs& a) {
-  if (!uses_brick(a)) return 0;
+  const int64_t per = static_cast<int64_t>(a.d) * a.h * a.w * a.cout;
+  if (!uses_brick(a)) {
+    const int sp = generic_splits(a, INT64_MAX);
+    return sp > 1 ? sp * per : 0;
+  }
   const int sp = brick_splits(a, INT64_MAX);
-  return sp > 1 ? sp * static_cast<int64_t>(a.d) * a.h * a.w * a.cout : 0;
+  return sp > 1 ? sp * per : 0;
 }
 
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
@@ -1105,16 +1160,22 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
     if (sp > 1) split_reduce_kernel<<<blocks_for(M * a.cout), 256, 0, s>>>(a, sp);
     return hipGetLastError();
   }
+  const int sp = a.part ? generic_splits(a, a.part_cap) : 1;
   const dim3 grid(static_cast<unsigned>((M + kBM - 1) / kBM),
-                  static_cast<unsigned>((a.cout + 16 * nb - 1) / (16 * nb)), a.geo == kUp ? 8 : 1);
+                  static_cast<unsigned>((a.cout + 16 * nb - 1) / (16 * nb)),
+                  a.geo == kUp ? 8 : static_cast<unsigned>(sp));
   const bool vec = a.cin % 8 == 0;
+  const bool deep = a.k >= 4 * kBK;  // four reduction steps per stage
 #define MCX_CONV(NB)                                                   \
-  if (vec)                                                             \
-    conv_kernel<NB, true><<<grid, 256, 0, s>>>(a);                     \
+  if (vec && deep)                                                     \
+    conv_kernel<NB, true, 4><<<grid, 256, 0, s>>>(a);                  \
+  else if (vec)                                                        \
+    conv_kernel<NB, true, 1><<<grid, 256, 0, s>>>(a);                  \
   else                                                                 \
-    conv_kernel<NB, false><<<grid, 256, 0, s>>>(a);
+    conv_kernel<NB, false, 1><<<grid, 256, 0, s>>>(a);
   if (nb == 4) { MCX_CONV(4) } else if (nb == 2) { MCX_CONV(2) } else { MCX_CONV(1) }
 #undef MCX_CONV
+  if (sp > 1) split_reduce_kernel<<<blocks_for(M * a.cout), 256, 0, s>>>(a, sp);
   return hipGetLastError();
 }
 
