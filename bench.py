@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-denoise", action="store_true")
     ap.add_argument("--dn-train", type=int, default=64, help="denoiser training volumes")
-    ap.add_argument("--dn-steps", type=int, default=12000, help="denoiser training steps")
+    ap.add_argument("--dn-steps", type=int, default=20000, help="denoiser training steps")
     ap.add_argument("--dn-batch", type=int, default=4, help="volumes per training step")
     ap.add_argument("--dn-clip", type=float, default=0.1, help="gradient-norm clip")
     ap.add_argument("--dn-target", type=float, default=1e8, help="target photons per volume")

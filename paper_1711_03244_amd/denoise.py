@@ -317,7 +317,7 @@ def summarise(rows, plain_photons, input_photons, batched=None) -> dict:
 def main(argv=None) -> dict:
     """Command line: simulate a training set, train, evaluate; prints JSON.
 
-        python -m paper_1711_03244_amd.denoise [--train 64] [--steps 12000]
+        python -m paper_1711_03244_amd.denoise [--train 64] [--steps 20000]
             [--side 64] [--inputs 1e5,1e6,1e7] [--target 1e8] [--eval 2]
             [--plain 1e9] [--ref-runs 2] [--lr 1e-3] [--batch 4] [--max-norm 0.1]
             [--augment 1] [--batch-volumes 32]
@@ -328,7 +328,7 @@ def main(argv=None) -> dict:
 
     ap = argparse.ArgumentParser(prog="python -m paper_1711_03244_amd.denoise")
     ap.add_argument("--train", type=int, default=64)
-    ap.add_argument("--steps", type=int, default=12000)
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--side", type=int, default=64)
     ap.add_argument("--inputs", default="1e5,1e6,1e7")
     ap.add_argument("--target", type=float, default=1e8)
