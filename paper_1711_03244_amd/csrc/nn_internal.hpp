@@ -74,6 +74,26 @@ hipError_t launch_from_log(const float* r, const float* u, int64_t n, float* out
 constexpr int kBiasBlocks = 2048;
 hipError_t launch_relu_grad(const float* g, const uint16_t* skip16, const uint16_t* y16, int64_t n,
                             int cout, uint16_t* g16, float* gb, float* partial, hipStream_t s);
+// The same with the bias sums deferred: when relu_grad_defers(cout), the
+// per-block channel sums go to partial[relu_grad_blocks(n)][cout] and a
+// later launch_bias_sums adds them to the gradients; otherwise the bias
+// gradient is added at once, as launch_relu_grad does.
+bool relu_grad_defers(int cout);
+int relu_grad_blocks(int64_t n);
+hipError_t launch_relu_grad_deferred(const float* g, const uint16_t* skip16, const uint16_t* y16,
+                                     int64_t n, int cout, uint16_t* g16, float* gb, float* partial,
+                                     hipStream_t s);
+// One deferred bias sum: grads[gb_off + c] += sum over b < blocks of
+// partial[partial_off + b * cout + c], c < cout.
+struct BiasJob {
+  int64_t partial_off;
+  int64_t gb_off;
+  int32_t blocks;
+  int32_t cout;
+};
+// all jobs (a device array) in one launch; channels = sum of their couts
+hipError_t launch_bias_sums(const BiasJob* jobs, int njobs, int channels, const float* partial,
+                            float* grads, hipStream_t s);
 // masked MSE in u space; target voxels with phi >= rel_floor * max(phi)
 // count; grad = 2 (out - t) / count there.  acc[0] = sum of squares,
 // acc[1] = count (FP64); phi_max: one float of scratch

@@ -926,6 +926,24 @@ __global__ void __launch_bounds__(256) bias_sum_kernel(const float* partial, int
   if (threadIdx.x == 0) gb[c] += sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// the bias_sum_kernel sums of several layers in one launch: workgroup x
+// takes channel x of the concatenated channels of `jobs`
+__global__ void __launch_bounds__(256) bias_sums_kernel(const BiasJob* jobs, int njobs,
+                                                        const float* partial, float* grads) {
+  __shared__ float sh[4];
+  int c = blockIdx.x, j = 0;
+  while (j + 1 < njobs && c >= jobs[j].cout) c -= jobs[j++].cout;
+  const BiasJob J = jobs[j];
+  const float* p = partial + J.partial_off;
+  float t = 0.f;
+  for (int b = threadIdx.x; b < J.blocks; b += blockDim.x)
+    t += p[static_cast<int64_t>(b) * J.cout + c];
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) grads[J.gb_off + c] += sh[0] + sh[1] + sh[2] + sh[3];
+}
+
 // block-wide sum of one double per thread (256 threads), returned to thread 0
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -1347,6 +1365,25 @@ hipError_t launch_relu_grad(const float* g, const uint16_t* skip16, const uint16
     return hipGetLastError();
   }
   if (gb) return launch_bias_grad(g16, n / cout, cout, gb, s);
+  return hipGetLastError();
+}
+
+bool relu_grad_defers(int cout) { return cout <= 256 && 256 % cout == 0; }
+
+int relu_grad_blocks(int64_t n) { return blocks_for(n, 256, kBiasBlocks); }
+
+hipError_t launch_relu_grad_deferred(const float* g, const uint16_t* skip16, const uint16_t* y16,
+                                     int64_t n, int cout, uint16_t* g16, float* gb, float* partial,
+                                     hipStream_t s) {
+  if (!relu_grad_defers(cout)) return launch_relu_grad(g, skip16, y16, n, cout, g16, gb, nullptr, s);
+  relu_grad_kernel<<<relu_grad_blocks(n), 256, 0, s>>>(g, skip16, y16, n, cout, g16, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_sums(const BiasJob* jobs, int njobs, int channels, const float* partial,
+                            float* grads, hipStream_t s) {
+  if (njobs > 0 && channels > 0)
+    bias_sums_kernel<<<channels, 256, 0, s>>>(jobs, njobs, partial, grads);
   return hipGetLastError();
 }
 

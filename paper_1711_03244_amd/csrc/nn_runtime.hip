@@ -225,7 +225,10 @@ struct mcx_nn {
   std::vector<uint16_t*> skip_grad;  // per level 0..L-2
   double* acc = nullptr;
   float* phimax = nullptr;
-  float* bias_partial = nullptr;  // per-block channel sums of the bias gradients
+  float* bias_partial = nullptr;  // per-block channel sums of the bias gradients, per layer
+  std::vector<int64_t> bias_off;  // each layer's region of bias_partial
+  BiasJob* bias_jobs = nullptr;   // device table of the deferred bias sums
+  int nbias_jobs = 0, bias_channels = 0;
   double* norm_partial = nullptr; // per-block sums of squares of the gradients
   float* part = nullptr;          // split-reduction workspace of the convolutions
   int64_t part_cap = 0;           // its size in floats
@@ -307,8 +310,8 @@ mcx_status run_backward(mcx_nn* nn, bool accumulate, hipStream_t s) {
     if (L.kind == MCX_NN_UP) gy = nn->skip_grad[L.up_level];  // also the skip's gradient
     const uint16_t* skip = (L.skip_level >= 0 && L.skip_level < nn->L - 1)
                                ? nn->skip_grad[L.skip_level] : nullptr;
-    NN_HIP(launch_relu_grad(g, skip, i == last ? nullptr : L.act, nout, L.cout, gy,
-                            nn->grads + L.boff, nn->bias_partial, s));
+    NN_HIP(launch_relu_grad_deferred(g, skip, i == last ? nullptr : L.act, nout, L.cout, gy,
+                                     nn->grads + L.boff, nn->bias_partial + nn->bias_off[i], s));
     WgradArgs wa = wgrad_args(L, layer_input(nn, i), gy, nn->grads + L.woff);
     wa.part = nn->part;
     wa.part_cap = nn->part_cap;
@@ -321,6 +324,9 @@ mcx_status run_backward(mcx_nn* nn, bool accumulate, hipStream_t s) {
       g = nn->gx;
     }
   }
+  // the bias gradients of every layer whose sums were deferred, in one launch
+  NN_HIP(launch_bias_sums(nn->bias_jobs, nn->nbias_jobs, nn->bias_channels, nn->bias_partial,
+                          nn->grads, s));
   return MCX_OK;
 }
 
@@ -408,9 +414,22 @@ mcx_status mcx_nn_create(const int32_t* channels, int32_t nlevels, int32_t nx, i
     for (int l = 0; l + 1 < L; ++l)
       NN_TRY(nn_alloc(nn, &nn->skip_grad[l], static_cast<size_t>(level(l).vox() * c[l])));
     NN_TRY(nn_alloc(nn, &nn->acc, 2));
-    int max_c = 1;
-    for (const Layer& Ly : nn->layers) max_c = std::max(max_c, Ly.cout);
-    NN_TRY(nn_alloc(nn, &nn->bias_partial, static_cast<size_t>(kBiasBlocks) * max_c));
+    std::vector<BiasJob> jobs;
+    int64_t bias_floats = 0;
+    for (const Layer& Ly : nn->layers) {
+      nn->bias_off.push_back(bias_floats);
+      if (!relu_grad_defers(Ly.cout)) continue;
+      const int blocks = relu_grad_blocks(Ly.out.vox() * Ly.cout);
+      jobs.push_back(BiasJob{bias_floats, static_cast<int64_t>(Ly.boff), blocks, Ly.cout});
+      bias_floats += static_cast<int64_t>(blocks) * Ly.cout;
+      nn->bias_channels += Ly.cout;
+    }
+    NN_TRY(nn_alloc(nn, &nn->bias_partial, static_cast<size_t>(std::max<int64_t>(bias_floats, 1))));
+    nn->nbias_jobs = static_cast<int>(jobs.size());
+    NN_TRY(nn_alloc(nn, &nn->bias_jobs, jobs.size()));
+    if (!jobs.empty())
+      NN_HIP(hipMemcpy(nn->bias_jobs, jobs.data(), jobs.size() * sizeof(BiasJob),
+                       hipMemcpyHostToDevice));
     NN_TRY(nn_alloc(nn, &nn->norm_partial, static_cast<size_t>(kNormBlocks)));
     NN_TRY(nn_alloc(nn, &nn->phimax, 1));
     for (const Layer& Ly : nn->layers) {
