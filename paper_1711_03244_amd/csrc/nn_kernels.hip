@@ -19,6 +19,15 @@
 // The down layer's input gradient is a kUp product and the up layer's a
 // kDown product, each with transposed weights.
 //
+// Kernels: conv_kernel is the generic implicit GEMM (every geometry);
+// 3x3x3 products get dedicated kernels that stage operands in LDS --
+// conv3_brick_kernel (a multiple of 32 gathered channels), conv3_scalar_kernel
+// (one gathered channel), wgrad_slab_kernel and wgrad_onechannel_kernel
+// (weight gradients) -- and wgrad_kernel covers the remaining weight
+// gradients.  Products that launch too few workgroups split their
+// reduction and finish in split_reduce_kernel / wgrad_reduce_kernel, which
+// add FP32 partial sums in a fixed order.
+//
 // MFMA v_mfma_f32_16x16x32_bf16: lane l supplies A[l % 16][8(l / 16) + j]
 // and B[8(l / 16) + j][l % 16] (j = 0..7) and receives
 // D[4(l / 16) + i][l % 16] (i = 0..3).
