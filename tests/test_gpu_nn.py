@@ -327,9 +327,16 @@ def test_denoiser_gain_on_held_out_volumes():
         before = mean_loss()
         denoise.train(d, ds, 500, lr=1e-3, log_every=100, batch=4, max_norm=0.1, say=print)
         after = mean_loss()
-        ev = denoise.evaluate(d, [700001, 700002, 700003], side, 1e7, 2, [5e4, 5e5], say=print)
+        ev = denoise.evaluate(d, [700001, 700002, 700003], side, 1e7, 2, [5e4, 5e5], say=print,
+                              batch_seeds=[710001, 710002, 710003, 710004])
     print("mean training loss", before, "->", after, ev, flush=True)
     assert after < 0.5 * before
+    # batched timing: per-volume times of a shared launch, a fitted model, a ratio per input
+    b = ev["batched"]
+    assert len(b["per_volume_ms"]) == 3 and all(t > 0 for _, t in b["per_volume_ms"])
+    assert b["time_model"]["ms_per_photon"] > 0
+    assert all(r["batched_time_ratio"] is None or r["batched_time_ratio"] > 0
+               for r in ev["per_input"])
     # at the lowest input count the noise is far above the targets' (1e7
     # photons): there the network must remove a large part of it
     low = ev["per_input"][0]

@@ -485,3 +485,27 @@ def test_gates_with_nonzero_start_time():
     assert g["raw"].sum() > 0 and g["stats"]["timeout"] == o["counts"]["timeout"] == N
     # and the same gate of every cell holds the weight
     assert np.array_equal(g["raw"] > 0, o["tally"] > 0)
+
+
+def test_zero_photon_run_then_a_real_one():
+    """A run of no photons launches nothing, leaves the map and ledger
+    empty and cannot be normalised; the context then runs normally and
+    matches a fresh context photon for photon."""
+    p = W.cube_homogeneous(n=16).replace(src_pos=(7.5, 7.5, 0.0))
+    say("[gpu] zero-photon run, then 2000 photons")
+    with mcx.Simulation(p, ndigest=2000) as sim:
+        sim.run(0, 1)
+        st = sim.stats()
+        assert st["launched"] == 0 and st["events"] == 0 and st["absorbed_grid"] == 0.0
+        assert not np.any(sim.fluence(mcx.MCX_RAW, f64=True))
+        with pytest.raises(mcx.McxError) as e:
+            sim.fluence(mcx.MCX_FLUENCE)
+        assert e.value.status == mcx.MCX_ESTATE
+        sim.run(2000, 3)
+        raw = sim.fluence(mcx.MCX_RAW, f64=True)
+        dig = sim.digest()
+    with mcx.Simulation(p, ndigest=2000) as fresh:
+        fresh.run(2000, 3)
+        assert np.array_equal(fresh.digest(), dig)
+        big = raw > 1e-9 * raw.max()
+        assert np.allclose(fresh.fluence(mcx.MCX_RAW, f64=True)[big], raw[big], rtol=1e-9)
