@@ -3,7 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--photons N]
                     [--launch BLOCK,CHUNK,WINDOW] [--head-launch BLOCK,CHUNK,WINDOW]
                     [--no-cpu-baseline] [--head-photons M] [--no-head] [--no-batch]
-                    [--no-denoise]
+                    [--no-denoise] [--no-scaling]
 
 Workload: the paper's heterogeneous cube benchmark as configured here -- a
 60 x 60 x 60 grid of 1 mm voxels, background mua 0.005/mm, mus 1.0/mm,
@@ -28,6 +28,8 @@ timed once after a warm-up launch: `head_volume` (the seeded 181 x 217 x
 each, 5.4e8 photons in one launch, with the fixed launch shape -- 64-thread
 workgroups, one photon per lane per job, direct atomics -- and with the
 shape the autotuner picks from pilot launches of 1/50 of the photons).
+`photon_scaling` runs the sphere benchmark at 1e6 .. 1e9 photons and fits
+the paper's device model T = a n + T0.
 `denoiser` trains the 3-D U-Net on simulator pairs of 64^3 volumes (inputs
 at 1e5, 1e6 and 1e7 photons, targets at 1e8) and reports, on held-out
 volumes, the error of the denoised and the plain maps against a reference
@@ -64,6 +66,7 @@ def main():
     ap.add_argument("--no-head", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-denoise", action="store_true")
+    ap.add_argument("--no-scaling", action="store_true")
     ap.add_argument("--dn-train", type=int, default=64, help="denoiser training volumes")
     ap.add_argument("--dn-steps", type=int, default=20000, help="denoiser training steps")
     ap.add_argument("--dn-batch", type=int, default=4, help="volumes per training step")
@@ -135,6 +138,7 @@ def main():
     roof = roofline.valu_roofline(last, ksec)
     roof["traffic"] = roofline.measured_traffic(N, tune["lds_window_cells"])
     atom = roofline.atomic_roofline(last, ksec)
+    scaling = None if args.no_scaling else scaling_leg(sim, args.seed)
     sim.close()
 
     cube1 = None if args.no_head else cube1_leg(mcx, W)
@@ -182,12 +186,32 @@ def main():
         "atomic_roofline": atom,
         "cpu_baseline": cpu,
         "cpu_single_thread": cpu1,
+        "photon_scaling": scaling,
         "homogeneous_cube": cube1,
         "head_volume": head,
         "batched": batched,
         "denoiser": denoised,
     }
     print(json.dumps(line), flush=True)
+
+
+def scaling_leg(sim, seed):
+    """The sphere benchmark at 1e6 .. 1e9 photons with the timed steps'
+    launch shape: run time (clear + transport + reductions, HIP events)
+    against photons, and the paper's device model T = a n + T0 fitted to
+    it (the study of its Fig. 3(b))."""
+    import numpy as np
+    counts = [1_000_000, 10_000_000, 100_000_000, 1_000_000_000]
+    kernel, run = [], []
+    for n in counts:
+        sim.run(n, seed + 5000)
+        st = sim.stats()
+        kernel.append(st["kernel_ms"])
+        run.append(st["run_ms"])
+    a, t0 = np.polyfit(np.array(counts, float), np.array(run), 1)
+    return {"photons": counts, "kernel_ms": kernel, "run_ms": run,
+            "photons_per_ms": [n / t for n, t in zip(counts, run)],
+            "model": {"ms_per_photon": float(a), "overhead_ms": float(t0)}}
 
 
 def best_median(mcx, sim, N, seeds):
