@@ -109,7 +109,7 @@ typedef struct {
   uint64_t ndigest;       /* per-photon digest rows kept for photons [first, first+ndigest) */
   int32_t lds_window_cells; /* cells around the source summed per workgroup in LDS before they
                                reach the map; 0 = library default (8192), < 0 = none,
-                               at most 16384 (128 KB) */
+                               at most 18432 (144 KB) */
   int32_t accurate_math;  /* 0: hardware transcendentals (~1 ulp); 1: device math library */
 } mcx_options;
 
@@ -209,7 +209,7 @@ mcx_status mcx_batch_digest(mcx_ctx *ctx, int32_t sim, double *host_out, uint64_
 
 /* Launch shape: threads per workgroup (0 = the size that keeps the most waves
  * resident), photons per job (0 = default 256), LDS window cells (0 = default
- * 8192, < 0 = none, at most 16384; in a batch each workgroup keeps the window
+ * 8192, < 0 = none, at most 18432; in a batch each workgroup keeps the window
  * of the simulation its first wave starts on).  Waits for the stream. */
 mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk,
                           int32_t lds_window_cells);
@@ -217,7 +217,7 @@ mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk
 /* Autotuner: times pilot launches of pilot_photons[i] photons (seed[i]) per
  * simulation over block sizes {64, 256, 448, 512, 768, 1024} x jobs of {64,
  * 256, 1024} photons (1 to 16 photons per lane) x deposit schemes {direct
- * global atomics, LDS window of 4096, 8192 or 16384 cells} (shapes that do
+ * global atomics, LDS window of 4096, 8192, 16384 or 18432 cells} (shapes that do
  * not fit on a compute unit are skipped), keeps the fastest shape, and fits
  * the linear device runtime model T = a n + T0 of the paper's device-level
  * load balancing (the study of Fig. 3(b)) from pilots of n and n/2 photons.

@@ -26,7 +26,7 @@ namespace {
 constexpr double kCmmPerNs = 299.792458;  // speed of light in vacuum, mm/ns
 constexpr int kDefaultChunk = 256;
 constexpr int kDefaultWindow = 8192;       // FP64 cells, 64 KB of LDS
-constexpr int kMaxWindow = 16384;          // 128 KB of the 160 KB of LDS per CU
+constexpr int kMaxWindow = 18432;          // 144 KB of the 160 KB of LDS per CU
 constexpr uint64_t kMaxLaunchPhotons = 1ull << 31;  // per simulation and launch
 
 thread_local std::string g_error;
@@ -224,7 +224,7 @@ static mcx_status validate_options(const mcx_options* o) {
   if (o->max_events == 0 || o->max_events > 0xffffffffull)
     return fail(MCX_EINVAL, "max_events must be in [1, 2^32-1]");
   if (o->lds_window_cells > kMaxWindow)
-    return fail(MCX_EINVAL, "lds_window_cells must be <= %d (128 KB of LDS)", kMaxWindow);
+    return fail(MCX_EINVAL, "lds_window_cells must be <= %d (144 KB of LDS)", kMaxWindow);
   return MCX_OK;
 }
 
@@ -952,8 +952,8 @@ mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_
   memset(out, 0, sizeof(*out));
   const int blocks[] = {64, 256, 448, 512, 768, 1024};
   const int chunks[] = {64, 256, 1024};
-  const int windows[] = {-1, 4096, 8192, 16384};
-  const int nwin = 4;
+  const int windows[] = {-1, 4096, 8192, 16384, kMaxWindow};
+  const int nwin = 5;
   // the untuned default shape first (after one warm-up launch)
   MCX_TRY(mcx_set_launch(c, 0, 0, 0));
   float ms = 0.f;

@@ -84,10 +84,11 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(photons: int, lds_window_cells: int):
     """HBM-side bytes per transport launch from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE counters, scaled by the copy-kernel calibration
-    and by photons; None when the counters were taken on other kernel source
-    or with another LDS window (the window decides how many deposits reach
-    memory as atomics)."""
+    FETCH_SIZE / WRITE_SIZE counters (one entry per LDS window size they
+    were taken with), scaled by the copy-kernel calibration and by photons;
+    None when the counters were taken on other kernel source or no entry
+    has this LDS window (the window decides how many deposits reach memory
+    as atomics)."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -95,8 +96,9 @@ def measured_traffic(photons: int, lds_window_cells: int):
         return None
     if c.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    if c.get("launch", {}).get("lds_window_cells") != lds_window_cells:
+    e = c.get("by_window", {}).get(str(lds_window_cells))
+    if e is None or e["launch"]["lds_window_cells"] != lds_window_cells:
         return None
-    per_photon = (c["fetch_kib"] * c["fetch_factor"] + c["write_kib"] * c["write_factor"]) * 1024.0 \
+    per_photon = (e["fetch_kib"] * c["fetch_factor"] + e["write_kib"] * c["write_factor"]) * 1024.0 \
         / c["photons"]
     return per_photon * photons

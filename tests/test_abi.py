@@ -107,7 +107,7 @@ def test_bad_detector_rejected():
 def test_bad_launch_options_rejected():
     p = W.cube_homogeneous(n=8).replace(src_pos=(3.5, 3.5, 0.0))
     for kw in [dict(block_size=100), dict(block_size=2048), dict(refill_chunk=5),
-               dict(max_events=0)]:
+               dict(max_events=0), dict(lds_window_cells=18433)]:
         with pytest.raises(mcx.McxError) as e:
             mcx.mcx_create(p, **kw)
         assert e.value.status == mcx.MCX_EINVAL
