@@ -20,7 +20,7 @@ Prints one JSON line.  `roofline` is the transport kernel's algorithmic VALU
 work over its HIP-event time; `atomic_roofline` its memory-side atomic rate;
 `cpu_baseline` the FP64 oracle on the host cores over a prefix of the same
 photons.  The launch shape of the timed steps is the one the library's
-autotuner picks (before the timed region) from pilot launches of 1/50 of the
+autotuner picks (before the timed region) from pilot launches of 1/20 of the
 photons; the rate of the default shape is reported beside it.  Two further workloads are reported beside the main one, each
 timed once after a warm-up launch: `head_volume` (the seeded 181 x 217 x
 181 layered head phantom, 10 gates of 0.5 ns, 1e8 photons) and `batched`
@@ -104,13 +104,14 @@ def main():
         chosen_by = "--launch"
     else:
         # the library's default launch shape, for context, then the shape the
-        # autotuner picks from pilot launches of N/50 photons (kept for the steps)
+        # autotuner picks from pilot launches of N/20 photons (kept for the
+        # steps; shorter pilots overweight the end-of-launch window flush)
         sim.run(N // 100, args.seed + 2000)
         sim.run(N, args.seed + 2001)
         default_rate = N / sim.stats()["kernel_ms"]
         t_tune = time.perf_counter()
-        tune = sim.autotune(max(1000, N // 50), args.seed + 3000)
-        chosen_by = (f"autotuner, {tune['candidates']} shapes, pilots of {N // 50} photons, "
+        tune = sim.autotune(max(1000, N // 20), args.seed + 3000)
+        chosen_by = (f"autotuner, {tune['candidates']} shapes, pilots of {N // 20} photons, "
                      f"{time.perf_counter() - t_tune:.1f} s before the timed steps")
 
     def step(i):

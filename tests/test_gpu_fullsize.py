@@ -1,6 +1,6 @@
 """The benchmark workloads at full size (1e8 photons), in the launch
 configuration bench.py times (the shape the autotuner picks from pilots of
-1/50 of the photons, no digests).
+1/20 of the photons, no digests).
 
 At this size the oracle cannot follow every photon, so the checks are
 properties that hold at any size -- every photon launched and terminated
@@ -41,7 +41,7 @@ def energy_residual(st):
 def whole_and_split(p, N, seed, tune=False):
     with mcx.Simulation(p) as sim:
         if tune:
-            t = sim.autotune(max(1000, N // 50), seed + 3000)
+            t = sim.autotune(max(1000, N // 20), seed + 3000)
             say("autotuned shape: block", t["block_size"], "chunk", t["refill_chunk"],
                 "window", t["lds_window_cells"])
         sim.run(N, seed)
