@@ -76,6 +76,15 @@ mcx_status mcx_nn_set_params(mcx_nn *nn, const float *host, uint64_t n);
 mcx_status mcx_nn_get_params(mcx_nn *nn, float *host, uint64_t n);
 mcx_status mcx_nn_get_grads(mcx_nn *nn, float *host, uint64_t n);
 
+/* Adam's state, for checkpoints: first and second moments (host arrays of
+ * mcx_nn_param_count floats each, in parameter order) and the step count
+ * (the next step uses step + 1 in its bias corrections).  Set it after
+ * mcx_nn_set_params, which clears it.  MCX_ERANGE when n differs from
+ * mcx_nn_param_count, MCX_EINVAL for a NULL array or a negative step.
+ * Blocking. */
+mcx_status mcx_nn_get_adam(mcx_nn *nn, float *m, float *v, uint64_t n, int32_t *step);
+mcx_status mcx_nn_set_adam(mcx_nn *nn, const float *m, const float *v, uint64_t n, int32_t step);
+
 /* Denoise phi_in into phi_out (fluence, may be NULL) and/or u_out (the
  * network output in u space, may be NULL).  Async. */
 mcx_status mcx_nn_forward(mcx_nn *nn, const float *phi_in, float *phi_out, float *u_out,

@@ -493,6 +493,23 @@ mcx_status mcx_nn_get_grads(mcx_nn* nn, float* host, uint64_t n) {
   return copy_params(nn, nn ? nn->grads : nullptr, host, n, false);
 }
 
+mcx_status mcx_nn_get_adam(mcx_nn* nn, float* m, float* v, uint64_t n, int32_t* step) {
+  if (!m || !v || !step) return nfail(MCX_EINVAL, "m, v and step are required");
+  NN_TRY(copy_params(nn, nn ? nn->adam_m : nullptr, m, n, false));
+  NN_TRY(copy_params(nn, nn->adam_v, v, n, false));
+  *step = nn->step;
+  return MCX_OK;
+}
+
+mcx_status mcx_nn_set_adam(mcx_nn* nn, const float* m, const float* v, uint64_t n, int32_t step) {
+  if (!m || !v) return nfail(MCX_EINVAL, "m and v are required");
+  if (step < 0) return nfail(MCX_EINVAL, "step must be >= 0");
+  NN_TRY(copy_params(nn, nn ? nn->adam_m : nullptr, const_cast<float*>(m), n, true));
+  NN_TRY(copy_params(nn, nn->adam_v, const_cast<float*>(v), n, true));
+  nn->step = step;
+  return MCX_OK;
+}
+
 mcx_status mcx_nn_forward(mcx_nn* nn, const float* phi_in, float* phi_out, float* u_out,
                           void* stream) {
   if (!nn || !phi_in) return nfail(MCX_EINVAL, "network and input are required");

@@ -14,7 +14,8 @@ import numpy as np
 from . import mcx
 
 EXPORTS = ["mcx_nn_create", "mcx_nn_destroy", "mcx_nn_param_count", "mcx_nn_set_params",
-           "mcx_nn_get_params", "mcx_nn_get_grads", "mcx_nn_forward", "mcx_nn_loss_grad",
+           "mcx_nn_get_params", "mcx_nn_get_grads", "mcx_nn_get_adam", "mcx_nn_set_adam",
+           "mcx_nn_forward", "mcx_nn_loss_grad",
            "mcx_nn_adam", "mcx_nn_train_step", "mcx_nn_mirror_xy", "mcx_nn_layer_forward",
            "mcx_nn_layer_backward"]
 
@@ -35,6 +36,8 @@ def lib() -> C.CDLL:
             "mcx_nn_set_params": (C.c_int, [vp, vp, u64]),
             "mcx_nn_get_params": (C.c_int, [vp, vp, u64]),
             "mcx_nn_get_grads": (C.c_int, [vp, vp, u64]),
+            "mcx_nn_get_adam": (C.c_int, [vp, vp, vp, u64, C.POINTER(i32)]),
+            "mcx_nn_set_adam": (C.c_int, [vp, vp, vp, u64, i32]),
             "mcx_nn_forward": (C.c_int, [vp, vp, vp, vp, vp]),
             "mcx_nn_loss_grad": (C.c_int, [vp, vp, vp, i32, C.POINTER(C.c_double), vp]),
             "mcx_nn_adam": (C.c_int, [vp, f32, f32, f32, vp]),
@@ -101,6 +104,21 @@ def mcx_nn_get_grads(h) -> np.ndarray:
     out = np.empty(mcx_nn_param_count(h), np.float32)
     mcx._check(lib().mcx_nn_get_grads(h, out.ctypes.data, out.size))
     return out
+
+
+def mcx_nn_get_adam(h):
+    """(m, v, step): Adam's moments as numpy float32 arrays and its step count."""
+    n = mcx_nn_param_count(h)
+    m, v, step = np.empty(n, np.float32), np.empty(n, np.float32), C.c_int32()
+    mcx._check(lib().mcx_nn_get_adam(h, m.ctypes.data, v.ctypes.data, n, C.byref(step)))
+    return m, v, int(step.value)
+
+
+def mcx_nn_set_adam(h, m, v, step: int):
+    m = np.ascontiguousarray(m, np.float32)
+    v = np.ascontiguousarray(v, np.float32)
+    mcx._check(lib().mcx_nn_set_adam(h, m.ctypes.data, v.ctypes.data, m.size if m.size == v.size
+                                     else -1, int(step)))
 
 
 def mcx_nn_forward(h, phi_in, phi_out=None, u_out=None, stream=None):
@@ -176,6 +194,23 @@ class Denoiser:
 
     def grads(self) -> np.ndarray:
         return mcx_nn_get_grads(self.h)
+
+    def save(self, path):
+        """Checkpoint: parameters, Adam's moments and step count, channels and
+        volume shape, as a numpy .npz archive."""
+        m, v, step = mcx_nn_get_adam(self.h)
+        np.savez(path, params=self.params(), adam_m=m, adam_v=v, step=np.int64(step),
+                 channels=np.array(self.channels, np.int64), shape=np.array(self.shape, np.int64))
+
+    def load(self, path):
+        """Restore a checkpoint written by save() for the same channels and
+        shape (read without unpickling)."""
+        with np.load(path, allow_pickle=False) as z:
+            if tuple(z["channels"]) != self.channels or tuple(z["shape"]) != self.shape:
+                raise ValueError(f"checkpoint is for channels {tuple(z['channels'])} and shape "
+                                 f"{tuple(z['shape'])}, not {self.channels} and {self.shape}")
+            self.set_params(z["params"])
+            mcx_nn_set_adam(self.h, z["adam_m"], z["adam_v"], int(z["step"]))
 
     def _vol(self, t):
         _check_volume(t, int(np.prod(self.shape)))

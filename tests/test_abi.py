@@ -154,6 +154,11 @@ def test_denoiser_arguments_checked_before_the_gpu():
     assert L.mcx_nn_mirror_xy(a, b, 4, 4, 0, 1, None) == mcx.MCX_EINVAL
     assert L.mcx_nn_mirror_xy(a, b, 4, 5, 4, 4, None) == mcx.MCX_EINVAL
     assert "nx == ny" in mcx.mcx_last_error()
+    step = C.c_int32()
+    assert L.mcx_nn_get_adam(None, a, b, 4, C.byref(step)) == mcx.MCX_EINVAL
+    assert L.mcx_nn_get_adam(a, None, b, 4, C.byref(step)) == mcx.MCX_EINVAL
+    assert L.mcx_nn_set_adam(a, a, None, 4, 0) == mcx.MCX_EINVAL
+    assert L.mcx_nn_set_adam(a, a, b, 4, -1) == mcx.MCX_EINVAL
 
 
 def test_denoiser_reports_no_device_without_gpu():

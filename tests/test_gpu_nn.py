@@ -298,6 +298,34 @@ def test_untrained_network_returns_its_input():
     assert np.allclose(out[~keep], 1e-12, rtol=1e-5)
 
 
+def test_checkpoint_round_trip(tmp_path):
+    """save() after some training and load() into a fresh network restore
+    parameters and Adam's state exactly; the forward pass is bit-identical."""
+    channels, shape = (8, 16), (8, 8, 8)
+    _, flat = make_net(channels, shape, 17, zero_output=True)
+    noisy, clean = fluence_pair(shape, 18)
+    x, y = dev_f32(noisy), dev_f32(clean)
+    path = tmp_path / "denoiser.npz"
+    with nn.Denoiser(channels, shape) as d:
+        d.set_params(flat)
+        for _ in range(5):
+            d.train_step(x, y, 1e-3)
+        d.save(path)
+        ref_params = d.params()
+        ref_m, ref_v, ref_step = nn.mcx_nn_get_adam(d.h)
+        ref_out = host(d.forward(x))
+    assert ref_step == 5 and np.any(ref_m != 0) and np.any(ref_v != 0)
+    with nn.Denoiser(channels, shape) as e:
+        e.load(path)
+        m, v, step = nn.mcx_nn_get_adam(e.h)
+        assert np.array_equal(e.params(), ref_params)
+        assert np.array_equal(m, ref_m) and np.array_equal(v, ref_v) and step == ref_step
+        assert np.array_equal(host(e.forward(x)), ref_out)
+    with nn.Denoiser(channels, (8, 8, 16)) as f:
+        with pytest.raises(ValueError):
+            f.load(path)
+
+
 def test_training_reduces_the_loss():
     t = torch()
     channels, shape = (8, 16, 32), (16, 16, 16)
