@@ -117,8 +117,9 @@ def mcx_nn_get_adam(h):
 def mcx_nn_set_adam(h, m, v, step: int):
     m = np.ascontiguousarray(m, np.float32)
     v = np.ascontiguousarray(v, np.float32)
-    mcx._check(lib().mcx_nn_set_adam(h, m.ctypes.data, v.ctypes.data, m.size if m.size == v.size
-                                     else -1, int(step)))
+    if m.size != v.size:
+        raise ValueError(f"m has {m.size} values and v {v.size}")
+    mcx._check(lib().mcx_nn_set_adam(h, m.ctypes.data, v.ctypes.data, m.size, int(step)))
 
 
 def mcx_nn_forward(h, phi_in, phi_out=None, u_out=None, stream=None):
