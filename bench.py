@@ -54,7 +54,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--photons", type=int, default=100_000_000)
-    ap.add_argument("--cpu-photons", type=int, default=3_000_000)
+    ap.add_argument("--cpu-photons", type=int, default=6_000_000)
     ap.add_argument("--launch", default=None, metavar="BLOCK,CHUNK,WINDOW",
                     help="fix the transport launch shape (skips the autotuner and the "
                          "default-shape context run, e.g. for profiling)")
