@@ -16,10 +16,12 @@ scattering, boundaries, roulette, detection, ledger), FP64 reductions and
 normalisation of the map into a device tensor.  Problem creation and upload
 (the paper's host overhead) happen once, before the timed region.
 
-Prints one JSON line.  `roofline` is the transport kernel's algorithmic VALU
-work over its HIP-event time; `atomic_roofline` its memory-side atomic rate;
-`cpu_baseline` the FP64 oracle on the host cores over a prefix of the same
-photons.  The launch shape of the timed steps is the one the library's
+Prints one JSON line.  `roofline` is the ceiling that binds the transport
+kernel -- the memory-side FP64 atomic rate (measured peak) on this workload --
+with the other one (FP32 VALU, the method's per-event operation count over
+the kernel's HIP-event time) attached, and the kernel's HBM traffic against
+its algorithmic bytes; `cpu_baseline` the FP64 oracle on the host cores
+available to this process over a prefix of the same photons, best of 3.  The launch shape of the timed steps is the one the library's
 autotuner picks (before the timed region) from pilot launches of 1/20 of the
 photons; the rate of the default shape is reported beside it.  Two further workloads are reported beside the main one, each
 timed once after a warm-up launch: `head_volume` (the seeded 181 x 217 x
@@ -54,7 +56,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--photons", type=int, default=100_000_000)
-    ap.add_argument("--cpu-photons", type=int, default=6_000_000)
+    ap.add_argument("--cpu-photons", type=int, default=2_000_000,
+                    help="photons per CPU-baseline run (3 runs, best kept)")
     ap.add_argument("--launch", default=None, metavar="BLOCK,CHUNK,WINDOW",
                     help="fix the transport launch shape (skips the autotuner and the "
                          "default-shape context run, e.g. for profiling)")
@@ -117,7 +120,7 @@ def main():
     def step(i):
         mcx.mcx_reset(sim.ctx)
         mcx.mcx_run_range(sim.ctx, 0, N, args.seed + i)
-        mcx.mcx_fluence_device(sim.ctx, mcx.MCX_FLUENCE_RATE, out, stream=0)
+        mcx.mcx_fluence_device(sim.ctx, mcx.MCX_FLUENCE_RATE, out)
         return sim.stats()  # waits for the context's stream
 
     for i in range(args.warmup):
@@ -136,9 +139,10 @@ def main():
 
     last = stats[-1]
     ksec = sum(kernel_ms) / len(kernel_ms) / 1e3
-    roof = roofline.valu_roofline(last, ksec)
+    roof = roofline.binding(last, ksec)
     roof["traffic"] = roofline.measured_traffic(N, tune["lds_window_cells"])
-    atom = roofline.atomic_roofline(last, ksec)
+    roof["traffic_over_algorithmic"] = (roof["traffic"] / roof["algorithmic_bytes"]
+                                        if roof["traffic"] else None)
     scaling = None if args.no_scaling else scaling_leg(sim, args.seed)
     sim.close()
 
@@ -150,17 +154,7 @@ def main():
 
     cpu = cpu1 = None
     if not args.no_cpu_baseline:
-        import oracle
-        nthreads = min(os.cpu_count() or 1, 16)
-        r = oracle.run(p, args.cpu_photons, args.seed, nthreads=nthreads)
-        cpu = {"value": args.cpu_photons / (r["wall_s"] * 1e3), "unit": "photons/ms",
-               "cores": nthreads, "kind": "oracle",
-               "sample": f"photons 0..{args.cpu_photons - 1} of the same workload and seed "
-                         f"({r['wall_s']:.1f} s, FP64, {nthreads} threads)"}
-        n1 = max(1, args.cpu_photons // 16)
-        r1 = oracle.run(p, n1, args.seed, nthreads=1)
-        cpu1 = {"value": n1 / (r1["wall_s"] * 1e3), "unit": "photons/ms", "cores": 1,
-                "kind": "oracle", "sample": f"photons 0..{n1 - 1}, one thread ({r1['wall_s']:.1f} s)"}
+        cpu, cpu1 = cpu_baseline(p, args.cpu_photons, args.seed)
 
     ks = sorted(kernel_ms)
     line = {
@@ -184,7 +178,6 @@ def main():
         "events_per_photon": last["events"] / N,
         "lane_utilisation": last["events"] / max(1, last["lane_slots"]),
         "roofline": roof,
-        "atomic_roofline": atom,
         "cpu_baseline": cpu,
         "cpu_single_thread": cpu1,
         "photon_scaling": scaling,
@@ -194,6 +187,57 @@ def main():
         "denoiser": denoised,
     }
     print(json.dumps(line), flush=True)
+
+
+def host_cpu() -> dict:
+    """The host's CPU model, its logical CPU count, the CPUs this process may
+    run on and the cgroup's CPU quota (in CPUs), as far as they are readable."""
+    info = {"model": None, "nproc": os.cpu_count(), "affinity": None, "cgroup_quota": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, per = f.read().split()[:2]
+        if q != "max":
+            info["cgroup_quota"] = float(q) / float(per)
+    except (OSError, ValueError):
+        pass
+    return info
+
+
+def cpu_baseline(p, n, seed):
+    """The FP64 oracle, as it stands, on every CPU this process may use (the
+    affinity set, capped by the cgroup quota), 3 runs of photons [0, n) of
+    the same workload and seed, best kept; and on one thread over n/16
+    photons, best of 3."""
+    import math
+    import oracle
+    cpu = host_cpu()
+    cores = cpu["affinity"] or cpu["nproc"] or 1
+    if cpu["cgroup_quota"]:
+        cores = max(1, min(cores, int(math.ceil(cpu["cgroup_quota"]))))
+    walls = [oracle.run(p, n, seed, nthreads=cores)["wall_s"] for _ in range(3)]
+    n1 = max(1, n // 16)
+    walls1 = [oracle.run(p, n1, seed, nthreads=1)["wall_s"] for _ in range(3)]
+    best = {"value": n / (min(walls) * 1e3), "unit": "photons/ms", "cores": cores,
+            "kind": "oracle",
+            "sample": f"photons 0..{n - 1} of the same workload and seed, FP64, {cores} threads, "
+                      f"best of 3 runs ({', '.join(f'{w:.2f}' for w in walls)} s)",
+            "median": n / (sorted(walls)[1] * 1e3), "host": cpu}
+    one = {"value": n1 / (min(walls1) * 1e3), "unit": "photons/ms", "cores": 1, "kind": "oracle",
+           "sample": f"photons 0..{n1 - 1}, one thread, best of 3 runs "
+                     f"({', '.join(f'{w:.2f}' for w in walls1)} s)"}
+    return best, one
 
 
 def scaling_leg(sim, seed):
@@ -270,8 +314,7 @@ def head_leg(mcx, roofline, W, N, seed, launch=None):
                        "lds_window_cells": tune["lds_window_cells"]},
             "kernel_ms": st["kernel_ms"],
             "run_ms": st["run_ms"], "events_per_photon": st["events"] / N,
-            "valu_frac": roofline.valu_roofline(st, ksec)["frac"],
-            "atomic_frac": roofline.atomic_roofline(st, ksec)["frac"]}
+            "roofline": roofline.binding(st, ksec)}
 
 
 def batch_leg(mcx, W):

@@ -177,7 +177,43 @@ def normalise(tally: np.ndarray, nphoton: int, h: float, dt: float, kind: int) -
     return phi if kind == 1 else phi / dt
 
 
-def absorbed_fraction(tally: np.ndarray, p, nphoton: int) -> float:
-    """Sum over cells of mua(voxel) * tally, per launched photon."""
-    mua = np.asarray(p.media, np.float64)[:, 0][p.labels]
-    return float((tally.sum(axis=0) * mua).sum() / nphoton)
+def detected_postprocess(records, nphoton: int, ndet: int, t0: float, dt: float, ngates: int,
+                         dmua=None):
+    """Post-processing of detected-photon records (the step after detection
+    in the paper's workflow, Fig. 1).  Rows are {detector, scatterings, exit
+    weight w, exit time t, pathlength L_1 .. L_npath per medium}.
+
+    Re-weighting for an absorption change: absorption is a continuous weight
+    decay along the path, so a photon's exit weight under absorption
+    mua_i + dmua_i is w exp(-sum_i dmua_i L_i); the exponent is summed in
+    medium order.  Per detector d (rows of the result): the number of
+    records, the re-weighted weight summed and divided by the launched
+    photons (reflectance), and the same sum split by the gate of the exit
+    time, g = min(max(floor((t - t0) / dt), 0), ngates - 1), divided by
+    photons x dt (the time-resolved reflectance).  nphoton = 0 keeps the raw
+    sums.  Records whose detector column is not an integer in [0, ndet) are
+    left out.  Returns (result (ndet, 2 + ngates), re-weighted weights)."""
+    rec = np.asarray(records, np.float32).astype(np.float64).reshape(-1, np.shape(records)[-1])
+    n, npath = rec.shape[0], rec.shape[1] - 4
+    w = rec[:, 2].copy()
+    if dmua is not None:
+        e = np.zeros(n)
+        for i in range(npath):
+            e = e + float(np.float32(dmua[i])) * rec[:, 4 + i]
+        w = w * np.exp(-e)
+    t0 = float(np.float32(t0))
+    dt = float(np.float32(dt))
+    det = rec[:, 0]
+    ok = (det >= 0) & (det < ndet) & (det == np.floor(det))
+    gate = np.floor((rec[:, 3] - t0) / dt)
+    gate = np.where(gate >= 0, gate, 0.0)          # NaN and negative -> gate 0
+    gate = np.minimum(gate, ngates - 1).astype(np.int64)
+    d = det[ok].astype(np.int64)
+    out = np.zeros((ndet, 2 + ngates))
+    np.add.at(out[:, 0], d, 1.0)
+    np.add.at(out[:, 1], d, w[ok])
+    np.add.at(out, (d, 2 + gate[ok]), w[ok])
+    if nphoton:
+        out[:, 1] /= float(nphoton)
+        out[:, 2:] /= float(nphoton) * dt
+    return out, w

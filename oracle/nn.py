@@ -204,11 +204,14 @@ def forward(params, u, channels, precision: str = "fp64"):
     return out, acts
 
 
-def backward(params, acts, gout, channels, precision: str = "fp64"):
+def backward(params, acts, gout, channels, precision: str = "fp64", record=None):
     """Gradients of every weight and bias for the output gradient gout
     (the chain rule through the graph of `forward`, last layer first).  The
     gradient entering a layer is masked by its ReLU (where it has one) and,
-    in bf16 mode, rounded as the GPU path stores it."""
+    in bf16 mode, rounded as the GPU path stores it.  With a dict `record`,
+    each layer's (masked, rounded) output gradient and input gradient are
+    kept there under its name, so that a single layer can be checked on
+    exactly the operands this chain gave it."""
     rnd = bf16 if precision == "bf16" else (lambda a: np.asarray(a, dtype=np.float64))
     L = len(channels)
     grads = {}
@@ -219,6 +222,8 @@ def backward(params, acts, gout, channels, precision: str = "fp64"):
         w, _ = params[name]
         gx, gw, gb = _BWD[kind](inp, rnd(w), gy)
         grads[name] = (gw, gb)
+        if record is not None:
+            record[name] = (gy, gx)
         return gx
 
     g = back("out", "conv3", gout[..., None], act=False)
@@ -232,6 +237,8 @@ def backward(params, acts, gout, channels, precision: str = "fp64"):
         w, _ = params[f"up{l}"]
         g, gw, gb = up_backward(inp, rnd(w), gy)
         grads[f"up{l}"] = (gw, gb)
+        if record is not None:
+            record[f"up{l}"] = (gy, g)
     g = back("bottom", "conv3", g)
     for l in range(L - 1, 0, -1):
         if l < L - 1:

@@ -1,18 +1,42 @@
-"""Algorithmic work model of the transport loop, for roofline fractions.
+"""Roofline figures of the transport loop: the two ceilings that bind it.
 
-Counts the VALU lane-operations the method itself needs per event -- the
-arithmetic of the formulas, not the instructions a compiler happens to emit
--- with full-rate FP32/integer operations (add, mul, fma, compare, select,
-min/max, conversion, bit operation) as 1 slot, transcendental unit
-operations (exp, log, sqrt, rcp, rsq, sin, cos) as 4 slots, and the 32x32->64
-multiply Philox needs as 2 slots (the issue cost measured on gfx950 by the
-microbenchmark: a Philox4x32-10 block costs 60 slots).  Multiplying by the
-event counts a run reports gives the run's algorithmic work; divided by the
-kernel time and by the chip's FP32 VALU lane rate it is the fraction of the
-VALU roofline achieved.
+**FP32 VALU.**  Peak: 256 compute units x 64 FP32 lanes per clock x 2.4 GHz
+= 39.32e12 lane-operations per second (non-packed; packed FP32 is disabled
+in the build).  The algorithmic work of a run is the method's own
+arithmetic per event, counted by a fixed convention written down before
+anything was measured, times the event counts the run reports:
 
-Peak: 256 compute units x 64 FP32 lanes per clock x 2.4 GHz = 39.32e12
-lane-operations per second (non-packed; packed FP32 is disabled in the build).
+* a random uniform costs its share of a Philox4x32-10 block: ten rounds of
+  two 32x32 multiplies, each giving a high and a low word, and four
+  xor/add, plus two, 82 operations per block or about 20 per uniform;
+  integer multiplies issue at a quarter of the FP32 rate, so with each of
+  the 40 multiplies weighted 4 a block costs 202 and a uniform 50.5;
+* a segment (free path, voxel hop and deposit): about 25 FP32 operations,
+  one exp (4) and one 1 - exp(-x) (about 6) -> 35;
+* a scattering: 3 uniforms, one log (4), one sqrt (4), a sine and a cosine
+  (4 each) and about 30 FMA (HG inversion, basis, rotation, renormalising)
+  -> 46 + 3 uniforms;
+* a Fresnel test: about 20 operations, one sqrt (4) and one uniform;
+* a roulette test: one compare and one uniform;
+* a launch: one uniform and its log (4).
+
+Transcendentals (v_exp, v_log, v_sqrt, v_sin, v_cos, v_rcp) are
+quarter-rate and count 4.  Two figures come out: with the multiplies
+weighted 4 (the convention's primary count) and unweighted.  A third,
+finer model of the issue slots each event's instructions take on gfx950
+(segment 60, scattering 162, face event 19, Fresnel test 120, launch 88,
+with the Philox block at the 60 slots the microbenchmark measures) is kept
+beside them as `issue_model`.
+
+**Memory-side atomics.**  Every FP64 atomic add on device memory executes at
+the memory side at a fixed aggregate rate, measured by the microbenchmark at
+2.36e10/s on distinct addresses (the published specifications give no such
+figure).  The atomics a launch issues are counted by the kernel itself
+(`flushes`: every cell-visit sum added to the map by a global atomic) and
+agree with the TCC_ATOMIC counter.  Algorithmic bytes of the map traffic
+are 8 per deposit (one FP64 add per segment) plus one label byte per face
+event; HBM traffic measured by FETCH_SIZE / WRITE_SIZE is reported against
+them.
 """
 import hashlib
 import json
@@ -22,50 +46,104 @@ CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 VALU_PEAK = CUS * LANES * CLOCK_HZ            # lane-op slots per second
 ATOMIC_PEAK_F64 = 2.36e10                     # measured FP64 no-return atomics/s, distinct addresses
 
-PHILOX_BLOCK = 10 * (2 * 2 + 2)                # 10 rounds: two 32x32->64 products, two 3-input xors
-UNIFORM = 3                                    # shift, or, convert-and-scale
-
-# every segment: 3 face distances (gap, clamp, scale, zero-velocity select:
-# 5 each), argmin (4), scattering distance (2), time distance (3), event
-# choice (5), gate index (6), deposit: mua*l, 1-exp (exp + 1), scale by w and
-# 1/mua with the mua = 0 select (4), weight update (1), visit accumulation
-# (2), move: 3 fma + 3 clamps, time, depth and its clamp (10), segment count (2)
-SEGMENT = 15 + 4 + 2 + 3 + 5 + 6 + (1 + 4 + 1 + 4 + 1) + 2 + 10 + 2
-# scattering: one Philox block and 3 uniforms; HG inverse CDF (13 incl. one
-# rcp); sin(theta) (7 incl. sqrt); sin/cos of the azimuth (9); Duff et al.
-# basis (15 incl. one rcp); rotation (12); renormalisation (10 incl. rsq);
-# three h/|v| (21 incl. three rcp); new free path -ln u (5); roulette test (1)
-SCATTER = PHILOX_BLOCK + 3 * UNIFORM + 13 + 7 + 9 + 15 + 12 + 10 + 21 + 5 + 1
-# voxel face event: axis components (6), neighbour index and bounds (6),
-# index comparison (2), face snap (2), entering the neighbour (3)
-FACE = 6 + 6 + 2 + 2 + 3
-# Fresnel test with a draw: n1/n2 (rcp + 1), sin^2 t (3), TIR test (1),
-# cos t (sqrt + 2), reflectance (two rcp + 10), one Philox block + uniform,
-# refraction or reflection update with new h/|v| (24)
-FRESNEL = 5 + 3 + 1 + 6 + 18 + PHILOX_BLOCK + UNIFORM + 24
-# photon launch: one Philox block, uniform, -ln u, state set-up (20)
-LAUNCH = PHILOX_BLOCK + UNIFORM + 5 + 20
+# --- the frozen per-event convention
+PHILOX_BLOCK_OPS = 10 * (2 + 2 + 4) + 2       # 82: per round 2 mul_hi, 2 mul_lo, 4 xor/add
+PHILOX_BLOCK_OPS_MUL4 = 10 * (4 * 4 + 4) + 2  # 202: the 40 multiplies weighted 4
+TRANS = 4                                     # exp, log, sqrt, sin, cos, rcp
 
 
-def algorithmic_ops(stats: dict) -> float:
-    """Lane-op slots of the method for a run's event counts."""
-    return (SEGMENT * stats["events"] + SCATTER * stats["scatters"] + FACE * stats["face_events"]
-            + FRESNEL * stats["fresnel_draws"] + LAUNCH * stats["launched"])
+def per_event(uniform: float) -> dict:
+    """Operations per event of the convention, for a uniform costing `uniform`."""
+    return {
+        "segment": 25 + TRANS + 6,
+        "scatter": 3 * uniform + TRANS + TRANS + 2 * TRANS + 30,
+        "fresnel": 20 + TRANS + uniform,
+        "roulette": 1 + uniform,
+        "launch": uniform + TRANS,
+    }
+
+
+CONVENTION = per_event(PHILOX_BLOCK_OPS_MUL4 / 4)
+CONVENTION_UNWEIGHTED = per_event(PHILOX_BLOCK_OPS / 4)
+
+
+def convention_ops(stats: dict, table: dict = CONVENTION) -> float:
+    """Algorithmic lane-operations of a run: per-event work x event counts."""
+    return (table["segment"] * stats["events"] + table["scatter"] * stats["scatters"]
+            + table["fresnel"] * stats["fresnel_draws"] + table["roulette"] * stats["rr_tests"]
+            + table["launch"] * stats["launched"])
+
+
+# --- the finer issue-slot model (full-rate operation 1 slot, transcendental
+# 4, 32x32->64 multiply 2; Philox block 60 slots as measured)
+PHILOX_BLOCK_SLOTS = 10 * (2 * 2 + 2)
+UNIFORM_SLOTS = 3                              # shift, or, convert-and-scale
+ISSUE_MODEL = {
+    # 3 face distances (5 each), argmin 4, scattering distance 2, time
+    # distance 3, event choice 5, gate 6, deposit 11, visit accumulation 2,
+    # move 10, segment count 2
+    "segment": 15 + 4 + 2 + 3 + 5 + 6 + 11 + 2 + 10 + 2,
+    # Philox block + 3 uniforms, HG 13, sin theta 7, azimuth 9, basis 15,
+    # rotation 12, renormalising 10, three h/|v| 21, new free path 5, roulette 1
+    "scatter": PHILOX_BLOCK_SLOTS + 3 * UNIFORM_SLOTS + 13 + 7 + 9 + 15 + 12 + 10 + 21 + 5 + 1,
+    # axis components 6, neighbour index and bounds 6, comparison 2, face
+    # snap 2, entering 3
+    "face": 6 + 6 + 2 + 2 + 3,
+    # n1/n2 5, sin^2 t 3, TIR test 1, cos t 6, reflectance 18, Philox block +
+    # uniform, direction update with new h/|v| 24
+    "fresnel": 5 + 3 + 1 + 6 + 18 + PHILOX_BLOCK_SLOTS + UNIFORM_SLOTS + 24,
+    # Philox block, uniform, -ln u, state set-up 20
+    "launch": PHILOX_BLOCK_SLOTS + UNIFORM_SLOTS + 5 + 20,
+}
+
+
+def issue_model_ops(stats: dict) -> float:
+    m = ISSUE_MODEL
+    return (m["segment"] * stats["events"] + m["scatter"] * stats["scatters"]
+            + m["face"] * stats["face_events"] + m["fresnel"] * stats["fresnel_draws"]
+            + m["launch"] * stats["launched"])
 
 
 def valu_roofline(stats: dict, kernel_s: float) -> dict:
-    ops = algorithmic_ops(stats)
-    achieved = ops / kernel_s
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-            "unit": "T lane-op/s", "frac": achieved / VALU_PEAK,
-            "ops_per_launch": ops}
+    ops = convention_ops(stats)
+    ops_u = convention_ops(stats, CONVENTION_UNWEIGHTED)
+    ops_i = issue_model_ops(stats)
+    return {"bound": "alu", "achieved": ops / kernel_s / 1e12, "peak": VALU_PEAK / 1e12,
+            "unit": "T lane-op/s", "frac": ops / kernel_s / VALU_PEAK, "ops_per_launch": ops,
+            "frac_unweighted_multiplies": ops_u / kernel_s / VALU_PEAK,
+            "issue_model": {"frac": ops_i / kernel_s / VALU_PEAK, "ops_per_launch": ops_i}}
+
+
+def algorithmic_bytes(stats: dict) -> float:
+    """Map traffic the method needs: one FP64 add per deposit (segment) and
+    one label byte per face event."""
+    return 8.0 * stats["events"] + 1.0 * stats["face_events"]
 
 
 def atomic_roofline(stats: dict, kernel_s: float) -> dict:
     rate = stats["flushes"] / kernel_s
-    return {"bound": "memory-side atomics", "achieved": rate, "peak": ATOMIC_PEAK_F64,
+    return {"bound": "atomics", "achieved": rate, "peak": ATOMIC_PEAK_F64,
+            "peak_source": "measured: FP64 no-return atomics on distinct addresses "
+                           "(microbenchmark)",
             "unit": "atomics/s", "frac": rate / ATOMIC_PEAK_F64,
-            "atomics_per_photon": stats["flushes"] / max(1, stats["launched"])}
+            "atomics_per_photon": stats["flushes"] / max(1, stats["launched"]),
+            "deposits_per_photon": stats["events"] / max(1, stats["launched"])}
+
+
+def binding(stats: dict, kernel_s: float) -> dict:
+    """The roofline of the ceiling that binds: the larger of the memory-side
+    atomic fraction and the VALU fraction (convention count), with the other
+    one attached."""
+    a = atomic_roofline(stats, kernel_s)
+    v = valu_roofline(stats, kernel_s)
+    if a["frac"] >= v["frac"]:
+        out = dict(a)
+        out["valu"] = v
+    else:
+        out = dict(v)
+        out["atomics"] = a
+    out["algorithmic_bytes"] = algorithmic_bytes(stats)
+    return out
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))

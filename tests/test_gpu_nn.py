@@ -222,9 +222,61 @@ def test_network_gradients_match_oracle():
         s = np.abs(gw_ref).max() + 1e-30
         rel = np.abs(gw - gw_ref).max() / s
         print(name, "max rel weight-gradient difference", rel, flush=True)
-        assert rel < 5e-2, name
-        assert np.abs(gb - gb_ref).max() <= 5e-2 * (np.abs(gb_ref).max() + 1e-30), name
+        # the chain's BF16 roundings match the oracle's bf16 mode; what is
+        # left is FP32 accumulation (measured ~2e-7 of the layer's largest)
+        assert rel < 1e-5, name
+        assert np.abs(gb - gb_ref).max() <= 1e-5 * (np.abs(gb_ref).max() + 1e-30), name
     assert off == g.size
+
+
+def test_network_64cube_every_layer_backward_on_the_chains_operands():
+    """Loss and gradients of the full (32, 64, 128, 256) network on a 64^3
+    volume, layer by layer: the oracle runs the whole bf16-mode forward pass,
+    loss and backward chain and records each layer's operands (its BF16
+    input, its masked and rounded output gradient); the GPU's layer kernels
+    -- the same launches the network's backward pass makes, including the
+    64^3 brick input gradient with two z-slices per wave and the 64^3 slab
+    weight gradients -- then get exactly those operands.  Every input,
+    weight and bias gradient must agree within 1e-5 of its sum of absolute
+    terms (the FP32 accumulation bound).  (The whole network is not
+    compared end to end at this size: BF16 roundings that land next to a
+    midpoint flip either way and the flips propagate.)"""
+    t = torch()
+    channels, shape = W.DENOISER_CHANNELS, (64, 64, 64)
+    ws, _ = make_net(channels, shape, 12)
+    params = O.params_from_list(channels, [(w.astype(np.float64), b.astype(np.float64)) for w, b in ws])
+    noisy, clean = fluence_pair(shape, 13)
+    u32 = ((np.log(np.maximum(noisy, np.float32(1e-12))).astype(np.float32) + np.float32(16))
+           * np.float32(0.25)).astype(np.float64)
+    t32 = ((np.log(np.maximum(clean, np.float32(1e-12))).astype(np.float32) + np.float32(16))
+           * np.float32(0.25)).astype(np.float64)
+    out, acts = O.forward(params, u32, channels, precision="bf16")
+    mask = O.loss_mask(clean.astype(np.float64))
+    loss, gout = O.loss_and_grad(out, t32, mask)
+    rec = {}
+    grads = O.backward(params, acts, gout, channels, precision="bf16", record=rec)
+    print("64^3 loss", loss, flush=True)
+    for name, kind, ci, co in O.layers(channels):
+        inp, _ = acts[name]
+        gy, gx_ref = rec[name]
+        gw_ref, gb_ref = grads[name]
+        w = params[name][0]
+        wq = O.bf16(w)
+        ishape = inp.shape[:3]
+        print(f"[gpu] layer {name} {kind} {ishape} {ci}->{co}", flush=True)
+        gx = t.empty(tuple(ishape) + (ci,), dtype=t.float32, device="cuda")
+        gw = t.empty(w.shape, dtype=t.float32, device="cuda")
+        gb = t.empty(co, dtype=t.float32, device="cuda")
+        nn.mcx_nn_layer_backward(KIND[kind], ishape, ci, co, dev_bf16(inp), dev_f32(w),
+                                 dev_bf16(gy), gx, gw, gb)
+        sx, sw, _ = BWD[kind](np.abs(inp), np.abs(wq), np.abs(gy))
+        sb = np.abs(gy).reshape(-1, co).sum(axis=0)
+        for got, ref, sc, what in [(host(gx), gx_ref, sx, "input"), (host(gw), gw_ref, sw, "weight"),
+                                   (host(gb), gb_ref, sb, "bias")]:
+            d = np.abs(got - ref)
+            print(f"  {what} gradient: max |diff| / sum|terms| {np.max(d / (sc + 1e-30)):.2e}, "
+                  f"of the layer's largest {d.max() / (np.abs(ref).max() + 1e-30):.2e}", flush=True)
+            assert np.all(d <= 1e-5 * sc + 1e-30), (name, what)
 
 
 def test_adam_step_matches_oracle():

@@ -1,11 +1,12 @@
 """GPU path against the FP64 oracle on the same seeds (same Philox streams).
 
 Bars: launched = terminated = N; per-photon digests coupled; absorbed
-fraction within 1e-4 relative (or, where trajectories decouple, within the
-noise of the decoupled photons measured from their digests); fluence within
-1e-3 relative in cells with >= 1e4 oracle deposits and within 3 sigma of
-seed-repeat noise elsewhere; exact closed forms where the oracle's pins are
-exact.
+fraction within 1e-4 relative (the benchmark workloads at photon counts
+where the noise of the few decoupled photons is well below that bar);
+fluence within 1e-3 relative in cells with >= 1e4 oracle deposits and
+within 3 sigma of seed-repeat noise elsewhere; normalised maps of every
+kind against the oracle's normalisation, also at voxel sizes and gate
+widths other than 1; exact closed forms where the oracle's pins are exact.
 """
 import math
 import sys
@@ -25,11 +26,15 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu(p, N, seed, **opt):
+def gpu(p, N, seed, kinds=False, **opt):
     say(f"[gpu] {p.name or 'problem'} N={N} seed={seed} opt={opt}")
     with mcx.Simulation(p, **opt) as sim:
         sim.run(N, seed)
         out = {"raw": sim.fluence(mcx.MCX_RAW, f64=True), "stats": sim.stats()}
+        if kinds:
+            out[1] = sim.fluence(mcx.MCX_FLUENCE, f64=True)
+            out[2] = sim.fluence(mcx.MCX_FLUENCE_RATE, f64=True)
+            out["k1_f32"] = sim.fluence(mcx.MCX_FLUENCE)
         if opt.get("ndigest"):
             out["digest"] = sim.digest()
         if p.ndet:
@@ -58,14 +63,18 @@ def terminated(st):
 
 def sigma_test(g_raw, o_raw, seeds_raw, o_dep, mask):
     """Fraction of masked cells within 3 and beyond 6 sigma of seed-repeat
-    noise.  sigma combines the spread of 8 independent oracle seeds with a
-    Poisson floor (cell value / sqrt(deposits)) for sparse cells, where 8
-    seeds cannot estimate a spread (a cell no seed happened to visit)."""
+    noise, sigma being the spread of 8 independent oracle seeds at the same
+    photon count.  Only where those 8 seeds spread by exactly zero (no seed
+    deposited into the cell) is sigma taken as the Poisson estimate of the
+    cell's own deposits, cell value / sqrt(deposits); everywhere else the
+    measured spread alone is the bar."""
     sd = np.std(np.stack(seeds_raw), axis=0, ddof=1)
-    floor = np.maximum(np.abs(g_raw), np.abs(o_raw)) / np.sqrt(np.maximum(o_dep, 1))
-    sig = np.sqrt(sd ** 2 + floor ** 2)[mask]
+    poisson = np.maximum(np.abs(g_raw), np.abs(o_raw)) / np.sqrt(np.maximum(o_dep, 1))
+    sig = np.where(sd > 0, sd, poisson)[mask]
     d = np.abs(g_raw - o_raw)[mask]
     z = np.where(sig > 0, d / np.where(sig > 0, sig, 1), np.where(d == 0, 0.0, np.inf))
+    say("sigma test: cells", int(mask.sum()), "with zero seed spread",
+        int(np.sum((sd == 0)[mask])))
     return float(np.mean(z <= 3)), int(np.sum(z > 6)), int(mask.sum())
 
 
@@ -89,9 +98,11 @@ def test_beer_lambert_exact():
     assert abs(energy_residual(st)) < 1e-6
 
 
-def test_compensated_tally_keeps_fp32_sums_exact():
-    # 2e6 deposits of ~1 into the first voxel: a plain FP32 accumulator is off
-    # by ~1e-2 relative at this count; the value+compensation pair is not.
+def test_fp64_tally_sums_two_million_deposits_exactly():
+    # 2e6 deposits of ~1 into the first voxel, each flushed once per photon
+    # (FP32 visit sum) into the FP64 tally through the LDS window: a plain
+    # FP32 accumulator would be off by ~1e-2 relative at this count, the
+    # FP64 cell is not.
     p = W.slab_column(nz=4, mua=0.005, mus=0.0)
     N = 2_000_000
     g = gpu(p, N, 3)
@@ -185,8 +196,10 @@ def test_cube1_fluence_cells(cube1):
 
 @pytest.fixture(scope="module")
 def cube2():
+    """The sphere benchmark over its first 1e6 photons: the prefix the
+    per-cell and record checks use, with 8 oracle seeds for the sigma test."""
     p = W.cube_sphere()
-    N = 50_000
+    N = 1_000_000
     g = gpu(p, N, 1, ndigest=N)
     o = orc(p, N, 1, deposits=True, ndigest=N)
     seeds = [orc(p, N, s)["tally"] for s in range(2, 10)]
@@ -208,17 +221,38 @@ def test_cube2_counts_and_coupling(cube2):
         assert abs(st[k] - o["counts"][k]) <= 5 * math.sqrt((1 - same.mean()) * N) + 2, k
 
 
-def test_cube2_absorbed_fraction(cube2):
+def test_cube2_absorbed_difference_is_the_decoupled_photons(cube2):
+    """At 1e6 photons the whole absorbed-weight difference is carried by the
+    photons whose trajectories decoupled (their digests say by how much)."""
     p, N, g, o, _ = cube2
     a_g = g["stats"]["absorbed_grid"] / N
     a_o = absorbed(p, o["tally"]) / N
     # per-photon absorbed weight is 1 - final weight (no roulette here)
     d = (1 - g["digest"][:, 4]) - (1 - o["digest"][:, 4])
     se = math.sqrt(np.mean(d * d) / N)
-    say("cube2 absorbed", a_g, a_o, "rel", (a_g - a_o) / a_o, "decoupling SE", se)
-    assert abs((a_g - a_o) - d.mean()) <= 1e-5 * a_o   # digests explain the difference
-    assert abs(a_g - a_o) <= max(1e-4 * a_o, 4 * se)
+    say("cube2 1e6 absorbed", a_g, a_o, "rel", (a_g - a_o) / a_o, "decoupling SE rel", se / a_o)
+    assert abs((a_g - a_o) - d.mean()) <= 1e-5 * a_o
     assert abs(energy_residual(g["stats"])) < 1e-5
+
+
+def test_cube2_absorbed_fraction_1e7():
+    """The spec bar as stated: total absorbed fraction within 1e-4
+    relative of the oracle on the same seed, asserted directly.  Run at 1e7
+    photons, where the noise of the ~4 % decoupled photons (standard error
+    logged beside it) is far below the bar."""
+    p = W.cube_sphere()
+    N = 10_000_000
+    g = gpu(p, N, 1, ndigest=N)
+    o = orc(p, N, 1, ndigest=N)
+    st = g["stats"]
+    assert st["launched"] == N and terminated(st) == N
+    a_g = st["absorbed_grid"] / N
+    a_o = absorbed(p, o["tally"]) / N
+    d = (1 - g["digest"][:, 4]) - (1 - o["digest"][:, 4])
+    se = math.sqrt(np.mean(d * d) / N)
+    say("cube2 1e7 absorbed", a_g, a_o, "rel", (a_g - a_o) / a_o, "decoupling SE rel", se / a_o)
+    assert abs(a_g - a_o) <= 1e-4 * a_o
+    assert abs(energy_residual(st)) < 1e-5
 
 
 def test_cube2_fluence_cells(cube2):
@@ -257,6 +291,87 @@ def test_cube2_detector_records(cube2):
     nn = np.asarray(p.media, np.float64)[1:, 3]
     assert np.allclose(rec[:, 2], np.exp(-(rec[:, 4:] * mua).sum(1)), rtol=1e-4)
     assert np.allclose(rec[:, 3], (rec[:, 4:] * nn).sum(1) / C, rtol=1e-4)
+
+
+# ----------------------------------------- voxel size and gate width
+
+def scaled_sphere(h, n, radius, ngates, dt, t0, det_offsets, det_r):
+    """A cube of n voxels of h mm with a centred sphere of `radius` mm (the
+    sphere benchmark's media), Fresnel boundaries, a pencil beam down the
+    middle of the z = 0 face and disk detectors at the given (dx, dy) mm
+    offsets from the source."""
+    side = n * h
+    labels = np.ones((n, n, n), np.uint8)
+    labels[W.sphere_mask(labels.shape, (side / 2,) * 3, radius, h=h)] = 2
+    sx = sy = (n // 2 - 0.5) * h
+    dets = np.array([(sx + dx, sy + dy, 0.0, det_r) for dx, dy in det_offsets], np.float32)
+    return W.Problem(labels=labels, media=W._media(W.CUBE_MEDIUM, W.SPHERE_MEDIUM),
+                     src_pos=(sx, sy, 0.0), src_dir=(0.0, 0.0, 1.0), h=h, detectors=dets,
+                     t0=t0, dt=dt, ngates=ngates, reflect=True,
+                     name=f"sphere_h{h}_dt{dt}")
+
+
+SCALED = {
+    "h2": dict(h=2.0, n=30, radius=15.0, ngates=8, dt=0.25, t0=0.1,
+               det_offsets=[(10, 0), (-10, 0), (0, 20), (0, -20)], det_r=2.0),
+    "h05": dict(h=0.5, n=40, radius=5.0, ngates=12, dt=0.05, t0=0.0,
+                det_offsets=[(4, 0), (-4, 0), (0, 6), (0, -6)], det_r=0.5),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SCALED))
+def test_voxel_size_and_gate_width_normalisation(case):
+    """Voxel sizes of 2 and 0.5 mm and gate widths of 0.25 and 0.05 ns (one
+    starting at t0 = 0.1 ns), with detectors: every normalised kind of the
+    GPU map against the oracle's normalisation of its own tally, cell by
+    cell; the GPU's own scale factors against their definitions; detector
+    records of coupled photons against the oracle's."""
+    p = scaled_sphere(**SCALED[case])
+    N = 100_000
+    g = gpu(p, N, 3, kinds=True, ndigest=N)
+    o = orc(p, N, 3, deposits=True, ndigest=N)
+    seeds = [orc(p, N, s)["tally"] for s in range(11, 19)]
+    st = g["stats"]
+    assert st["launched"] == N and terminated(st) == N
+    assert abs(energy_residual(st)) < 1e-5
+    same = np.all(g["digest"][:, [0, 1, 3]] == o["digest"][:, [0, 1, 3]], axis=1)
+    say(case, "coupled fraction", same.mean())
+    assert same.mean() >= 0.9
+    h, dt = p.h, p.dt
+    # the GPU's normalisation: raw / (N h^3), then / dt, in FP64
+    assert np.allclose(g[1], g["raw"] / (N * h ** 3), rtol=1e-14, atol=0)
+    assert np.allclose(g[2], g[1] / dt, rtol=1e-14, atol=0)
+    assert np.allclose(g["k1_f32"], g[1], rtol=6e-8, atol=0)
+    hi = o["deposits"] >= 10_000
+    lo = (~hi) & ((o["tally"] > 0) | (g["raw"] > 0))
+    assert hi.sum() >= 10
+    for kind in (1, 2):
+        ok = oracle.normalise(o["tally"], N, h, dt, kind)
+        rel = np.abs(g[kind][hi] - ok[hi]) / ok[hi]
+        say(case, "kind", kind, ">=1e4-deposit cells", int(hi.sum()), "max rel", rel.max())
+        assert rel.max() <= 1e-3
+        sk = [oracle.normalise(t, N, h, dt, kind) for t in seeds]
+        within3, beyond6, n = sigma_test(g[kind], ok, sk, o["deposits"], lo)
+        say(case, "kind", kind, "other cells", n, "within 3 sigma", within3, "beyond 6", beyond6)
+        assert within3 >= 0.99 and beyond6 <= 0.001 * n
+    # absorbed weight: the difference is the decoupled photons'
+    a_g, a_o = st["absorbed_grid"] / N, absorbed(p, o["tally"]) / N
+    d = o["digest"][:, 4] - g["digest"][:, 4]
+    say(case, "absorbed", a_g, a_o, "rel", (a_g - a_o) / a_o)
+    assert abs((a_g - a_o) - d.mean()) <= 1e-5 * a_o
+    # detector positions in mm and records at this voxel size
+    om = {int(k): r for k, r in zip(o["record_photon"], o["records"])}
+    gd, od = g["digest"], o["digest"]
+    coupled = (same & np.isclose(gd[:, 4], od[:, 4], rtol=1e-5, atol=0)
+               & np.isclose(gd[:, 5], od[:, 5], rtol=1e-5, atol=0))
+    matched = 0
+    for k, r in zip(g["rec_photon"], g["rec"]):
+        if coupled[int(k)]:
+            assert np.allclose(r, om[int(k)], rtol=1e-4, atol=1e-5 * h), (k, r, om[int(k)])
+            matched += 1
+    say(case, "records", len(g["rec"]), "oracle", len(o["records"]), "matched", matched)
+    assert matched >= 20 and g["dropped"] == 0
+    assert abs(len(g["rec"]) - len(o["records"])) <= 5 * math.sqrt((1 - same.mean()) * N) + 2
 
 
 # ------------------------------------------------------------ edge cases
@@ -397,6 +512,41 @@ def test_fluence_into_torch_tensor():
         assert e.value.status == mcx.MCX_ERANGE
 
 
+def test_async_runs_and_device_fluence_are_ordered_across_streams():
+    """run_range then mcx_fluence_device with default arguments and no
+    synchronisation in between, then the same with the run on a side stream
+    and the normalisation on torch's current stream: the library orders
+    both after the run, so the maps equal a blocking run's host read."""
+    import torch
+    p = W.cube_sphere(n=30, ngates=5, dt=1.0).replace(name="cube30_sphere")
+    N = 200_000
+    with mcx.Simulation(p) as sim:
+        sim.run(N, 5)
+        want = sim.fluence(mcx.MCX_FLUENCE)
+        ref_stats = sim.stats()
+        t = torch.empty(p.tally_shape, dtype=torch.float32, device="cuda")
+        sim.reset()
+        sim.run_range(0, N, 5)
+        mcx.mcx_fluence_device(sim.ctx, mcx.MCX_FLUENCE, t)
+        got = t.cpu().numpy()  # the copy waits for torch's stream only
+        torch.cuda.synchronize()
+        assert np.allclose(got, want, rtol=1e-6, atol=0), "device map read before the run ended"
+        side = torch.cuda.Stream()
+        t.zero_()
+        torch.cuda.synchronize()
+        sim.reset(stream=side)
+        sim.run_range(0, N, 5, stream=side)
+        st = sim.stats()  # waits for the run on the side stream
+        assert st["launched"] == N and st["scatters"] == ref_stats["scatters"]
+        sim.reset(stream=side)
+        sim.run_range(0, N, 5, stream=side)
+        mcx.mcx_fluence_device(sim.ctx, mcx.MCX_FLUENCE, t,
+                               stream=torch.cuda.current_stream())
+        got = t.cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.allclose(got, want, rtol=1e-6, atol=0), "cross-stream normalise not ordered"
+
+
 def test_detector_overflow_is_counted():
     p = W.cube_sphere(n=30, ngates=1, dt=5.0).replace(name="cube30_sphere")
     d = p.detectors.copy()
@@ -412,25 +562,61 @@ def test_detector_overflow_is_counted():
 
 # ------------------------------------------------------------ head volume
 
-def test_head_volume_parity():
+@pytest.fixture(scope="module")
+def head():
+    """The head phantom over its first 1e5 photons, with deposit counts and
+    8 oracle seeds for the per-voxel checks."""
     p = W.head_phantom(1)
-    N = 4000
+    N = 100_000
     g = gpu(p, N, 1, ndigest=N)
-    o = orc(p, N, 1, ndigest=N)
+    o = orc(p, N, 1, deposits=True, ndigest=N)
+    seeds = [orc(p, N, s)["tally"] for s in range(2, 10)]
+    return p, N, g, o, seeds
+
+
+def test_head_counts_and_coupling(head):
+    p, N, g, o, _ = head
     st = g["stats"]
     assert st["launched"] == N and terminated(st) == N
     same = np.all(g["digest"][:, [0, 1, 3]] == o["digest"][:, [0, 1, 3]], axis=1)
     say("head coupled fraction", same.mean(), "roulette tests", st["rr_tests"])
     # mus jumps of up to 4500x between CSF and white matter make trajectories
-    # far more sensitive to rounding than in the cubes
-    assert same.mean() >= 0.5
+    # more sensitive to rounding than in the cubes: 91-92 % stay identical
+    assert same.mean() >= 0.88
+    for k in ["escaped", "timeout", "rr_dead"]:
+        assert abs(st[k] - o["counts"][k]) <= 5 * math.sqrt((1 - same.mean()) * N) + 2, k
     assert abs(energy_residual(st)) < 1e-5
+
+
+def test_head_fluence_cells(head):
+    p, N, g, o, seeds = head
+    hi = o["deposits"] >= 10_000
+    rel = np.abs(g["raw"][hi] - o["tally"][hi]) / o["tally"][hi]
+    say("head >=1e4-deposit cells", int(hi.sum()), "max rel", rel.max() if hi.any() else None)
+    assert hi.sum() >= 100 and rel.max() <= 1e-3
+    lo = (~hi) & ((o["tally"] > 0) | (g["raw"] > 0))
+    within3, beyond6, n = sigma_test(g["raw"], o["tally"], seeds, o["deposits"], lo)
+    say("head other cells", n, "within 3 sigma", within3, "beyond 6 sigma", beyond6)
+    assert within3 >= 0.99 and beyond6 <= 0.001 * n
+
+
+def test_head_absorbed_fraction_1e6():
+    """Total absorbed fraction of the head phantom within 1e-4 relative of
+    the oracle on the same seed, asserted directly at 1e6 photons (the
+    decoupled photons' standard error is logged beside it)."""
+    p = W.head_phantom(1)
+    N = 1_000_000
+    g = gpu(p, N, 1, ndigest=N)
+    o = orc(p, N, 1, ndigest=N)
+    st = g["stats"]
+    assert st["launched"] == N and terminated(st) == N
     a_g, a_o = st["absorbed_grid"] / N, absorbed(p, o["tally"]) / N
     # per-photon absorbed weight = 1 + roulette gains - final weight sink
     d = g["digest"][:, 4] - o["digest"][:, 4]
-    se = math.sqrt(st["w_rr_gain"] / N + np.mean(d * d)) / math.sqrt(N) + 1e-12
-    say("head absorbed", a_g, a_o, "se", se)
-    assert abs(a_g - a_o) <= max(1e-4 * a_o, 5 * se)
+    se = math.sqrt(np.mean(d * d) / N)
+    say("head 1e6 absorbed", a_g, a_o, "rel", (a_g - a_o) / a_o, "decoupling SE rel", se / a_o)
+    assert abs(a_g - a_o) <= 1e-4 * a_o
+    assert abs(energy_residual(st)) < 1e-5
 
 
 # ------------------------------------------------------------- edge cases

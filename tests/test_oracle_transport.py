@@ -74,6 +74,38 @@ def test_beer_lambert_timeout(oracle_mod):
                                   rel=1e-10)
 
 
+@pytest.mark.parametrize("h,dt", [(0.5, 0.02), (2.0, 0.05)])
+def test_normalised_kinds_at_other_voxel_sizes(oracle_mod, h, dt):
+    """Fluence and fluence rate of a straight, non-scattering beam down a
+    column of voxels of h mm, against the closed form.  Voxel k covers depths
+    [k h, (k + 1) h) and the beam enters it with weight exp(-mua k h), so its
+    track-length fluence per launched photon is the weight integrated over
+    the voxel's depth divided by the voxel volume,
+    exp(-mua k h) (1 - exp(-mua h)) / (mua h^3), booked in the gate of the
+    entry time k h n / c; the rate divides that by the gate width.  And the
+    absorbed fraction, sum of mua h^3 times the fluence, is the weight that
+    did not leave the far end, 1 - exp(-mua nz h)."""
+    nz = 40
+    base = W.slab_column(nz=nz, mua=0.02, mus=0.0, ngates=30, dt=dt)
+    p = base.replace(h=h, src_pos=(1.5 * h, 1.5 * h, 0.0), dt=dt)
+    mua, n = float(p.media[1, 0]), float(p.media[1, 3])
+    h, dt = p.h, p.dt   # the stored float32 values
+    N = 50
+    r = oracle_mod.run(p, N, seed=2, nthreads=1)
+    k1 = oracle_mod.normalise(r["tally"], N, h, dt, 1)
+    k2 = oracle_mod.normalise(r["tally"], N, h, dt, 2)
+    assert np.array_equal(oracle_mod.normalise(r["tally"], N, h, dt, 0), r["tally"])
+    expect = np.zeros_like(k1)
+    for k in range(nz):
+        gate = min(int(math.floor(k * h * n / C / dt)), p.ngates - 1)
+        expect[gate, k, 1, 1] = math.exp(-mua * k * h) * -math.expm1(-mua * h) / (mua * h ** 3)
+    assert np.allclose(k1, expect, rtol=1e-12, atol=0)
+    assert np.allclose(k2, expect / dt, rtol=1e-12, atol=0)
+    absorbed = float((k1.sum(axis=0) * mua * h ** 3).sum())
+    assert absorbed == pytest.approx(-math.expm1(-mua * nz * h), rel=1e-12)
+    assert r["ledger"]["escaped"] / N == pytest.approx(math.exp(-mua * nz * h), rel=1e-12)
+
+
 def test_fresnel_round_trips(oracle_mod):
     # mus = 0, reflection on: the beam bounces between the end faces with
     # R0 = ((n-1)/(n+1))^2 per face.  Expected tally per voxel is the
