@@ -226,6 +226,30 @@ mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk
 mcx_status mcx_autotune(mcx_ctx *ctx, const uint64_t *pilot_photons, const uint64_t *seed,
                         mcx_tune_result *out);
 
+/* Least-squares line y = a x + b through k >= 2 points (host only, no GPU):
+ * the fit of the paper's device runtime model T = a n + T0 (device-level
+ * load balancing, Fig. 3(b)).  MCX_EINVAL for NULL arrays, k < 2, a
+ * non-finite point or fewer than two distinct x. */
+mcx_status mcx_fit_linear(const double *x, const double *y, int32_t k, double *a, double *b);
+
+/* The paper's device runtime model per simulation: T = a n + T0 (kernel
+ * time in ms against photons) from two timed pilot launches of n1[i] and
+ * n2[i] photons (NULL: the paper's 1e6 and 5e6) of simulation i alone, with
+ * seed[i] and the current launch shape.  a[i] (ms per photon; 1/a is the
+ * throughput) and t0[i] (ms) receive the fit.  Tallies are cleared on
+ * return.  Blocking. */
+mcx_status mcx_fit_runtime(mcx_ctx *ctx, const uint64_t *n1, const uint64_t *n2,
+                           const uint64_t *seed, double *a, double *t0);
+
+/* Device-level load balancing inside one launch, by throughput (the paper's
+ * S2 partition, shares proportional to the work estimated from 1/a): with
+ * cost_per_photon[i] = a_i (e.g. from mcx_fit_runtime), every later launch
+ * spreads the waves' home simulations in proportion to a_i n_i instead of
+ * the job counts; NULL restores job counts.  Only the schedule changes:
+ * every photon's history and every result stay the same.  MCX_EINVAL for a
+ * negative or non-finite cost. */
+mcx_status mcx_set_balance(mcx_ctx *ctx, const double *cost_per_photon);
+
 /* Clear tallies, detector records, ledger and counters, run photons
  * [0, nphoton) with `seed`, reduce, and wait.  Blocking. */
 mcx_status mcx_run(mcx_ctx *ctx, uint64_t nphoton, uint64_t seed);
@@ -234,8 +258,10 @@ mcx_status mcx_run(mcx_ctx *ctx, uint64_t nphoton, uint64_t seed);
  * hipStream_t; NULL = the context's own stream), accumulating into the
  * current tallies; returns without waiting.  Runs with different seeds may
  * be accumulated; the normalisation divides by the total photon count.
- * Runs of one context are ordered by their stream: enqueue them on one
- * stream (or synchronise between streams). */
+ * The work of one context is ordered whatever streams it is enqueued on:
+ * every clear, launch and device-side normalisation first waits (on the
+ * device) for the context's previous one, and every call that reads results
+ * back to the host waits for it too. */
 mcx_status mcx_run_range(mcx_ctx *ctx, uint64_t first, uint64_t n, uint64_t seed,
                          void *hip_stream);
 
@@ -254,7 +280,8 @@ uint64_t mcx_ncells(const mcx_ctx *ctx);
 mcx_status mcx_fluence(mcx_ctx *ctx, int32_t kind, float *host_out, uint64_t ncells);
 mcx_status mcx_fluence_f64(mcx_ctx *ctx, int32_t kind, double *host_out, uint64_t ncells);
 
-/* Same, written to device memory on hip_stream (NULL = own stream); async. */
+/* Same, written to device memory on hip_stream (NULL = own stream), after
+ * the context's last clear or launch on any stream; async. */
 mcx_status mcx_fluence_device(mcx_ctx *ctx, int32_t kind, float *dev_out, uint64_t ncells,
                               void *hip_stream);
 
@@ -267,6 +294,66 @@ mcx_status mcx_fluence_device(mcx_ctx *ctx, int32_t kind, float *dev_out, uint64
  * Blocking. */
 mcx_status mcx_detected(mcx_ctx *ctx, float *host_rec, uint64_t *host_photon, uint64_t cap,
                         uint64_t *nrec, uint64_t *ndropped);
+
+/* ------------------------------------------------ detected-photon post-processing
+ *
+ * The step after detection in the paper's workflow (Fig. 1: detected-photon
+ * data are read back and processed).  Records are rows of 4 + npath floats,
+ * as mcx_detected returns them: {detector, scatterings, exit weight w, exit
+ * time t (ns), pathlength L_1 .. L_npath in media 1 .. npath (mm)}.
+ *
+ * Per record: w' = w exp(-(dmua[0] L_1 + ... + dmua[npath-1] L_npath)), the
+ * weight the photon would have left with had medium i's absorption been
+ * mua_i + dmua[i-1]: absorption is a continuous weight decay, so paths depend
+ * only on the scattering properties and the stored pathlengths fix the
+ * detected weight for any absorption change (valid while roulette, whose
+ * decisions depend on the weight, did not act on the photon).  dmua NULL:
+ * w' = w.  The exponent is summed in medium order in FP64, each product
+ * rounded on its own.
+ *
+ * Per detector d, row d of `out` (2 + ngates doubles):
+ *   out[d][0]      number of records of detector d;
+ *   out[d][1]      sum of w' / nphoton: detected weight per launched photon
+ *                  (the detector's diffuse reflectance, not divided by its area);
+ *   out[d][2 + g]  sum of w' over the records whose exit time is in gate g,
+ *                  g = min(max(floor((t - t0) / dt), 0), ngates - 1) in FP64,
+ *                  / (nphoton dt): the time-resolved reflectance (TPSF), 1/ns
+ *                  per launched photon.
+ * nphoton = 0 returns the raw sums (no division at all).  Records whose
+ * detector column is not an integer in [0, ndet) are skipped.  Sums are FP64
+ * over per-workgroup partial sums added in a fixed order. */
+typedef struct {
+  int32_t ndet;     /* detectors, 1..4096 */
+  int32_t npath;    /* pathlength columns (nmedia - 1), 1..255; rows have 4 + npath floats */
+  float t0_ns;      /* start of gate 0 (finite) */
+  float dt_ns;      /* gate width (> 0, finite) */
+  int32_t ngates;   /* 1..8190 */
+  uint64_t nphoton; /* launched photons to divide by; 0 = raw sums */
+} mcx_detpost;
+
+/* Post-process nrec records in device memory (dev_rec, nrec rows; may be
+ * NULL when nrec == 0) into dev_out (ndet * (2 + ngates) doubles, device)
+ * and, when dev_weight is not NULL, the re-weighted weight of every record
+ * (nrec doubles, device, record order).  dev_dmua: npath floats in device
+ * memory, or NULL.  Enqueued on hip_stream (NULL = the null stream); the
+ * per-workgroup partial sums go to a workspace the call allocates, and it
+ * waits for the stream before returning to free it.  Errors: MCX_EINVAL for
+ * a bad spec or NULL buffers (checked before any HIP call), MCX_ENOMEM,
+ * MCX_EDEVICE. */
+mcx_status mcx_detpost_device(const float *dev_rec, uint64_t nrec, const mcx_detpost *spec,
+                              const float *dev_dmua, double *dev_out, double *dev_weight,
+                              void *hip_stream);
+
+/* The same for the records simulation `sim` of a context holds (those
+ * mcx_batch_detected would return, in the same order): ndet, npath and the
+ * gates are the simulation's, nphoton the photons run since the last reset.
+ * host_dmua: npath = nmedia - 1 floats, or NULL.  host_out must hold nout >=
+ * ndet * (2 + ngates) doubles (else MCX_ERANGE); host_weight (may be NULL)
+ * nweight >= stored records.  MCX_ESTATE when no photons were run since the
+ * last reset.  Blocking. */
+mcx_status mcx_detected_process(mcx_ctx *ctx, int32_t sim, const float *host_dmua,
+                                double *host_out, uint64_t nout, double *host_weight,
+                                uint64_t nweight);
 
 /* Statistics of the runs since the last reset (waits for the stream). */
 mcx_status mcx_stats(mcx_ctx *ctx, mcx_run_stats *out);

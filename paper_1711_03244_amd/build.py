@@ -13,9 +13,9 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcx.so")
 MICROBENCH = os.path.join(HERE, "mcx_microbench")
-SOURCES = ["mcx_transport.hip", "mcx_tally.hip", "mcx_runtime.hip", "nn_kernels.hip",
-           "nn_runtime.hip"]
-HEADERS = ["mcx_internal.hpp", "nn_internal.hpp", os.path.join("..", "..", "include", "mcx.h"),
+SOURCES = ["mcx_transport.hip", "mcx_tally.hip", "mcx_detpost.hip", "mcx_runtime.hip",
+           "nn_kernels.hip", "nn_runtime.hip"]
+HEADERS = ["mcx_internal.hpp", "mcx_detpost.hpp", "nn_internal.hpp", os.path.join("..", "..", "include", "mcx.h"),
            os.path.join("..", "..", "include", "mcx_nn.h")]
 ARCH = "gfx950"
 

@@ -72,8 +72,8 @@ struct SimDesc {
 // `chunk` photons of one simulation: simulation s has jobs
 // job_start[s+1] - job_start[s], taken in order through its own counter.
 // Each wave starts on a home simulation (waves are spread over simulations
-// in proportion to their job counts) and moves on to the following
-// simulations once its home has no jobs left.
+// in proportion to their shares, see home_start) and moves on to the
+// following simulations once its home has no jobs left.
 struct LaunchParams {
   const SimDesc* sims;
   int32_t nsims;
@@ -81,6 +81,11 @@ struct LaunchParams {
   uint64_t njobs;
   uint32_t chunk;
   unsigned long long* job_counters;  // nsims entries, zero at launch
+  // Shares of the home simulations: prefix sums (nsims + 1 entries) of each
+  // simulation's job count, or of its estimated work a_i n_i scaled to
+  // integers; nhome = home_start[nsims] (> 0).
+  const uint64_t* home_start;
+  uint64_t nhome;
   float rr_threshold, rr_p, rr_m;
   uint32_t max_events;
   int32_t table_rows;            // LDS rows per wave for the current simulation's tables

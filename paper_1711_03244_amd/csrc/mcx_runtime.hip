@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/mcx.h"
+#include "mcx_detpost.hpp"
 #include "mcx_internal.hpp"
 
 namespace {
@@ -116,12 +117,30 @@ struct mcx_ctx {
   double* d_digest = nullptr;
   mcx::SimDesc* d_desc = nullptr;
   uint64_t* d_job_start = nullptr;
+  uint64_t* d_home_start = nullptr;
   unsigned long long* d_job_counter = nullptr;  // one per simulation
+  // estimated cost per photon of every simulation (ms); empty: home waves by
+  // job counts
+  std::vector<double> cost;
   mcx::LaunchParams* d_launch = nullptr;
   float* d_stage32 = nullptr;
   double* d_stage64 = nullptr;
+  // detected-photon post-processing: absorption changes, per-detector
+  // output, re-weighted record weights and the partial-sum workspace
+  // (allocated on first use, grown as needed)
+  float* d_dmua = nullptr;
+  double* d_post = nullptr;
+  double* d_post_w = nullptr;
+  double* d_post_ws = nullptr;
+  uint64_t post_cap = 0, post_w_cap = 0, post_ws_cap = 0;
   hipEvent_t ev_begin = nullptr, ev_k0 = nullptr, ev_k1 = nullptr, ev_end = nullptr;
   bool have_timing = false;
+  // Recorded after every clear or launch, on whichever stream it was
+  // enqueued: later work of the context on any stream waits for it, and the
+  // calls that read results back wait for it, so the context's work is
+  // ordered however callers pick streams.
+  hipEvent_t ev_done = nullptr;
+  bool done_pending = false;
 };
 
 extern "C" {
@@ -235,10 +254,12 @@ static void release(mcx_ctx* c) {
   void* bufs[] = {c->d_labels,      c->d_tables,     c->d_tally,   c->d_ledger,
                   c->d_counts,      c->d_det_count,  c->d_reduce,  c->d_rec,
                   c->d_rec_photon,  c->d_digest,     c->d_desc,    c->d_job_start,
-                  c->d_job_counter, c->d_launch,     c->d_stage32, c->d_stage64};
+                  c->d_job_counter, c->d_launch,     c->d_stage32, c->d_stage64,
+                  c->d_dmua,        c->d_post,       c->d_post_w,  c->d_post_ws,
+                  c->d_home_start};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
-  hipEvent_t evs[] = {c->ev_begin, c->ev_k0, c->ev_k1, c->ev_end};
+  hipEvent_t evs[] = {c->ev_begin, c->ev_k0, c->ev_k1, c->ev_end, c->ev_done};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -354,7 +375,29 @@ static mcx_status set_shape(mcx_ctx* c, int block) {
   return MCX_OK;
 }
 
+// Make stream st wait for the context's last clear or launch.
+static mcx_status wait_done(mcx_ctx* c, hipStream_t st) {
+  if (c->done_pending) HIP_TRY(hipStreamWaitEvent(st, c->ev_done, 0));
+  return MCX_OK;
+}
+
+// Mark the end of the work just enqueued on st.
+static mcx_status mark_done(mcx_ctx* c, hipStream_t st) {
+  HIP_TRY(hipEventRecord(c->ev_done, st));
+  c->done_pending = true;
+  return MCX_OK;
+}
+
+// Block the host until the context's last clear or launch has finished
+// (whatever stream it went to) and its own stream is idle.
+static mcx_status host_wait(mcx_ctx* c) {
+  if (c->done_pending) HIP_TRY(hipEventSynchronize(c->ev_done));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MCX_OK;
+}
+
 static mcx_status clear_all(mcx_ctx* c, hipStream_t st) {
+  MCX_TRY(wait_done(c, st));
   HIP_TRY(mcx::launch_clear(c->d_tally, c->total_cells, c->d_ledger, c->d_counts, c->d_det_count,
                             static_cast<int>(c->sims.size()), st));
   if (c->diag)
@@ -362,7 +405,7 @@ static mcx_status clear_all(mcx_ctx* c, hipStream_t st) {
                            c->sims.size() * c->opt.ndigest * mcx::kDigestN * sizeof(double), st));
   for (SimHost& sh : c->sims) sh.photons = 0;
   c->have_timing = false;
-  return MCX_OK;
+  return mark_done(c, st);
 }
 
 static mcx_status setup(mcx_ctx* c, const mcx_sim* sims) {
@@ -378,6 +421,7 @@ static mcx_status setup(mcx_ctx* c, const mcx_sim* sims) {
   HIP_TRY(hipEventCreate(&c->ev_k0));
   HIP_TRY(hipEventCreate(&c->ev_k1));
   HIP_TRY(hipEventCreate(&c->ev_end));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
 
   const size_t n = c->sims.size();
   uint64_t labels = 0, tables = 0, recs = 0, rec_rows = 0;
@@ -405,6 +449,7 @@ static mcx_status setup(mcx_ctx* c, const mcx_sim* sims) {
   HIP_TRY(hipMalloc(&c->d_reduce, n * 2 * sizeof(double)));
   HIP_TRY(hipMalloc(&c->d_desc, n * sizeof(mcx::SimDesc)));
   HIP_TRY(hipMalloc(&c->d_job_start, (n + 1) * sizeof(uint64_t)));
+  HIP_TRY(hipMalloc(&c->d_home_start, (n + 1) * sizeof(uint64_t)));
   HIP_TRY(hipMalloc(&c->d_job_counter, n * sizeof(unsigned long long)));
   HIP_TRY(hipMalloc(&c->d_launch, sizeof(mcx::LaunchParams)));
   if (recs > 0) {
@@ -491,6 +536,7 @@ mcx_status mcx_batch_create(const mcx_sim* sims, int32_t nsims, const mcx_option
 void mcx_destroy(mcx_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  if (c->done_pending) (void)hipEventSynchronize(c->ev_done);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   release(c);
 }
@@ -581,11 +627,28 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
     d.wng = sh.win[6];
     job_start[i + 1] = job_start[i] + (n[i] + c->chunk - 1) / c->chunk;
   }
+  // Home-wave shares: the job counts, or -- once per-simulation costs are
+  // set (device-level balancing by throughput) -- each simulation's
+  // estimated work cost_i n_i, scaled to integers summing to about 2^40.
+  std::vector<uint64_t> home_start(job_start);
+  if (!c->cost.empty()) {
+    double total = 0.0;
+    for (size_t i = 0; i < ns; ++i) total += c->cost[i] * static_cast<double>(n[i]);
+    if (total > 0.0) {
+      for (size_t i = 0; i < ns; ++i) {
+        const double share = c->cost[i] * static_cast<double>(n[i]) / total;
+        home_start[i + 1] = home_start[i] + static_cast<uint64_t>(std::llround(share * 0x1p40));
+      }
+      if (home_start[ns] == 0) home_start = job_start;
+    }
+  }
   mcx::LaunchParams lp{};
   lp.sims = c->d_desc;
   lp.nsims = static_cast<int32_t>(ns);
   lp.job_start = c->d_job_start;
   lp.njobs = job_start[ns];
+  lp.home_start = c->d_home_start;
+  lp.nhome = home_start[ns];
   lp.chunk = static_cast<uint32_t>(c->chunk);
   lp.job_counters = c->d_job_counter;
   lp.rr_threshold = c->opt.rr_threshold;
@@ -598,9 +661,12 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
 
   // Parameter blocks are copied in stream order before the launch that reads
   // them (pageable sources are staged by the runtime before the call returns).
+  MCX_TRY(wait_done(c, st));
   HIP_TRY(hipMemcpyAsync(c->d_desc, desc.data(), ns * sizeof(mcx::SimDesc),
                          hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(c->d_job_start, job_start.data(), (ns + 1) * sizeof(uint64_t),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->d_home_start, home_start.data(), (ns + 1) * sizeof(uint64_t),
                          hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(c->d_launch, &lp, sizeof(lp), hipMemcpyHostToDevice, st));
   HIP_TRY(mcx::launch_reset_counters(c->d_job_counter, static_cast<int>(ns), st));
@@ -618,7 +684,7 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
   HIP_TRY(hipEventRecord(c->ev_end, st));
   for (size_t i = 0; i < ns; ++i) c->sims[i].photons += n[i];
   c->have_timing = true;
-  return MCX_OK;
+  return mark_done(c, st);
 }
 
 // Split ranges longer than one launch allows into several launches.
@@ -697,8 +763,7 @@ mcx_status mcx_batch_run(mcx_ctx* c, const uint64_t* nphoton, const uint64_t* se
 mcx_status mcx_sync(mcx_ctx* c) {
   if (!c) return fail(MCX_EINVAL, "context is NULL");
   HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return MCX_OK;
+  return host_wait(c);
 }
 
 }  // extern "C"
@@ -739,6 +804,7 @@ static mcx_status fluence_host(mcx_ctx* c, int32_t sim, int32_t kind, void* host
   double scale = 1.0;
   MCX_TRY(scale_for(sh, kind, &scale));
   HIP_TRY(hipSetDevice(c->device));
+  MCX_TRY(wait_done(c, c->stream));
   const double* tally = c->d_tally + sh.tally_off;
   if (f64) {
     if (!c->d_stage64) HIP_TRY(hipMalloc(&c->d_stage64, c->max_cells * sizeof(double)));
@@ -759,7 +825,7 @@ static mcx_status stats_of(mcx_ctx* c, int32_t sim, mcx_run_stats* o) {
   MCX_TRY(check_sim(c, sim));
   if (!o) return fail(MCX_EINVAL, "output is NULL");
   HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  MCX_TRY(host_wait(c));
   double led[mcx::kLedgerN];
   unsigned long long cnt[mcx::kCountN];
   unsigned long long det_total = 0;
@@ -839,9 +905,11 @@ mcx_status mcx_fluence_device(mcx_ctx* c, int32_t kind, float* dev_out, uint64_t
   double scale = 1.0;
   MCX_TRY(scale_for(sh, kind, &scale));
   HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(mcx::launch_normalise_f32(c->d_tally + sh.tally_off, sh.ncells(), scale, dev_out,
-                                    pick_stream(c, stream)));
-  return MCX_OK;
+  hipStream_t st = pick_stream(c, stream);
+  MCX_TRY(wait_done(c, st));
+  HIP_TRY(mcx::launch_normalise_f32(c->d_tally + sh.tally_off, sh.ncells(), scale, dev_out, st));
+  // a later clear or launch must not overwrite the tally before this reads it
+  return mark_done(c, st);
 }
 
 }  // extern "C"
@@ -851,7 +919,7 @@ static mcx_status detected_of(mcx_ctx* c, int32_t sim, float* host_rec, uint64_t
   MCX_TRY(check_sim(c, sim));
   if (cap > 0 && !host_rec) return fail(MCX_EINVAL, "record buffer is NULL");
   HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  MCX_TRY(host_wait(c));
   const SimHost& sh = c->sims[sim];
   unsigned long long total = 0;
   HIP_TRY(hipMemcpy(&total, c->d_det_count + sim, sizeof(total), hipMemcpyDeviceToHost));
@@ -878,7 +946,7 @@ static mcx_status digest_of(mcx_ctx* c, int32_t sim, double* host_out, uint64_t 
     return fail(MCX_ERANGE, "only %llu digest rows are kept",
                 static_cast<unsigned long long>(c->opt.ndigest));
   HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  MCX_TRY(host_wait(c));
   HIP_TRY(hipMemcpy(host_out, c->d_digest + sim * c->opt.ndigest * mcx::kDigestN,
                     nrows * mcx::kDigestN * sizeof(double), hipMemcpyDeviceToHost));
   return MCX_OK;
@@ -897,6 +965,139 @@ mcx_status mcx_batch_detected(mcx_ctx* c, int32_t sim, float* host_rec, uint64_t
 }
 
 mcx_status mcx_stats(mcx_ctx* c, mcx_run_stats* o) { return stats_of(c, 0, o); }
+
+}  // extern "C"
+
+// ------------------------------------------ detected-photon post-processing
+
+static mcx_status check_detpost(const mcx_detpost* sp) {
+  if (!sp) return fail(MCX_EINVAL, "post-processing spec is NULL");
+  if (sp->ndet < 1 || sp->ndet > 4096) return fail(MCX_EINVAL, "ndet must be in [1, 4096]");
+  if (sp->npath < 1 || sp->npath > 255) return fail(MCX_EINVAL, "npath must be in [1, 255]");
+  if (!(sp->dt_ns > 0.f) || !finite(sp->dt_ns) || !finite(sp->t0_ns))
+    return fail(MCX_EINVAL, "gate width must be positive and t0 finite");
+  if (sp->ngates < 1 || sp->ngates > mcx::kDetpostHistMax - 2)
+    return fail(MCX_EINVAL, "ngates must be in [1, %d]", mcx::kDetpostHistMax - 2);
+  return MCX_OK;
+}
+
+static mcx::DetpostArgs detpost_args(const float* rec, uint64_t nrec, const mcx_detpost& sp,
+                                     const float* dmua, double* out, double* weight) {
+  mcx::DetpostArgs a{};
+  a.rec = rec;
+  a.nrec = nrec;
+  a.npath = sp.npath;
+  a.rec_len = 4 + sp.npath;
+  a.dmua = dmua;
+  a.ndet = sp.ndet;
+  a.t0 = sp.t0_ns;
+  a.dt = sp.dt_ns;
+  a.ngates = sp.ngates;
+  a.nphoton = sp.nphoton;
+  a.out = out;
+  a.weight_out = weight;
+  return a;
+}
+
+// Doubles of partial sums the passes over `a` need with nblocks workgroups.
+static uint64_t detpost_workspace(const mcx::DetpostArgs& a, int nblocks) {
+  const int per = std::min(a.ndet, mcx::detpost_dets_per_pass(a.ngates));
+  return static_cast<uint64_t>(nblocks) * per * (2 + a.ngates);
+}
+
+// Every pass over detector ranges, partial sums in `ws`.
+static mcx_status detpost_passes(const mcx::DetpostArgs& a, double* ws, int nblocks,
+                                 hipStream_t st) {
+  const int per = mcx::detpost_dets_per_pass(a.ngates);
+  for (int lo = 0; lo < a.ndet; lo += per)
+    HIP_TRY(mcx::launch_detpost(a, ws, nblocks, lo, std::min(a.ndet, lo + per), st));
+  return MCX_OK;
+}
+
+// Grow a lazily allocated device buffer to at least n elements.
+template <typename T>
+static mcx_status ensure(T** p, uint64_t* cap, uint64_t n) {
+  if (*cap >= n && *p) return MCX_OK;
+  if (*p) HIP_TRY(hipFree(*p));
+  *p = nullptr;
+  *cap = 0;
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(p), std::max<uint64_t>(n, 1) * sizeof(T)));
+  *cap = n;
+  return MCX_OK;
+}
+
+extern "C" {
+
+mcx_status mcx_detpost_device(const float* dev_rec, uint64_t nrec, const mcx_detpost* spec,
+                              const float* dev_dmua, double* dev_out, double* dev_weight,
+                              void* stream) {
+  MCX_TRY(check_detpost(spec));
+  if (nrec > 0 && !dev_rec) return fail(MCX_EINVAL, "records are NULL");
+  if (!dev_out) return fail(MCX_EINVAL, "output is NULL");
+  if (nrec > (1ull << 40)) return fail(MCX_EINVAL, "too many records");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const mcx::DetpostArgs a = detpost_args(dev_rec, nrec, *spec, dev_dmua, dev_out, dev_weight);
+  const int nblocks = mcx::detpost_blocks(nrec);
+  double* ws = nullptr;
+  HIP_TRY(hipMalloc(&ws, detpost_workspace(a, nblocks) * sizeof(double)));
+  mcx_status r = detpost_passes(a, ws, nblocks, st);
+  const hipError_t e = hipStreamSynchronize(st);
+  (void)hipFree(ws);
+  if (r != MCX_OK) return r;
+  if (e != hipSuccess) return fail(MCX_EDEVICE, "post-processing: %s", hipGetErrorString(e));
+  return MCX_OK;
+}
+
+mcx_status mcx_detected_process(mcx_ctx* c, int32_t sim, const float* host_dmua,
+                                double* host_out, uint64_t nout, double* host_weight,
+                                uint64_t nweight) {
+  MCX_TRY(check_sim(c, sim));
+  const SimHost& sh = c->sims[sim];
+  if (sh.ndet <= 0) return fail(MCX_EINVAL, "simulation %d has no detectors", sim);
+  if (!host_out) return fail(MCX_EINVAL, "output is NULL");
+  mcx_detpost sp{};
+  sp.ndet = sh.ndet;
+  sp.npath = sh.nmedia - 1;
+  sp.t0_ns = sh.t0;
+  sp.dt_ns = sh.dt;
+  sp.ngates = sh.ngates;
+  sp.nphoton = sh.photons;
+  MCX_TRY(check_detpost(&sp));
+  const uint64_t nres = static_cast<uint64_t>(sp.ndet) * (2 + sp.ngates);
+  if (nout < nres)
+    return fail(MCX_ERANGE, "output holds %llu values, need %llu",
+                static_cast<unsigned long long>(nout), static_cast<unsigned long long>(nres));
+  if (sh.photons == 0) return fail(MCX_ESTATE, "no photons simulated since the last reset");
+  HIP_TRY(hipSetDevice(c->device));
+  MCX_TRY(host_wait(c));
+  unsigned long long total = 0;
+  HIP_TRY(hipMemcpy(&total, c->d_det_count + sim, sizeof(total), hipMemcpyDeviceToHost));
+  const uint64_t nrec = std::min<uint64_t>(total, c->d_rec ? c->opt.max_detected : 0);
+  if (host_weight && nweight < nrec)
+    return fail(MCX_ERANGE, "weight buffer holds %llu values, need %llu",
+                static_cast<unsigned long long>(nweight), static_cast<unsigned long long>(nrec));
+  const float* dmua = nullptr;
+  if (host_dmua) {
+    if (!c->d_dmua) HIP_TRY(hipMalloc(&c->d_dmua, 256 * sizeof(float)));
+    HIP_TRY(hipMemcpyAsync(c->d_dmua, host_dmua, sp.npath * sizeof(float),
+                           hipMemcpyHostToDevice, c->stream));
+    dmua = c->d_dmua;
+  }
+  MCX_TRY(ensure(&c->d_post, &c->post_cap, nres));
+  if (host_weight) MCX_TRY(ensure(&c->d_post_w, &c->post_w_cap, nrec));
+  const mcx::DetpostArgs a = detpost_args(c->d_rec ? c->d_rec + sh.rec_foff : nullptr, nrec, sp,
+                                          dmua, c->d_post, host_weight ? c->d_post_w : nullptr);
+  const int nblocks = mcx::detpost_blocks(nrec);
+  MCX_TRY(ensure(&c->d_post_ws, &c->post_ws_cap, detpost_workspace(a, nblocks)));
+  MCX_TRY(detpost_passes(a, c->d_post_ws, nblocks, c->stream));
+  HIP_TRY(hipMemcpyAsync(host_out, c->d_post, nres * sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream));
+  if (host_weight && nrec > 0)
+    HIP_TRY(hipMemcpyAsync(host_weight, c->d_post_w, nrec * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MCX_OK;
+}
 
 mcx_status mcx_batch_stats(mcx_ctx* c, int32_t sim, mcx_run_stats* o) {
   return stats_of(c, sim, o);
@@ -920,7 +1121,7 @@ mcx_status mcx_set_launch(mcx_ctx* c, int32_t block_size, int32_t refill_chunk,
   if (lds_window_cells > kMaxWindow)
     return fail(MCX_EINVAL, "lds_window_cells must be <= %d", kMaxWindow);
   HIP_TRY(hipSetDevice(c->device));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  MCX_TRY(host_wait(c));
   set_window(c, lds_window_cells == 0 ? kDefaultWindow : lds_window_cells);
   c->chunk = refill_chunk > 0 ? refill_chunk : kDefaultChunk;
   return set_shape(c, block_size);
@@ -992,11 +1193,88 @@ mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_
     n_half += half[i];
   }
   if (n_full > n_half) {
-    out->ms_per_photon = (t_full - t_half) / static_cast<double>(n_full - n_half);
-    out->overhead_ms = t_full - out->ms_per_photon * static_cast<double>(n_full);
+    const double xs[2] = {static_cast<double>(n_half), static_cast<double>(n_full)};
+    const double ts[2] = {t_half, t_full};
+    MCX_TRY(mcx_fit_linear(xs, ts, 2, &out->ms_per_photon, &out->overhead_ms));
   }
   MCX_TRY(clear_all(c, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return MCX_OK;
+}
+
+mcx_status mcx_fit_linear(const double* x, const double* y, int32_t k, double* a, double* b) {
+  if (!x || !y || !a || !b) return fail(MCX_EINVAL, "points and outputs are required");
+  if (k < 2) return fail(MCX_EINVAL, "need at least 2 points (got %d)", k);
+  double mx = 0.0, my = 0.0;
+  for (int i = 0; i < k; ++i) {
+    if (!std::isfinite(x[i]) || !std::isfinite(y[i]))
+      return fail(MCX_EINVAL, "point %d is not finite", i);
+    mx += x[i];
+    my += y[i];
+  }
+  mx /= k;
+  my /= k;
+  double sxx = 0.0, sxy = 0.0;
+  for (int i = 0; i < k; ++i) {
+    sxx += (x[i] - mx) * (x[i] - mx);
+    sxy += (x[i] - mx) * (y[i] - my);
+  }
+  if (!(sxx > 0.0)) return fail(MCX_EINVAL, "the points need at least two distinct x");
+  *a = sxy / sxx;
+  *b = my - *a * mx;
+  return MCX_OK;
+}
+
+mcx_status mcx_fit_runtime(mcx_ctx* c, const uint64_t* n1, const uint64_t* n2,
+                           const uint64_t* seed, double* a, double* t0) {
+  if (!c || !seed || !a || !t0) return fail(MCX_EINVAL, "context, seeds and outputs are required");
+  const size_t ns = c->sims.size();
+  std::vector<uint64_t> p1(ns, 1000000), p2(ns, 5000000);
+  for (size_t i = 0; i < ns; ++i) {
+    if (n1) p1[i] = n1[i];
+    if (n2) p2[i] = n2[i];
+    if (p1[i] == p2[i] || p1[i] == 0 || p2[i] == 0)
+      return fail(MCX_EINVAL, "simulation %zu: pilot sizes must be distinct and positive", i);
+    if (p1[i] > kMaxLaunchPhotons || p2[i] > kMaxLaunchPhotons)
+      return fail(MCX_EINVAL, "simulation %zu: pilots are limited to 2^31 photons", i);
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  std::vector<uint64_t> zero(ns, 0), n(ns, 0);
+  auto pilot = [&](size_t i, uint64_t count, float* ms) -> mcx_status {
+    std::fill(n.begin(), n.end(), 0);
+    n[i] = count;
+    MCX_TRY(clear_all(c, c->stream));
+    MCX_TRY(enqueue(c, zero.data(), n.data(), seed, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipEventElapsedTime(ms, c->ev_k0, c->ev_k1));
+    return MCX_OK;
+  };
+  float warm = 0.f;
+  MCX_TRY(pilot(0, p1[0], &warm));  // first launch: caches and code cold
+  for (size_t i = 0; i < ns; ++i) {
+    float m1 = 0.f, m2 = 0.f;
+    MCX_TRY(pilot(i, p1[i], &m1));
+    MCX_TRY(pilot(i, p2[i], &m2));
+    const double xs[2] = {static_cast<double>(p1[i]), static_cast<double>(p2[i])};
+    const double ts[2] = {m1, m2};
+    MCX_TRY(mcx_fit_linear(xs, ts, 2, a + i, t0 + i));
+  }
+  MCX_TRY(clear_all(c, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MCX_OK;
+}
+
+mcx_status mcx_set_balance(mcx_ctx* c, const double* cost_per_photon) {
+  if (!c) return fail(MCX_EINVAL, "context is NULL");
+  if (!cost_per_photon) {
+    c->cost.clear();
+    return MCX_OK;
+  }
+  const size_t ns = c->sims.size();
+  for (size_t i = 0; i < ns; ++i)
+    if (!(cost_per_photon[i] >= 0.0) || !std::isfinite(cost_per_photon[i]))
+      return fail(MCX_EINVAL, "simulation %zu: cost per photon must be finite and >= 0", i);
+  c->cost.assign(cost_per_photon, cost_per_photon + ns);
   return MCX_OK;
 }
 

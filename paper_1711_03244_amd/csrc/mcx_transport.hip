@@ -280,20 +280,23 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   int pend_sim = 0;
   uint64_t pend_first = 0, pend_end = 0;
   const MCX_CONST uint64_t* js = as_const(L.job_start);
-  // Home simulation: the one holding job ((2 v + 1) / 2) * njobs / nwaves,
-  // where v numbers the waves so that the workgroups of one XCD (dispatched
-  // round-robin over the 8 XCDs) are consecutive; the waves of a simulation
-  // then share an XCD and its L2 as far as the counts allow.
+  const MCX_CONST uint64_t* hs = as_const(L.home_start);
+  // Home simulation: the one whose share of home_start holds point
+  // ((2 v + 1) / 2) * nhome / nwaves -- shares are the simulations' job
+  // counts, or their estimated work (device-level balancing by throughput)
+  // -- where v numbers the waves so that the workgroups of one XCD
+  // (dispatched round-robin over the 8 XCDs) are consecutive; the waves of a
+  // simulation then share an XCD and its L2 as far as the shares allow.
   const uint32_t nb = gridDim.x;
   const uint32_t vb = (nb % 8u == 0u) ? (blockIdx.x % 8u) * (nb / 8u) + blockIdx.x / 8u
                                       : blockIdx.x;
   const uint64_t wpb = bdim >> 6;
   auto home_of = [&](uint64_t v) -> int {
-    const uint64_t target = ((2 * v + 1) * L.njobs) / (2 * nb * wpb);
-    int lo = 0, hi = L.nsims;  // job_start[lo] <= target < job_start[hi]
+    const uint64_t target = ((2 * v + 1) * L.nhome) / (2 * nb * wpb);
+    int lo = 0, hi = L.nsims;  // home_start[lo] <= target < home_start[hi]
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (js[mid] <= target) lo = mid; else hi = mid;
+      if (hs[mid] <= target) lo = mid; else hi = mid;
     }
     return lo;
   };
@@ -443,7 +446,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
     // ----------------------------------------------------------------- event
     int end = kAlive;
     int det_hit = -1;
-    bool f_scat = false, f_face = false, f_fres = false, f_flush = false, f_flush2 = false;
+    bool f_scat = false, f_face = false, f_fres = false;
+    int n_flush = 0;  // global atomics this lane issued in this iteration (at most 3)
     if (alive) {
       if (nev >= L.max_events) {
         end = kEndCapped;
@@ -502,7 +506,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
         } else {
           if (old_cell != 0xffffffffu && old_acc != 0.f) {
             deposit(D->tally, s_win, old_cell, old_slot, old_acc);
-            f_flush = old_slot < 0;
+            n_flush += old_slot < 0;
           }
           old_cell = acc_cell;
           old_slot = acc_slot;
@@ -635,11 +639,11 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
       if (end != kAlive) {
         if (acc != 0.f && acc_cell != 0xffffffffu) {
           deposit(D->tally, s_win, acc_cell, acc_slot, acc);
-          f_flush = acc_slot < 0;
+          n_flush += acc_slot < 0;
         }
         if (old_acc != 0.f && old_cell != 0xffffffffu) {
           deposit(D->tally, s_win, old_cell, old_slot, old_acc);
-          f_flush2 = old_slot < 0;
+          n_flush += old_slot < 0;
         }
         const double wd = static_cast<double>(w);
         const int end_slot = end == kEndEscape ? kCntEscaped
@@ -705,7 +709,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
     c_scat += wave_count(f_scat);
     c_face += wave_count(f_face);
     c_fres += wave_count(f_fres);
-    c_flush += wave_count(f_flush) + wave_count(f_flush2);
+    c_flush += wave_count(n_flush >= 1) + wave_count(n_flush >= 2) +
+               wave_count(n_flush >= 3);
   }
   flush_wave();
 

@@ -33,7 +33,8 @@ EXPORTS = ["mcx_default_options", "mcx_create", "mcx_run", "mcx_run_range", "mcx
            "mcx_batch_create", "mcx_batch_size", "mcx_batch_ncells", "mcx_batch_run",
            "mcx_batch_run_range", "mcx_batch_fluence", "mcx_batch_fluence_f64",
            "mcx_batch_stats", "mcx_batch_detected", "mcx_batch_digest", "mcx_set_launch",
-           "mcx_autotune"]
+           "mcx_autotune", "mcx_detpost_device", "mcx_detected_process", "mcx_fit_linear",
+           "mcx_fit_runtime", "mcx_set_balance"]
 
 
 class McxError(RuntimeError):
@@ -82,6 +83,11 @@ class mcx_options(C.Structure):
                 ("device", C.c_int32), ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_chunk", C.c_int32), ("ndigest", C.c_uint64),
                 ("lds_window_cells", C.c_int32), ("accurate_math", C.c_int32)]
+
+
+class mcx_detpost(C.Structure):
+    _fields_ = [("ndet", C.c_int32), ("npath", C.c_int32), ("t0_ns", C.c_float),
+                ("dt_ns", C.c_float), ("ngates", C.c_int32), ("nphoton", C.c_uint64)]
 
 
 class mcx_run_stats(C.Structure):
@@ -147,6 +153,12 @@ def lib() -> C.CDLL:
             "mcx_batch_digest": (C.c_int, [vp, i32, vp, u64]),
             "mcx_set_launch": (C.c_int, [vp, i32, i32, i32]),
             "mcx_autotune": (C.c_int, [vp, vp, vp, C.POINTER(mcx_tune_result)]),
+            "mcx_detpost_device": (C.c_int, [vp, u64, C.POINTER(mcx_detpost), vp, vp, vp, vp]),
+            "mcx_detected_process": (C.c_int, [vp, i32, vp, vp, u64, vp, u64]),
+            "mcx_fit_linear": (C.c_int, [vp, vp, i32, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]),
+            "mcx_fit_runtime": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+            "mcx_set_balance": (C.c_int, [vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -286,6 +298,41 @@ def mcx_autotune(ctx, pilot_photons, seed) -> dict:
     return {name: getattr(r, name) for name, _ in mcx_tune_result._fields_}
 
 
+def mcx_fit_linear(x, y):
+    """Least-squares line y = a x + b (host only); returns (a, b)."""
+    xs = np.ascontiguousarray(np.asarray(x, np.float64))
+    ys = np.ascontiguousarray(np.asarray(y, np.float64))
+    if xs.shape != ys.shape:
+        raise ValueError("x and y differ in length")
+    a, b = C.c_double(), C.c_double()
+    _check(lib().mcx_fit_linear(xs.ctypes.data, ys.ctypes.data, xs.size, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def mcx_fit_runtime(ctx, n1=None, n2=None, seed=None):
+    """T = a n + T0 per simulation from pilots of n1 and n2 photons (None:
+    1e6 and 5e6); returns (a, t0) arrays (ms per photon, ms)."""
+    ns = mcx_batch_size(ctx)
+    a, t0 = np.zeros(ns), np.zeros(ns)
+    u1 = _u64(n1) if n1 is not None else None
+    u2 = _u64(n2) if n2 is not None else None
+    sd = _u64(seed if seed is not None else [1] * ns)
+    _check(lib().mcx_fit_runtime(ctx, u1.ctypes.data if u1 is not None else None,
+                                 u2.ctypes.data if u2 is not None else None, sd.ctypes.data,
+                                 a.ctypes.data, t0.ctypes.data))
+    return a, t0
+
+
+def mcx_set_balance(ctx, cost_per_photon=None):
+    """Home waves by estimated work cost_i n_i (None: by job counts)."""
+    if cost_per_photon is None:
+        _check(lib().mcx_set_balance(ctx, None))
+        return
+    c = np.ascontiguousarray(np.asarray(cost_per_photon, np.float64))
+    assert c.size == mcx_batch_size(ctx)
+    _check(lib().mcx_set_balance(ctx, c.ctypes.data))
+
+
 def mcx_create(p, **options) -> C.c_void_p:
     """Create a context for a workloads.Problem; keyword arguments override
     mcx_options fields (block_size, refill_chunk, ndigest, device, ...)."""
@@ -342,11 +389,12 @@ def mcx_fluence_f64(ctx, kind: int = MCX_FLUENCE, out: Optional[np.ndarray] = No
 
 def mcx_fluence_device(ctx, kind: int, tensor, stream=None):
     """Write the normalised map into a contiguous float32 torch tensor on the
-    context's device (enqueued on `stream`, default torch's current stream)."""
+    context's device, enqueued on `stream` (None: the context's own stream,
+    as for every other call here; pass torch.cuda.current_stream() to have
+    torch's later work on that stream see the result).  The library orders
+    it after the context's last clear or launch on any stream."""
     import torch
     assert tensor.is_cuda and tensor.dtype == torch.float32 and tensor.is_contiguous()
-    if stream is None:
-        stream = torch.cuda.current_stream(tensor.device)
     _check(lib().mcx_fluence_device(ctx, int(kind), C.c_void_p(tensor.data_ptr()),
                                     tensor.numel(), _stream(stream)))
     return tensor
@@ -372,6 +420,52 @@ def mcx_digest(ctx, nrows: int) -> np.ndarray:
     out = np.zeros((nrows, len(DIGEST)), np.float64)
     _check(lib().mcx_digest(ctx, out.ctypes.data, nrows))
     return out
+
+
+def mcx_detpost_device(rec, spec: dict, dmua=None, out=None, weight=None, stream=None):
+    """Post-process detector records held in a float32 torch tensor (nrec,
+    4 + npath) on the GPU: `spec` has ndet, npath, t0, dt, ngates, nphoton;
+    `dmua` an optional float32 device tensor of npath absorption changes.
+    Returns the (ndet, 2 + ngates) float64 device tensor `out` (count,
+    reflectance, TPSF per gate) and, if `weight` is given or True, the
+    re-weighted weight of every record."""
+    import torch
+    assert rec.is_cuda and rec.dtype == torch.float32 and rec.is_contiguous()
+    sp = mcx_detpost(int(spec["ndet"]), int(spec["npath"]), float(spec["t0"]),
+                     float(spec["dt"]), int(spec["ngates"]), int(spec["nphoton"]))
+    nrec = rec.shape[0] if rec.dim() == 2 else 0
+    if nrec:
+        assert rec.shape[1] == 4 + sp.npath, "records need 4 + npath columns"
+    if out is None:
+        out = torch.empty((sp.ndet, 2 + sp.ngates), dtype=torch.float64, device=rec.device)
+    if weight is True:
+        weight = torch.empty(nrec, dtype=torch.float64, device=rec.device)
+    if dmua is not None:
+        assert dmua.is_cuda and dmua.dtype == torch.float32 and dmua.numel() >= sp.npath
+    _check(lib().mcx_detpost_device(C.c_void_p(rec.data_ptr()) if nrec else None, nrec,
+                                    C.byref(sp),
+                                    C.c_void_p(dmua.data_ptr()) if dmua is not None else None,
+                                    C.c_void_p(out.data_ptr()),
+                                    C.c_void_p(weight.data_ptr()) if weight is not None else None,
+                                    _stream(stream)))
+    return out, weight
+
+
+def mcx_detected_process(ctx, sim: int, ndet: int, ngates: int, npath: int, dmua=None,
+                         weights: bool = False, nrec: int = 0):
+    """Post-process the stored records of simulation `sim` on the GPU:
+    returns (out (ndet, 2 + ngates) float64, weights of the nrec records in
+    record order or None)."""
+    out = np.zeros((ndet, 2 + ngates), np.float64)
+    w = np.zeros(max(nrec, 1), np.float64) if weights else None
+    d = None if dmua is None else np.ascontiguousarray(np.asarray(dmua, np.float32).ravel()[:npath])
+    if d is not None and d.size < npath:
+        raise ValueError(f"need {npath} absorption changes")
+    _check(lib().mcx_detected_process(ctx, int(sim), d.ctypes.data if d is not None else None,
+                                      out.ctypes.data, out.size,
+                                      w.ctypes.data if w is not None else None,
+                                      w.size if w is not None else 0))
+    return out, (w[:nrec] if w is not None else None)
 
 
 def mcx_destroy(ctx):
@@ -407,8 +501,8 @@ class Batch:
         mcx_batch_run_range(self.ctx, first, n, seed, stream)
         return self
 
-    def reset(self):
-        mcx_reset(self.ctx)
+    def reset(self, stream=None):
+        mcx_reset(self.ctx, stream)
 
     def sync(self):
         mcx_sync(self.ctx)
@@ -428,11 +522,23 @@ class Batch:
     def digest(self, sim: int, nrows: Optional[int] = None) -> np.ndarray:
         return mcx_batch_digest(self.ctx, sim, self.ndigest if nrows is None else nrows)
 
+    def detected_process(self, sim: int, dmua=None, weights: bool = False):
+        p = self.problems[sim]
+        nrec = int(self.stats(sim)["det_records"]) if weights else 0
+        return mcx_detected_process(self.ctx, sim, p.ndet, p.ngates, p.nmedia - 1, dmua,
+                                    weights, nrec)
+
     def autotune(self, pilot_photons, seed) -> dict:
         return mcx_autotune(self.ctx, pilot_photons, seed)
 
     def set_launch(self, block_size=0, refill_chunk=0, lds_window_cells=0):
         mcx_set_launch(self.ctx, block_size, refill_chunk, lds_window_cells)
+
+    def fit_runtime(self, n1=None, n2=None, seed=None):
+        return mcx_fit_runtime(self.ctx, n1, n2, seed)
+
+    def set_balance(self, cost_per_photon=None):
+        mcx_set_balance(self.ctx, cost_per_photon)
 
     def close(self):
         if self.ctx:
@@ -468,8 +574,8 @@ class Simulation:
         mcx_run_range(self.ctx, first, n, seed, stream)
         return self
 
-    def reset(self):
-        mcx_reset(self.ctx)
+    def reset(self, stream=None):
+        mcx_reset(self.ctx, stream)
 
     def sync(self):
         mcx_sync(self.ctx)
@@ -489,8 +595,22 @@ class Simulation:
     def digest(self, nrows: Optional[int] = None) -> np.ndarray:
         return mcx_digest(self.ctx, self.ndigest if nrows is None else nrows)
 
+    def detected_process(self, dmua=None, weights: bool = False):
+        """Per-detector record count, reflectance and TPSF (and optionally
+        the re-weighted record weights) from the stored detector records,
+        for absorption changes dmua (one per medium 1..nmedia-1)."""
+        p = self.problem
+        nrec = int(self.stats()["det_records"]) if weights else 0
+        return mcx_detected_process(self.ctx, 0, p.ndet, p.ngates, p.nmedia - 1, dmua,
+                                    weights, nrec)
+
     def autotune(self, pilot_photons: int, seed: int) -> dict:
         return mcx_autotune(self.ctx, [pilot_photons], [seed])
+
+    def fit_runtime(self, n1: int = 1_000_000, n2: int = 5_000_000, seed: int = 1):
+        """The paper's T = a n + T0 from two pilots; returns (a, t0)."""
+        a, t0 = mcx_fit_runtime(self.ctx, [n1], [n2], [seed])
+        return float(a[0]), float(t0[0])
 
     def set_launch(self, block_size=0, refill_chunk=0, lds_window_cells=0):
         mcx_set_launch(self.ctx, block_size, refill_chunk, lds_window_cells)

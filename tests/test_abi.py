@@ -50,6 +50,26 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(mcx.mcx_gates) == 12
     assert C.sizeof(mcx.mcx_options) == 4 * 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4
     assert C.sizeof(mcx.mcx_run_stats) == 17 * 8 + 11 * 8 + 8
+    assert C.sizeof(mcx.mcx_detpost) == 5 * 4 + 4 + 8
+
+
+@pytest.mark.parametrize("bad", [dict(ndet=0), dict(ndet=5000), dict(npath=0), dict(npath=256),
+                                 dict(dt_ns=0.0), dict(dt_ns=float("nan")),
+                                 dict(t0_ns=float("inf")), dict(ngates=0), dict(ngates=8191)])
+def test_detpost_spec_checked_before_the_gpu(bad):
+    """Every invalid post-processing spec is refused before any HIP call
+    (the record and output pointers are never touched)."""
+    spec = dict(ndet=4, npath=2, t0_ns=0.0, dt_ns=0.1, ngates=50, nphoton=1000)
+    spec.update(bad)
+    sp = mcx.mcx_detpost(spec["ndet"], spec["npath"], spec["t0_ns"], spec["dt_ns"],
+                         spec["ngates"], spec["nphoton"])
+    st = mcx.lib().mcx_detpost_device(None, 0, C.byref(sp), None, None, None, None)
+    assert st == mcx.MCX_EINVAL, mcx.mcx_last_error()
+    st = mcx.lib().mcx_detpost_device(None, 10, C.byref(sp), None, None, None, None)
+    assert st == mcx.MCX_EINVAL
+    assert mcx.lib().mcx_detpost_device(None, 0, None, None, None, None, None) == mcx.MCX_EINVAL
+    out = (C.c_double * 8)()
+    assert mcx.lib().mcx_detected_process(None, 0, None, out, 8, None, 0) == mcx.MCX_EINVAL
 
 
 BAD = {

@@ -296,3 +296,51 @@ def test_batch_detector_records_of_several_simulations():
         o1, o2 = np.argsort(ph), np.argsort(ph1)
         assert np.array_equal(ph[o1], ph1[o2]), p.name
         assert np.array_equal(rec[o1], rec1[o2]), p.name
+
+
+def test_throughput_balanced_homes_keep_every_photon_history():
+    """The paper's device-level balancing by throughput (S2), applied to the
+    simulations of one launch: per-simulation T = a n + T0 from two timed
+    pilots, then home waves in proportion to a_i n_i.  Only the schedule
+    changes: counts, per-photon digests and tallies equal the job-count
+    split's."""
+    items = W.batch_workload(nsims=12, seed=7, scale=0.01)
+    probs = [it.problem for it in items]
+    n = [it.nphoton for it in items]
+    seeds = [it.seed for it in items]
+    nd = max(n)
+    say(f"[gpu] 12-cube batch, N={n}")
+    with mcx.Batch(probs, ndigest=nd) as b:
+        b.run(n, seeds)
+        base = [(b.stats(i), b.digest(i), b.fluence(i, mcx.MCX_RAW, f64=True))
+                for i in range(len(probs))]
+        a, t0 = b.fit_runtime([20_000] * len(probs), [100_000] * len(probs), seeds)
+        say("a (ms/photon)", a, "T0 (ms)", t0)
+        assert np.all(np.isfinite(a)) and np.all(np.isfinite(t0))
+        b.set_balance(np.maximum(a, 0.0))
+        b.run(n, seeds)
+        for i in range(len(probs)):
+            st, dg, raw = b.stats(i), b.digest(i), b.fluence(i, mcx.MCX_RAW, f64=True)
+            for k in COUNT_KEYS:
+                assert st[k] == base[i][0][k], (i, k)
+            assert np.array_equal(dg[:n[i]], base[i][1][:n[i]]), i
+            big = base[i][2] > 1e-9 * base[i][2].max()
+            assert np.allclose(raw[big], base[i][2][big], rtol=1e-10), i
+        b.set_balance(None)
+        with pytest.raises(mcx.McxError):
+            b.set_balance([-1.0] * len(probs))
+
+
+def test_runtime_model_from_the_papers_pilots():
+    """T = a n + T0 from pilots of 1e6 and 5e6 photons (the paper's sizes) on
+    the sphere benchmark: a positive slope, and a prediction for 2e7 photons
+    within 30 % of the measured kernel time (logged)."""
+    p = W.cube_sphere()
+    with mcx.Simulation(p) as sim:
+        a, t0 = sim.fit_runtime(1_000_000, 5_000_000, 1)
+        sim.run(20_000_000, 2)
+        t = sim.stats()["kernel_ms"]
+    pred = a * 20_000_000 + t0
+    say("a", a, "ms/photon (", 1 / a, "photons/ms ), T0", t0, "ms; 2e7 photons predicted", pred,
+        "measured", t)
+    assert a > 0 and abs(pred / t - 1) < 0.3
