@@ -32,25 +32,53 @@ __device__ __forceinline__ uint32_t mix(uint32_t x) {
 
 // Each thread performs `iters` atomics; the index is a hash of (thread,
 // iteration) masked to `mask` (a power of two minus one), or fixed among
-// `hot` addresses when hot > 0.
+// `hot` addresses when hot > 0.  Modes: 0 FP32 no return, 1 FP32 with the
+// returned value used, 2 FP64 no return, 3 64-bit integer no return, 4 32-bit
+// integer no return, 5 FP64 no return with the 64 lanes of a wave on 64
+// consecutive cells (8 cache lines of 64 B per instruction).
 template <int kMode>
 __global__ void __launch_bounds__(256) atomic_kernel(float* f32, double* f64, uint32_t mask,
                                                      uint32_t hot, int iters, float* sink) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   float acc = 0.f;
   for (int i = 0; i < iters; ++i) {
-    const uint32_t h = mix(tid * 0x9E3779B9u + i);
-    const uint32_t idx = hot ? (h % hot) * 32u : (h & mask);
+    uint32_t h = mix(tid * 0x9E3779B9u + i);
+    if constexpr (kMode == 5) h = mix((tid >> 6) * 0x9E3779B9u + i);
+    uint32_t idx = hot ? (h % hot) * 32u : (h & mask);
+    if constexpr (kMode == 5) idx = hot ? idx : ((h & mask & ~63u) | (tid & 63u));
     const float v = 1.0f + (h & 0xff) * 1e-3f;
-    if constexpr (kMode == 0) {         // FP32, no return
+    if constexpr (kMode == 0) {
       unsafeAtomicAdd(f32 + idx, v);
-    } else if constexpr (kMode == 1) {  // FP32, returned value used
+    } else if constexpr (kMode == 1) {
       acc += unsafeAtomicAdd(f32 + idx, v);
-    } else {                            // FP64, no return
+    } else if constexpr (kMode == 2 || kMode == 5) {
       unsafeAtomicAdd(f64 + idx, static_cast<double>(v));
+    } else if constexpr (kMode == 3) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(f64) + idx,
+                static_cast<unsigned long long>(h & 0xffffu));
+    } else {
+      atomicAdd(reinterpret_cast<unsigned int*>(f32) + idx, h & 0xffffu);
     }
   }
   if (kMode == 1 && acc == -1.f) sink[0] = acc;
+}
+
+template <int kMode>
+static void launch_atomic(int grid, int block, float* f32, double* f64, uint32_t mask,
+                          uint32_t hot, int iters, float* sink) {
+  atomic_kernel<kMode><<<grid, block>>>(f32, f64, mask, hot, iters, sink);
+}
+
+static void launch_atomic_mode(int mode, int grid, int block, float* f32, double* f64,
+                               uint32_t mask, uint32_t hot, int iters, float* sink) {
+  switch (mode) {
+    case 0: launch_atomic<0>(grid, block, f32, f64, mask, hot, iters, sink); break;
+    case 1: launch_atomic<1>(grid, block, f32, f64, mask, hot, iters, sink); break;
+    case 2: launch_atomic<2>(grid, block, f32, f64, mask, hot, iters, sink); break;
+    case 3: launch_atomic<3>(grid, block, f32, f64, mask, hot, iters, sink); break;
+    case 4: launch_atomic<4>(grid, block, f32, f64, mask, hot, iters, sink); break;
+    default: launch_atomic<5>(grid, block, f32, f64, mask, hot, iters, sink); break;
+  }
 }
 
 // Independent FMA chains: 8 per thread, `iters` rounds.
@@ -161,25 +189,24 @@ int main(int argc, char** argv) {
   CHECK(hipEventCreate(&e0));
   CHECK(hipEventCreate(&e1));
 
-  const char* modes[3] = {"f32_noret", "f32_ret", "f64_noret"};
+  const char* modes[6] = {"f32_noret", "f32_ret", "f64_noret", "u64_noret", "u32_noret",
+                          "f64_noret_wave_lines"};
   // working sets in bytes of FP64 cells (FP32 uses half the bytes, same count)
   const uint64_t sets[] = {1ull << 20, 2ull << 20, 64ull << 20, 512ull << 20};
-  for (int mode = 0; mode < 3; ++mode) {
+  for (int mode = 0; mode < 6; ++mode) {
     for (uint64_t ws : sets) {
       const uint32_t cells = static_cast<uint32_t>(ws / 8);
       const uint32_t mask = cells - 1;
       for (int rep = 0; rep < 2; ++rep) {
         CHECK(hipEventRecord(e0));
-        if (mode == 0) atomic_kernel<0><<<grid, block>>>(f32, f64, mask, 0, iters, sink);
-        if (mode == 1) atomic_kernel<1><<<grid, block>>>(f32, f64, mask, 0, iters, sink);
-        if (mode == 2) atomic_kernel<2><<<grid, block>>>(f32, f64, mask, 0, iters, sink);
+        launch_atomic_mode(mode, grid, block, f32, f64, mask, 0, iters, sink);
         CHECK(hipEventRecord(e1));
         CHECK(hipEventSynchronize(e1));
         if (rep == 1) {
           const double ms = time_ms(e0, e1);
           printf("{\"bench\": \"atomic\", \"mode\": \"%s\", \"cells\": %u, \"working_set_MB\": %.1f, "
                  "\"atomics_per_s\": %.4g, \"ms\": %.3f}\n",
-                 modes[mode], cells, cells * (mode == 2 ? 8.0 : 4.0) / 1048576.0,
+                 modes[mode], cells, cells * (mode == 0 || mode == 1 || mode == 4 ? 4.0 : 8.0) / 1048576.0,
                  threads * iters / (ms * 1e-3), ms);
         }
       }
@@ -188,9 +215,7 @@ int main(int argc, char** argv) {
       for (int rep = 0; rep < 2; ++rep) {
         const int it = hot < 64 ? 4 : iters;
         CHECK(hipEventRecord(e0));
-        if (mode == 0) atomic_kernel<0><<<grid, block>>>(f32, f64, 0, hot, it, sink);
-        if (mode == 1) atomic_kernel<1><<<grid, block>>>(f32, f64, 0, hot, it, sink);
-        if (mode == 2) atomic_kernel<2><<<grid, block>>>(f32, f64, 0, hot, it, sink);
+        launch_atomic_mode(mode, grid, block, f32, f64, 0, hot, it, sink);
         CHECK(hipEventRecord(e1));
         CHECK(hipEventSynchronize(e1));
         if (rep == 1) {
