@@ -344,6 +344,25 @@ mcx_status mcx_detpost_device(const float *dev_rec, uint64_t nrec, const mcx_det
                               const float *dev_dmua, double *dev_out, double *dev_weight,
                               void *hip_stream);
 
+/* mcx_detpost_device for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, results and errors, but the partial sums go
+ * to a workspace the library keeps in device memory for the life of the
+ * process (128 x 8192 doubles, 8 MB per device, its address looked up on
+ * the first call on each device), and the call returns once the work is
+ * enqueued (no stream wait).  At most 128 workgroups per pass, so for more
+ * than 32768 records the partial sums are added in another order than
+ * mcx_detpost_device's (results agree to FP64 rounding).  A pass that would
+ * need more workspace than the library holds is rejected with MCX_ERANGE;
+ * none can with the current limits (ngates <= 8190, passes over detector
+ * ranges).  Every call on one device shares the workspace: calls that
+ * overlap on one device (different streams, or threads) race and must be
+ * ordered by the caller.  No hipMalloc, hipFree or allocating library
+ * routine is called. */
+mcx_status mcx_detpost_device_noalloc(const float *dev_rec, uint64_t nrec,
+                                      const mcx_detpost *spec, const float *dev_dmua,
+                                      double *dev_out, double *dev_weight, void *hip_stream);
+
 /* The same for the records simulation `sim` of a context holds (those
  * mcx_batch_detected would return, in the same order): ndet, npath and the
  * gates are the simulation's, nphoton the photons run since the last reset.

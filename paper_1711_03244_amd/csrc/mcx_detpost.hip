@@ -21,12 +21,20 @@
 // are processed in several passes over detector ranges.
 #include <math.h>
 
+#include <mutex>
+
 #include "mcx_detpost.hpp"
 
 namespace mcx {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kMaxDevices = 64;
+
+// Workspace of partial sums for callers that cannot allocate device memory.
+// In host code this name stands for the variable, not for its device
+// address: kernels get the address detpost_scratch() looks up.
+static __device__ __align__(256) double scratch[kDetpostScratch];
 
 __global__ void __launch_bounds__(kBlock)
     detpost_partial_kernel(const float* __restrict__ rec, uint64_t nrec, int rec_len, int npath,
@@ -88,6 +96,24 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 }  // namespace
+
+hipError_t detpost_scratch(double** ptr) {
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 int detpost_dets_per_pass(int ngates) {
   return kDetpostHistMax / (2 + ngates);

@@ -24,6 +24,13 @@ struct DetpostArgs {
   double* weight_out;   // device, nrec, or nullptr
 };
 
+// Workgroups of a pass of the entry point that allocates nothing, and the
+// doubles of its device-resident workspace: every pass (at most
+// kDetpostHistMax histogram entries per workgroup) fits it.
+constexpr int kDetpostNoallocBlocks = 128;
+constexpr uint64_t kDetpostScratch =
+    static_cast<uint64_t>(kDetpostNoallocBlocks) * kDetpostHistMax;  // 8 MB
+
 // Detectors one pass can hold, and the workgroups of a pass over nrec records.
 int detpost_dets_per_pass(int ngates);
 int detpost_blocks(uint64_t nrec);
@@ -33,5 +40,10 @@ int detpost_blocks(uint64_t nrec);
 // totals into a.out.  Pass det_lo = 0 also writes the re-weighted weights.
 hipError_t launch_detpost(const DetpostArgs& a, double* partial, int nblocks, int det_lo,
                           int det_hi, hipStream_t s);
+
+// Address, on the current device, of the library's own workspace of
+// kDetpostScratch doubles (looked up once per device, then cached).  The
+// workspace lives as long as the process; every call on a device shares it.
+hipError_t detpost_scratch(double** ptr);
 
 }  // namespace mcx

@@ -1048,6 +1048,25 @@ mcx_status mcx_detpost_device(const float* dev_rec, uint64_t nrec, const mcx_det
   return MCX_OK;
 }
 
+mcx_status mcx_detpost_device_noalloc(const float* dev_rec, uint64_t nrec,
+                                      const mcx_detpost* spec, const float* dev_dmua,
+                                      double* dev_out, double* dev_weight, void* stream) {
+  MCX_TRY(check_detpost(spec));
+  if (nrec > 0 && !dev_rec) return fail(MCX_EINVAL, "records are NULL");
+  if (!dev_out) return fail(MCX_EINVAL, "output is NULL");
+  if (nrec > (1ull << 40)) return fail(MCX_EINVAL, "too many records");
+  const mcx::DetpostArgs a = detpost_args(dev_rec, nrec, *spec, dev_dmua, dev_out, dev_weight);
+  const int nblocks = std::min(mcx::detpost_blocks(nrec), mcx::kDetpostNoallocBlocks);
+  const uint64_t need = detpost_workspace(a, nblocks);
+  if (need > mcx::kDetpostScratch)
+    return fail(MCX_ERANGE, "a pass needs %llu doubles of workspace, the library holds %llu",
+                static_cast<unsigned long long>(need),
+                static_cast<unsigned long long>(mcx::kDetpostScratch));
+  double* ws = nullptr;
+  HIP_TRY(mcx::detpost_scratch(&ws));
+  return detpost_passes(a, ws, nblocks, static_cast<hipStream_t>(stream));
+}
+
 mcx_status mcx_detected_process(mcx_ctx* c, int32_t sim, const float* host_dmua,
                                 double* host_out, uint64_t nout, double* host_weight,
                                 uint64_t nweight) {

@@ -33,7 +33,8 @@ EXPORTS = ["mcx_default_options", "mcx_create", "mcx_run", "mcx_run_range", "mcx
            "mcx_batch_create", "mcx_batch_size", "mcx_batch_ncells", "mcx_batch_run",
            "mcx_batch_run_range", "mcx_batch_fluence", "mcx_batch_fluence_f64",
            "mcx_batch_stats", "mcx_batch_detected", "mcx_batch_digest", "mcx_set_launch",
-           "mcx_autotune", "mcx_detpost_device", "mcx_detected_process", "mcx_fit_linear",
+           "mcx_autotune", "mcx_detpost_device", "mcx_detpost_device_noalloc",
+           "mcx_detected_process", "mcx_fit_linear",
            "mcx_fit_runtime", "mcx_set_balance"]
 
 
@@ -154,6 +155,8 @@ def lib() -> C.CDLL:
             "mcx_set_launch": (C.c_int, [vp, i32, i32, i32]),
             "mcx_autotune": (C.c_int, [vp, vp, vp, C.POINTER(mcx_tune_result)]),
             "mcx_detpost_device": (C.c_int, [vp, u64, C.POINTER(mcx_detpost), vp, vp, vp, vp]),
+            "mcx_detpost_device_noalloc": (C.c_int, [vp, u64, C.POINTER(mcx_detpost), vp, vp, vp,
+                                                     vp]),
             "mcx_detected_process": (C.c_int, [vp, i32, vp, vp, u64, vp, u64]),
             "mcx_fit_linear": (C.c_int, [vp, vp, i32, C.POINTER(C.c_double),
                                          C.POINTER(C.c_double)]),
@@ -422,13 +425,16 @@ def mcx_digest(ctx, nrows: int) -> np.ndarray:
     return out
 
 
-def mcx_detpost_device(rec, spec: dict, dmua=None, out=None, weight=None, stream=None):
+def mcx_detpost_device(rec, spec: dict, dmua=None, out=None, weight=None, stream=None,
+                       noalloc: bool = False):
     """Post-process detector records held in a float32 torch tensor (nrec,
     4 + npath) on the GPU: `spec` has ndet, npath, t0, dt, ngates, nphoton;
     `dmua` an optional float32 device tensor of npath absorption changes.
     Returns the (ndet, 2 + ngates) float64 device tensor `out` (count,
     reflectance, TPSF per gate) and, if `weight` is given or True, the
-    re-weighted weight of every record."""
+    re-weighted weight of every record.  noalloc=True calls
+    mcx_detpost_device_noalloc (the library's own workspace, no stream wait);
+    pass `out` (and a `weight` tensor) to keep the call free of allocations."""
     import torch
     assert rec.is_cuda and rec.dtype == torch.float32 and rec.is_contiguous()
     sp = mcx_detpost(int(spec["ndet"]), int(spec["npath"]), float(spec["t0"]),
@@ -442,12 +448,12 @@ def mcx_detpost_device(rec, spec: dict, dmua=None, out=None, weight=None, stream
         weight = torch.empty(nrec, dtype=torch.float64, device=rec.device)
     if dmua is not None:
         assert dmua.is_cuda and dmua.dtype == torch.float32 and dmua.numel() >= sp.npath
-    _check(lib().mcx_detpost_device(C.c_void_p(rec.data_ptr()) if nrec else None, nrec,
-                                    C.byref(sp),
-                                    C.c_void_p(dmua.data_ptr()) if dmua is not None else None,
-                                    C.c_void_p(out.data_ptr()),
-                                    C.c_void_p(weight.data_ptr()) if weight is not None else None,
-                                    _stream(stream)))
+    fn = lib().mcx_detpost_device_noalloc if noalloc else lib().mcx_detpost_device
+    _check(fn(C.c_void_p(rec.data_ptr()) if nrec else None, nrec, C.byref(sp),
+              C.c_void_p(dmua.data_ptr()) if dmua is not None else None,
+              C.c_void_p(out.data_ptr()),
+              C.c_void_p(weight.data_ptr()) if weight is not None else None,
+              _stream(stream)))
     return out, weight
 
 

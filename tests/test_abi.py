@@ -68,6 +68,10 @@ def test_detpost_spec_checked_before_the_gpu(bad):
     st = mcx.lib().mcx_detpost_device(None, 10, C.byref(sp), None, None, None, None)
     assert st == mcx.MCX_EINVAL
     assert mcx.lib().mcx_detpost_device(None, 0, None, None, None, None, None) == mcx.MCX_EINVAL
+    for fn in (mcx.lib().mcx_detpost_device_noalloc,):
+        assert fn(None, 0, C.byref(sp), None, None, None, None) == mcx.MCX_EINVAL
+        assert fn(None, 10, C.byref(sp), None, None, None, None) == mcx.MCX_EINVAL
+        assert fn(None, 0, None, None, None, None, None) == mcx.MCX_EINVAL
     out = (C.c_double * 8)()
     assert mcx.lib().mcx_detected_process(None, 0, None, out, 8, None, 0) == mcx.MCX_EINVAL
 
