@@ -40,7 +40,7 @@ class _Output(C.Structure):
                 ("ledger", C.c_double * len(LEDGER)), ("counts", C.c_int64 * len(COUNTS)),
                 ("det_rec", C.c_void_p), ("det_photon", C.c_void_p), ("det_cap", C.c_uint64),
                 ("det_total", C.c_uint64), ("det_written", C.c_uint64),
-                ("digest", C.c_void_p), ("ndigest", C.c_uint64)]
+                ("digest", C.c_void_p), ("ndigest", C.c_uint64), ("visits", C.c_void_p)]
 
 
 _lib = None
@@ -102,21 +102,26 @@ def validate(p) -> int:
 
 
 def run(p, nphoton: int, seed: int, first: int = 0, nthreads: int | None = None,
-        deposits: bool = False, det_cap: int = 1 << 20, ndigest: int = 0) -> dict:
+        deposits: bool = False, det_cap: int = 1 << 20, ndigest: int = 0,
+        visits: bool = False) -> dict:
     """Simulate photons [first, first+nphoton) and return the raw tally
     (ngates, nz, ny, nx) in weight*mm, the ledger, counters, detector
-    records and optional per-photon digests."""
+    records and optional per-photon digests; with `deposits` the segments
+    that deposited into each cell, with `visits` the photon visits of each
+    cell (maximal runs of one photon's consecutive deposits into it)."""
     if nthreads is None:
         nthreads = min(os.cpu_count() or 1, 16)
     s, keep = _pack(p)
     tally = np.zeros(p.tally_shape, np.float64)
     dep = np.zeros(p.tally_shape, np.int64) if deposits else None
+    vis = np.zeros(p.tally_shape, np.int64) if visits else None
     rec = np.zeros((det_cap, p.record_len), np.float32)
     rec_ph = np.zeros(det_cap, np.uint64)
     dig = np.zeros((ndigest, len(DIGEST)), np.float64) if ndigest else None
     o = _Output()
     o.tally = tally.ctypes.data
     o.deposits = dep.ctypes.data if dep is not None else None
+    o.visits = vis.ctypes.data if vis is not None else None
     o.det_rec = rec.ctypes.data if det_cap else None
     o.det_photon = rec_ph.ctypes.data if det_cap else None
     o.det_cap = det_cap
@@ -128,7 +133,7 @@ def run(p, nphoton: int, seed: int, first: int = 0, nthreads: int | None = None,
     if rc != 0:
         raise ValueError(f"oracle rejected the problem (code {rc})")
     nw = int(o.det_written)
-    return {"tally": tally, "deposits": dep,
+    return {"tally": tally, "deposits": dep, "visits": vis,
             "ledger": dict(zip(LEDGER, list(o.ledger))),
             "counts": dict(zip(COUNTS, list(o.counts))),
             "records": rec[:nw].copy(), "record_photon": rec_ph[:nw].copy(),

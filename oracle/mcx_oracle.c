@@ -214,6 +214,7 @@ typedef struct {
   uint64_t first, n, seed;
   double *tally;
   int64_t *deposits;
+  int64_t *visits;     /* may be NULL */
   double ledger[ORC_LEDGER_N];
   int64_t counts[ORC_CNT_N];
   float *rec;          /* growable */
@@ -261,6 +262,7 @@ static void simulate_photon(worker_t *wk, uint64_t k, const uint32_t key[2], dou
   double v[3] = {p->src_dir[0], p->src_dir[1], p->src_dir[2]};
   double w = 1.0, t = p->t0;
   int64_t nscat = 0, events = 0;
+  int64_t last_cell = -1; /* cell of the photon's previous deposit (visit count) */
   int reason = 0, det_hit = -1;
   for (int m = 0; m < p->nmedia; m++) L[m] = 0.0;
   wk->counts[ORC_CNT_LAUNCHED]++;
@@ -316,8 +318,11 @@ static void simulate_photon(worker_t *wk, uint64_t k, const uint32_t key[2], dou
     double dep = mua > 0 ? w * (-expm1(-mua * l)) / mua : w * l;
     wk->tally[gate * dp->nvox + lin] += dep;
     if (dep > 0) {
+      const int64_t cell = gate * dp->nvox + lin;
       wk->counts[ORC_CNT_DEPOSITS]++;
-      if (wk->deposits) wk->deposits[gate * dp->nvox + lin]++;
+      if (wk->deposits) wk->deposits[cell]++;
+      if (wk->visits && cell != last_cell) wk->visits[cell]++;
+      last_cell = cell;
     }
     wk->ledger[ORC_LEDGER_ABSORBED] += w - wn;
     w = wn;
@@ -498,10 +503,13 @@ int orc_run(const orc_problem *p, uint64_t first, uint64_t n, uint64_t seed, int
     if (nthreads == 1) {
       wk[i].tally = out->tally;
       wk[i].deposits = out->deposits;
+      wk[i].visits = out->visits;
     } else {
       wk[i].tally = calloc(cells, sizeof(double));
       wk[i].deposits = out->deposits ? calloc(cells, sizeof(int64_t)) : NULL;
-      if (!wk[i].tally || (out->deposits && !wk[i].deposits)) rc = ORC_ENOMEM;
+      wk[i].visits = out->visits ? calloc(cells, sizeof(int64_t)) : NULL;
+      if (!wk[i].tally || (out->deposits && !wk[i].deposits) || (out->visits && !wk[i].visits))
+        rc = ORC_ENOMEM;
     }
   }
   if (rc == ORC_OK) {
@@ -519,6 +527,8 @@ int orc_run(const orc_problem *p, uint64_t first, uint64_t n, uint64_t seed, int
       for (uint64_t c = 0; c < cells; c++) out->tally[c] += wk[i].tally[c];
       if (out->deposits)
         for (uint64_t c = 0; c < cells; c++) out->deposits[c] += wk[i].deposits[c];
+      if (out->visits)
+        for (uint64_t c = 0; c < cells; c++) out->visits[c] += wk[i].visits[c];
     }
     for (int j = 0; j < ORC_LEDGER_N; j++) out->ledger[j] += wk[i].ledger[j];
     for (int j = 0; j < ORC_CNT_N; j++) {
@@ -543,6 +553,7 @@ int orc_run(const orc_problem *p, uint64_t first, uint64_t n, uint64_t seed, int
     if (nthreads > 1) {
       free(wk[i].tally);
       free(wk[i].deposits);
+      free(wk[i].visits);
     }
     free(wk[i].rec);
     free(wk[i].rec_photon);

@@ -108,6 +108,9 @@ typedef struct {
   uint64_t det_written;     /* out: rows written (<= det_cap) */
   double *digest;           /* ndigest rows of ORC_DG_N, photons first.., may be NULL */
   uint64_t ndigest;
+  int64_t *visits;          /* ngates*nvox, accumulated, may be NULL: per cell, the photon
+                               visits (maximal runs of one photon's consecutive deposits
+                               into that cell) */
 } orc_output;
 
 /* Simulate photons [first, first + n) with run seed `seed` on `nthreads`

@@ -368,3 +368,24 @@ def test_xy_symmetry_of_cube(oracle_mod):
     mx, my = np.array(mx), np.array(my)
     d = mx - my
     assert abs(d.mean()) < 4 * d.std(ddof=1) / math.sqrt(len(d)) + 1e-12
+
+
+def test_visit_counter_counts_runs_of_one_photons_deposits(oracle_mod):
+    """Pins of the oracle's per-cell visit counter (a visit = a maximal run
+    of one photon's consecutive deposits into one cell): a straight column
+    visits every cell once per photon; a photon scattering inside a single
+    voxel until it escapes leaves one visit however many segments it
+    deposits; and visits never exceed deposits."""
+    N = 500
+    p = W.slab_column(nz=20, mua=0.01, mus=0.0)
+    r = oracle_mod.run(p, N, 1, nthreads=2, deposits=True, visits=True)
+    on_axis = r["visits"][0, :, 1, 1]
+    assert np.all(on_axis == N) and np.array_equal(r["visits"], r["deposits"])
+    q = W.cube_homogeneous(n=1).replace(src_pos=(0.5, 0.5, 0.0), reflect=True,
+                                        media=np.array([[0, 0, 1, 1], [0.01, 3.0, 0.5, 1.37]],
+                                                       np.float32))
+    r = oracle_mod.run(q, N, 2, nthreads=2, deposits=True, visits=True)
+    assert r["visits"].sum() == N and r["deposits"].sum() > 3 * N
+    c = W.cube_homogeneous(n=12).replace(src_pos=(5.5, 5.5, 0.0))
+    r = oracle_mod.run(c, 2000, 3, nthreads=2, deposits=True, visits=True)
+    assert np.all(r["visits"] <= r["deposits"]) and r["visits"].sum() < r["deposits"].sum()
