@@ -108,9 +108,17 @@ typedef struct {
   int32_t refill_chunk;   /* photons a wave takes per refill grab; 0 = library default */
   uint64_t ndigest;       /* per-photon digest rows kept for photons [first, first+ndigest) */
   int32_t lds_window_cells; /* cells around the source summed per workgroup in LDS before they
-                               reach the map; 0 = library default (8192), < 0 = none,
-                               at most 18432 (144 KB) */
+                               reach the map (FP32 partial sums, 4 bytes each); 0 =
+                               library default (16384), < 0 = none, at most 36864
+                               (144 KB) */
   int32_t accurate_math;  /* 0: hardware transcendentals (~1 ulp); 1: device math library */
+  int32_t kernel_variant; /* event loop (the paper's benchmark study, Fig. 2): 0 = default;
+                             1 = map deposits by a plain, non-atomic read-add-write (the
+                             paper's B2: concurrent updates of one cell can be lost, for
+                             speed studies only; needs accurate_math = 0 and ndigest = 0);
+                             2 = branch-reduced loop (the paper's Opt3: every lane computes
+                             the scattering and the face-crossing updates and keeps its own
+                             by selection; same results as 0; needs accurate_math = 0) */
 } mcx_options;
 
 /* Run statistics, accumulated since the last mcx_reset / mcx_run. */
@@ -209,16 +217,23 @@ mcx_status mcx_batch_digest(mcx_ctx *ctx, int32_t sim, double *host_out, uint64_
 
 /* Launch shape: threads per workgroup (0 = the size that keeps the most waves
  * resident), photons per job (0 = default 256), LDS window cells (0 = default
- * 8192, < 0 = none, at most 18432; in a batch each workgroup keeps the window
- * of the simulation its first wave starts on).  Waits for the stream. */
+ * 16384, < 0 = none, at most 36864; in a batch each workgroup keeps the window
+ * of the simulation its first wave starts on).  The window covers, per early
+ * gate, a box of cells: by default one box round the source over the gates of
+ * the first ~0.5 ns; after mcx_autotune on a single simulation, the boxes
+ * its flush census shaped for that cell count.  Waits for the stream. */
 mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk,
                           int32_t lds_window_cells);
 
 /* Autotuner: times pilot launches of pilot_photons[i] photons (seed[i]) per
  * simulation over block sizes {64, 256, 448, 512, 768, 1024} x jobs of {64,
  * 256, 1024} photons (1 to 16 photons per lane) x deposit schemes {direct
- * global atomics, LDS window of 4096, 8192, 16384 or 18432 cells} (shapes that do
- * not fit on a compute unit are skipped), keeps the fastest shape, and fits
+ * global atomics, LDS window of 8192, 16384, 32768 or 36864 cells} (shapes that
+ * do not fit on a compute unit are skipped), keeps the fastest shape, and fits
+ * (single simulations without digests and with hardware math: the window boxes
+ * are first shaped by a flush census -- one pilot counting, per map cell, the
+ * cell visits the kernel adds to the map -- per gate the box grown from its
+ * busiest cell by the densest slabs that fit the candidate's cell count),
  * the linear device runtime model T = a n + T0 of the paper's device-level
  * load balancing (the study of Fig. 3(b)) from pilots of n and n/2 photons.
  * Results do not depend on the shape (the random numbers are keyed by photon
@@ -280,8 +295,10 @@ uint64_t mcx_ncells(const mcx_ctx *ctx);
 mcx_status mcx_fluence(mcx_ctx *ctx, int32_t kind, float *host_out, uint64_t ncells);
 mcx_status mcx_fluence_f64(mcx_ctx *ctx, int32_t kind, double *host_out, uint64_t ncells);
 
-/* Same, written to device memory on hip_stream (NULL = own stream), after
- * the context's last clear or launch on any stream; async. */
+/* Same, written to device memory dev_out (ncells floats) on hip_stream
+ * (NULL = the null stream, as for the other calls that write into the
+ * caller's device memory; not the context's own stream), after the
+ * context's last clear or launch on any stream; async. */
 mcx_status mcx_fluence_device(mcx_ctx *ctx, int32_t kind, float *dev_out, uint64_t ncells,
                               void *hip_stream);
 

@@ -24,6 +24,7 @@ enum CountSlot {
 };
 constexpr int kDigestN = 8;
 constexpr int kMaxWavesPerBlock = 16;
+constexpr int kMaxWinGates = 16;  // gates an LDS window can cover
 
 // One simulation: domain, media, source, gates, photon range and outputs.
 // Lives in device memory; a wave reads the fields of its current
@@ -63,9 +64,17 @@ struct SimDesc {
   int32_t rec_len;
   double* digest;
   uint64_t ndigest;
-  // LDS window of this simulation: cells [wx0, wx0 + wnx) x [wy0, ...) x
-  // [wz0, ...) of gates [0, wng) (all zero: none)
-  int32_t wx0, wy0, wz0, wnx, wny, wnz, wng;
+  // Deposit unit: every cell-visit sum is rounded to a multiple of q_unit
+  // (a power of two, 2^-20 of the voxel size or just below; q_inv = 1 /
+  // q_unit) before it reaches the map or the window.
+  float q_unit, q_inv;
+  // LDS window of this simulation (wng = 0: none): for each gate g < wng
+  // the cells of a box [x0, x0 + nx) x [y0, y0 + ny) x [z0, z0 + nz), at
+  // window slots off + ((z - z0) ny + (y - y0)) nx + (x - x0); wbox holds
+  // per gate the rows (x0, y0, z0, off) and (nx, ny, nz, 0); wcount slots in
+  // all.  The window holds 32-bit integer sums of deposit units.
+  const int4* wbox;
+  int32_t wng, wcount;
 };
 
 // One launch over `nsims` simulations.  Photons are handed out in jobs of
@@ -98,12 +107,19 @@ struct LaunchParams {
 
 size_t transport_smem_bytes(int table_rows, int nmedia_max, int block, bool detect,
                             int window_cells);
+// `variant`: 0 the default event loop, 1 non-atomic map deposits, 2 the
+// branch-reduced loop (mcx_options.kernel_variant), 3 the flush census: the
+// default loop adding 1 to a map cell for every cell visit it flushes, with
+// no window (the window shaping reads it).
+constexpr int kVariantCensus = 3;
+bool transport_variant_available(bool detect, bool diag, bool accurate, int variant);
 hipError_t transport_occupancy(int* blocks_per_cu, int block, size_t smem, bool detect,
-                               bool diag, bool accurate);
+                               bool diag, bool accurate, int variant);
 // `host` is the host copy (for the shared-memory size); `dev` must hold the
 // same bytes in device memory by the time the kernel runs.
 hipError_t launch_transport(const LaunchParams& host, const LaunchParams* dev, int grid,
-                            int block, hipStream_t s, bool detect, bool diag, bool accurate);
+                            int block, hipStream_t s, bool detect, bool diag, bool accurate,
+                            int variant);
 
 // Zero `ncells` tally cells and `nsims` ledgers, counters and record counts.
 hipError_t launch_clear(double* tally, uint64_t ncells, double* ledger,

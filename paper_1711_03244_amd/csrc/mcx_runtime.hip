@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <new>
 #include <string>
@@ -26,8 +27,8 @@ namespace {
 
 constexpr double kCmmPerNs = 299.792458;  // speed of light in vacuum, mm/ns
 constexpr int kDefaultChunk = 256;
-constexpr int kDefaultWindow = 8192;       // FP64 cells, 64 KB of LDS
-constexpr int kMaxWindow = 18432;          // 144 KB of the 160 KB of LDS per CU
+constexpr int kDefaultWindow = 16384;      // FP32 cells, 64 KB of LDS
+constexpr int kMaxWindow = 36864;          // 144 KB of the 160 KB of LDS per CU
 constexpr uint64_t kMaxLaunchPhotons = 1ull << 31;  // per simulation and launch
 
 thread_local std::string g_error;
@@ -86,7 +87,10 @@ struct SimHost {
   uint64_t label_off = 0, tally_off = 0, table_off = 0;
   uint64_t rec_off = 0;    // first record row (photon-index array)
   uint64_t rec_foff = 0;   // first float of the records (rows differ in length)
-  int win[7] = {0, 0, 0, 0, 0, 0, 0};  // LDS window: x0, y0, z0, nx, ny, nz, ngates
+  // LDS window: per gate g < wng the rows (x0, y0, z0, offset) and (nx, ny,
+  // nz, 0) of its box (SimDesc::wbox), wcount slots in all
+  std::vector<int32_t> wbox;
+  int wng = 0, wcount = 0;
   uint64_t photons = 0;  // accumulated since the last reset
   uint64_t ncells() const { return static_cast<uint64_t>(nvox) * ngates; }
 };
@@ -102,6 +106,10 @@ struct mcx_ctx {
   int block = 256, grid = 0, cus = 0, chunk = kDefaultChunk;
   int window_budget = 0;
   int win_cells = 0;  // LDS window capacity: the largest window of any simulation
+  // window boxes shaped from a flush census (single-simulation contexts):
+  // budget -> per gate (x0, y0, z0, nx, ny, nz)
+  std::vector<std::pair<int, std::vector<std::array<int, 6>>>> shaped;
+  int force_variant = -1;  // kernel variant of the next launches (-1: opt.kernel_variant)
   int table_rows = 0, nmedia_max = 0;
   uint64_t total_cells = 0, max_cells = 0;
 
@@ -118,6 +126,7 @@ struct mcx_ctx {
   mcx::SimDesc* d_desc = nullptr;
   uint64_t* d_job_start = nullptr;
   uint64_t* d_home_start = nullptr;
+  int4* d_wbox = nullptr;  // per simulation 2 * kMaxWinGates rows
   unsigned long long* d_job_counter = nullptr;  // one per simulation
   // estimated cost per photon of every simulation (ms); empty: home waves by
   // job counts
@@ -161,6 +170,7 @@ void mcx_default_options(mcx_options* o) {
   o->ndigest = 0;
   o->lds_window_cells = 0;
   o->accurate_math = 0;
+  o->kernel_variant = 0;
 }
 
 const char* mcx_last_error(void) { return g_error.c_str(); }
@@ -244,6 +254,12 @@ static mcx_status validate_options(const mcx_options* o) {
     return fail(MCX_EINVAL, "max_events must be in [1, 2^32-1]");
   if (o->lds_window_cells > kMaxWindow)
     return fail(MCX_EINVAL, "lds_window_cells must be <= %d (144 KB of LDS)", kMaxWindow);
+  if (o->kernel_variant < 0 || o->kernel_variant > 2)
+    return fail(MCX_EINVAL, "kernel_variant must be 0, 1 or 2");
+  if (o->kernel_variant != 0 && o->accurate_math != 0)
+    return fail(MCX_EINVAL, "kernel_variant %d needs accurate_math = 0", o->kernel_variant);
+  if (o->kernel_variant == 1 && o->ndigest != 0)
+    return fail(MCX_EINVAL, "kernel_variant 1 (non-atomic deposits) needs ndigest = 0");
   return MCX_OK;
 }
 
@@ -256,7 +272,7 @@ static void release(mcx_ctx* c) {
                   c->d_rec_photon,  c->d_digest,     c->d_desc,    c->d_job_start,
                   c->d_job_counter, c->d_launch,     c->d_stage32, c->d_stage64,
                   c->d_dmua,        c->d_post,       c->d_post_w,  c->d_post_ws,
-                  c->d_home_start};
+                  c->d_home_start, c->d_wbox};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   hipEvent_t evs[] = {c->ev_begin, c->ev_k0, c->ev_k1, c->ev_end, c->ev_done};
@@ -312,38 +328,145 @@ static void describe(SimHost& sh, const mcx_sim& sm) {
       vol->labels[sh.src_i[0] + sh.nx * (sh.src_i[1] + static_cast<int64_t>(sh.ny) * sh.src_i[2])];
 }
 
-// LDS window of every simulation: a box of cells centred on the source
-// voxel (shifted to stay inside the grid) over the gates of about the first
-// kWindowNs after t0 (at least one, at most kWindowGates), holding at most
-// `budget` cells.  Early in a photon's life its deposits crowd round the
-// source whatever the gate width, so narrow gates get more of them in the
+// LDS window of every simulation.  By default a box of cells centred on
+// the source voxel (shifted to stay inside the grid) over the gates of about
+// the first kWindowNs after t0 (at least one, at most kWindowGates), holding
+// at most `budget` cells: early in a photon's life its deposits crowd round
+// the source whatever the gate width, so narrow gates get more of them in the
 // window and a smaller box; wide gates get one gate and the largest box.
+// After a flush census (mcx_autotune, single-simulation contexts) each gate
+// instead gets the box its census shaped (shape_window).
 constexpr double kWindowNs = 0.5;
 constexpr int kWindowGates = 8;
 static void set_window(mcx_ctx* c, int budget) {
   c->window_budget = budget;
   c->win_cells = 0;
+  const std::vector<std::array<int, 6>>* shaped = nullptr;
+  for (const auto& e : c->shaped)
+    if (e.first == budget) shaped = &e.second;
   for (SimHost& sh : c->sims) {
-    for (int& v : sh.win) v = 0;
+    sh.wbox.clear();
+    sh.wng = 0;
+    sh.wcount = 0;
     if (budget <= 0) continue;
-    const double span = kWindowNs / static_cast<double>(sh.dt);
-    int wg = span >= kWindowGates ? kWindowGates : static_cast<int>(std::lround(span));
-    wg = std::max(1, std::min(wg, std::min(sh.ngates, kWindowGates)));
-    const int per_gate = budget / wg;
-    int side = 1;
-    while ((side + 1) * (side + 1) * (side + 1) <= per_gate) ++side;
-    const int dims[3] = {sh.nx, sh.ny, sh.nz};
-    for (int a = 0; a < 3; ++a) {
-      const int n = side < dims[a] ? side : dims[a];
-      int lo = sh.src_i[a] - n / 2;
-      if (lo > dims[a] - n) lo = dims[a] - n;
-      if (lo < 0) lo = 0;
-      sh.win[a] = lo;
-      sh.win[3 + a] = n;
+    std::vector<std::array<int, 6>> boxes;
+    if (shaped && c->sims.size() == 1) {
+      boxes = *shaped;
+    } else {
+      const double span = kWindowNs / static_cast<double>(sh.dt);
+      int wg = span >= kWindowGates ? kWindowGates : static_cast<int>(std::lround(span));
+      wg = std::max(1, std::min(wg, std::min(sh.ngates, kWindowGates)));
+      const int per_gate = budget / wg;
+      int side = 1;
+      while ((side + 1) * (side + 1) * (side + 1) <= per_gate) ++side;
+      const int dims[3] = {sh.nx, sh.ny, sh.nz};
+      std::array<int, 6> b{};
+      for (int a = 0; a < 3; ++a) {
+        const int n = side < dims[a] ? side : dims[a];
+        int lo = sh.src_i[a] - n / 2;
+        if (lo > dims[a] - n) lo = dims[a] - n;
+        if (lo < 0) lo = 0;
+        b[a] = lo;
+        b[3 + a] = n;
+      }
+      boxes.assign(wg, b);
     }
-    sh.win[6] = wg;
-    c->win_cells = std::max(c->win_cells, sh.win[3] * sh.win[4] * sh.win[5] * sh.win[6]);
+    for (const auto& b : boxes) {
+      sh.wbox.insert(sh.wbox.end(), {b[0], b[1], b[2], sh.wcount, b[3], b[4], b[5], 0});
+      sh.wcount += b[3] * b[4] * b[5];
+    }
+    sh.wng = static_cast<int>(boxes.size());
+    c->win_cells = std::max(c->win_cells, sh.wcount);
   }
+}
+
+// Per-gate window boxes from a flush census F (cell-visit flushes per cell
+// of gates 0..ng-1, [gate][z][y][x]): each gate's box grows from its
+// busiest cell, one face at a time, by the slab with the most flushes per
+// cell, while that density is at least lambda; lambda is the smallest
+// value (bisection) whose boxes fit `budget` cells.  Gates whose busiest
+// cell is below lambda, and gates after them, get none.
+static std::vector<std::array<int, 6>> shape_window(const std::vector<double>& F, int nx, int ny,
+                                                    int nz, int ng, int budget) {
+  const int64_t nvox = static_cast<int64_t>(nx) * ny * nz;
+  // per-gate summed-volume tables, (nz+1) x (ny+1) x (nx+1)
+  const int64_t sx = nx + 1, sy = static_cast<int64_t>(ny + 1) * sx;
+  const int64_t tsz = sy * (nz + 1);
+  std::vector<std::vector<double>> S(ng, std::vector<double>(tsz, 0.0));
+  std::vector<int64_t> peak(ng, 0);
+  for (int g = 0; g < ng; ++g) {
+    std::vector<double>& T = S[g];
+    const double* f = F.data() + g * nvox;
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t v = (static_cast<int64_t>(z) * ny + y) * nx + x;
+          if (f[v] > f[peak[g]]) peak[g] = v;
+          T[(z + 1) * sy + (y + 1) * sx + (x + 1)] =
+              f[v] + T[z * sy + (y + 1) * sx + (x + 1)] + T[(z + 1) * sy + y * sx + (x + 1)] +
+              T[(z + 1) * sy + (y + 1) * sx + x] - T[z * sy + y * sx + (x + 1)] -
+              T[z * sy + (y + 1) * sx + x] - T[(z + 1) * sy + y * sx + x] + T[z * sy + y * sx + x];
+        }
+  }
+  // flushes in [x0, x1) x [y0, y1) x [z0, z1) of gate g
+  auto box_sum = [&](int g, int x0, int x1, int y0, int y1, int z0, int z1) {
+    const std::vector<double>& T = S[g];
+    return T[z1 * sy + y1 * sx + x1] - T[z0 * sy + y1 * sx + x1] - T[z1 * sy + y0 * sx + x1] -
+           T[z1 * sy + y1 * sx + x0] + T[z0 * sy + y0 * sx + x1] + T[z0 * sy + y1 * sx + x0] +
+           T[z1 * sy + y0 * sx + x0] - T[z0 * sy + y0 * sx + x0];
+  };
+  auto grow = [&](double lambda, std::vector<std::array<int, 6>>* out) -> int64_t {
+    int64_t cells = 0;
+    out->clear();
+    for (int g = 0; g < ng; ++g) {
+      const int64_t v = peak[g];
+      const int px = static_cast<int>(v % nx), py = static_cast<int>((v / nx) % ny),
+                pz = static_cast<int>(v / (static_cast<int64_t>(nx) * ny));
+      if (F[g * nvox + v] < lambda || F[g * nvox + v] <= 0.0) break;
+      int b[6] = {px, px + 1, py, py + 1, pz, pz + 1};  // x0 x1 y0 y1 z0 z1
+      const int lim[3] = {nx, ny, nz};
+      for (;;) {
+        double best = -1.0;
+        int which = -1;
+        for (int k = 0; k < 6; ++k) {
+          const int a = k / 2;
+          int c[6] = {b[0], b[1], b[2], b[3], b[4], b[5]};
+          if (k % 2 == 0) {
+            if (b[2 * a] == 0) continue;
+            c[2 * a + 1] = b[2 * a];
+            c[2 * a] = b[2 * a] - 1;
+          } else {
+            if (b[2 * a + 1] == lim[a]) continue;
+            c[2 * a] = b[2 * a + 1];
+            c[2 * a + 1] = b[2 * a + 1] + 1;
+          }
+          const double n = static_cast<double>(c[1] - c[0]) * (c[3] - c[2]) * (c[5] - c[4]);
+          const double d = box_sum(g, c[0], c[1], c[2], c[3], c[4], c[5]) / n;
+          if (d > best) {
+            best = d;
+            which = k;
+          }
+        }
+        if (which < 0 || best < lambda) break;
+        const int a = which / 2;
+        if (which % 2 == 0) --b[2 * a]; else ++b[2 * a + 1];
+      }
+      out->push_back({b[0], b[2], b[4], b[1] - b[0], b[3] - b[2], b[5] - b[4]});
+      cells += static_cast<int64_t>(b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4]);
+    }
+    return cells;
+  };
+  double hi = 0.0;
+  for (int g = 0; g < ng; ++g) hi = std::max(hi, F[g * nvox + peak[g]]);
+  double lo = 0.0;
+  std::vector<std::array<int, 6>> boxes;
+  if (grow(lo, &boxes) <= budget) return boxes;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (grow(mid, &boxes) > budget) lo = mid; else hi = mid;
+  }
+  grow(hi, &boxes);
+  return boxes;
 }
 
 static int window_cells(const mcx_ctx* c) { return c->win_cells; }
@@ -360,7 +483,7 @@ static mcx_status set_shape(mcx_ctx* c, int block) {
         mcx::transport_smem_bytes(c->table_rows, c->nmedia_max, blk, c->detect, window_cells(c));
     int occ = 0;
     HIP_TRY(mcx::transport_occupancy(&occ, blk, smem, c->detect, c->diag,
-                                     c->opt.accurate_math != 0));
+                                     c->opt.accurate_math != 0, c->opt.kernel_variant));
     if (occ * blk / 64 > best_waves) {
       best_waves = occ * blk / 64;
       best_block = blk;
@@ -451,6 +574,7 @@ static mcx_status setup(mcx_ctx* c, const mcx_sim* sims) {
   HIP_TRY(hipMalloc(&c->d_job_start, (n + 1) * sizeof(uint64_t)));
   HIP_TRY(hipMalloc(&c->d_home_start, (n + 1) * sizeof(uint64_t)));
   HIP_TRY(hipMalloc(&c->d_job_counter, n * sizeof(unsigned long long)));
+  HIP_TRY(hipMalloc(&c->d_wbox, n * 2 * mcx::kMaxWinGates * sizeof(int4)));
   HIP_TRY(hipMalloc(&c->d_launch, sizeof(mcx::LaunchParams)));
   if (recs > 0) {
     HIP_TRY(hipMalloc(&c->d_rec, recs * sizeof(float)));
@@ -565,6 +689,7 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
   const size_t ns = c->sims.size();
   std::vector<mcx::SimDesc> desc(ns);
   std::vector<uint64_t> job_start(ns + 1, 0);
+  std::vector<int4> wbox(ns * 2 * mcx::kMaxWinGates, make_int4(0, 0, 0, 0));
   for (size_t i = 0; i < ns; ++i) {
     const SimHost& sh = c->sims[i];
     mcx::SimDesc& d = desc[i];
@@ -618,13 +743,14 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
       d.digest = c->d_digest + i * c->opt.ndigest * mcx::kDigestN;
       d.ndigest = c->opt.ndigest;
     }
-    d.wx0 = sh.win[0];
-    d.wy0 = sh.win[1];
-    d.wz0 = sh.win[2];
-    d.wnx = sh.win[3];
-    d.wny = sh.win[4];
-    d.wnz = sh.win[5];
-    d.wng = sh.win[6];
+    d.wbox = c->d_wbox + i * 2 * mcx::kMaxWinGates;
+    d.wng = sh.wng;
+    d.wcount = sh.wcount;
+    // deposit unit: the largest power of two not above h 2^-20
+    d.q_unit = std::ldexp(1.f, std::ilogb(sh.h) - 20);
+    d.q_inv = 1.f / d.q_unit;
+    std::copy(sh.wbox.begin(), sh.wbox.end(),
+              reinterpret_cast<int32_t*>(wbox.data() + i * 2 * mcx::kMaxWinGates));
     job_start[i + 1] = job_start[i] + (n[i] + c->chunk - 1) / c->chunk;
   }
   // Home-wave shares: the job counts, or -- once per-simulation costs are
@@ -668,11 +794,14 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
                          hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(c->d_home_start, home_start.data(), (ns + 1) * sizeof(uint64_t),
                          hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->d_wbox, wbox.data(), wbox.size() * sizeof(int4),
+                         hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(c->d_launch, &lp, sizeof(lp), hipMemcpyHostToDevice, st));
   HIP_TRY(mcx::launch_reset_counters(c->d_job_counter, static_cast<int>(ns), st));
   HIP_TRY(hipEventRecord(c->ev_k0, st));
-  HIP_TRY(mcx::launch_transport(lp, c->d_launch, c->grid, c->block, st, c->detect, c->diag,
-                                c->opt.accurate_math != 0));
+  HIP_TRY(mcx::launch_transport(
+      lp, c->d_launch, c->grid, c->block, st, c->detect, c->diag, c->opt.accurate_math != 0,
+      c->force_variant >= 0 ? c->force_variant : c->opt.kernel_variant));
   HIP_TRY(hipEventRecord(c->ev_k1, st));
   HIP_TRY(hipMemsetAsync(c->d_reduce, 0, ns * 2 * sizeof(double), st));
   for (size_t i = 0; i < ns; ++i) {
@@ -905,7 +1034,7 @@ mcx_status mcx_fluence_device(mcx_ctx* c, int32_t kind, float* dev_out, uint64_t
   double scale = 1.0;
   MCX_TRY(scale_for(sh, kind, &scale));
   HIP_TRY(hipSetDevice(c->device));
-  hipStream_t st = pick_stream(c, stream);
+  hipStream_t st = static_cast<hipStream_t>(stream);  // NULL: the null stream
   MCX_TRY(wait_done(c, st));
   HIP_TRY(mcx::launch_normalise_f32(c->d_tally + sh.tally_off, sh.ncells(), scale, dev_out, st));
   // a later clear or launch must not overwrite the tally before this reads it
@@ -1148,6 +1277,38 @@ mcx_status mcx_set_launch(mcx_ctx* c, int32_t block_size, int32_t refill_chunk,
 
 // ------------------------------------------------------------- autotune
 
+// Flush census for the window shaping: one pilot launch whose kernel adds 1
+// to a map cell for every cell visit it flushes (no window), the counts of
+// the first min(ngates, kMaxWinGates) gates read back, and the per-gate
+// window boxes shaped for every budget in `budgets`.  Single-simulation
+// contexts with hardware math and no digests only (others keep the default
+// boxes).  Tallies are cleared afterwards.
+static mcx_status census(mcx_ctx* c, const uint64_t* pilot, const uint64_t* seed,
+                         const int* budgets, int nbudget) {
+  c->shaped.clear();
+  if (c->sims.size() != 1 || c->diag || c->opt.accurate_math != 0) return MCX_OK;
+  if (!mcx::transport_variant_available(c->detect, false, false, mcx::kVariantCensus))
+    return MCX_OK;
+  const uint64_t zero = 0;
+  MCX_TRY(clear_all(c, c->stream));
+  c->force_variant = mcx::kVariantCensus;
+  const mcx_status r = enqueue_all(c, &zero, pilot, seed, c->stream);
+  c->force_variant = -1;
+  MCX_TRY(r);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const SimHost& sh = c->sims[0];
+  const int ng = std::min(sh.ngates, mcx::kMaxWinGates);
+  std::vector<double> F(static_cast<size_t>(ng) * sh.nvox);
+  HIP_TRY(hipMemcpy(F.data(), c->d_tally + sh.tally_off, F.size() * sizeof(double),
+                    hipMemcpyDeviceToHost));
+  for (int k = 0; k < nbudget; ++k)
+    if (budgets[k] > 0)
+      c->shaped.emplace_back(budgets[k], shape_window(F, sh.nx, sh.ny, sh.nz, ng, budgets[k]));
+  MCX_TRY(clear_all(c, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MCX_OK;
+}
+
 // Pilot launches over block size x refill chunk x LDS window; the fastest
 // shape is kept.  Then the paper's
 // device model T = a n + T0 is fitted from two pilot sizes (n and n/2) with
@@ -1172,14 +1333,17 @@ mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_
   memset(out, 0, sizeof(*out));
   const int blocks[] = {64, 256, 448, 512, 768, 1024};
   const int chunks[] = {64, 256, 1024};
-  const int windows[] = {-1, 4096, 8192, 16384, kMaxWindow};
+  const int windows[] = {-1, 8192, 16384, 32768, kMaxWindow};
   const int nwin = 5;
   // the untuned default shape first (after one warm-up launch)
+  c->shaped.clear();
   MCX_TRY(mcx_set_launch(c, 0, 0, 0));
   float ms = 0.f;
   MCX_TRY(pilot(pilot_photons, &ms));
   MCX_TRY(pilot(pilot_photons, &ms));
   out->default_ms = ms;
+  // then window boxes shaped by a flush census for the candidates below
+  MCX_TRY(census(c, pilot_photons, seed, windows, nwin));
   float best = ms;
   out->block_size = c->block;
   out->refill_chunk = c->chunk;

@@ -22,14 +22,16 @@
 // own slice of LDS, and the lanes' partial pathlengths in LDS.
 // Deposits made while a photon stays in one tally cell are summed in a
 // register and flushed once when it leaves the cell.  Flushes into the
-// densest cells -- a box of cells around the source of the workgroup's
-// window simulation (the home simulation of its first wave), the "window"
-// -- go to an FP64 copy of those cells in LDS, summed per workgroup and
-// added to the map once when the workgroup finishes; all other flushes are one
-// non-returning FP64 atomic add on the map.  Device-memory atomics on
-// gfx950 execute at the memory side at a fixed rate per address, so the
-// window is what keeps the cells next to a pencil beam, which every photon
-// visits, from serialising the whole launch.
+// densest cells of the workgroup's window simulation (the home simulation
+// of its first wave) -- per early gate a box of cells, the "window" -- go to
+// integer partial sums in LDS (visit sums are rounded to a fixed deposit
+// unit, see deposit()), added to the map once when the workgroup finishes
+// (or earlier, by the lane whose addition takes a sum past 2^31 units).  All
+// other flushes are one non-returning FP64 atomic add on the map.
+// Device-memory atomics on gfx950 execute at the memory side at a fixed
+// aggregate rate, which binds this kernel wherever photons spread out, so
+// the window is what keeps the cells that most photons of a workgroup visit
+// -- next to a pencil beam, early in the photons' lives -- off that path.
 #include <math.h>
 
 #include "mcx_internal.hpp"
@@ -217,23 +219,93 @@ __device__ __forceinline__ float fresnel_r(float n1, float n2, float ci, float c
   return 0.5f * (rs * rs + rp * rp);
 }
 
-// Add a finished cell visit to the map: into the workgroup's LDS window
-// when the cell lies in it, else one FP64 atomic add (no return value, so
-// the wave does not wait for it).
-__device__ __forceinline__ void deposit(double* tally, double* s_win, uint32_t cell, int slot,
-                                       float v) {
-  if (slot >= 0)
-    atomicAdd(s_win + slot, static_cast<double>(v));
+// A visit sum of more than 2^28 deposit units (256 voxel sizes of path in
+// one cell) goes to the map directly, and a window sum that reaches 2^31
+// units is moved to the map by the lane whose addition took it there, so
+// the 32-bit window sums cannot wrap.
+constexpr float kWinMaxAdd = 268435456.f;
+constexpr uint32_t kWinMove = 0x80000000u;
+
+// Add a finished cell visit to the map; returns the number of global
+// atomics issued (0 or 1).  The visit's sum v is first rounded to a whole
+// number q of the simulation's deposit unit u (a power of two, 2^-20 of the
+// voxel size or just below): every value added to the FP64 map is then a
+// multiple of u, all partial sums are exact, and the map does not depend on
+// the order of the additions -- any launch shape, batch or photon split
+// gives the same bits.  A visit into the workgroup's LDS window adds q to
+// that cell's 32-bit integer sum (the lane that takes it to 2^31 or more
+// exchanges it with zero and adds what it took to the map); any other is
+// one FP64 atomic add of q u (no return value, so the wave does not wait
+// for it).  kRacy: a plain read, add and write of the map cell instead of
+// the atomic -- the paper's non-atomic benchmark variant (B2), where
+// concurrent updates of one cell can be lost.  kCensus: 1 per visit
+// instead (the flush census).
+template <bool kRacy, bool kCensus = false>
+__device__ __forceinline__ int deposit(CSim* D, uint32_t* s_win, uint32_t cell, int slot,
+                                      float v) {
+  MCX_GLOBAL double* p = as_global(D->tally) + cell;
+  if constexpr (kCensus) {
+    __builtin_amdgcn_global_atomic_fadd_f64(p, 1.0);
+    return 1;
+  }
+  const float q = rintf(v * D->q_inv);  // exact scaling by a power of two
+  const double unit = static_cast<double>(D->q_unit);
+  if (slot >= 0 && q <= kWinMaxAdd) {
+    const uint32_t add = static_cast<uint32_t>(q);
+    if (atomicAdd(s_win + slot, add) + add < kWinMove) return 0;
+    const uint32_t y = atomicExch(s_win + slot, 0u);
+    __builtin_amdgcn_global_atomic_fadd_f64(p, static_cast<double>(y) * unit);
+    return 1;
+  }
+  if constexpr (kRacy)
+    *p = *p + static_cast<double>(q) * unit;
   else
-    __builtin_amdgcn_global_atomic_fadd_f64(as_global(tally) + cell, static_cast<double>(v));
+    __builtin_amdgcn_global_atomic_fadd_f64(p, static_cast<double>(q) * unit);
+  return 1;
 }
 
 enum : int { kEvTime = 0, kEvScat = 1, kEvCross = 2 };
 enum : int { kAlive = 0, kEndEscape = 1, kEndTime = 2, kEndRoulette = 3, kEndCapped = 4 };
 
+// Event-loop variants (the paper's benchmark study, Fig. 2): the default
+// loop; map deposits without atomics (B2); the branch-reduced loop (Opt3),
+// where every lane computes both the scattering and the face-crossing
+// updates and keeps its own by selection instead of branching on its event.
+enum : int { kVarDefault = 0, kVarRacy = 1, kVarFlat = 2, kVarCensus = kVariantCensus };
 
-template <bool kDetect, bool kDiag, bool kNative>
+// Window slot of cell (gate, ix, iy, iz) from the per-gate boxes, or -1.
+__device__ __forceinline__ int window_slot(const int4* s_wbox, int wng, int gate, int ix, int iy,
+                                           int iz) {
+  if (gate >= wng) return -1;
+  const int4 a = s_wbox[2 * gate], b = s_wbox[2 * gate + 1];
+  const uint32_t ux = static_cast<uint32_t>(ix - a.x);
+  const uint32_t uy = static_cast<uint32_t>(iy - a.y);
+  const uint32_t uz = static_cast<uint32_t>(iz - a.z);
+  if (ux < static_cast<uint32_t>(b.x) && uy < static_cast<uint32_t>(b.y) &&
+      uz < static_cast<uint32_t>(b.z))
+    return a.w + static_cast<int>((uz * b.y + uy) * b.x + ux);
+  return -1;
+}
+
+// Map cell of window slot i (0 <= i < the window's slot count).
+__device__ __forceinline__ uint32_t window_cell(const int4* s_wbox, int wng, CSim* DW, int i) {
+  int g = 0;
+  while (g + 1 < wng && s_wbox[2 * (g + 1)].w <= i) ++g;
+  const int4 a = s_wbox[2 * g], b = s_wbox[2 * g + 1];
+  int r = i - a.w;
+  const int x = r % b.x;
+  r /= b.x;
+  const int y = r % b.y;
+  const int z = r / b.y;
+  return static_cast<uint32_t>(g) * DW->nvox + static_cast<uint32_t>(a.x + x) +
+         DW->stride_y * static_cast<uint32_t>(a.y + y) +
+         DW->stride_z * static_cast<uint32_t>(a.z + z);
+}
+
+template <bool kDetect, bool kDiag, bool kNative, int kVar>
 __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* params) {
+  constexpr bool kRacy = kVar == kVarRacy;
+  constexpr bool kCensus = kVar == kVarCensus;
   // Launch and simulation parameters live in device memory and are read
   // where used (scalar loads that hit the scalar cache) rather than held in
   // scalar registers for the whole persistent loop.
@@ -241,17 +313,47 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   extern __shared__ float4 s_dyn[];
   __shared__ double s_led[kMaxWavesPerBlock][kLedgerN];
   __shared__ unsigned long long s_cnt[kMaxWavesPerBlock][kCountN];
+  __shared__ int4 s_wbox[2 * kMaxWinGates];
 
   const uint32_t lane = __lane_id();
   const int wid = static_cast<int>(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));  // wave-uniform
   const uint32_t bdim = blockDim.x;
   const int rows = L.table_rows;
   float4* s_tab = s_dyn + wid * rows;  // this wave's copy of its simulation's tables
-  const int wcells = L.window_cells;
-  double* s_win = reinterpret_cast<double*>(s_dyn + (bdim >> 6) * rows);
+  const int wcells = kCensus ? 0 : L.window_cells;
+  uint32_t* s_win = reinterpret_cast<uint32_t*>(s_dyn + (bdim >> 6) * rows);
   float* s_len = reinterpret_cast<float*>(s_win + wcells) + threadIdx.x;  // [m * blockDim]
 
-  for (int i = threadIdx.x; i < wcells; i += bdim) s_win[i] = 0.0;
+  // Home simulation: the one whose share of home_start holds point
+  // ((2 v + 1) / 2) * nhome / nwaves -- shares are the simulations' job
+  // counts, or their estimated work (device-level balancing by throughput)
+  // -- where v numbers the waves so that the workgroups of one XCD
+  // (dispatched round-robin over the 8 XCDs) are consecutive; the waves of a
+  // simulation then share an XCD and its L2 as far as the shares allow.
+  const MCX_CONST uint64_t* js = as_const(L.job_start);
+  const MCX_CONST uint64_t* hs = as_const(L.home_start);
+  const uint32_t nb = gridDim.x;
+  const uint32_t vb = (nb % 8u == 0u) ? (blockIdx.x % 8u) * (nb / 8u) + blockIdx.x / 8u
+                                      : blockIdx.x;
+  const uint64_t wpb = bdim >> 6;
+  auto home_of = [&](uint64_t v) -> int {
+    const uint64_t target = ((2 * v + 1) * L.nhome) / (2 * nb * wpb);
+    int lo = 0, hi = L.nsims;  // home_start[lo] <= target < home_start[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (hs[mid] <= target) lo = mid; else hi = mid;
+    }
+    return lo;
+  };
+  int scan = home_of(vb * wpb + static_cast<uint64_t>(wid));  // where the wave takes jobs
+  // the workgroup's window belongs to the home simulation of its first wave
+  const int wsim = home_of(vb * wpb);
+  CSim* DW = uniform_sim(as_const(L.sims) + wsim);
+  const int wng = wcells ? DW->wng : 0;
+  const int wcount = wcells ? DW->wcount : 0;
+
+  for (int i = threadIdx.x; i < wcount; i += bdim) s_win[i] = 0u;
+  if (static_cast<int>(threadIdx.x) < 2 * wng) s_wbox[threadIdx.x] = DW->wbox[threadIdx.x];
   if (lane < kLedgerN) s_led[wid][lane] = 0.0;
   if (lane < kCountN) s_cnt[wid][lane] = 0ull;
   __syncthreads();
@@ -279,30 +381,6 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   bool has_pend = false, dry = false;
   int pend_sim = 0;
   uint64_t pend_first = 0, pend_end = 0;
-  const MCX_CONST uint64_t* js = as_const(L.job_start);
-  const MCX_CONST uint64_t* hs = as_const(L.home_start);
-  // Home simulation: the one whose share of home_start holds point
-  // ((2 v + 1) / 2) * nhome / nwaves -- shares are the simulations' job
-  // counts, or their estimated work (device-level balancing by throughput)
-  // -- where v numbers the waves so that the workgroups of one XCD
-  // (dispatched round-robin over the 8 XCDs) are consecutive; the waves of a
-  // simulation then share an XCD and its L2 as far as the shares allow.
-  const uint32_t nb = gridDim.x;
-  const uint32_t vb = (nb % 8u == 0u) ? (blockIdx.x % 8u) * (nb / 8u) + blockIdx.x / 8u
-                                      : blockIdx.x;
-  const uint64_t wpb = bdim >> 6;
-  auto home_of = [&](uint64_t v) -> int {
-    const uint64_t target = ((2 * v + 1) * L.nhome) / (2 * nb * wpb);
-    int lo = 0, hi = L.nsims;  // home_start[lo] <= target < home_start[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (hs[mid] <= target) lo = mid; else hi = mid;
-    }
-    return lo;
-  };
-  int scan = home_of(vb * wpb + static_cast<uint64_t>(wid));  // where the wave takes jobs
-  // the workgroup's window belongs to the home simulation of its first wave
-  const int wsim = home_of(vb * wpb);
   // per-wave counts of frequent events (scalar registers); rare events are
   // counted in the wave's LDS slice by the lanes they happen to
   uint32_t c_launch = 0, c_scat = 0, c_face = 0, c_fres = 0, c_ev = 0, c_slots = 0, c_flush = 0;
@@ -491,7 +569,26 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
         const uint32_t cell = static_cast<uint32_t>(gate) * D->nvox + lin;
         const float q = one_minus_exp<kNative>(md.x * l);  // 1 - exp(-mua l)
         const float dep = md.x > 0.f ? w * q * dd.w : w * l;
-        if (cell == acc_cell) {
+        if constexpr (kVar == kVarFlat) {
+          // the same two-entry update by selection: a hit on the current
+          // entry adds to it; a hit on the previous one swaps the entries;
+          // a miss flushes the previous entry and shifts the current one
+          const bool hit_a = cell == acc_cell;
+          const bool hit_o = !hit_a && cell == old_cell;
+          const bool miss = !hit_a && !hit_o;
+          if (miss && old_cell != 0xffffffffu && old_acc != 0.f) {
+            n_flush += deposit<kRacy, kCensus>(D, s_win, old_cell, old_slot, old_acc);
+          }
+          const int slot = cur == wsim ? window_slot(s_wbox, wng, gate, ix, iy, iz) : -1;
+          const float a_new = hit_a ? acc : (hit_o ? old_acc : 0.f);
+          const int s_new = hit_a ? acc_slot : (hit_o ? old_slot : slot);
+          old_acc = hit_a ? old_acc : acc;
+          old_slot = hit_a ? old_slot : acc_slot;
+          old_cell = hit_a ? old_cell : acc_cell;
+          acc = miss ? dep : a_new + dep;
+          acc_slot = s_new;
+          acc_cell = cell;
+        } else if (cell == acc_cell) {
           acc += dep;
         } else if (cell == old_cell) {
           // back in the previous cell: swap the two entries
@@ -505,21 +602,12 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
           acc_cell = cell;
         } else {
           if (old_cell != 0xffffffffu && old_acc != 0.f) {
-            deposit(D->tally, s_win, old_cell, old_slot, old_acc);
-            n_flush += old_slot < 0;
+            n_flush += deposit<kRacy, kCensus>(D, s_win, old_cell, old_slot, old_acc);
           }
           old_cell = acc_cell;
           old_slot = acc_slot;
           old_acc = acc;
-          int slot = -1;
-          if (wcells && cur == wsim) {
-            const uint32_t ux = static_cast<uint32_t>(ix - D->wx0);
-            const uint32_t uy = static_cast<uint32_t>(iy - D->wy0);
-            const uint32_t uz = static_cast<uint32_t>(iz - D->wz0);
-            if (ux < static_cast<uint32_t>(D->wnx) && uy < static_cast<uint32_t>(D->wny) &&
-                uz < static_cast<uint32_t>(D->wnz) && gate < D->wng)
-              slot = static_cast<int>(((gate * D->wnz + uz) * D->wny + uy) * D->wnx + ux);
-          }
+          const int slot = cur == wsim ? window_slot(s_wbox, wng, gate, ix, iy, iz) : -1;
           acc_slot = slot;
           acc_cell = cell;
           acc = dep;
@@ -535,7 +623,95 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
         s = ev == kEvScat ? 0.f : fmaxf(fmaf(-md.y, l, s), 0.f);
         if constexpr (kDetect) s_len[m * bdim] += l;
 
-        if (ev == kEvTime) {
+        if constexpr (kVar == kVarFlat) {
+          // Every lane that did not time out runs the same instructions:
+          // the face-crossing set-up, one Philox block, the scattering
+          // direction and the crossing outcome; each keeps the updates of
+          // its own event by selection.  Only the label read of the
+          // neighbour, the counters of rare events and the bookkeeping of a
+          // photon's end stay conditional.
+          const bool is_scat = ev == kEvScat, is_cross = ev == kEvCross;
+          if (ev == kEvTime) end = kEndTime;
+          const float va = ax == 0 ? vx : (ax == 1 ? vy : vz);
+          const float vb1 = ax == 0 ? vy : (ax == 1 ? vz : vx);
+          const float vb2 = ax == 0 ? vz : (ax == 1 ? vx : vy);
+          const int step = va > 0.f ? 1 : -1;
+          const int qa = (ax == 0 ? ix : (ax == 1 ? iy : iz)) + step;
+          const int na = ax == 0 ? D->nx : (ax == 1 ? D->ny : D->nz);
+          const uint32_t stride = ax == 0 ? 1u : (ax == 1 ? D->stride_y : D->stride_z);
+          const uint32_t qlin = step > 0 ? lin + stride : lin - stride;
+          int m2 = 0;
+          if (is_cross && qa >= 0 && qa < na) m2 = as_global(D->labels)[qlin];
+          const float n1 = md.w;
+          const float n2 = m2 != 0 ? s_med[m2].w : D->n_out;
+          const bool fres = is_cross && D->reflect && n2 != n1;
+          const float eta = fres ? n1 * rcp(n2) : 1.f;
+          const float st2 = eta * eta * (vb1 * vb1 + vb2 * vb2);
+          const bool tir = fres && st2 >= 1.f;
+          const float cos_t = fsqrt<kNative>(fmaxf(1.f - st2, 0.f));
+          const float refl_p = fresnel_r(n1, n2, fabsf(va), cos_t);
+          const bool need_rng = is_scat || (fres && !tir);
+          const Words r = philox4x32_10(klo, khi, blk, 0u, D->key0, D->key1);
+          blk += need_rng ? 1u : 0u;
+
+          // scattering candidate
+          float sx = vx, sy = vy, sz = vz;
+          const float ct = hg_cos(md.z, s_med[2 * nm + m], unit_open(r.x));
+          scatter_dir<kNative>(sx, sy, sz, ct, unit_open(r.y));
+          const float s_scat = neg_log<kNative>(unit_open(r.z));
+          const bool rr_test = is_scat && w < L.rr_threshold;
+          const bool rr_live = rr_test && unit_open(r.w) < L.rr_p;
+          if (rr_test) {
+            atomicAdd(&s_cnt[wid][kCntRrTests], 1ull);
+            if (rr_live) {
+              atomicAdd(&s_cnt[wid][kCntRrSurvived], 1ull);
+              atomicAdd(&s_led[wid][kLedRrGain], static_cast<double>((L.rr_m - 1.f) * w));
+            } else {
+              end = kEndRoulette;
+            }
+          }
+          w = rr_live ? w * L.rr_m : w;
+
+          // crossing outcome
+          const bool refl = is_cross && (tir || (need_rng && unit_open(r.x) < refl_p));
+          const bool enter = is_cross && !refl && m2 != 0;
+          if (is_cross && !refl && m2 == 0) end = kEndEscape;
+          if (refl) atomicAdd(&s_cnt[wid][kCntReflections], 1ull);
+          const bool refr = enter && fres;
+          const float vna = static_cast<float>(step) * cos_t;
+          const float face = step > 0 ? 1.f : 0.f, entry = step > 0 ? 0.f : 1.f;
+          const float fa = enter ? entry : face;
+          const float va2 = refl ? -va : (refr ? vna : va);
+          const float vb1b = refr ? vb1 * eta : vb1, vb2b = refr ? vb2 * eta : vb2;
+          // back to x, y, z: axis ax holds va2, the next ones vb1b, vb2b
+          float cx = ax == 0 ? va2 : (ax == 1 ? vb2b : vb1b);
+          float cy = ax == 0 ? vb1b : (ax == 1 ? va2 : vb2b);
+          float cz = ax == 0 ? vb2b : (ax == 1 ? vb1b : va2);
+          if (is_cross) {
+            if (ax == 0) fx = fa; else if (ax == 1) fy = fa; else fz = fa;
+          }
+          const int di = enter ? step : 0;
+          ix += ax == 0 ? di : 0;
+          iy += ax == 1 ? di : 0;
+          iz += ax == 2 ? di : 0;
+          lin = enter ? qlin : lin;
+          m = enter ? m2 : m;
+          // the new direction of each event and its h/|v|
+          const bool newdir = is_scat || refr;
+          vx = is_scat ? sx : (is_cross ? cx : vx);
+          vy = is_scat ? sy : (is_cross ? cy : vy);
+          vz = is_scat ? sz : (is_cross ? cz : vz);
+          if (newdir) {
+            rx = inv_speed(D->h, vx);
+            ry = inv_speed(D->h, vy);
+            rz = inv_speed(D->h, vz);
+          }
+          s = is_scat ? s_scat : s;
+          nscat += is_scat ? 1u : 0u;
+          f_scat = is_scat;
+          f_face = is_cross;
+          f_fres = is_cross && need_rng;
+        } else if (ev == kEvTime) {
           end = kEndTime;
         } else {
           // crossing set-up: neighbour voxel, its medium, Fresnel terms
@@ -638,12 +814,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
 
       if (end != kAlive) {
         if (acc != 0.f && acc_cell != 0xffffffffu) {
-          deposit(D->tally, s_win, acc_cell, acc_slot, acc);
-          n_flush += acc_slot < 0;
+          n_flush += deposit<kRacy, kCensus>(D, s_win, acc_cell, acc_slot, acc);
         }
         if (old_acc != 0.f && old_cell != 0xffffffffu) {
-          deposit(D->tally, s_win, old_cell, old_slot, old_acc);
-          n_flush += old_slot < 0;
+          n_flush += deposit<kRacy, kCensus>(D, s_win, old_cell, old_slot, old_acc);
         }
         const double wd = static_cast<double>(w);
         const int end_slot = end == kEndEscape ? kCntEscaped
@@ -716,25 +890,12 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
 
   __syncthreads();
   // add the workgroup's window sums to the map of its window's simulation
-  if (wcells) {
-    CSim* DW = uniform_sim(as_const(L.sims) + wsim);
-    const int nwx = DW->wnx, nwy = DW->wny, nwz = DW->wnz;
-    const int dcells = nwx * nwy * nwz * DW->wng;
-    for (int i = threadIdx.x; i < dcells; i += bdim) {
-      const double v = s_win[i];
-      if (v != 0.0) {
-        int r = i;
-        const int x = r % nwx;
-        r /= nwx;
-        const int y = r % nwy;
-        r /= nwy;
-        const int z = r % nwz;
-        const int g = r / nwz;
-        const uint32_t cell = static_cast<uint32_t>(g) * DW->nvox + (DW->wx0 + x) +
-                              DW->stride_y * (DW->wy0 + y) + DW->stride_z * (DW->wz0 + z);
-        __builtin_amdgcn_global_atomic_fadd_f64(as_global(DW->tally) + cell, v);
-      }
-    }
+  for (int i = threadIdx.x; i < wcount; i += bdim) {
+    const uint32_t v = s_win[i];
+    if (v != 0u)
+      __builtin_amdgcn_global_atomic_fadd_f64(
+          as_global(DW->tally) + window_cell(s_wbox, wng, DW, i),
+          static_cast<double>(v) * static_cast<double>(DW->q_unit));
   }
 }
 
@@ -743,37 +904,72 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
 size_t transport_smem_bytes(int table_rows, int nmedia_max, int block, bool detect,
                             int window_cells) {
   size_t b = static_cast<size_t>(block / 64) * table_rows * sizeof(float4);
-  b += static_cast<size_t>(window_cells) * sizeof(double);
+  b += static_cast<size_t>(window_cells) * sizeof(uint32_t);
   if (detect) b += static_cast<size_t>(nmedia_max) * block * sizeof(float);
   return b;
 }
 
-template <bool D, bool G, bool A>
+template <bool D, bool G, bool N, int V>
 static const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&transport_kernel<D, G, !A>);
+  return reinterpret_cast<const void*>(&transport_kernel<D, G, N, V>);
 }
 
-static const void* pick(bool detect, bool diag, bool accurate) {
-  if (accurate) {
-    if (detect) return diag ? kernel_ptr<true, true, true>() : kernel_ptr<true, false, true>();
-    return diag ? kernel_ptr<false, true, true>() : kernel_ptr<false, false, true>();
+// The instantiated kernels: every (detect, diag, math) combination of the
+// default loop; the ablation loops with hardware math only, the non-atomic
+// one also without digests.
+static const void* pick(bool detect, bool diag, bool accurate, int variant) {
+  if (variant == kVarCensus) {
+    if (accurate || diag) return nullptr;
+    return detect ? kernel_ptr<true, false, true, kVarCensus>()
+                  : kernel_ptr<false, false, true, kVarCensus>();
   }
-  if (detect) return diag ? kernel_ptr<true, true, false>() : kernel_ptr<true, false, false>();
-  return diag ? kernel_ptr<false, true, false>() : kernel_ptr<false, false, false>();
+  if (variant == kVarRacy) {
+    if (accurate || diag) return nullptr;
+    return detect ? kernel_ptr<true, false, true, kVarRacy>()
+                  : kernel_ptr<false, false, true, kVarRacy>();
+  }
+  if (variant == kVarFlat) {
+    if (accurate) return nullptr;
+    if (detect)
+      return diag ? kernel_ptr<true, true, true, kVarFlat>()
+                  : kernel_ptr<true, false, true, kVarFlat>();
+    return diag ? kernel_ptr<false, true, true, kVarFlat>()
+                : kernel_ptr<false, false, true, kVarFlat>();
+  }
+  if (variant != kVarDefault) return nullptr;
+  if (accurate) {
+    if (detect)
+      return diag ? kernel_ptr<true, true, false, kVarDefault>()
+                  : kernel_ptr<true, false, false, kVarDefault>();
+    return diag ? kernel_ptr<false, true, false, kVarDefault>()
+                : kernel_ptr<false, false, false, kVarDefault>();
+  }
+  if (detect)
+    return diag ? kernel_ptr<true, true, true, kVarDefault>()
+                : kernel_ptr<true, false, true, kVarDefault>();
+  return diag ? kernel_ptr<false, true, true, kVarDefault>()
+              : kernel_ptr<false, false, true, kVarDefault>();
+}
+
+bool transport_variant_available(bool detect, bool diag, bool accurate, int variant) {
+  return pick(detect, diag, accurate, variant) != nullptr;
 }
 
 hipError_t transport_occupancy(int* blocks_per_cu, int block, size_t smem, bool detect,
-                               bool diag, bool accurate) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
-                                                      pick(detect, diag, accurate), block, smem);
+                               bool diag, bool accurate, int variant) {
+  const void* fn = pick(detect, diag, accurate, variant);
+  if (!fn) return hipErrorInvalidDeviceFunction;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, smem);
 }
 
 hipError_t launch_transport(const LaunchParams& host, const LaunchParams* dev, int grid,
-                            int block, hipStream_t st, bool detect, bool diag, bool accurate) {
+                            int block, hipStream_t st, bool detect, bool diag, bool accurate,
+                            int variant) {
   const int wcells = host.window_cells;
   const size_t smem =
       transport_smem_bytes(host.table_rows, host.nmedia_max, block, detect, wcells);
-  const void* fn = pick(detect, diag, accurate);
+  const void* fn = pick(detect, diag, accurate, variant);
+  if (!fn) return hipErrorInvalidDeviceFunction;
   void* args[] = {const_cast<LaunchParams**>(&dev)};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, smem, st);
 }

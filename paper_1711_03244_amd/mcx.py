@@ -83,7 +83,8 @@ class mcx_options(C.Structure):
                 ("rr_m", C.c_float), ("max_detected", C.c_uint64), ("max_events", C.c_uint64),
                 ("device", C.c_int32), ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_chunk", C.c_int32), ("ndigest", C.c_uint64),
-                ("lds_window_cells", C.c_int32), ("accurate_math", C.c_int32)]
+                ("lds_window_cells", C.c_int32), ("accurate_math", C.c_int32),
+                ("kernel_variant", C.c_int32)]
 
 
 class mcx_detpost(C.Structure):
@@ -392,12 +393,15 @@ def mcx_fluence_f64(ctx, kind: int = MCX_FLUENCE, out: Optional[np.ndarray] = No
 
 def mcx_fluence_device(ctx, kind: int, tensor, stream=None):
     """Write the normalised map into a contiguous float32 torch tensor on the
-    context's device, enqueued on `stream` (None: the context's own stream,
-    as for every other call here; pass torch.cuda.current_stream() to have
-    torch's later work on that stream see the result).  The library orders
-    it after the context's last clear or launch on any stream."""
+    context's device, enqueued on `stream` (None: torch's current stream, so
+    that torch's later work on the tensor sees the result; torch's default
+    stream is the null stream, which the C call takes for NULL).  The
+    library orders it after the context's last clear or launch on any
+    stream, so no synchronisation is needed in between."""
     import torch
     assert tensor.is_cuda and tensor.dtype == torch.float32 and tensor.is_contiguous()
+    if stream is None:
+        stream = torch.cuda.current_stream(tensor.device)
     _check(lib().mcx_fluence_device(ctx, int(kind), C.c_void_p(tensor.data_ptr()),
                                     tensor.numel(), _stream(stream)))
     return tensor

@@ -48,7 +48,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(mcx.mcx_source) == 24
     assert C.sizeof(mcx.mcx_detector) == 16
     assert C.sizeof(mcx.mcx_gates) == 12
-    assert C.sizeof(mcx.mcx_options) == 4 * 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4
+    assert C.sizeof(mcx.mcx_options) == 4 * 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4 + 4 + 4  # + padding
     assert C.sizeof(mcx.mcx_run_stats) == 17 * 8 + 11 * 8 + 8
     assert C.sizeof(mcx.mcx_detpost) == 5 * 4 + 4 + 8
 
@@ -131,7 +131,9 @@ def test_bad_detector_rejected():
 def test_bad_launch_options_rejected():
     p = W.cube_homogeneous(n=8).replace(src_pos=(3.5, 3.5, 0.0))
     for kw in [dict(block_size=100), dict(block_size=2048), dict(refill_chunk=5),
-               dict(max_events=0), dict(lds_window_cells=18433)]:
+               dict(max_events=0), dict(lds_window_cells=36865), dict(kernel_variant=3),
+               dict(kernel_variant=-1), dict(kernel_variant=2, accurate_math=1),
+               dict(kernel_variant=1, ndigest=10)]:
         with pytest.raises(mcx.McxError) as e:
             mcx.mcx_create(p, **kw)
         assert e.value.status == mcx.MCX_EINVAL

@@ -61,24 +61,109 @@ def terminated(st):
     return st["escaped"] + st["timeout"] + st["rr_dead"] + st["capped"]
 
 
-def sigma_test(g_raw, o_raw, seeds_raw, o_dep, mask):
-    """Fraction of masked cells within 3 and beyond 6 sigma of seed-repeat
-    noise, sigma being the spread of 8 independent oracle seeds at the same
-    photon count.  Only where those 8 seeds spread by exactly zero (no seed
-    deposited into the cell) is sigma taken as the Poisson estimate of the
-    cell's own deposits, cell value / sqrt(deposits); everywhere else the
-    measured spread alone is the bar."""
-    sd = np.std(np.stack(seeds_raw), axis=0, ddof=1)
-    poisson = np.maximum(np.abs(g_raw), np.abs(o_raw)) / np.sqrt(np.maximum(o_dep, 1))
-    sig = np.where(sd > 0, sd, poisson)[mask]
-    d = np.abs(g_raw - o_raw)[mask]
-    z = np.where(sig > 0, d / np.where(sig > 0, sig, 1), np.where(d == 0, 0.0, np.inf))
-    say("sigma test: cells", int(mask.sum()), "with zero seed spread",
-        int(np.sum((sd == 0)[mask])))
-    return float(np.mean(z <= 3)), int(np.sum(z > 6)), int(mask.sum())
+def _zscores(g, o, seeds, dep):
+    """|g - o| over the spread of the difference of two independent runs,
+    sqrt(2) times the spread (std, ddof 1) of the 8 seeds' values of the
+    same quantity; where the seeds spread by exactly zero (none deposited),
+    sqrt(2) times the Poisson estimate of the quantity's own deposits."""
+    sd = np.std(np.stack(seeds), axis=0, ddof=1)
+    poisson = np.maximum(np.abs(g), np.abs(o)) / np.sqrt(np.maximum(dep, 1))
+    sig = math.sqrt(2.0) * np.where(sd > 0, sd, poisson)
+    d = np.abs(g - o)
+    return np.where(sig > 0, d / np.where(sig > 0, sig, 1), np.where(d == 0, 0.0, np.inf))
 
 
-# ----------------------------------------------------------- closed forms
+def _block_sums(a, b):
+    """Sums over b x b x b voxel blocks of each gate ([gate][z][y][x], the
+    grid padded with zeros to a multiple of b)."""
+    a = np.pad(a, [(0, 0)] + [(0, (-n) % b) for n in a.shape[1:]])
+    g, z, y, x = a.shape
+    return a.reshape(g, z // b, b, y // b, b, x // b, b).sum(axis=(2, 4, 6))
+
+
+def sigma_test(g_raw, o_raw, seeds_raw, seeds_dep, seeds_vis, min_vis=100, block=4,
+               hi_dep=10_000):
+    """Seed-repeat noise test of every cell outside the >= 1e4-deposit rule,
+    at the scale where that noise is a usable sigma.
+    A cell visited by a handful of photons has a seed-to-seed distribution
+    far from Gaussian -- one photon's visit is a many-sigma event for a cell
+    that most runs never see -- so the test takes three levels: cells with
+    a mean of >= min_vis photon visits over 8 independent oracle seeds, one
+    by one; the remaining cells summed over block^3 voxel blocks of one
+    gate, blocks with >= min_vis such visits; what still remains summed per
+    gate.  Visits, not deposits, count the independent contributions: in
+    white matter a photon leaves ~40 deposits per millimetre, so a hundred
+    deposits can be three photons.  Which cells are tested, and at which
+    level, is decided by the independent seeds' mean counts (>= 1e4
+    deposits: the other rule), never by the two runs compared: a split by
+    their own counts or by where they are non-zero would select cells where
+    they happened to be high.  At each level z = |GPU -
+    oracle| / sigma, sigma the spread of the 8 seeds' values of the same
+    quantity, the noise of the difference of two independent runs: where
+    the GPU and the oracle follow the same photons the difference is far
+    smaller, and where long-lived photons have decoupled (the late gates of
+    the sphere benchmark) the two runs are independent samples there.
+    Returns {level: (items, fraction within 3 sigma, items beyond 6
+    sigma)}."""
+    mask = np.mean(np.stack(seeds_dep).astype(np.float64), axis=0) < hi_dep
+    dep = np.mean(np.stack(seeds_vis).astype(np.float64), axis=0)  # visits
+    out = {}
+    l1 = mask & (dep >= min_vis)
+    out["cells"] = _zscores(g_raw[l1], o_raw[l1], [s[l1] for s in seeds_raw], dep[l1])
+    rest = mask & ~l1
+    f = lambda a: _block_sums(np.where(rest, a, 0.0), block)
+    bd = f(dep)
+    bg, bo, bs = f(g_raw), f(o_raw), [f(s) for s in seeds_raw]
+    used = bd >= min_vis
+    out["blocks"] = _zscores(bg[used], bo[used], [s[used] for s in bs], bd[used])
+    left = ~used
+    gsum = lambda a: np.where(left, a, 0.0).sum(axis=(1, 2, 3))
+    gd = gsum(bd)
+    gok = gd >= min_vis
+    out["gates"] = _zscores(gsum(bg)[gok], gsum(bo)[gok], [gsum(s)[gok] for s in bs], gd[gok])
+    res = {}
+    for k, z in out.items():
+        res[k] = (len(z), float(np.mean(z <= 3)) if len(z) else 1.0, int(np.sum(z > 6)))
+    # what is too sparse for any usable sigma: its share of the map's weight
+    total = np.abs(np.where(mask, g_raw, 0.0)).sum() + np.abs(np.where(mask, o_raw, 0.0)).sum()
+    rest_gates = (~gok)[:, None, None, None] & left
+    res["untested_share"] = float((np.abs(bg[rest_gates]).sum() + np.abs(bo[rest_gates]).sum())
+                                  / max(total, 1e-300))
+    say("sigma test (items, within 3 sigma, beyond 6 sigma):", res)
+    say("per-gate leftover z:", np.round(out["gates"], 2).tolist(), "deposits:",
+        np.round(gd, 1).tolist())
+    zg = out["gates"]
+    for k in np.argsort(-zg)[:4]:
+        gi = np.nonzero(gok)[0][k]
+        say(f"  gate {gi}: GPU {gsum(bg)[gi]:.6g} oracle {gsum(bo)[gi]:.6g} seeds",
+            [float(f"{gsum(x)[gi]:.6g}") for x in bs])
+    # per-gate totals of all masked cells: GPU, oracle, seeds' mean and spread
+    tot = lambda a: np.where(mask, a, 0.0).sum(axis=(1, 2, 3))
+    st = np.stack([tot(x) for x in seeds_raw])
+    zt = (tot(g_raw) - tot(o_raw)) / np.maximum(st.std(axis=0, ddof=1), 1e-300)
+    say("per-gate totals, (GPU - oracle) / seed spread:", np.round(zt, 2).tolist())
+    return res
+
+
+def assert_sigma(res):
+    """Bars from the noise model: with sigma estimated from 8 samples, z of
+    two fully independent Gaussian runs follows Student's t with 7 degrees
+    of freedom, beyond 3 with probability 2.0 % and beyond 6 with 0.054 %;
+    coupled photons only shrink z.  Cells and blocks (thousands of items, so
+    their fractions sit close to those probabilities): >= 97.5 % within 3
+    sigma and <= 0.2 % beyond 6.  The per-gate sums with enough visits (at
+    most one per gate): >= 90 % within 3 sigma and none beyond 6.  What no
+    level can test -- gates whose leftover cells hold fewer than min_vis
+    visits -- must hold less than 1e-4 of the map's weight (the absorbed-
+    fraction bar), so no error hidden there can move the absorbed fraction
+    past it."""
+    for k in ("cells", "blocks"):
+        n, w3, b6 = res[k]
+        assert w3 >= 0.975 and b6 <= 0.002 * n, (k, res[k])
+    n, w3, b6 = res["gates"]
+    assert w3 >= 0.9 and b6 == 0, ("gates", res["gates"])
+    assert res["untested_share"] < 1e-4, res["untested_share"]
+
 
 def test_beer_lambert_exact():
     p = W.slab_column(nz=60, mua=0.005, mus=0.0)
@@ -113,15 +198,20 @@ def test_fp64_tally_sums_two_million_deposits_exactly():
 
 
 def test_gates_and_timeout_exact():
+    # every photon visits each cell of the column once, and a visit's sum
+    # reaches the map rounded to the deposit unit 2^-20 (h = 1 mm): a cell
+    # of N identical photons is off by at most N 2^-21 in absolute terms,
+    # which matters for the short last segment before the time-out
+    quant = 640 * 2.0 ** -21
     p = W.slab_column(nz=60, mua=0.01, mus=0.0, ngates=20, dt=0.02)
     g = gpu(p, 640, 1)
     o = orc(p, 640, 1)
-    assert np.allclose(g["raw"], o["tally"], rtol=2e-6, atol=1e-9)
+    assert np.allclose(g["raw"], o["tally"], rtol=2e-6, atol=quant)
     p = W.slab_column(nz=60, mua=0.01, mus=0.0, ngates=1, dt=0.1)
     g = gpu(p, 640, 1)
     o = orc(p, 640, 1)
     assert g["stats"]["timeout"] == 640
-    assert np.allclose(g["raw"], o["tally"], rtol=2e-6, atol=1e-9)
+    assert np.allclose(g["raw"], o["tally"], rtol=2e-6, atol=quant)
     assert g["stats"]["w_timeout"] == pytest.approx(o["ledger"]["timeout"], rel=2e-6)
 
 
@@ -151,8 +241,9 @@ def cube1():
     N = 100_000
     g = gpu(p, N, 1, ndigest=20_000)
     o = orc(p, N, 1, deposits=True, ndigest=20_000)
-    seeds = [orc(p, N, s)["tally"] for s in range(2, 10)]
-    return p, N, g, o, seeds
+    seeds = [orc(p, N, s, deposits=True, visits=True) for s in range(2, 10)]
+    return p, N, g, o, ([r["tally"] for r in seeds], [r["deposits"] for r in seeds],
+                        [r["visits"] for r in seeds])
 
 
 def test_cube1_counts(cube1):
@@ -188,10 +279,7 @@ def test_cube1_fluence_cells(cube1):
     rel = np.abs(g["raw"][hi] - o["tally"][hi]) / o["tally"][hi]
     say("cube1 >=1e4-deposit cells", int(hi.sum()), "max rel", rel.max())
     assert rel.max() <= 1e-3
-    lo = (~hi) & ((o["tally"] > 0) | (g["raw"] > 0))
-    within3, beyond6, n = sigma_test(g["raw"], o["tally"], seeds, o["deposits"], lo)
-    say("cube1 other cells", n, "within 3 sigma", within3, "beyond 6 sigma", beyond6)
-    assert within3 >= 0.99 and beyond6 <= 0.001 * n
+    assert_sigma(sigma_test(g["raw"], o["tally"], *seeds))
 
 
 @pytest.fixture(scope="module")
@@ -202,8 +290,9 @@ def cube2():
     N = 1_000_000
     g = gpu(p, N, 1, ndigest=N)
     o = orc(p, N, 1, deposits=True, ndigest=N)
-    seeds = [orc(p, N, s)["tally"] for s in range(2, 10)]
-    return p, N, g, o, seeds
+    seeds = [orc(p, N, s, deposits=True, visits=True) for s in range(2, 10)]
+    return p, N, g, o, ([r["tally"] for r in seeds], [r["deposits"] for r in seeds],
+                        [r["visits"] for r in seeds])
 
 
 def test_cube2_counts_and_coupling(cube2):
@@ -213,6 +302,11 @@ def test_cube2_counts_and_coupling(cube2):
     assert st["rr_tests"] == 0 and o["counts"]["rr_tests"] == 0
     same = np.all(g["digest"][:, [0, 1, 3]] == o["digest"][:, [0, 1, 3]], axis=1)
     say("cube2 coupled fraction", same.mean())
+    t_end = o["digest"][:, 5]
+    for lo_t, hi_t in [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5.01)]:
+        sel = (t_end >= lo_t) & (t_end < hi_t)
+        say(f"  photons ending in [{lo_t}, {hi_t}) ns: {int(sel.sum())}, coupled "
+            f"{same[sel].mean() if sel.any() else float('nan'):.3f}")
     # The mus jump at the voxelised sphere amplifies rounding differences;
     # two FP64 implementations that differ only in operation order keep
     # about 96% of photons coupled on this geometry.
@@ -261,10 +355,7 @@ def test_cube2_fluence_cells(cube2):
     rel = np.abs(g["raw"][hi] - o["tally"][hi]) / o["tally"][hi]
     say("cube2 >=1e4-deposit cells", int(hi.sum()), "max rel", rel.max() if hi.any() else None)
     assert hi.sum() >= 10 and rel.max() <= 1e-3
-    lo = (~hi) & ((o["tally"] > 0) | (g["raw"] > 0))
-    within3, beyond6, n = sigma_test(g["raw"], o["tally"], seeds, o["deposits"], lo)
-    say("cube2 other cells", n, "within 3 sigma", within3, "beyond 6 sigma", beyond6)
-    assert within3 >= 0.99 and beyond6 <= 0.001 * n
+    assert_sigma(sigma_test(g["raw"], o["tally"], *seeds))
 
 
 def test_cube2_detector_records(cube2):
@@ -277,12 +368,20 @@ def test_cube2_detector_records(cube2):
     coupled = (np.all(gd[:, [0, 1, 3]] == od[:, [0, 1, 3]], axis=1)
                & np.isclose(gd[:, 4], od[:, 4], rtol=1e-5, atol=0)
                & np.isclose(gd[:, 5], od[:, 5], rtol=1e-5, atol=0))
+    # A coupled photon's record: detector and scatterings exact; weight and
+    # time to the 1e-5 that defines coupling; each medium's pathlength to
+    # 2e-5 of the photon's whole path -- the same relative agreement on the
+    # total path that t implies, which the split between media can move by
+    # (a long path in FP32 drifts by micrometres without changing any event).
     matched = 0
     for k, r in zip(g["rec_photon"], g["rec"]):
         k = int(k)
         if coupled[k]:
             assert k in om
-            assert np.allclose(r, om[k], rtol=1e-4, atol=1e-5), (k, r, om[k])
+            ref = om[k]
+            assert r[0] == ref[0] and r[1] == ref[1], (k, r, ref)
+            assert np.allclose(r[2:4], ref[2:4], rtol=1e-5, atol=0), (k, r, ref)
+            assert np.all(np.abs(r[4:] - ref[4:]) <= 2e-5 * ref[4:].sum() + 1e-5), (k, r, ref)
             matched += 1
     assert matched > 20 and g["dropped"] == 0
     # detector weights are exp(-sum mua_i L_i) and times sum n_i L_i / c
@@ -330,7 +429,8 @@ def test_voxel_size_and_gate_width_normalisation(case):
     N = 100_000
     g = gpu(p, N, 3, kinds=True, ndigest=N)
     o = orc(p, N, 3, deposits=True, ndigest=N)
-    seeds = [orc(p, N, s)["tally"] for s in range(11, 19)]
+    runs = [orc(p, N, s, deposits=True, visits=True) for s in range(11, 19)]
+    seeds = [r["tally"] for r in runs]
     st = g["stats"]
     assert st["launched"] == N and terminated(st) == N
     assert abs(energy_residual(st)) < 1e-5
@@ -343,7 +443,6 @@ def test_voxel_size_and_gate_width_normalisation(case):
     assert np.allclose(g[2], g[1] / dt, rtol=1e-14, atol=0)
     assert np.allclose(g["k1_f32"], g[1], rtol=6e-8, atol=0)
     hi = o["deposits"] >= 10_000
-    lo = (~hi) & ((o["tally"] > 0) | (g["raw"] > 0))
     assert hi.sum() >= 10
     for kind in (1, 2):
         ok = oracle.normalise(o["tally"], N, h, dt, kind)
@@ -351,9 +450,9 @@ def test_voxel_size_and_gate_width_normalisation(case):
         say(case, "kind", kind, ">=1e4-deposit cells", int(hi.sum()), "max rel", rel.max())
         assert rel.max() <= 1e-3
         sk = [oracle.normalise(t, N, h, dt, kind) for t in seeds]
-        within3, beyond6, n = sigma_test(g[kind], ok, sk, o["deposits"], lo)
-        say(case, "kind", kind, "other cells", n, "within 3 sigma", within3, "beyond 6", beyond6)
-        assert within3 >= 0.99 and beyond6 <= 0.001 * n
+        say(case, "kind", kind)
+        assert_sigma(sigma_test(g[kind], ok, sk, [r["deposits"] for r in runs],
+                                [r["visits"] for r in runs]))
     # absorbed weight: the difference is the decoupled photons'
     a_g, a_o = st["absorbed_grid"] / N, absorbed(p, o["tally"]) / N
     d = o["digest"][:, 4] - g["digest"][:, 4]
@@ -367,7 +466,10 @@ def test_voxel_size_and_gate_width_normalisation(case):
     matched = 0
     for k, r in zip(g["rec_photon"], g["rec"]):
         if coupled[int(k)]:
-            assert np.allclose(r, om[int(k)], rtol=1e-4, atol=1e-5 * h), (k, r, om[int(k)])
+            ref = om[int(k)]  # the bars of the sphere benchmark's records
+            assert r[0] == ref[0] and r[1] == ref[1], (k, r, ref)
+            assert np.allclose(r[2:4], ref[2:4], rtol=1e-5, atol=0), (k, r, ref)
+            assert np.all(np.abs(r[4:] - ref[4:]) <= 2e-5 * ref[4:].sum() + 1e-5 * h), (k, r, ref)
             matched += 1
     say(case, "records", len(g["rec"]), "oracle", len(o["records"]), "matched", matched)
     assert matched >= 20 and g["dropped"] == 0
@@ -487,14 +589,55 @@ def test_split_runs_accumulate_and_reproduce():
                                  dict(refill_chunk=64), dict(refill_chunk=8192),
                                  dict(blocks_per_cu=1)])
 def test_launch_shape_does_not_change_results(opt):
+    """Every visit sum reaches the map as a whole number of deposit units
+    (a power of two), so every partial sum is exact and the map is the same
+    to the last bit whatever the launch shape."""
     p = W.cube_homogeneous(n=30).replace(src_pos=(14.5, 14.5, 0.0), name="cube30")
     N = 30_000
     base = gpu(p, N, 5)
     g = gpu(p, N, 5, **opt)
     for k in ["launched", "escaped", "timeout", "scatters", "face_events"]:
         assert g["stats"][k] == base["stats"][k]
-    big = base["raw"] > 1e-3 * base["raw"].max()
-    assert np.allclose(g["raw"][big], base["raw"][big], rtol=1e-9)
+    assert np.array_equal(g["raw"], base["raw"])
+
+
+def test_window_sums_with_one_running_wave_per_workgroup():
+    """Jobs of 32768 photons leave one running wave in a few workgroups, which
+    then sums every visit of its photons to the source cells in its LDS
+    window; the 32-bit sums must be moved to the map before they wrap, so
+    the map equals the default launch's bit for bit."""
+    p = W.cube_homogeneous(n=30).replace(src_pos=(14.5, 14.5, 0.0), name="cube30")
+    N = 120_000
+    base = gpu(p, N, 6)
+    g = gpu(p, N, 6, refill_chunk=32768)
+    assert g["stats"]["launched"] == N
+    assert np.array_equal(g["raw"], base["raw"])
+
+
+@pytest.mark.parametrize("name", ["sphere", "head"])
+def test_census_shaped_window_does_not_change_results(name):
+    """After the autotuner shaped the LDS window from a flush census, every
+    count is the default launch's and the map is the same bit for bit: the
+    window only changes where a visit's whole number of deposit units is
+    summed, and every such sum is exact."""
+    if name == "sphere":
+        p, N = W.cube_sphere().replace(name="cube60_sphere"), 2_000_000
+    else:
+        p, N = W.head_phantom(1), 300_000
+    say(f"[gpu] {p.name}: default launch vs census-shaped window, N={N}")
+    with mcx.Simulation(p) as sim:
+        sim.run(N, 8)
+        base, sb = sim.fluence(mcx.MCX_RAW, f64=True), sim.stats()
+        tune = sim.autotune(N // 4, 9)
+        sim.run(N, 8)
+        tuned, st = sim.fluence(mcx.MCX_RAW, f64=True), sim.stats()
+    say("tuned", tune, "flushes per photon", sb["flushes"] / N, "->", st["flushes"] / N)
+    for k in ["launched", "escaped", "timeout", "rr_dead", "scatters", "face_events", "events",
+              "detected"]:
+        assert st[k] == sb[k], k
+    assert np.array_equal(tuned, base)
+    # the reduction over cells adds its per-block sums in no fixed order
+    assert st["absorbed_grid"] == pytest.approx(sb["absorbed_grid"], rel=1e-12)
 
 
 def test_fluence_into_torch_tensor():
@@ -570,8 +713,9 @@ def head():
     N = 100_000
     g = gpu(p, N, 1, ndigest=N)
     o = orc(p, N, 1, deposits=True, ndigest=N)
-    seeds = [orc(p, N, s)["tally"] for s in range(2, 10)]
-    return p, N, g, o, seeds
+    seeds = [orc(p, N, s, deposits=True, visits=True) for s in range(2, 10)]
+    return p, N, g, o, ([r["tally"] for r in seeds], [r["deposits"] for r in seeds],
+                        [r["visits"] for r in seeds])
 
 
 def test_head_counts_and_coupling(head):
@@ -589,15 +733,29 @@ def test_head_counts_and_coupling(head):
 
 
 def test_head_fluence_cells(head):
+    """Cells with >= 1e4 oracle deposits within 1e-3 relative -- a bar met
+    through coupling.  In the head 8-9 % of the photons decouple (mus jumps
+    of up to 4500x between CSF and white matter), many of them near the
+    source, and in white matter a photon leaves ~40 deposits per mm, so a
+    cell's 1e4 deposits may come from a few hundred visits: where the
+    decoupled photons' visits alone exceed 1e-3 of a cell, the cell is held
+    to the noise of two independent runs instead (3 sqrt(2) sigma of the 8
+    oracle seeds); the test reports how many cells needed that, and at
+    least 90 % must meet 1e-3 outright.  The remaining cells take the
+    seed-repeat test."""
     p, N, g, o, seeds = head
     hi = o["deposits"] >= 10_000
-    rel = np.abs(g["raw"][hi] - o["tally"][hi]) / o["tally"][hi]
-    say("head >=1e4-deposit cells", int(hi.sum()), "max rel", rel.max() if hi.any() else None)
-    assert hi.sum() >= 100 and rel.max() <= 1e-3
-    lo = (~hi) & ((o["tally"] > 0) | (g["raw"] > 0))
-    within3, beyond6, n = sigma_test(g["raw"], o["tally"], seeds, o["deposits"], lo)
-    say("head other cells", n, "within 3 sigma", within3, "beyond 6 sigma", beyond6)
-    assert within3 >= 0.99 and beyond6 <= 0.001 * n
+    d = np.abs(g["raw"][hi] - o["tally"][hi])
+    rel = d / o["tally"][hi]
+    sd = np.std(np.stack([t[hi] for t in seeds[0]]), axis=0, ddof=1)
+    strict = rel <= 1e-3
+    noise = d <= 3 * math.sqrt(2.0) * sd
+    say("head >=1e4-deposit cells", int(hi.sum()), "within 1e-3", float(strict.mean()),
+        "max rel", float(rel.max()), "beyond 1e-3 but within two-run noise",
+        int(np.sum(~strict & noise)), "max z there",
+        float(np.max(d[~strict] / (math.sqrt(2.0) * sd[~strict]))) if (~strict).any() else 0.0)
+    assert hi.sum() >= 100 and np.all(strict | noise) and strict.mean() >= 0.9
+    assert_sigma(sigma_test(g["raw"], o["tally"], *seeds))
 
 
 def test_head_absorbed_fraction_1e6():
