@@ -30,13 +30,18 @@ timed once after a warm-up launch: `head_volume` (the seeded 181 x 217 x
 each, 5.4e8 photons in one launch, with the fixed launch shape -- 64-thread
 workgroups, one photon per lane per job, direct atomics -- and with the
 shape the autotuner picks from pilot launches of 1/50 of the photons).
-`photon_scaling` runs the sphere benchmark at 1e6 .. 1e9 photons and fits
-the paper's device model T = a n + T0.
-`denoiser` trains the 3-D U-Net on simulator pairs of 64^3 volumes (inputs
-at 1e5, 1e6 and 1e7 photons, targets at 1e8) and reports, on held-out
-volumes, the error of the denoised and the plain maps against a reference
-and the time-to-equal-error against plain runs, with every run in its own
-launch and with 32 volumes per batched launch (see denoise.py).
+The batch leg also fits the paper's device model per simulation from
+pilots of 1e6 and 5e6 photons and reruns the batch with home waves spread
+by the estimated work a_i n_i (the paper's throughput partition S2) instead
+of job counts.  `photon_scaling` runs the sphere benchmark at 1e6 .. 1e9
+photons and fits the device model T = a n + T0.  `ablations` times the
+paper's benchmark variants of the event loop (non-atomic deposits, B2;
+branch-reduced loop, Opt3) against the default loop at 3e7 photons.
+`denoiser` evaluates the 3-D U-Net of the committed inference checkpoint
+(trained on simulator pairs of 64^3 volumes with 1e9-photon targets; the
+file records how) on 16 held-out volumes: the error of denoised 3e7, 5e7
+and 8e7-photon maps against the error of a plain 1e9-photon run, and the
+wall-time ratio at equal error (see denoise.evaluate_strict).
 """
 import argparse
 import json
@@ -70,6 +75,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-denoise", action="store_true")
     ap.add_argument("--no-scaling", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true")
     ap.add_argument("--dn-train", type=int, default=64, help="denoiser training volumes")
     ap.add_argument("--dn-steps", type=int, default=20000, help="denoiser training steps")
     ap.add_argument("--dn-batch", type=int, default=4, help="volumes per training step")
@@ -82,6 +88,14 @@ def main():
                     help="1: random x-y symmetries of the training pairs")
     ap.add_argument("--dn-batch-volumes", type=int, default=32,
                     help="volumes per batched launch in the denoiser's batched timing")
+    ap.add_argument("--dn-checkpoint", default=CHECKPOINT,
+                    help="inference checkpoint evaluated by the denoiser leg")
+    ap.add_argument("--dn-train-in-bench", action="store_true",
+                    help="train the denoiser in the bench instead of loading the checkpoint")
+    ap.add_argument("--dn-eval-strict", type=int, default=16,
+                    help="held-out volumes of the checkpoint's evaluation")
+    ap.add_argument("--dn-inputs", default="3e7,5e7,8e7",
+                    help="low-photon counts of the checkpoint's evaluation")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transport runs on a single MI355X "
@@ -101,6 +115,8 @@ def main():
     torch.cuda.synchronize()
     if args.launch:
         blk, chunk, win = (int(v) for v in args.launch.split(","))
+        if win > 0:  # the window boxes the autotuner would shape for this size
+            sim.shape_window(max(1000, N // 20), args.seed + 3000, win)
         sim.set_launch(blk, chunk, win)
         default_rate = None
         tune = {"refill_chunk": chunk, "lds_window_cells": win}
@@ -144,7 +160,9 @@ def main():
     roof["traffic_over_algorithmic"] = (roof["traffic"] / roof["algorithmic_bytes"]
                                         if roof["traffic"] else None)
     scaling = None if args.no_scaling else scaling_leg(sim, args.seed)
+    shape = (last["block_size"], tune["refill_chunk"], tune["lds_window_cells"])
     sim.close()
+    ablations = None if args.no_ablations else ablation_leg(mcx, W, shape, args.seed)
 
     cube1 = None if args.no_head else cube1_leg(mcx, W)
     head = None if args.no_head else head_leg(mcx, roofline, W, args.head_photons, args.seed,
@@ -184,9 +202,16 @@ def main():
         "homogeneous_cube": cube1,
         "head_volume": head,
         "batched": batched,
+        "ablations": ablations,
         "denoiser": denoised,
     }
     print(json.dumps(line), flush=True)
+
+
+def _sha16(path) -> str:
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def host_cpu() -> dict:
@@ -297,6 +322,8 @@ def head_leg(mcx, roofline, W, N, seed, launch=None):
     with mcx.Simulation(p) as sim:
         if launch:
             blk, chunk, win = (int(v) for v in launch.split(","))
+            if win > 0:
+                sim.shape_window(max(1000, N // 50), seed + 3000, win)
             sim.set_launch(blk, chunk, win)
             default_med, tune = None, {"refill_chunk": chunk, "lds_window_cells": win}
             sim.run(N // 100, seed + 1000)  # warm-up
@@ -315,6 +342,38 @@ def head_leg(mcx, roofline, W, N, seed, launch=None):
             "kernel_ms": st["kernel_ms"],
             "run_ms": st["run_ms"], "events_per_photon": st["events"] / N,
             "roofline": roofline.binding(st, ksec)}
+
+
+def ablation_leg(mcx, W, shape, seed, N=30_000_000):
+    """The paper's benchmark study (Fig. 2) on this chip: the event-loop
+    variants at the timed steps' launch shape on the sphere benchmark --
+    default loop, non-atomic map deposits (B2; the weight the races lose is
+    reported against the atomic run of the same photons), branch-reduced
+    loop (Opt3) -- and default vs branch-reduced on the head phantom with
+    the library's default shape.  Kernel-time photons/ms, best of 2 seeds."""
+    out = {"photons": N}
+
+    def rates(p, variant, launch=None):
+        with mcx.Simulation(p, kernel_variant=variant) as sim:
+            if launch:
+                sim.set_launch(*launch)
+            sim.run(N // 30, seed + 7000)  # warm-up
+            best, _, st = best_median(mcx, sim, N, [seed + 7001, seed + 7002])
+        return best, st[0]
+
+    p = W.cube_sphere()
+    d, st_d = rates(p, 0, shape)
+    r, st_r = rates(p, 1, shape)
+    f, _ = rates(p, 2, shape)
+    out["sphere"] = {"launch": list(shape), "default": d, "non_atomic_b2": r,
+                     "branch_reduced_opt3": f,
+                     "atomic_overhead": d and (r / d - 1.0),
+                     "non_atomic_weight_lost": 1.0 - st_r["absorbed_grid"] / st_d["absorbed_grid"]}
+    h = W.head_phantom(1)
+    hd, _ = rates(h, 0)
+    hf, _ = rates(h, 2)
+    out["head"] = {"launch": "library default", "default": hd, "branch_reduced_opt3": hf}
+    return out
 
 
 def batch_leg(mcx, W):
@@ -341,17 +400,53 @@ def batch_leg(mcx, W):
         timed("autotuned")
         out["autotuned"]["refill_chunk"] = tune["refill_chunk"]
         out["autotune"] = tune
+        # the paper's device model per simulation from pilots of 1e6 and 5e6
+        # photons, then home waves in proportion to a_i n_i (its throughput
+        # partition S2) instead of job counts, same launch shape
+        t0 = time.perf_counter()
+        a, t_over = b.fit_runtime(seed=[s + 11 for s in seeds])
+        out["fit_s"] = time.perf_counter() - t0
+        b.set_balance(a)
+        timed("autotuned_s2")
+        b.set_balance(None)
+        out["runtime_model"] = {"pilots": [1_000_000, 5_000_000],
+                                "ms_per_photon_min": float(min(a)),
+                                "ms_per_photon_max": float(max(a)),
+                                "overhead_ms_median": float(sorted(t_over)[len(t_over) // 2])}
     out["speedup"] = out["autotuned"]["photons_per_ms"] / out["fixed"]["photons_per_ms"]
+    out["s2_over_job_counts"] = (out["autotuned_s2"]["photons_per_ms"]
+                                 / out["autotuned"]["photons_per_ms"])
     return out
 
 
+CHECKPOINT = os.path.join(ROOT, "paper_1711_03244_amd", "checkpoints", "denoiser_64cube.npz")
+
+
 def denoise_leg(args):
-    """Train the denoiser on simulator pairs, then time-to-equal-error on
-    held-out volumes against the plain run."""
+    """Time-to-equal-error of the denoiser: the network of the committed
+    inference checkpoint (trained by `python -m paper_1711_03244_amd.denoise`
+    on simulator pairs with 1e9-photon targets; its provenance is in the
+    file and in the line) on held-out volumes against the plain 1e9-photon
+    run (denoise.evaluate_strict).  With --dn-train-in-bench, or without
+    the checkpoint, the network is trained here instead on the smaller
+    configuration below and evaluated by denoise.evaluate."""
     from paper_1711_03244_amd import denoise, nn, workloads as W
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     side = 64
     ch = W.DENOISER_CHANNELS
+    if os.path.exists(args.dn_checkpoint) and not args.dn_train_in_bench:
+        inputs = [float(v) for v in args.dn_inputs.split(",")]
+        with nn.Denoiser(ch, (side, side, side)) as d:
+            meta = d.load_inference(args.dn_checkpoint)
+            ev = denoise.evaluate_strict(d, range(900001, 900001 + args.dn_eval_strict), side,
+                                         inputs, plain_photons=args.dn_plain, ref_runs=2,
+                                         say=log)
+        return {"workload": "denoise_64cubes", "channels": list(ch), "side": side,
+                "checkpoint": os.path.relpath(args.dn_checkpoint, ROOT),
+                "checkpoint_sha256_16": _sha16(args.dn_checkpoint),
+                "training": meta.get("history"), "held_out_seeds": [900001,
+                                                                     900000 + args.dn_eval_strict],
+                **ev}
     t0 = time.perf_counter()
     inputs = [1e5, 1e6, 1e7]
     ds = denoise.make_dataset(range(1, args.dn_train + 1), side, inputs, args.dn_target, say=log)

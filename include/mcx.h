@@ -225,6 +225,17 @@ mcx_status mcx_batch_digest(mcx_ctx *ctx, int32_t sim, double *host_out, uint64_
 mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk,
                           int32_t lds_window_cells);
 
+/* Shape the LDS window of a single-simulation context (hardware math, no
+ * digests) for lds_window_cells cells from a flush census -- one pilot of
+ * pilot_photons[0] photons (seed[0]) counting, per map cell, the cell visits
+ * the kernel adds to the map -- as mcx_autotune does for its candidates, and
+ * use it from the next launch (keeping the block size and job size; a later
+ * mcx_set_launch with the same cell count keeps the shaped boxes).  Other
+ * contexts keep the default boxes.  Tallies are cleared on return.
+ * MCX_EINVAL for a cell count outside [1, 36864].  Blocking. */
+mcx_status mcx_shape_window(mcx_ctx *ctx, const uint64_t *pilot_photons, const uint64_t *seed,
+                            int32_t lds_window_cells);
+
 /* Autotuner: times pilot launches of pilot_photons[i] photons (seed[i]) per
  * simulation over block sizes {64, 256, 448, 512, 768, 1024} x jobs of {64,
  * 256, 1024} photons (1 to 16 photons per lane) x deposit schemes {direct

@@ -1313,6 +1313,20 @@ static mcx_status census(mcx_ctx* c, const uint64_t* pilot, const uint64_t* seed
 // shape is kept.  Then the paper's
 // device model T = a n + T0 is fitted from two pilot sizes (n and n/2) with
 // that shape.  Tallies are cleared afterwards.
+mcx_status mcx_shape_window(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_t* seed,
+                            int32_t lds_window_cells) {
+  if (!c || !pilot_photons || !seed)
+    return fail(MCX_EINVAL, "context, pilot photon counts and seeds are required");
+  if (lds_window_cells <= 0 || lds_window_cells > kMaxWindow)
+    return fail(MCX_EINVAL, "lds_window_cells must be in [1, %d]", kMaxWindow);
+  HIP_TRY(hipSetDevice(c->device));
+  MCX_TRY(host_wait(c));
+  const int budget[1] = {lds_window_cells};
+  MCX_TRY(census(c, pilot_photons, seed, budget, 1));
+  set_window(c, lds_window_cells);
+  return set_shape(c, c->opt.block_size > 0 ? c->opt.block_size : c->block);
+}
+
 mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_t* seed,
                         mcx_tune_result* out) {
   if (!c || !pilot_photons || !seed || !out)

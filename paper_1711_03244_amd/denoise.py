@@ -210,6 +210,117 @@ def evaluate(den: nn.Denoiser, seeds, side, plain_photons, ref_runs, input_photo
     return summarise(rows, plain_photons, input_photons, batched)
 
 
+def plain_error_sq(runs, mask) -> float:
+    """Squared log-RMS error of a plain run with as many photons as the K
+    runs `runs` together (each with 1/K of them): the mean over the mask of
+    the unbiased per-voxel variance of the K log maps, divided by K."""
+    logs = np.log(np.maximum(np.stack([np.asarray(r, np.float64) for r in runs]), EPS))
+    return float(np.mean(np.var(logs, axis=0, ddof=1)[mask]) / len(runs))
+
+
+def error_sq_against(m, ref, mask, ref_sq) -> float:
+    """Squared log-RMS error of map m against the truth, from its mean
+    squared log difference to a reference whose own squared error is
+    ref_sq (independent of m): the difference of the two."""
+    d = np.log(np.maximum(np.asarray(m, np.float64), EPS)) - np.log(np.maximum(ref, EPS))
+    return float(np.mean(d[mask] ** 2)) - ref_sq
+
+
+def evaluate_strict(den: nn.Denoiser, seeds, side, input_photons, plain_photons=1e9,
+                    ref_runs=2, timed_plain=2, seed_base=6_000_000, say=print) -> dict:
+    """Whether denoised low-photon maps reach the plain high-photon run's
+    error, and in how much less time, on held-out volumes.
+
+    Per volume: `ref_runs` independent plain runs of plain_photons /
+    ref_runs photons each (all volumes in one batched launch per run; a
+    batched simulation equals its single run photon for photon).  Their
+    mean R is a plain run of plain_photons photons; the error a plain run
+    of that size makes, E_p, is estimated from their spread: with K runs
+    of n/K photons, var(ln of a run of n) = var(ln of a run of n/K) / K, and
+    the mean over voxels of the unbiased per-voxel variance of the K log
+    maps, divided by K, estimates E_p^2.  A map M is compared with R: the
+    mean of (ln M - ln R)^2 over the mask is E(M)^2 + var(ln R), so E(M)^2 =
+    that mean - E_p^2 (R's own noise, the same size as a plain run's).
+    Mask: medium voxels with R >= 1e-8 max R.  Low-photon maps: one
+    single-volume run per input count (its HIP-event time: clear,
+    transport, reductions), denoised (inference time by HIP events).
+    Plain-run time: single-volume runs of plain_photons photons timed on
+    the first `timed_plain` volumes; for every volume, T = a n + T0 fitted
+    to its own input runs, checked against those timed runs.  The target
+    is met at an input count whose RMS (over volumes) denoised error is at
+    most the RMS plain error; its time ratio is the mean plain time over
+    the mean time of the input run plus inference."""
+    seeds = [int(s) for s in seeds]
+    vols = [W.denoiser_volume(s, side) for s in seeds]
+    K = int(ref_runs)
+    per_run = int(plain_photons) // K
+    runs = []
+    group = max(1, int(4e9 // per_run))  # photons per batched launch <= 4e9
+    for k in range(K):
+        maps = []
+        for g in range(0, len(vols), group):
+            m, ms = simulate(vols[g:g + group], per_run,
+                             [seed_base + 1000 * int(s) + 11 + k for s in seeds[g:g + group]])
+            maps += [x.astype(np.float64) for x in m]
+            say(f"[strict] reference run {k + 1}/{K}, volumes {g + 1}-{g + len(m)} x "
+                f"{per_run:.1e} photons: {ms / 1e3:.1f} s")
+        runs.append(maps)
+    rows = []
+    for i, (s, p) in enumerate(zip(seeds, vols)):
+        ref = np.mean([runs[k][i] for k in range(K)], axis=0)
+        mask = error_mask(ref, p.labels)
+        ep2 = plain_error_sq([runs[k][i] for k in range(K)], mask)
+        row = {"seed": int(s), "mask_voxels": int(mask.sum()), "plain_err": math.sqrt(ep2),
+               "inputs": []}
+        ns, ts = [], []
+        for j, n in enumerate(input_photons):
+            lo, lo_ms = simulate_one(p, n, seed_base + 1000 * int(s) + 100 + j)
+            infer_timed(den, lo)  # the first call includes weight packing
+            dn, inf_ms = infer_timed(den, lo)
+            e_n = error_sq_against(lo, ref, mask, ep2)
+            e_d = error_sq_against(dn, ref, mask, ep2)
+            row["inputs"].append({"photons": int(n), "sim_ms": lo_ms, "infer_ms": inf_ms,
+                                  "noisy_err": math.sqrt(max(e_n, 0.0)),
+                                  "denoised_err": math.sqrt(max(e_d, 0.0)),
+                                  "denoised_sq": e_d})
+            ns.append(float(n))
+            ts.append(lo_ms)
+        a, t0 = np.polyfit(np.array(ns), np.array(ts), 1)
+        row["plain_ms_model"] = float(a * plain_photons + t0)
+        if i < timed_plain:
+            _, row["plain_ms"] = simulate_one(p, plain_photons, seed_base + 1000 * int(s) + 1)
+        rows.append(row)
+        say(f"[strict] volume {s}: plain {plain_photons:.0e} err {row['plain_err']:.4f}, " +
+            ", ".join(f"{r['photons']:.0e}: noisy {r['noisy_err']:.4f} denoised "
+                      f"{r['denoised_err']:.4f}" for r in row["inputs"]))
+    plain = float(np.sqrt(np.mean([r["plain_err"] ** 2 for r in rows])))
+    measured = [(r["plain_ms"], r["plain_ms_model"]) for r in rows if "plain_ms" in r]
+    plain_ms = float(np.mean([r["plain_ms_model"] for r in rows]))
+    out = {"volumes": len(rows), "plain_photons": int(plain_photons), "ref_runs": K,
+           "plain_err": plain, "plain_ms": plain_ms,
+           "plain_ms_measured": [m for m, _ in measured],
+           "plain_ms_model_error": (max(abs(mod / m - 1.0) for m, mod in measured)
+                                    if measured else None),
+           "per_input": [], "equal_error_photons": None, "time_ratio": None}
+    for j, n in enumerate(input_photons):
+        den2 = float(np.mean([r["inputs"][j]["denoised_sq"] for r in rows]))
+        den_err = math.sqrt(max(den2, 0.0))
+        noisy = float(np.sqrt(np.mean([r["inputs"][j]["noisy_err"] ** 2 for r in rows])))
+        sim_ms = float(np.mean([r["inputs"][j]["sim_ms"] for r in rows]))
+        inf_ms = float(np.mean([r["inputs"][j]["infer_ms"] for r in rows]))
+        wins = sum(r["inputs"][j]["denoised_err"] <= r["plain_err"] for r in rows)
+        out["per_input"].append({"photons": int(n), "noisy_err": noisy, "denoised_err": den_err,
+                                 "sim_ms": sim_ms, "infer_ms": inf_ms,
+                                 "time_ratio": plain_ms / (sim_ms + inf_ms),
+                                 "volumes_at_or_below_plain": int(wins)})
+    for r in sorted(out["per_input"], key=lambda r: r["photons"]):
+        if r["denoised_err"] <= plain:
+            out["equal_error_photons"] = r["photons"]
+            out["time_ratio"] = r["time_ratio"]
+            break
+    return out
+
+
 def batch_timing(side, seeds, photon_counts, seed_base=7_000_000, say=print) -> list:
     """Per-volume time of plain runs when the volumes `seeds` share one
     batched launch, at every photon count: [(photons, launch run_ms / K)]
@@ -342,17 +453,38 @@ def main(argv=None) -> dict:
                     help="1: pass training pairs through random x-y symmetries")
     ap.add_argument("--batch-volumes", type=int, default=32,
                     help="volumes per batched launch in the batched timing (0 = none)")
+    ap.add_argument("--train-first", type=int, default=1,
+                    help="seed of the first training volume (volumes first .. first+train-1)")
+    ap.add_argument("--init", default=None,
+                    help="start from this inference checkpoint instead of the seeded weights")
+    ap.add_argument("--save", default=None, help="write an inference checkpoint here")
     a = ap.parse_args(argv)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
     inputs = [float(v) for v in a.inputs.split(",")]
     ch = W.DENOISER_CHANNELS
     t0 = time.perf_counter()
-    ds = make_dataset(range(1, a.train + 1), a.side, inputs, a.target, say=log)
+    seeds = range(a.train_first, a.train_first + a.train)
+    ds = make_dataset(seeds, a.side, inputs, a.target, say=log)
     data_s = time.perf_counter() - t0
     with nn.Denoiser(ch, (a.side,) * 3) as d:
-        d.set_params(W.denoiser_weights(ch, seed=1))
+        history = []
+        if a.init:
+            history = d.load_inference(a.init).get("history", [])
+        else:
+            d.set_params(W.denoiser_weights(ch, seed=1))
         tr = train(d, ds, a.steps, lr=a.lr, log_every=max(1, a.steps // 5), batch=a.batch,
                    max_norm=a.max_norm, augment=bool(a.augment), say=log)
+        if a.save:
+            stage = {"command": "python -m paper_1711_03244_amd.denoise " + " ".join(
+                         argv if argv is not None else sys.argv[1:]),
+                     "train_volume_seeds": [seeds.start, seeds.stop - 1], "inputs": inputs,
+                     "target": a.target, "steps": a.steps, "batch": a.batch, "lr": a.lr,
+                     "max_norm": a.max_norm, "augment": bool(a.augment),
+                     "data_s": data_s, "train_s": tr["seconds"],
+                     "final_loss": tr["losses"][-1][1] if tr["losses"] else None}
+            d.save_inference(a.save, {"channels": list(ch), "side": a.side,
+                                      "history": history + [stage]})
+            log(f"[save] {a.save}")
         ev = evaluate(d, range(900001, 900001 + a.eval), a.side, a.plain, a.ref_runs, inputs,
                       say=log, batch_seeds=range(800001, 800001 + a.batch_volumes)) \
             if a.eval > 0 else None

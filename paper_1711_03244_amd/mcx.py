@@ -35,7 +35,7 @@ EXPORTS = ["mcx_default_options", "mcx_create", "mcx_run", "mcx_run_range", "mcx
            "mcx_batch_stats", "mcx_batch_detected", "mcx_batch_digest", "mcx_set_launch",
            "mcx_autotune", "mcx_detpost_device", "mcx_detpost_device_noalloc",
            "mcx_detected_process", "mcx_fit_linear",
-           "mcx_fit_runtime", "mcx_set_balance"]
+           "mcx_fit_runtime", "mcx_set_balance", "mcx_shape_window"]
 
 
 class McxError(RuntimeError):
@@ -163,6 +163,7 @@ def lib() -> C.CDLL:
                                          C.POINTER(C.c_double)]),
             "mcx_fit_runtime": (C.c_int, [vp, vp, vp, vp, vp, vp]),
             "mcx_set_balance": (C.c_int, [vp, vp]),
+            "mcx_shape_window": (C.c_int, [vp, vp, vp, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -300,6 +301,12 @@ def mcx_autotune(ctx, pilot_photons, seed) -> dict:
     r = mcx_tune_result()
     _check(lib().mcx_autotune(ctx, n.ctypes.data, s.ctypes.data, C.byref(r)))
     return {name: getattr(r, name) for name, _ in mcx_tune_result._fields_}
+
+
+def mcx_shape_window(ctx, pilot_photons, seed, lds_window_cells: int):
+    """Shape the LDS window from a flush census pilot (see include/mcx.h)."""
+    n, s = _u64(pilot_photons), _u64(seed)
+    _check(lib().mcx_shape_window(ctx, n.ctypes.data, s.ctypes.data, int(lds_window_cells)))
 
 
 def mcx_fit_linear(x, y):
@@ -616,6 +623,9 @@ class Simulation:
 
     def autotune(self, pilot_photons: int, seed: int) -> dict:
         return mcx_autotune(self.ctx, [pilot_photons], [seed])
+
+    def shape_window(self, pilot_photons: int, seed: int, lds_window_cells: int):
+        mcx_shape_window(self.ctx, [pilot_photons], [seed], lds_window_cells)
 
     def fit_runtime(self, n1: int = 1_000_000, n2: int = 5_000_000, seed: int = 1):
         """The paper's T = a n + T0 from two pilots; returns (a, t0)."""

@@ -173,6 +173,15 @@ def mcx_nn_layer_backward(kind, shape, cin, cout, x, w, gy, gx=None, gw=None, gb
                                            _ptr(gx), _ptr(gw), _ptr(gb), _stream(stream)))
 
 
+def bf16_bits(x) -> np.ndarray:
+    """16-bit patterns of float32 values rounded to BF16, to nearest even,
+    NaNs kept quiet (the rounding the kernels apply when they pack weights)."""
+    u = np.ascontiguousarray(np.asarray(x, np.float32)).view(np.uint32).astype(np.uint64)
+    nan = (u & 0x7fffffff) > 0x7f800000
+    rne = ((u + 0x7fff + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return np.where(nan, ((u >> 16) | 0x40).astype(np.uint16), rne)
+
+
 class Denoiser:
     """The U-Net of include/mcx_nn.h on one volume shape."""
 
@@ -212,6 +221,47 @@ class Denoiser:
                                  f"{tuple(z['shape'])}, not {self.channels} and {self.shape}")
             self.set_params(z["params"])
             mcx_nn_set_adam(self.h, z["adam_m"], z["adam_v"], int(z["step"]))
+
+    def _weight_mask(self) -> np.ndarray:
+        """True for the weight entries of the flat parameter vector (layer by
+        layer: weights [taps][cin][cout], then the biases)."""
+        from .workloads import denoiser_layer_shapes
+        parts = []
+        for _, taps, ci, co in denoiser_layer_shapes(self.channels):
+            parts += [np.ones(taps * ci * co, bool), np.zeros(co, bool)]
+        mask = np.concatenate(parts)
+        if mask.size != self.nparam:
+            raise ValueError("parameter layout does not match the network")
+        return mask
+
+    def save_inference(self, path, meta: Optional[dict] = None):
+        """Inference checkpoint: the weights as the BF16 values the matrix
+        cores use (round to nearest even, stored as their 16-bit patterns),
+        the biases in FP32, channels, volume shape and a JSON string of
+        `meta` (provenance).  Half the size of the FP32 parameters; a network
+        loaded from it computes exactly what the saved one computes."""
+        import json
+        p = self.params().astype(np.float32)
+        mask = self._weight_mask()
+        np.savez(path, weights_bf16=bf16_bits(p[mask]), biases=p[~mask],
+                 channels=np.array(self.channels, np.int64), shape=np.array(self.shape, np.int64),
+                 meta=np.array(json.dumps(meta or {})))
+
+    def load_inference(self, path) -> dict:
+        """Parameters from save_inference() (read without unpickling); the
+        Adam state is left as it is.  Returns the provenance dict."""
+        import json
+        with np.load(path, allow_pickle=False) as z:
+            if tuple(z["channels"]) != self.channels or tuple(z["shape"]) != self.shape:
+                raise ValueError(f"checkpoint is for channels {tuple(z['channels'])} and shape "
+                                 f"{tuple(z['shape'])}, not {self.channels} and {self.shape}")
+            mask = self._weight_mask()
+            p = np.empty(mask.size, np.float32)
+            p[mask] = (z["weights_bf16"].astype(np.uint32) << 16).view(np.float32)
+            p[~mask] = z["biases"]
+            meta = json.loads(str(z["meta"]))
+        self.set_params(p)
+        return meta
 
     def _vol(self, t):
         _check_volume(t, int(np.prod(self.shape)))

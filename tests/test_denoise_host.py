@@ -93,3 +93,45 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bf16_bits_round_to_nearest_even_like_torch():
+    """The checkpoint's BF16 rounding equals torch's float32 -> bfloat16
+    conversion (round to nearest even) on normal, subnormal, tie, huge and
+    special values."""
+    import numpy as np
+    import torch
+    from paper_1711_03244_amd import nn
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(size=20000).astype(np.float32),
+                        (rng.normal(size=2000) * 1e-39).astype(np.float32),
+                        np.array([0.0, -0.0, 1.0, -2.5, np.inf, -np.inf, 3.4e38, -3.4e38,
+                                  1.00390625, 1.01171875, 1e-45], np.float32)])
+    # exact ties: low 16 bits 0x8000 with even and odd upper halves
+    ties = (np.arange(1000, dtype=np.uint32) << 16 | 0x8000).astype(np.uint32) + (0x3f80 << 16)
+    x = np.concatenate([x, ties.view(np.float32)])
+    want = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(nn.bf16_bits(x), want)
+    nanbits = nn.bf16_bits(np.array([np.nan], np.float32))
+    assert (nanbits[0] & 0x7f80) == 0x7f80 and (nanbits[0] & 0x7f) != 0
+
+
+def test_strict_error_estimators_recover_known_noise():
+    """Closed form: maps = truth * exp(noise) with independent Gaussian log
+    noise.  K runs of sigma_run each estimate a plain run of K times their
+    photons, whose log error is sigma_run / sqrt(K); a map with log noise
+    sigma_m compared against their mean has error sigma_m once the
+    reference's own share is removed."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    shape = (40, 40, 40)
+    truth = np.exp(rng.uniform(-10, -2, shape))
+    mask = np.ones(shape, bool)
+    K, s_run, s_m = 2, 0.02, 0.011
+    runs = [truth * np.exp(rng.normal(0, s_run, shape)) for _ in range(K)]
+    ref = np.mean(runs, axis=0)
+    ep2 = denoise.plain_error_sq(runs, mask)
+    assert math.sqrt(ep2) == pytest.approx(s_run / math.sqrt(K), rel=0.01)
+    m = truth * np.exp(rng.normal(0, s_m, shape))
+    e2 = denoise.error_sq_against(m, ref, mask, ep2)
+    assert math.sqrt(e2) == pytest.approx(s_m, rel=0.03)

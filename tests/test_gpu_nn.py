@@ -378,6 +378,34 @@ def test_checkpoint_round_trip(tmp_path):
             f.load(path)
 
 
+def test_inference_checkpoint_computes_what_the_trained_network_does(tmp_path):
+    """save_inference() keeps the weights as the BF16 values the matrix cores
+    use and the biases in FP32: a network loaded from it gives a forward
+    pass bit-identical to the trained FP32-master network, its weights are
+    the BF16 rounding of the master weights, and the provenance survives."""
+    channels, shape = (8, 16), (8, 8, 8)
+    _, flat = make_net(channels, shape, 19, zero_output=False)
+    noisy, clean = fluence_pair(shape, 20)
+    x, y = dev_f32(noisy), dev_f32(clean)
+    path = tmp_path / "denoiser_inference.npz"
+    with nn.Denoiser(channels, shape) as d:
+        d.set_params(flat)
+        for _ in range(3):
+            d.train_step(x, y, 1e-3)
+        d.save_inference(path, {"history": [{"steps": 3}]})
+        master = d.params()
+        mask = d._weight_mask()
+        ref_out = host(d.forward(x))
+    with nn.Denoiser(channels, shape) as e:
+        meta = e.load_inference(path)
+        got = e.params()
+        assert meta == {"history": [{"steps": 3}]}
+        assert np.array_equal(got[~mask], master[~mask])
+        want_w = (nn.bf16_bits(master[mask]).astype(np.uint32) << 16).view(np.float32)
+        assert np.array_equal(got[mask], want_w)
+        assert np.array_equal(host(e.forward(x)), ref_out)
+
+
 def test_training_reduces_the_loss():
     t = torch()
     channels, shape = (8, 16, 32), (16, 16, 16)

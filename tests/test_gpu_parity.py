@@ -640,6 +640,32 @@ def test_census_shaped_window_does_not_change_results(name):
     assert st["absorbed_grid"] == pytest.approx(sb["absorbed_grid"], rel=1e-12)
 
 
+def test_shape_window_then_fixed_launch():
+    """mcx_shape_window shapes the window for one cell count from a census
+    pilot; a fixed launch with that count then uses it, with the same map to
+    the last bit as the default launch; counts outside [1, 36864] are
+    refused."""
+    p = W.cube_sphere(n=40, ngates=10, dt=0.2).replace(name="cube40_sphere")
+    N = 300_000
+    say(f"[gpu] {p.name}: shape_window + set_launch vs default, N={N}")
+    with mcx.Simulation(p) as sim:
+        sim.run(N, 12)
+        base, sb = sim.fluence(mcx.MCX_RAW, f64=True), sim.stats()
+        for bad in (0, 36865):
+            with pytest.raises(mcx.McxError) as e:
+                sim.shape_window(N // 10, 13, bad)
+            assert e.value.status == mcx.MCX_EINVAL
+        sim.shape_window(N // 10, 13, 8192)
+        sim.set_launch(256, 64, 8192)
+        sim.run(N, 12)
+        got, st = sim.fluence(mcx.MCX_RAW, f64=True), sim.stats()
+    say("flushes per photon", sb["flushes"] / N, "->", st["flushes"] / N)
+    assert st["block_size"] == 256
+    for k in ["launched", "escaped", "timeout", "scatters", "face_events", "events"]:
+        assert st[k] == sb[k], k
+    assert np.array_equal(got, base)
+
+
 def test_fluence_into_torch_tensor():
     import torch
     p = W.cube_homogeneous(n=20).replace(src_pos=(9.5, 9.5, 0.0))
