@@ -105,6 +105,7 @@ def main():
 
     import torch
     from paper_1711_03244_amd import mcx, roofline, workloads as W
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
 
     p = W.cube_sphere()
     N = args.photons
@@ -139,6 +140,7 @@ def main():
         mcx.mcx_fluence_device(sim.ctx, mcx.MCX_FLUENCE_RATE, out)
         return sim.stats()  # waits for the context's stream
 
+    log("launch shape:", chosen_by)
     for i in range(args.warmup):
         step(1000 + i)
     torch.cuda.synchronize()
@@ -159,19 +161,25 @@ def main():
     roof["traffic"] = roofline.measured_traffic(N, tune["lds_window_cells"])
     roof["traffic_over_algorithmic"] = (roof["traffic"] / roof["algorithmic_bytes"]
                                         if roof["traffic"] else None)
+    log(f"timed steps: {value:.1f} photons/ms")
     scaling = None if args.no_scaling else scaling_leg(sim, args.seed)
     shape = (last["block_size"], tune["refill_chunk"], tune["lds_window_cells"])
     sim.close()
+    log("ablations")
     ablations = None if args.no_ablations else ablation_leg(mcx, W, shape, args.seed)
+    log("homogeneous cube and head volume")
 
     cube1 = None if args.no_head else cube1_leg(mcx, W)
     head = None if args.no_head else head_leg(mcx, roofline, W, args.head_photons, args.seed,
                                               args.head_launch)
+    log("batched workload")
     batched = None if args.no_batch else batch_leg(mcx, W)
+    log("denoiser")
     denoised = None if args.no_denoise else denoise_leg(args)
 
     cpu = cpu1 = None
     if not args.no_cpu_baseline:
+        log("CPU baseline")
         cpu, cpu1 = cpu_baseline(p, args.cpu_photons, args.seed)
 
     ks = sorted(kernel_ms)
