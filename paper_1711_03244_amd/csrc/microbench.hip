@@ -1,8 +1,9 @@
 // Microbenchmarks behind the transport kernel's design choices on gfx950:
 //  - global atomic add throughput: FP32 with and without a returned value,
-//    FP64 without a return, on distinct addresses spread over working sets
-//    that fit L2 (4 MB per XCD), the MALL, or only HBM, and on a few hot
-//    addresses shared by every wave;
+//    FP64 and 64- and 32-bit integers without a return, on distinct
+//    addresses spread over working sets that fit L2 (4 MB per XCD), the
+//    MALL, or only HBM, on a few hot addresses shared by every wave, and
+//    with a wave's lanes on consecutive cells;
 //  - FP32 VALU issue rate (dependent FMA chains) and the Philox block rate,
 //    to anchor the ALU roofline of the transport kernel.
 // Prints one JSON object per measurement.
