@@ -135,3 +135,26 @@ def test_strict_error_estimators_recover_known_noise():
     m = truth * np.exp(rng.normal(0, s_m, shape))
     e2 = denoise.error_sq_against(m, ref, mask, ep2)
     assert math.sqrt(e2) == pytest.approx(s_m, rel=0.03)
+
+
+def test_committed_inference_checkpoint_is_plain_arrays_with_provenance():
+    """The bench's denoiser checkpoint loads without unpickling and says how
+    it was made: the command, the training-volume seeds (disjoint from the
+    held-out seeds 900001.. the bench evaluates), the photon counts and the
+    source commit."""
+    import json
+    import os
+    import numpy as np
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1711_03244_amd", "checkpoints", "denoiser_64cube.npz")
+    with np.load(path, allow_pickle=False) as z:
+        assert z["weights_bf16"].dtype == np.uint16 and z["biases"].dtype == np.float32
+        assert tuple(z["channels"]) == (32, 64, 128, 256) and tuple(z["shape"]) == (64, 64, 64)
+        assert np.all(np.isfinite(z["biases"]))
+        w = (z["weights_bf16"].astype(np.uint32) << 16).view(np.float32)
+        assert np.all(np.isfinite(w)) and np.abs(w).max() < 100
+        meta = json.loads(str(z["meta"]))
+    h = meta["history"][-1]
+    lo, hi = h["train_volume_seeds"]
+    assert hi < 900001
+    assert h["target"] == 1e9 and "denoise" in h["command"] and h["source_commit"]
