@@ -1,7 +1,7 @@
 """Throughput benchmark of the photon-transport hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--photons N]
-                    [--launch BLOCK,CHUNK,WINDOW] [--head-launch BLOCK,CHUNK,WINDOW]
+                    [--launch BLOCK,CHUNK,WINDOW[,ADDS]] [--head-launch BLOCK,CHUNK,WINDOW[,ADDS]]
                     [--no-cpu-baseline] [--head-photons M] [--no-head] [--no-batch]
                     [--no-denoise] [--no-scaling]
 
@@ -39,9 +39,11 @@ paper's benchmark variants of the event loop (non-atomic deposits, B2;
 branch-reduced loop, Opt3) against the default loop at 3e7 photons.
 `denoiser` evaluates the 3-D U-Net of the committed inference checkpoint
 (trained on simulator pairs of 64^3 volumes with 1e9-photon targets; the
-file records how) on 16 held-out volumes: the error of denoised 3e7, 5e7
-and 8e7-photon maps against the error of a plain 1e9-photon run, and the
-wall-time ratio at equal error (see denoise.evaluate_strict).
+file records how) on 16 held-out volumes: the error of denoised 5e7, 7e7,
+8e7 and 9e7-photon maps (each the mean, in log space, of the network's
+outputs for the 8 x-y symmetries of the input) against the error of a
+plain 1e9-photon run, and the wall-time ratio at equal error (see
+denoise.evaluate_strict).
 """
 import argparse
 import json
@@ -63,10 +65,11 @@ def main():
     ap.add_argument("--photons", type=int, default=100_000_000)
     ap.add_argument("--cpu-photons", type=int, default=2_000_000,
                     help="photons per CPU-baseline run (3 runs, best kept)")
-    ap.add_argument("--launch", default=None, metavar="BLOCK,CHUNK,WINDOW",
-                    help="fix the transport launch shape (skips the autotuner and the "
-                         "default-shape context run, e.g. for profiling)")
-    ap.add_argument("--head-launch", default=None, metavar="BLOCK,CHUNK,WINDOW",
+    ap.add_argument("--launch", default=None, metavar="BLOCK,CHUNK,WINDOW[,ADDS]",
+                    help="fix the transport launch shape and optionally the map adds "
+                         "(1: 64-bit, 2: 32-bit with carry; default automatic); skips the "
+                         "autotuner and the default-shape context run, e.g. for profiling")
+    ap.add_argument("--head-launch", default=None, metavar="BLOCK,CHUNK,WINDOW[,ADDS]",
                     help="the same for the head-volume leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
@@ -94,8 +97,10 @@ def main():
                     help="train the denoiser in the bench instead of loading the checkpoint")
     ap.add_argument("--dn-eval-strict", type=int, default=16,
                     help="held-out volumes of the checkpoint's evaluation")
-    ap.add_argument("--dn-inputs", default="3e7,5e7,8e7",
+    ap.add_argument("--dn-inputs", default="5e7,7e7,8e7,9e7",
                     help="low-photon counts of the checkpoint's evaluation")
+    ap.add_argument("--dn-symmetries", type=int, default=8,
+                    help="x-y symmetries averaged at inference (1, 2, 4 or 8)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transport runs on a single MI355X "
@@ -115,10 +120,11 @@ def main():
     out = torch.empty(p.tally_shape, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     if args.launch:
-        blk, chunk, win = (int(v) for v in args.launch.split(","))
+        blk, chunk, win, *adds = (int(v) for v in args.launch.split(","))
         if win > 0:  # the window boxes the autotuner would shape for this size
             sim.shape_window(max(1000, N // 20), args.seed + 3000, win)
         sim.set_launch(blk, chunk, win)
+        sim.set_map_adds(adds[0] if adds else mcx.MAP_ADDS_AUTO)
         default_rate = None
         tune = {"refill_chunk": chunk, "lds_window_cells": win}
         chosen_by = "--launch"
@@ -190,7 +196,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "cube60_sphere_b2a", "grid": [60, 60, 60], "voxel_mm": 1.0,
                    "photons_per_step": N, "gates": 50, "gate_ns": 0.1, "detectors": 4,
-                   "reflect": True, "seed": args.seed, "tally": "fp64"},
+                   "reflect": True, "seed": args.seed, "tally": "u64 deposit units"},
         "kernel_ms_per_step": sum(kernel_ms) / len(kernel_ms),
         "kernel_photons_per_ms": N / (sum(kernel_ms) / len(kernel_ms)),
         "kernel_photons_per_ms_best": N / ks[0],
@@ -199,6 +205,7 @@ def main():
         "launch": {"block_size": last["block_size"], "grid_blocks": last["grid_blocks"],
                    "refill_chunk": tune["refill_chunk"],
                    "lds_window_cells": tune["lds_window_cells"],
+                   "map_adds": {1: "64-bit", 2: "32-bit with carry"}[last["map_adds"]],
                    "chosen_by": chosen_by},
         "create_ms": create_ms,
         "events_per_photon": last["events"] / N,
@@ -329,10 +336,11 @@ def head_leg(mcx, roofline, W, N, seed, launch=None):
     p = W.head_phantom(1)
     with mcx.Simulation(p) as sim:
         if launch:
-            blk, chunk, win = (int(v) for v in launch.split(","))
+            blk, chunk, win, *adds = (int(v) for v in launch.split(","))
             if win > 0:
                 sim.shape_window(max(1000, N // 50), seed + 3000, win)
             sim.set_launch(blk, chunk, win)
+            sim.set_map_adds(adds[0] if adds else mcx.MAP_ADDS_AUTO)
             default_med, tune = None, {"refill_chunk": chunk, "lds_window_cells": win}
             sim.run(N // 100, seed + 1000)  # warm-up
         else:
@@ -346,7 +354,8 @@ def head_leg(mcx, roofline, W, N, seed, launch=None):
             "photons": N, "photons_per_ms": N / st["run_ms"], "photons_per_ms_best": best,
             "photons_per_ms_median": med, "photons_per_ms_median_default_launch": default_med,
             "launch": {"block_size": st["block_size"], "refill_chunk": tune["refill_chunk"],
-                       "lds_window_cells": tune["lds_window_cells"]},
+                       "lds_window_cells": tune["lds_window_cells"],
+                       "map_adds": {1: "64-bit", 2: "32-bit with carry"}[st["map_adds"]]},
             "kernel_ms": st["kernel_ms"],
             "run_ms": st["run_ms"], "events_per_photon": st["events"] / N,
             "roofline": roofline.binding(st, ksec)}
@@ -398,8 +407,10 @@ def batch_leg(mcx, W):
             st = b.stats(0)
             out[label] = {"photons_per_ms": total / st["run_ms"], "run_ms": st["run_ms"],
                           "kernel_ms": st["kernel_ms"], "block_size": st["block_size"],
-                          "grid_blocks": st["grid_blocks"]}
+                          "grid_blocks": st["grid_blocks"],
+                          "map_adds": {1: "64-bit", 2: "32-bit with carry"}[st["map_adds"]]}
         b.set_launch(64, 64, -1)
+        b.set_map_adds(mcx.MAP_ADDS_64)  # the fixed baseline: plain 64-bit atomic adds
         timed("fixed")
         out["fixed"]["refill_chunk"] = 64
         t0 = time.perf_counter()
@@ -448,7 +459,7 @@ def denoise_leg(args):
             meta = d.load_inference(args.dn_checkpoint)
             ev = denoise.evaluate_strict(d, range(900001, 900001 + args.dn_eval_strict), side,
                                          inputs, plain_photons=args.dn_plain, ref_runs=2,
-                                         say=log)
+                                         say=log, symmetries=args.dn_symmetries)
         return {"workload": "denoise_64cubes", "channels": list(ch), "side": side,
                 "checkpoint": os.path.relpath(args.dn_checkpoint, ROOT),
                 "checkpoint_sha256_16": _sha16(args.dn_checkpoint),

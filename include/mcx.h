@@ -108,7 +108,8 @@ typedef struct {
   int32_t refill_chunk;   /* photons a wave takes per refill grab; 0 = library default */
   uint64_t ndigest;       /* per-photon digest rows kept for photons [first, first+ndigest) */
   int32_t lds_window_cells; /* cells around the source summed per workgroup in LDS before they
-                               reach the map (FP32 partial sums, 4 bytes each); 0 =
+                               reach the map (32-bit integer sums of deposit units, 4 bytes
+                               each); 0 =
                                library default (16384), < 0 = none, at most 36864
                                (144 KB) */
   int32_t accurate_math;  /* 0: hardware transcendentals (~1 ulp); 1: device math library */
@@ -136,6 +137,8 @@ typedef struct {
   double kernel_ms;         /* transport kernel time of the last run (HIP events) */
   double run_ms;            /* whole last run: clear + transport + reductions */
   int32_t grid_blocks, block_size;
+  int32_t map_adds;         /* MCX_MAP_ADDS_64 or MCX_MAP_ADDS_32: the last launch's map adds */
+  int32_t reserved;
 } mcx_run_stats;
 
 /* One simulation of a batch (mcx_batch_create): everything mcx_create takes
@@ -160,7 +163,21 @@ typedef struct {
   double best_ms;           /* pilot kernel time with the chosen shape */
   double ms_per_photon;     /* slope a of T = a n + T0 fitted from two pilot sizes */
   double overhead_ms;       /* intercept T0 of that fit */
+  int32_t map_adds;         /* chosen MCX_MAP_ADDS_64 or MCX_MAP_ADDS_32 */
+  int32_t reserved;
 } mcx_tune_result;
+
+/* How the transport kernel adds to the map (mcx_set_map_adds).  The map
+ * holds one 64-bit integer per cell: the count of deposit units u (a power
+ * of two, 2^-20 of the voxel size or just below) the cell received; every
+ * cell-visit sum is rounded to whole units, so sums are exact and results
+ * do not depend on the order of the additions.  MCX_MAP_ADDS_64: one 64-bit
+ * atomic add per visit.  MCX_MAP_ADDS_32: a 32-bit atomic add to the low
+ * word whose returned value tells whether it carried into the high word
+ * (then one more add); faster at the memory side, but the wave waits for
+ * the returned value.  MCX_MAP_ADDS_AUTO: 32-bit adds when at least 16
+ * waves per compute unit are resident.  The maps are bit-identical. */
+enum { MCX_MAP_ADDS_AUTO = 0, MCX_MAP_ADDS_64 = 1, MCX_MAP_ADDS_32 = 2 };
 
 /* Output kinds for mcx_fluence*. */
 enum {
@@ -172,7 +189,7 @@ enum {
 void mcx_default_options(mcx_options *opt);
 
 /* Validate and deep-copy the problem, pick the device, allocate the tally
- * (one FP64 sum per cell, 8 bytes) and upload.
+ * (one 64-bit count of deposit units per cell, 8 bytes) and upload.
  * `det` may be NULL when ndet == 0; `opt` may be NULL for defaults.
  * Errors: MCX_EINVAL (bad argument, message says which), MCX_ENODEV,
  * MCX_ENOMEM, MCX_EDEVICE.  *out is set only on MCX_OK. */
@@ -225,6 +242,11 @@ mcx_status mcx_batch_digest(mcx_ctx *ctx, int32_t sim, double *host_out, uint64_
 mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk,
                           int32_t lds_window_cells);
 
+/* How later launches add to the map: MCX_MAP_ADDS_AUTO (the default),
+ * MCX_MAP_ADDS_64 or MCX_MAP_ADDS_32.  Only the speed changes, never a
+ * result.  MCX_EINVAL for another value.  Waits for the stream. */
+mcx_status mcx_set_map_adds(mcx_ctx *ctx, int32_t mode);
+
 /* Shape the LDS window of a single-simulation context (hardware math, no
  * digests) for lds_window_cells cells from a flush census -- one pilot of
  * pilot_photons[0] photons (seed[0]) counting, per map cell, the cell visits
@@ -240,7 +262,9 @@ mcx_status mcx_shape_window(mcx_ctx *ctx, const uint64_t *pilot_photons, const u
  * simulation over block sizes {64, 256, 448, 512, 768, 1024} x jobs of {64,
  * 256, 1024} photons (1 to 16 photons per lane) x deposit schemes {direct
  * global atomics, LDS window of 8192, 16384, 32768 or 36864 cells} (shapes that
- * do not fit on a compute unit are skipped), keeps the fastest shape, and fits
+ * do not fit on a compute unit are skipped; each timed with the map adds
+ * MCX_MAP_ADDS_AUTO picks for it, and the four fastest again with the other
+ * kind), keeps the fastest shape and map adds, and fits
  * (single simulations without digests and with hardware math: the window boxes
  * are first shaped by a flush census -- one pilot counting, per map cell, the
  * cell visits the kernel adds to the map -- per gate the box grown from its
@@ -301,7 +325,7 @@ mcx_status mcx_sync(mcx_ctx *ctx);
 uint64_t mcx_ncells(const mcx_ctx *ctx);
 
 /* Normalised map (kind = MCX_RAW / MCX_FLUENCE / MCX_FLUENCE_RATE), computed
- * on the GPU in FP64 from the FP64 tally and rounded once.  host_out
+ * on the GPU in FP64 from the map's integer counts and rounded once.  host_out
  * must hold ncells >= mcx_ncells() values (else MCX_ERANGE).  Blocking. */
 mcx_status mcx_fluence(mcx_ctx *ctx, int32_t kind, float *host_out, uint64_t ncells);
 mcx_status mcx_fluence_f64(mcx_ctx *ctx, int32_t kind, double *host_out, uint64_t ncells);

@@ -90,6 +90,20 @@ mcx_status mcx_nn_set_adam(mcx_nn *nn, const float *m, const float *v, uint64_t 
 mcx_status mcx_nn_forward(mcx_nn *nn, const float *phi_in, float *phi_out, float *u_out,
                           void *hip_stream);
 
+/* Denoise phi_in averaged over symmetries of the square x-y cross-section
+ * (those of mcx_nn_mirror_xy, ops 0 .. nsym-1): for each op the input is
+ * transformed, denoised, and the output in u space transformed back; the
+ * outputs are averaged in u space (u_out) and turned into fluence
+ * (phi_out).  For a source on the cross-section's centre line each
+ * transformed input is the map of the mirrored volume, so every pass
+ * estimates the same map (the training pairs are augmented with the same
+ * symmetries).  nsym = 1 is mcx_nn_forward.  Costs nsym forward passes;
+ * uses the network's loss buffers as scratch (do not overlap with
+ * mcx_nn_loss_grad / mcx_nn_train_step on the same network).  MCX_EINVAL
+ * for nsym not in {1, 2, 4, 8}, or 8 with nx != ny.  Async. */
+mcx_status mcx_nn_forward_sym(mcx_nn *nn, const float *phi_in, float *phi_out, float *u_out,
+                              int32_t nsym, void *hip_stream);
+
 /* Forward pass on phi_in, loss against phi_target and backward pass: the
  * gradients of every parameter (mcx_nn_get_grads), replacing the current
  * gradients, or added to them when accumulate != 0 (for steps over several

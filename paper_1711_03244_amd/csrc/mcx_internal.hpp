@@ -54,7 +54,7 @@ struct SimDesc {
   uint64_t first, nphoton;
   uint32_t key0, key1;
   // outputs
-  double* tally;                 // ngates * nvox FP64 sums
+  uint64_t* tally;               // ngates * nvox sums, integer counts of q_unit
   double* ledger;                // kLedgerN
   unsigned long long* counts;    // kCountN
   float* det_rec;
@@ -64,9 +64,10 @@ struct SimDesc {
   int32_t rec_len;
   double* digest;
   uint64_t ndigest;
-  // Deposit unit: every cell-visit sum is rounded to a multiple of q_unit
-  // (a power of two, 2^-20 of the voxel size or just below; q_inv = 1 /
-  // q_unit) before it reaches the map or the window.
+  // Deposit unit: every cell-visit sum is rounded to a whole number of
+  // q_unit (a power of two, 2^-20 of the voxel size or just below; q_inv =
+  // 1 / q_unit) before it reaches the map or the window; the map holds
+  // those numbers.
   float q_unit, q_inv;
   // LDS window of this simulation (wng = 0: none): for each gate g < wng
   // the cells of a box [x0, x0 + nx) x [y0, y0 + ny) x [z0, z0 + nz), at
@@ -103,6 +104,9 @@ struct LaunchParams {
   // window of one simulation -- the home simulation of its first wave -- and
   // its waves use it while they work on that simulation.
   int32_t window_cells;
+  // How the kernel adds to map cells: 1 a returning 32-bit add with a carry
+  // into the cell's high word, 0 one 64-bit add (see map_add).
+  int32_t map32;
 };
 
 size_t transport_smem_bytes(int table_rows, int nmedia_max, int block, bool detect,
@@ -122,15 +126,18 @@ hipError_t launch_transport(const LaunchParams& host, const LaunchParams* dev, i
                             int variant);
 
 // Zero `ncells` tally cells and `nsims` ledgers, counters and record counts.
-hipError_t launch_clear(double* tally, uint64_t ncells, double* ledger,
+hipError_t launch_clear(uint64_t* tally, uint64_t ncells, double* ledger,
                         unsigned long long* counts, unsigned long long* det_count,
                         int nsims, hipStream_t s);
 hipError_t launch_reset_counters(unsigned long long* counters, int n, hipStream_t s);
-hipError_t launch_reduce(const double* tally, const uint8_t* labels, const float4* media,
-                         uint32_t nvox, int ngates, double* out2, hipStream_t s);
-hipError_t launch_normalise_f32(const double* tally, uint64_t ncells, double scale, float* out,
+// out2[0] += unit * sum of the cells, out2[1] += unit * sum of mua * cell.
+hipError_t launch_reduce(const uint64_t* tally, double unit, const uint8_t* labels,
+                         const float4* media, uint32_t nvox, int ngates, double* out2,
+                         hipStream_t s);
+// out[i] = tally[i] * scale (scale includes the deposit unit).
+hipError_t launch_normalise_f32(const uint64_t* tally, uint64_t ncells, double scale, float* out,
                                 hipStream_t s);
-hipError_t launch_normalise_f64(const double* tally, uint64_t ncells, double scale, double* out,
-                                hipStream_t s);
+hipError_t launch_normalise_f64(const uint64_t* tally, uint64_t ncells, double scale,
+                                double* out, hipStream_t s);
 
 }  // namespace mcx

@@ -93,6 +93,8 @@ struct SimHost {
   int wng = 0, wcount = 0;
   uint64_t photons = 0;  // accumulated since the last reset
   uint64_t ncells() const { return static_cast<uint64_t>(nvox) * ngates; }
+  // the deposit unit: the map holds integer counts of it (SimDesc::q_unit)
+  double unit() const { return std::ldexp(1.0, std::ilogb(h) - 20); }
 };
 
 }  // namespace
@@ -110,12 +112,14 @@ struct mcx_ctx {
   // budget -> per gate (x0, y0, z0, nx, ny, nz)
   std::vector<std::pair<int, std::vector<std::array<int, 6>>>> shaped;
   int force_variant = -1;  // kernel variant of the next launches (-1: opt.kernel_variant)
+  int map_adds = MCX_MAP_ADDS_AUTO;  // how the kernel adds to map cells (mcx_set_map_adds)
+  bool last_map32 = false;           // the last launch's choice
   int table_rows = 0, nmedia_max = 0;
   uint64_t total_cells = 0, max_cells = 0;
 
   uint8_t* d_labels = nullptr;
   float4* d_tables = nullptr;
-  double* d_tally = nullptr;
+  uint64_t* d_tally = nullptr;  // integer counts of each simulation's deposit unit
   double* d_ledger = nullptr;
   unsigned long long* d_counts = nullptr;
   unsigned long long* d_det_count = nullptr;
@@ -498,6 +502,17 @@ static mcx_status set_shape(mcx_ctx* c, int block) {
   return MCX_OK;
 }
 
+// Whether launches add to map cells with 32-bit returning adds (plus a
+// carry) rather than 64-bit adds: by the context's setting, or, for
+// MCX_MAP_ADDS_AUTO, when at least 16 waves per compute unit are resident,
+// enough to cover the returned value's latency (measured: 32-bit adds win
+// with 16 waves of 1024-thread workgroups and lose with 12 of 768-thread
+// ones on the sphere benchmark).
+static bool map32(const mcx_ctx* c) {
+  if (c->map_adds != MCX_MAP_ADDS_AUTO) return c->map_adds == MCX_MAP_ADDS_32;
+  return c->cus > 0 && (c->grid / c->cus) * (c->block / 64) >= 16;
+}
+
 // Make stream st wait for the context's last clear or launch.
 static mcx_status wait_done(mcx_ctx* c, hipStream_t st) {
   if (c->done_pending) HIP_TRY(hipStreamWaitEvent(st, c->ev_done, 0));
@@ -565,7 +580,7 @@ static mcx_status setup(mcx_ctx* c, const mcx_sim* sims) {
   }
   HIP_TRY(hipMalloc(&c->d_labels, labels));
   HIP_TRY(hipMalloc(&c->d_tables, tables * sizeof(float4)));
-  HIP_TRY(hipMalloc(&c->d_tally, c->total_cells * sizeof(double)));
+  HIP_TRY(hipMalloc(&c->d_tally, c->total_cells * sizeof(uint64_t)));
   HIP_TRY(hipMalloc(&c->d_ledger, n * mcx::kLedgerN * sizeof(double)));
   HIP_TRY(hipMalloc(&c->d_counts, n * mcx::kCountN * sizeof(unsigned long long)));
   HIP_TRY(hipMalloc(&c->d_det_count, n * sizeof(unsigned long long)));
@@ -747,7 +762,7 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
     d.wng = sh.wng;
     d.wcount = sh.wcount;
     // deposit unit: the largest power of two not above h 2^-20
-    d.q_unit = std::ldexp(1.f, std::ilogb(sh.h) - 20);
+    d.q_unit = static_cast<float>(sh.unit());
     d.q_inv = 1.f / d.q_unit;
     std::copy(sh.wbox.begin(), sh.wbox.end(),
               reinterpret_cast<int32_t*>(wbox.data() + i * 2 * mcx::kMaxWinGates));
@@ -784,6 +799,8 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
   lp.table_rows = c->table_rows;
   lp.nmedia_max = c->nmedia_max;
   lp.window_cells = c->win_cells;
+  lp.map32 = map32(c) ? 1 : 0;
+  c->last_map32 = lp.map32 != 0;
 
   // Parameter blocks are copied in stream order before the launch that reads
   // them (pageable sources are staged by the runtime before the call returns).
@@ -806,7 +823,7 @@ static mcx_status enqueue(mcx_ctx* c, const uint64_t* first, const uint64_t* n,
   HIP_TRY(hipMemsetAsync(c->d_reduce, 0, ns * 2 * sizeof(double), st));
   for (size_t i = 0; i < ns; ++i) {
     const SimHost& sh = c->sims[i];
-    HIP_TRY(mcx::launch_reduce(c->d_tally + sh.tally_off, c->d_labels + sh.label_off,
+    HIP_TRY(mcx::launch_reduce(c->d_tally + sh.tally_off, sh.unit(), c->d_labels + sh.label_off,
                                c->d_tables + sh.table_off, sh.nvox, sh.ngates,
                                c->d_reduce + 2 * i, st));
   }
@@ -906,9 +923,10 @@ static mcx_status check_sim(const mcx_ctx* c, int32_t sim) {
   return MCX_OK;
 }
 
+// Factor from the map's integer counts to the output kind.
 static mcx_status scale_for(const SimHost& sh, int32_t kind, double* scale) {
   if (kind == MCX_RAW) {
-    *scale = 1.0;
+    *scale = sh.unit();
     return MCX_OK;
   }
   if (kind != MCX_FLUENCE && kind != MCX_FLUENCE_RATE)
@@ -917,7 +935,7 @@ static mcx_status scale_for(const SimHost& sh, int32_t kind, double* scale) {
   const double hv = static_cast<double>(sh.h);
   double s = 1.0 / (static_cast<double>(sh.photons) * hv * hv * hv);
   if (kind == MCX_FLUENCE_RATE) s /= static_cast<double>(sh.dt);
-  *scale = s;
+  *scale = s * sh.unit();  // a power of two: the product is exact
   return MCX_OK;
 }
 
@@ -934,7 +952,7 @@ static mcx_status fluence_host(mcx_ctx* c, int32_t sim, int32_t kind, void* host
   MCX_TRY(scale_for(sh, kind, &scale));
   HIP_TRY(hipSetDevice(c->device));
   MCX_TRY(wait_done(c, c->stream));
-  const double* tally = c->d_tally + sh.tally_off;
+  const uint64_t* tally = c->d_tally + sh.tally_off;
   if (f64) {
     if (!c->d_stage64) HIP_TRY(hipMalloc(&c->d_stage64, c->max_cells * sizeof(double)));
     HIP_TRY(mcx::launch_normalise_f64(tally, sh.ncells(), scale, c->d_stage64, c->stream));
@@ -999,6 +1017,7 @@ static mcx_status stats_of(mcx_ctx* c, int32_t sim, mcx_run_stats* o) {
   }
   o->grid_blocks = c->grid;
   o->block_size = c->block;
+  o->map_adds = c->last_map32 ? MCX_MAP_ADDS_32 : MCX_MAP_ADDS_64;
   return MCX_OK;
 }
 
@@ -1275,6 +1294,17 @@ mcx_status mcx_set_launch(mcx_ctx* c, int32_t block_size, int32_t refill_chunk,
   return set_shape(c, block_size);
 }
 
+mcx_status mcx_set_map_adds(mcx_ctx* c, int32_t mode) {
+  if (!c) return fail(MCX_EINVAL, "context is NULL");
+  if (mode != MCX_MAP_ADDS_AUTO && mode != MCX_MAP_ADDS_64 && mode != MCX_MAP_ADDS_32)
+    return fail(MCX_EINVAL, "map adds must be %d (auto), %d (64-bit) or %d (32-bit)",
+                MCX_MAP_ADDS_AUTO, MCX_MAP_ADDS_64, MCX_MAP_ADDS_32);
+  HIP_TRY(hipSetDevice(c->device));
+  MCX_TRY(host_wait(c));
+  c->map_adds = mode;
+  return MCX_OK;
+}
+
 // ------------------------------------------------------------- autotune
 
 // Flush census for the window shaping: one pilot launch whose kernel adds 1
@@ -1298,9 +1328,10 @@ static mcx_status census(mcx_ctx* c, const uint64_t* pilot, const uint64_t* seed
   HIP_TRY(hipStreamSynchronize(c->stream));
   const SimHost& sh = c->sims[0];
   const int ng = std::min(sh.ngates, mcx::kMaxWinGates);
-  std::vector<double> F(static_cast<size_t>(ng) * sh.nvox);
-  HIP_TRY(hipMemcpy(F.data(), c->d_tally + sh.tally_off, F.size() * sizeof(double),
+  std::vector<uint64_t> counts(static_cast<size_t>(ng) * sh.nvox);
+  HIP_TRY(hipMemcpy(counts.data(), c->d_tally + sh.tally_off, counts.size() * sizeof(uint64_t),
                     hipMemcpyDeviceToHost));
+  const std::vector<double> F(counts.begin(), counts.end());
   for (int k = 0; k < nbudget; ++k)
     if (budgets[k] > 0)
       c->shaped.emplace_back(budgets[k], shape_window(F, sh.nx, sh.ny, sh.nz, ng, budgets[k]));
@@ -1351,6 +1382,7 @@ mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_
   const int nwin = 5;
   // the untuned default shape first (after one warm-up launch)
   c->shaped.clear();
+  c->map_adds = MCX_MAP_ADDS_AUTO;
   MCX_TRY(mcx_set_launch(c, 0, 0, 0));
   float ms = 0.f;
   MCX_TRY(pilot(pilot_photons, &ms));
@@ -1358,29 +1390,44 @@ mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_
   out->default_ms = ms;
   // then window boxes shaped by a flush census for the candidates below
   MCX_TRY(census(c, pilot_photons, seed, windows, nwin));
-  float best = ms;
-  out->block_size = c->block;
-  out->refill_chunk = c->chunk;
-  out->lds_window_cells = kDefaultWindow;
-  int nc = 1;
+  struct Cand {
+    float ms;
+    int block, chunk, window, adds;
+  };
+  std::vector<Cand> timed;
+  timed.push_back({ms, c->block, c->chunk, kDefaultWindow, map32(c) ? MCX_MAP_ADDS_32 : MCX_MAP_ADDS_64});
   for (int wi = 0; wi < nwin; ++wi) {
     for (int b : blocks) {
       for (int ch : chunks) {
         if (mcx_set_launch(c, b, ch, windows[wi]) != MCX_OK) continue;
         MCX_TRY(pilot(pilot_photons, &ms));
-        ++nc;
-        if (ms < best) {
-          best = ms;
-          out->block_size = c->block;
-          out->refill_chunk = ch;
-          out->lds_window_cells = windows[wi];
-        }
+        timed.push_back({ms, c->block, ch, windows[wi],
+                         map32(c) ? MCX_MAP_ADDS_32 : MCX_MAP_ADDS_64});
       }
     }
   }
-  out->candidates = nc;
-  out->best_ms = best;
+  // the four fastest shapes again with the other kind of map add
+  std::sort(timed.begin(), timed.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+  const size_t nshape = timed.size();
+  for (size_t k = 0; k < std::min<size_t>(4, nshape); ++k) {
+    Cand t = timed[k];
+    t.adds = t.adds == MCX_MAP_ADDS_32 ? MCX_MAP_ADDS_64 : MCX_MAP_ADDS_32;
+    if (mcx_set_launch(c, t.block, t.chunk, t.window) != MCX_OK) continue;
+    c->map_adds = t.adds;
+    MCX_TRY(pilot(pilot_photons, &t.ms));
+    c->map_adds = MCX_MAP_ADDS_AUTO;
+    timed.push_back(t);
+  }
+  const Cand best = *std::min_element(
+      timed.begin(), timed.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+  out->block_size = best.block;
+  out->refill_chunk = best.chunk;
+  out->lds_window_cells = best.window;
+  out->map_adds = best.adds;
+  out->candidates = static_cast<int32_t>(timed.size());
+  out->best_ms = best.ms;
   MCX_TRY(mcx_set_launch(c, out->block_size, out->refill_chunk, out->lds_window_cells));
+  c->map_adds = best.adds;
   float t_full = 0.f, t_half = 0.f;
   MCX_TRY(pilot(pilot_photons, &t_full));
   MCX_TRY(pilot(half.data(), &t_half));

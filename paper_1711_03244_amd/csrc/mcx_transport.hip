@@ -27,7 +27,7 @@
 // integer partial sums in LDS (visit sums are rounded to a fixed deposit
 // unit, see deposit()), added to the map once when the workgroup finishes
 // (or earlier, by the lane whose addition takes a sum past 2^31 units).  All
-// other flushes are one non-returning FP64 atomic add on the map.
+// other flushes are one atomic add to the map's integer counts (map_add).
 // Device-memory atomics on gfx950 execute at the memory side at a fixed
 // aggregate rate, which binds this kernel wherever photons spread out, so
 // the window is what keeps the cells that most photons of a workgroup visit
@@ -223,44 +223,67 @@ __device__ __forceinline__ float fresnel_r(float n1, float n2, float ci, float c
 // one cell) goes to the map directly, and a window sum that reaches 2^31
 // units is moved to the map by the lane whose addition took it there, so
 // the 32-bit window sums cannot wrap.
-constexpr float kWinMaxAdd = 268435456.f;
+constexpr uint32_t kWinMaxAdd = 268435456u;
 constexpr uint32_t kWinMove = 0x80000000u;
+
+// Add q deposit units to map cell p, exactly.  The map holds 64-bit integer
+// sums of units.  map32: a returning 32-bit add to the cell's low word, and
+// when that add carries out of it (the returned old value plus q wraps), a
+// second add of 1 to the high word -- every carry is seen by exactly the
+// add that caused it, so the 64-bit sum is exact once the launch ends, and
+// 32-bit adds execute faster at the memory side than 64-bit ones (the wave
+// waits for the returned value, which pays only when enough waves are
+// resident to cover that latency).  Otherwise one 64-bit add without a
+// return value.
+__device__ __forceinline__ void map_add(MCX_GLOBAL uint64_t* p, uint32_t q, bool map32) {
+  if (map32) {
+    MCX_GLOBAL uint32_t* w = reinterpret_cast<MCX_GLOBAL uint32_t*>(p);
+    const uint32_t old = __hip_atomic_fetch_add(w, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + q < old) __hip_atomic_fetch_add(w + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_fetch_add(p, static_cast<uint64_t>(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
 
 // Add a finished cell visit to the map; returns the number of global
 // atomics issued (0 or 1).  The visit's sum v is first rounded to a whole
 // number q of the simulation's deposit unit u (a power of two, 2^-20 of the
-// voxel size or just below): every value added to the FP64 map is then a
-// multiple of u, all partial sums are exact, and the map does not depend on
-// the order of the additions -- any launch shape, batch or photon split
-// gives the same bits.  A visit into the workgroup's LDS window adds q to
-// that cell's 32-bit integer sum (the lane that takes it to 2^31 or more
-// exchanges it with zero and adds what it took to the map); any other is
-// one FP64 atomic add of q u (no return value, so the wave does not wait
-// for it).  kRacy: a plain read, add and write of the map cell instead of
-// the atomic -- the paper's non-atomic benchmark variant (B2), where
-// concurrent updates of one cell can be lost.  kCensus: 1 per visit
-// instead (the flush census).
+// voxel size or just below): the map holds integer counts of u, so every
+// sum is exact and the map does not depend on the order of the additions
+// -- any launch shape, batch or photon split gives the same bits.  A visit
+// into the workgroup's LDS window adds q to that cell's 32-bit integer sum
+// (the lane that takes it to 2^31 or more exchanges it with zero and adds
+// what it took to the map); any other is added to the map by map_add.
+// kRacy: a plain read, add and write of the map cell instead of the atomic
+// -- the paper's non-atomic benchmark variant (B2), where concurrent updates
+// of one cell can be lost.  kCensus: 1 per visit instead (the flush census).
 template <bool kRacy, bool kCensus = false>
 __device__ __forceinline__ int deposit(CSim* D, uint32_t* s_win, uint32_t cell, int slot,
-                                      float v) {
-  MCX_GLOBAL double* p = as_global(D->tally) + cell;
+                                      float v, bool map32) {
+  MCX_GLOBAL uint64_t* p = as_global(D->tally) + cell;
   if constexpr (kCensus) {
-    __builtin_amdgcn_global_atomic_fadd_f64(p, 1.0);
+    map_add(p, 1u, false);
     return 1;
   }
-  const float q = rintf(v * D->q_inv);  // exact scaling by a power of two
-  const double unit = static_cast<double>(D->q_unit);
+  const float qf = rintf(v * D->q_inv);  // an exact scaling by a power of two
+  if (qf >= 4294967296.f) {  // 2^32 units or more in one visit: one 64-bit add
+    if constexpr (kRacy)
+      *p = *p + static_cast<uint64_t>(qf);
+    else
+      __hip_atomic_fetch_add(p, static_cast<uint64_t>(qf), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    return 1;
+  }
+  const uint32_t q = static_cast<uint32_t>(qf);
   if (slot >= 0 && q <= kWinMaxAdd) {
-    const uint32_t add = static_cast<uint32_t>(q);
-    if (atomicAdd(s_win + slot, add) + add < kWinMove) return 0;
-    const uint32_t y = atomicExch(s_win + slot, 0u);
-    __builtin_amdgcn_global_atomic_fadd_f64(p, static_cast<double>(y) * unit);
+    if (atomicAdd(s_win + slot, q) + q < kWinMove) return 0;
+    map_add(p, atomicExch(s_win + slot, 0u), map32);
     return 1;
   }
   if constexpr (kRacy)
-    *p = *p + static_cast<double>(q) * unit;
+    *p = *p + q;
   else
-    __builtin_amdgcn_global_atomic_fadd_f64(p, static_cast<double>(q) * unit);
+    map_add(p, q, map32);
   return 1;
 }
 
@@ -321,6 +344,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   const int rows = L.table_rows;
   float4* s_tab = s_dyn + wid * rows;  // this wave's copy of its simulation's tables
   const int wcells = kCensus ? 0 : L.window_cells;
+  const bool map32 = L.map32 != 0;  // how map cells are added to (map_add)
   uint32_t* s_win = reinterpret_cast<uint32_t*>(s_dyn + (bdim >> 6) * rows);
   float* s_len = reinterpret_cast<float*>(s_win + wcells) + threadIdx.x;  // [m * blockDim]
 
@@ -577,7 +601,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
           const bool hit_o = !hit_a && cell == old_cell;
           const bool miss = !hit_a && !hit_o;
           if (miss && old_cell != 0xffffffffu && old_acc != 0.f) {
-            n_flush += deposit<kRacy, kCensus>(D, s_win, old_cell, old_slot, old_acc);
+            n_flush += deposit<kRacy, kCensus>(D, s_win, old_cell, old_slot, old_acc, map32);
           }
           const int slot = cur == wsim ? window_slot(s_wbox, wng, gate, ix, iy, iz) : -1;
           const float a_new = hit_a ? acc : (hit_o ? old_acc : 0.f);
@@ -602,7 +626,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
           acc_cell = cell;
         } else {
           if (old_cell != 0xffffffffu && old_acc != 0.f) {
-            n_flush += deposit<kRacy, kCensus>(D, s_win, old_cell, old_slot, old_acc);
+            n_flush += deposit<kRacy, kCensus>(D, s_win, old_cell, old_slot, old_acc, map32);
           }
           old_cell = acc_cell;
           old_slot = acc_slot;
@@ -814,10 +838,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
 
       if (end != kAlive) {
         if (acc != 0.f && acc_cell != 0xffffffffu) {
-          n_flush += deposit<kRacy, kCensus>(D, s_win, acc_cell, acc_slot, acc);
+          n_flush += deposit<kRacy, kCensus>(D, s_win, acc_cell, acc_slot, acc, map32);
         }
         if (old_acc != 0.f && old_cell != 0xffffffffu) {
-          n_flush += deposit<kRacy, kCensus>(D, s_win, old_cell, old_slot, old_acc);
+          n_flush += deposit<kRacy, kCensus>(D, s_win, old_cell, old_slot, old_acc, map32);
         }
         const double wd = static_cast<double>(w);
         const int end_slot = end == kEndEscape ? kCntEscaped
@@ -892,10 +916,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(const LaunchParams* par
   // add the workgroup's window sums to the map of its window's simulation
   for (int i = threadIdx.x; i < wcount; i += bdim) {
     const uint32_t v = s_win[i];
-    if (v != 0u)
-      __builtin_amdgcn_global_atomic_fadd_f64(
-          as_global(DW->tally) + window_cell(s_wbox, wng, DW, i),
-          static_cast<double>(v) * static_cast<double>(DW->q_unit));
+    if (v != 0u) map_add(as_global(DW->tally) + window_cell(s_wbox, wng, DW, i), v, map32);
   }
 }
 

@@ -36,7 +36,10 @@ __device__ __forceinline__ uint32_t mix(uint32_t x) {
 // `hot` addresses when hot > 0.  Modes: 0 FP32 no return, 1 FP32 with the
 // returned value used, 2 FP64 no return, 3 64-bit integer no return, 4 32-bit
 // integer no return, 5 FP64 no return with the 64 lanes of a wave on 64
-// consecutive cells (8 cache lines of 64 B per instruction).
+// consecutive cells (8 cache lines of 64 B per instruction), 6 32-bit integer
+// add into the low word of a 64-bit cell with the returned value checked for
+// a carry into the high word (an exact 64-bit integer sum from 32-bit
+// atomics), 7 the same without a return (low words of 64-bit cells).
 template <int kMode>
 __global__ void __launch_bounds__(256) atomic_kernel(float* f32, double* f64, uint32_t mask,
                                                      uint32_t hot, int iters, float* sink) {
@@ -57,8 +60,16 @@ __global__ void __launch_bounds__(256) atomic_kernel(float* f32, double* f64, ui
     } else if constexpr (kMode == 3) {
       atomicAdd(reinterpret_cast<unsigned long long*>(f64) + idx,
                 static_cast<unsigned long long>(h & 0xffffu));
-    } else {
+    } else if constexpr (kMode == 4) {
       atomicAdd(reinterpret_cast<unsigned int*>(f32) + idx, h & 0xffffu);
+    } else if constexpr (kMode == 6) {
+      unsigned int* w = reinterpret_cast<unsigned int*>(f64) + 2 * static_cast<uint64_t>(idx);
+      const unsigned int add = (h & 0xffffu) << 12;
+      const unsigned int old = atomicAdd(w, add);
+      if (old + add < old) atomicAdd(w + 1, 1u);
+    } else {
+      atomicAdd(reinterpret_cast<unsigned int*>(f64) + 2 * static_cast<uint64_t>(idx),
+                (h & 0xffffu) << 12);
     }
   }
   if (kMode == 1 && acc == -1.f) sink[0] = acc;
@@ -78,7 +89,9 @@ static void launch_atomic_mode(int mode, int grid, int block, float* f32, double
     case 2: launch_atomic<2>(grid, block, f32, f64, mask, hot, iters, sink); break;
     case 3: launch_atomic<3>(grid, block, f32, f64, mask, hot, iters, sink); break;
     case 4: launch_atomic<4>(grid, block, f32, f64, mask, hot, iters, sink); break;
-    default: launch_atomic<5>(grid, block, f32, f64, mask, hot, iters, sink); break;
+    case 5: launch_atomic<5>(grid, block, f32, f64, mask, hot, iters, sink); break;
+    case 6: launch_atomic<6>(grid, block, f32, f64, mask, hot, iters, sink); break;
+    default: launch_atomic<7>(grid, block, f32, f64, mask, hot, iters, sink); break;
   }
 }
 
@@ -190,11 +203,11 @@ int main(int argc, char** argv) {
   CHECK(hipEventCreate(&e0));
   CHECK(hipEventCreate(&e1));
 
-  const char* modes[6] = {"f32_noret", "f32_ret", "f64_noret", "u64_noret", "u32_noret",
-                          "f64_noret_wave_lines"};
+  const char* modes[8] = {"f32_noret", "f32_ret", "f64_noret", "u64_noret", "u32_noret",
+                          "f64_noret_wave_lines", "u32_ret_carry_in_u64", "u32_noret_in_u64"};
   // working sets in bytes of FP64 cells (FP32 uses half the bytes, same count)
   const uint64_t sets[] = {1ull << 20, 2ull << 20, 64ull << 20, 512ull << 20};
-  for (int mode = 0; mode < 6; ++mode) {
+  for (int mode = 0; mode < 8; ++mode) {
     for (uint64_t ws : sets) {
       const uint32_t cells = static_cast<uint32_t>(ws / 8);
       const uint32_t mask = cells - 1;

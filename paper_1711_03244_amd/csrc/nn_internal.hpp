@@ -66,6 +66,12 @@ hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_to_log(const float* phi, int64_t n, float* u, uint16_t* u16, hipStream_t s);
 hipError_t launch_mirror_xy(const float* in, float* out, int nx, int ny, int nz, int op,
                             hipStream_t s);
+// acc (= when first, else +=) the symmetry op of in (as launch_mirror_xy)
+hipError_t launch_mirror_acc(const float* in, float* acc, int nx, int ny, int nz, int op,
+                             bool first, hipStream_t s);
+// out_u = acc / nsym and phi = its fluence (either may be null)
+hipError_t launch_sym_finish(const float* acc, int64_t n, int nsym, float* out_u, float* phi,
+                             hipStream_t s);
 hipError_t launch_from_log(const float* r, const float* u, int64_t n, float* out_u, float* phi,
                            hipStream_t s);
 // g16 = bf16((g + skip16) * (y16 > 0)) over n = voxels * cout values;

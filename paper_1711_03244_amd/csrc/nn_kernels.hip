@@ -882,6 +882,36 @@ __global__ void mirror_xy_kernel(const float* in, float* out, int nx, int ny, in
   }
 }
 
+// acc[i] (= when first, else +=) in[src(i)]: the gather of mirror_xy_kernel
+// for the symmetry op, accumulated
+__global__ void mirror_acc_kernel(const float* in, float* acc, int nx, int ny, int64_t n, int op,
+                                  int first) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int x = static_cast<int>(i % nx);
+    const int64_t r = i / nx;
+    const int y = static_cast<int>(r % ny);
+    const int64_t z = r / ny;
+    int sx = (op & 4) ? y : x;
+    int sy = (op & 4) ? x : y;
+    if (op & 1) sx = nx - 1 - sx;
+    if (op & 2) sy = ny - 1 - sy;
+    const float v = in[(z * ny + sy) * nx + sx];
+    acc[i] = first ? v : acc[i] + v;
+  }
+}
+
+// the mean of nsym outputs in u space and its fluence
+__global__ void sym_finish_kernel(const float* acc, int64_t n, float inv_nsym, float scale,
+                                  float shift, float* out_u, float* phi) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float v = acc[i] * inv_nsym;
+    if (out_u) out_u[i] = v;
+    if (phi) phi[i] = expf(v * scale + shift);
+  }
+}
+
 // phi_out = exp((r + u) * scale + shift): output of the residual network
 __global__ void from_log_kernel(const float* r, const float* u, int64_t n, float scale, float shift,
                                 float* out_u, float* phi) {
@@ -1336,6 +1366,20 @@ hipError_t launch_mirror_xy(const float* in, float* out, int nx, int ny, int nz,
                             hipStream_t s) {
   const int64_t n = static_cast<int64_t>(nx) * ny * nz;
   mirror_xy_kernel<<<blocks_for(n), 256, 0, s>>>(in, out, nx, ny, n, op);
+  return hipGetLastError();
+}
+
+hipError_t launch_mirror_acc(const float* in, float* acc, int nx, int ny, int nz, int op,
+                             bool first, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(nx) * ny * nz;
+  mirror_acc_kernel<<<blocks_for(n), 256, 0, s>>>(in, acc, nx, ny, n, op, first ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_finish(const float* acc, int64_t n, int nsym, float* out_u, float* phi,
+                             hipStream_t s) {
+  sym_finish_kernel<<<blocks_for(n), 256, 0, s>>>(acc, n, 1.f / static_cast<float>(nsym),
+                                                  kLogScale, kLogShift, out_u, phi);
   return hipGetLastError();
 }
 

@@ -520,6 +520,35 @@ mcx_status mcx_nn_forward(mcx_nn* nn, const float* phi_in, float* phi_out, float
   return MCX_OK;
 }
 
+mcx_status mcx_nn_forward_sym(mcx_nn* nn, const float* phi_in, float* phi_out, float* u_out,
+                              int32_t nsym, void* stream) {
+  if (!nn || !phi_in) return nfail(MCX_EINVAL, "network and input are required");
+  if (nsym != 1 && nsym != 2 && nsym != 4 && nsym != 8)
+    return nfail(MCX_EINVAL, "nsym must be 1, 2, 4 or 8");
+  const Grid& g = nn->g0;
+  if (nsym == 8 && g.w != g.h) return nfail(MCX_EINVAL, "8 symmetries need nx == ny");
+  if (nsym == 1) return mcx_nn_forward(nn, phi_in, phi_out, u_out, stream);
+  NN_HIP(hipSetDevice(nn->device));
+  hipStream_t s = pick(nn, stream);
+  // the loss buffers are idle outside mcx_nn_loss_grad: tgt_u holds the
+  // transformed input, gout the sum of the outputs mapped back
+  for (int op = 0; op < nsym; ++op) {
+    const float* x = phi_in;
+    if (op > 0) {
+      NN_HIP(launch_mirror_xy(phi_in, nn->tgt_u, g.w, g.h, g.d, op, s));
+      x = nn->tgt_u;
+    }
+    NN_TRY(run_forward(nn, x, s));
+    NN_HIP(launch_from_log(nn->r, nn->u, g.vox(), nn->out_u, nullptr, s));
+    // the inverse of op: a flip is its own inverse; with the swap, the flips
+    // of x and y exchange
+    const int inv = (op & 4) ? (4 | ((op & 1) << 1) | ((op & 2) >> 1)) : op;
+    NN_HIP(launch_mirror_acc(nn->out_u, nn->gout, g.w, g.h, g.d, inv, op == 0, s));
+  }
+  NN_HIP(launch_sym_finish(nn->gout, g.vox(), nsym, u_out, phi_out, s));
+  return MCX_OK;
+}
+
 mcx_status mcx_nn_loss_grad(mcx_nn* nn, const float* phi_in, const float* phi_target,
                             int32_t accumulate, double* loss, void* stream) {
   if (!nn || !phi_in || !phi_target)

@@ -157,15 +157,17 @@ def train(den: nn.Denoiser, ds: DataSet, steps: int, lr: float = 1e-3, lr_min: f
             "seconds": time.perf_counter() - t0, "losses": losses}
 
 
-def infer_timed(den: nn.Denoiser, phi):
-    """Denoise one map; returns (map as numpy, inference ms by HIP events)."""
+def infer_timed(den: nn.Denoiser, phi, symmetries: int = 1):
+    """Denoise one map (averaged over `symmetries` x-y symmetries of the
+    input, Denoiser.forward); returns (map as numpy, inference ms by HIP
+    events)."""
     t = _torch()
     x = t.as_tensor(phi).cuda()
     out = t.empty_like(x)
     s = t.cuda.current_stream()
     e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
     e0.record(s)
-    den.forward(x, phi_out=out, stream=s)
+    den.forward(x, phi_out=out, stream=s, symmetries=symmetries)
     e1.record(s)
     e1.synchronize()
     return out.cpu().numpy(), e0.elapsed_time(e1)
@@ -227,7 +229,8 @@ def error_sq_against(m, ref, mask, ref_sq) -> float:
 
 
 def evaluate_strict(den: nn.Denoiser, seeds, side, input_photons, plain_photons=1e9,
-                    ref_runs=2, timed_plain=2, seed_base=6_000_000, say=print) -> dict:
+                    ref_runs=2, timed_plain=2, seed_base=6_000_000, say=print,
+                    symmetries: int = 1) -> dict:
     """Whether denoised low-photon maps reach the plain high-photon run's
     error, and in how much less time, on held-out volumes.
 
@@ -249,7 +252,9 @@ def evaluate_strict(den: nn.Denoiser, seeds, side, input_photons, plain_photons=
     to its own input runs, checked against those timed runs.  The target
     is met at an input count whose RMS (over volumes) denoised error is at
     most the RMS plain error; its time ratio is the mean plain time over
-    the mean time of the input run plus inference."""
+    the mean time of the input run plus inference.  symmetries: inference
+    averaged over that many x-y symmetries of the input (its cost is in the
+    inference time)."""
     seeds = [int(s) for s in seeds]
     vols = [W.denoiser_volume(s, side) for s in seeds]
     K = int(ref_runs)
@@ -275,8 +280,8 @@ def evaluate_strict(den: nn.Denoiser, seeds, side, input_photons, plain_photons=
         ns, ts = [], []
         for j, n in enumerate(input_photons):
             lo, lo_ms = simulate_one(p, n, seed_base + 1000 * int(s) + 100 + j)
-            infer_timed(den, lo)  # the first call includes weight packing
-            dn, inf_ms = infer_timed(den, lo)
+            infer_timed(den, lo, symmetries)  # the first call includes weight packing
+            dn, inf_ms = infer_timed(den, lo, symmetries)
             e_n = error_sq_against(lo, ref, mask, ep2)
             e_d = error_sq_against(dn, ref, mask, ep2)
             row["inputs"].append({"photons": int(n), "sim_ms": lo_ms, "infer_ms": inf_ms,
@@ -297,6 +302,7 @@ def evaluate_strict(den: nn.Denoiser, seeds, side, input_photons, plain_photons=
     measured = [(r["plain_ms"], r["plain_ms_model"]) for r in rows if "plain_ms" in r]
     plain_ms = float(np.mean([r["plain_ms_model"] for r in rows]))
     out = {"volumes": len(rows), "plain_photons": int(plain_photons), "ref_runs": K,
+           "symmetries": int(symmetries),
            "plain_err": plain, "plain_ms": plain_ms,
            "plain_ms_measured": [m for m, _ in measured],
            "plain_ms_model_error": (max(abs(mod / m - 1.0) for m, mod in measured)

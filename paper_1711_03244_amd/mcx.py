@@ -35,7 +35,7 @@ EXPORTS = ["mcx_default_options", "mcx_create", "mcx_run", "mcx_run_range", "mcx
            "mcx_batch_stats", "mcx_batch_detected", "mcx_batch_digest", "mcx_set_launch",
            "mcx_autotune", "mcx_detpost_device", "mcx_detpost_device_noalloc",
            "mcx_detected_process", "mcx_fit_linear",
-           "mcx_fit_runtime", "mcx_set_balance", "mcx_shape_window"]
+           "mcx_fit_runtime", "mcx_set_balance", "mcx_shape_window", "mcx_set_map_adds"]
 
 
 class McxError(RuntimeError):
@@ -75,7 +75,11 @@ class mcx_tune_result(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("refill_chunk", C.c_int32),
                 ("lds_window_cells", C.c_int32), ("candidates", C.c_int32),
                 ("default_ms", C.c_double), ("best_ms", C.c_double),
-                ("ms_per_photon", C.c_double), ("overhead_ms", C.c_double)]
+                ("ms_per_photon", C.c_double), ("overhead_ms", C.c_double),
+                ("map_adds", C.c_int32), ("reserved", C.c_int32)]
+
+# how the transport kernel adds to map cells (mcx_set_map_adds)
+MAP_ADDS_AUTO, MAP_ADDS_64, MAP_ADDS_32 = 0, 1, 2
 
 
 class mcx_options(C.Structure):
@@ -101,7 +105,8 @@ class mcx_run_stats(C.Structure):
                    ["w_launched", "w_escaped", "w_detected", "w_timeout", "w_rr_gain",
                     "w_rr_loss", "w_capped", "tally_sum", "absorbed_grid", "kernel_ms",
                     "run_ms"]]
-                + [("grid_blocks", C.c_int32), ("block_size", C.c_int32)])
+                + [("grid_blocks", C.c_int32), ("block_size", C.c_int32),
+                   ("map_adds", C.c_int32), ("reserved", C.c_int32)])
 
 
 _lib = None
@@ -164,6 +169,7 @@ def lib() -> C.CDLL:
             "mcx_fit_runtime": (C.c_int, [vp, vp, vp, vp, vp, vp]),
             "mcx_set_balance": (C.c_int, [vp, vp]),
             "mcx_shape_window": (C.c_int, [vp, vp, vp, i32]),
+            "mcx_set_map_adds": (C.c_int, [vp, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -294,6 +300,10 @@ def mcx_batch_stats(ctx, sim: int) -> dict:
 
 def mcx_set_launch(ctx, block_size: int = 0, refill_chunk: int = 0, lds_window_cells: int = 0):
     _check(lib().mcx_set_launch(ctx, block_size, refill_chunk, lds_window_cells))
+
+
+def mcx_set_map_adds(ctx, mode: int):
+    _check(lib().mcx_set_map_adds(ctx, int(mode)))
 
 
 def mcx_autotune(ctx, pilot_photons, seed) -> dict:
@@ -551,6 +561,9 @@ class Batch:
     def set_launch(self, block_size=0, refill_chunk=0, lds_window_cells=0):
         mcx_set_launch(self.ctx, block_size, refill_chunk, lds_window_cells)
 
+    def set_map_adds(self, mode: int):
+        mcx_set_map_adds(self.ctx, mode)
+
     def fit_runtime(self, n1=None, n2=None, seed=None):
         return mcx_fit_runtime(self.ctx, n1, n2, seed)
 
@@ -634,6 +647,9 @@ class Simulation:
 
     def set_launch(self, block_size=0, refill_chunk=0, lds_window_cells=0):
         mcx_set_launch(self.ctx, block_size, refill_chunk, lds_window_cells)
+
+    def set_map_adds(self, mode: int):
+        mcx_set_map_adds(self.ctx, mode)
 
     def close(self):
         if self.ctx:

@@ -15,7 +15,7 @@ from . import mcx
 
 EXPORTS = ["mcx_nn_create", "mcx_nn_destroy", "mcx_nn_param_count", "mcx_nn_set_params",
            "mcx_nn_get_params", "mcx_nn_get_grads", "mcx_nn_get_adam", "mcx_nn_set_adam",
-           "mcx_nn_forward", "mcx_nn_loss_grad",
+           "mcx_nn_forward", "mcx_nn_forward_sym", "mcx_nn_loss_grad",
            "mcx_nn_adam", "mcx_nn_train_step", "mcx_nn_mirror_xy", "mcx_nn_layer_forward",
            "mcx_nn_layer_backward"]
 
@@ -39,6 +39,7 @@ def lib() -> C.CDLL:
             "mcx_nn_get_adam": (C.c_int, [vp, vp, vp, u64, C.POINTER(i32)]),
             "mcx_nn_set_adam": (C.c_int, [vp, vp, vp, u64, i32]),
             "mcx_nn_forward": (C.c_int, [vp, vp, vp, vp, vp]),
+            "mcx_nn_forward_sym": (C.c_int, [vp, vp, vp, vp, i32, vp]),
             "mcx_nn_loss_grad": (C.c_int, [vp, vp, vp, i32, C.POINTER(C.c_double), vp]),
             "mcx_nn_adam": (C.c_int, [vp, f32, f32, f32, vp]),
             "mcx_nn_train_step": (C.c_int, [vp, vp, vp, f32, C.POINTER(C.c_double), vp]),
@@ -124,6 +125,11 @@ def mcx_nn_set_adam(h, m, v, step: int):
 
 def mcx_nn_forward(h, phi_in, phi_out=None, u_out=None, stream=None):
     mcx._check(lib().mcx_nn_forward(h, _ptr(phi_in), _ptr(phi_out), _ptr(u_out), _stream(stream)))
+
+
+def mcx_nn_forward_sym(h, phi_in, phi_out=None, u_out=None, nsym=8, stream=None):
+    mcx._check(lib().mcx_nn_forward_sym(h, _ptr(phi_in), _ptr(phi_out), _ptr(u_out), int(nsym),
+                                        _stream(stream)))
 
 
 def mcx_nn_loss_grad(h, phi_in, phi_target, want_loss=True, stream=None,
@@ -267,12 +273,17 @@ class Denoiser:
         _check_volume(t, int(np.prod(self.shape)))
         return t
 
-    def forward(self, phi_in, phi_out=None, u_out=None, stream=None):
+    def forward(self, phi_in, phi_out=None, u_out=None, stream=None, symmetries=1):
+        """Denoise; with symmetries = 2, 4 or 8 the outputs of that many
+        x-y symmetries of the input are averaged (mcx_nn_forward_sym)."""
         import torch
         self._vol(phi_in)
         if phi_out is None and u_out is None:
             phi_out = torch.empty_like(phi_in)
-        mcx_nn_forward(self.h, phi_in, phi_out, u_out, stream)
+        if symmetries == 1:
+            mcx_nn_forward(self.h, phi_in, phi_out, u_out, stream)
+        else:
+            mcx_nn_forward_sym(self.h, phi_in, phi_out, u_out, symmetries, stream)
         return phi_out if phi_out is not None else u_out
 
     def loss_grad(self, phi_in, phi_target, want_loss=True, stream=None, accumulate=False):

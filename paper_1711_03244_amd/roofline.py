@@ -28,13 +28,16 @@ finer model of the issue slots each event's instructions take on gfx950
 with the Philox block at the 60 slots the microbenchmark measures) is kept
 beside them as `issue_model`.
 
-**Memory-side atomics.**  Every FP64 atomic add on device memory executes at
-the memory side at a fixed aggregate rate, measured by the microbenchmark at
-2.36e10/s on distinct addresses (the published specifications give no such
-figure).  The atomics a launch issues are counted by the kernel itself
-(`flushes`: every cell-visit sum added to the map by a global atomic) and
+**Memory-side atomics.**  Every atomic add on device memory executes at the
+memory side at a fixed aggregate rate, measured by the microbenchmark on
+distinct addresses (the published specifications give no such figure):
+2.36e10/s for 64-bit (and FP64) adds without a return, 2.59e10/s for
+returning 32-bit adds followed by the carry test the map's 32-bit mode
+uses.  The atomics a launch issues are counted by the kernel itself
+(`flushes`: every cell-visit sum added to the map by a global atomic; a
+carry's second add, once per ~4000 adds to a cell, is not counted) and
 agree with the TCC_ATOMIC counter.  Algorithmic bytes of the map traffic
-are 8 per deposit (one FP64 add per segment) plus one label byte per face
+are 8 per deposit (one map update per segment) plus one label byte per face
 event; HBM traffic measured by FETCH_SIZE / WRITE_SIZE is reported against
 them.
 """
@@ -45,6 +48,9 @@ import os
 CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 VALU_PEAK = CUS * LANES * CLOCK_HZ            # lane-op slots per second
 ATOMIC_PEAK_F64 = 2.36e10                     # measured FP64 no-return atomics/s, distinct addresses
+ATOMIC_PEAK_U64 = 2.36e10                     # measured 64-bit integer no-return adds/s (the same)
+ATOMIC_PEAK_U32_CARRY = 2.59e10               # measured returning 32-bit adds/s with the carry test
+MAP_ADDS_32 = 2                               # mcx_run_stats.map_adds of a 32-bit-add launch
 
 # --- the frozen per-event convention
 PHILOX_BLOCK_OPS = 10 * (2 + 2 + 4) + 2       # 82: per round 2 mul_hi, 2 mul_lo, 4 xor/add
@@ -115,17 +121,24 @@ def valu_roofline(stats: dict, kernel_s: float) -> dict:
 
 
 def algorithmic_bytes(stats: dict) -> float:
-    """Map traffic the method needs: one FP64 add per deposit (segment) and
-    one label byte per face event."""
+    """Map traffic the method needs: one 8-byte map update per deposit
+    (segment) and one label byte per face event."""
     return 8.0 * stats["events"] + 1.0 * stats["face_events"]
 
 
 def atomic_roofline(stats: dict, kernel_s: float) -> dict:
+    """Map atomics of a launch against the measured rate of the kind of add
+    it used (stats["map_adds"]): 64-bit adds without a return, or 32-bit
+    returning adds with the carry test."""
     rate = stats["flushes"] / kernel_s
-    return {"bound": "atomics", "achieved": rate, "peak": ATOMIC_PEAK_F64,
-            "peak_source": "measured: FP64 no-return atomics on distinct addresses "
-                           "(microbenchmark)",
-            "unit": "atomics/s", "frac": rate / ATOMIC_PEAK_F64,
+    if stats.get("map_adds") == MAP_ADDS_32:
+        peak, src = ATOMIC_PEAK_U32_CARRY, ("measured: returning 32-bit atomic adds with the "
+                                            "carry test on distinct addresses (microbenchmark)")
+    else:
+        peak, src = ATOMIC_PEAK_U64, ("measured: 64-bit no-return atomic adds on distinct "
+                                      "addresses (microbenchmark)")
+    return {"bound": "atomics", "achieved": rate, "peak": peak, "peak_source": src,
+            "unit": "atomics/s", "frac": rate / peak,
             "atomics_per_photon": stats["flushes"] / max(1, stats["launched"]),
             "deposits_per_photon": stats["events"] / max(1, stats["launched"])}
 

@@ -41,16 +41,37 @@ def test_default_options():
     assert o.n_outside == 1.0 and o.max_detected == 1 << 20 and o.reflect == 0
 
 
-def test_struct_sizes_match_header_layout():
-    # natural alignment of the C structs in include/mcx.h
-    assert C.sizeof(mcx.mcx_medium) == 16
-    assert C.sizeof(mcx.mcx_volume) == 4 * 4 + 8 + 8 + 8
-    assert C.sizeof(mcx.mcx_source) == 24
-    assert C.sizeof(mcx.mcx_detector) == 16
-    assert C.sizeof(mcx.mcx_gates) == 12
-    assert C.sizeof(mcx.mcx_options) == 4 * 4 + 8 + 8 + 4 * 4 + 8 + 4 + 4 + 4 + 4  # + padding
-    assert C.sizeof(mcx.mcx_run_stats) == 17 * 8 + 11 * 8 + 8
-    assert C.sizeof(mcx.mcx_detpost) == 5 * 4 + 4 + 8
+STRUCTS = ["mcx_medium", "mcx_volume", "mcx_source", "mcx_detector", "mcx_gates",
+           "mcx_options", "mcx_run_stats", "mcx_sim", "mcx_tune_result", "mcx_detpost"]
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every ctypes struct of the binding has the size and field offsets the
+    C compiler gives the struct of include/mcx.h (compiled here with gcc)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(ROOT, "include")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mcx.h"', "int main(void) {"]
+    for name in STRUCTS:
+        st = getattr(mcx, name)
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in st._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for name in STRUCTS:
+        st = getattr(mcx, name)
+        assert int(got[f"{name} size"]) == C.sizeof(st), name
+        for field, _ in st._fields_:
+            assert int(got[f"{name} {field}"]) == getattr(st, field).offset, (name, field)
 
 
 @pytest.mark.parametrize("bad", [dict(ndet=0), dict(ndet=5000), dict(npath=0), dict(npath=256),
@@ -154,6 +175,8 @@ def test_null_context_calls_fail_cleanly():
     assert lib.mcx_run(None, 10, 1) == mcx.MCX_EINVAL
     assert lib.mcx_sync(None) == mcx.MCX_EINVAL
     assert lib.mcx_ncells(None) == 0
+    assert lib.mcx_set_map_adds(None, mcx.MAP_ADDS_32) == mcx.MCX_EINVAL
+    assert lib.mcx_set_launch(None, 0, 0, 0) == mcx.MCX_EINVAL
     lib.mcx_destroy(None)
 
 

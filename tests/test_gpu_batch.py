@@ -177,7 +177,10 @@ def test_autotune_keeps_results_and_reports_model():
         base = [b.stats(i) for i in range(len(probs))]
         r = b.autotune([max(2, x // 4) for x in n], seeds)
         say("[gpu] autotune", r)
-        assert 1 + 6 * 3 <= r["candidates"] <= 1 + 6 * 3 * 5
+        # the default shape, up to 6 blocks x 3 jobs x 5 windows, and the four
+        # fastest again with the other kind of map add
+        assert 1 + 6 * 3 <= r["candidates"] <= 1 + 6 * 3 * 5 + 4
+        assert r["map_adds"] in (mcx.MAP_ADDS_64, mcx.MAP_ADDS_32)
         assert r["block_size"] in (64, 256, 448, 512, 768, 1024)
         assert r["refill_chunk"] in (64, 256, 1024)
         assert r["lds_window_cells"] in (-1, 8192, 16384, 32768, 36864)
@@ -199,7 +202,10 @@ def test_autotune_single_simulation_tries_windows():
         base = s.stats()
         r = mcx.mcx_autotune(s.ctx, [20000], [3])
         say("[gpu] autotune single", r)
-        assert 1 + 6 * 3 <= r["candidates"] <= 1 + 6 * 3 * 5
+        # the default shape, up to 6 blocks x 3 jobs x 5 windows, and the four
+        # fastest again with the other kind of map add
+        assert 1 + 6 * 3 <= r["candidates"] <= 1 + 6 * 3 * 5 + 4
+        assert r["map_adds"] in (mcx.MAP_ADDS_64, mcx.MAP_ADDS_32)
         assert r["lds_window_cells"] in (-1, 8192, 16384, 32768, 36864)
         s.run(20000, 3)
         st = s.stats()

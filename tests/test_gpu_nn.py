@@ -73,7 +73,12 @@ CASES = [("conv3", (6, 5, 7), 1, 32), ("conv3", (4, 6, 5), 8, 16), ("conv3", (5,
          ("conv3", (15, 13, 18), 32, 32), ("conv3", (9, 10, 11), 64, 64),
          ("conv3", (10, 9, 12), 32, 1),
          # one-channel weight gradients summed over >= 64 workgroups
-         ("conv3", (20, 17, 24), 32, 1), ("conv3", (16, 20, 18), 1, 32)]
+         ("conv3", (20, 17, 24), 32, 1), ("conv3", (16, 20, 18), 1, 32),
+         # >= 1024 tiles of 4 x 4 x 8 gathering 32 channels: the resident-weights
+         # kernel (ragged in every direction; 32, 1 and 24 output channels --
+         # vector, one-column and element-wise output stores)
+         ("conv3", (36, 66, 62), 32, 32), ("conv3", (34, 64, 64), 32, 1),
+         ("conv3", (40, 64, 60), 32, 24)]
 
 
 @pytest.mark.parametrize("kind,shape,ci,co", CASES)
@@ -348,6 +353,59 @@ def test_untrained_network_returns_its_input():
     keep = noisy >= 1e-12
     assert np.allclose(out[keep], noisy[keep], rtol=1e-5)
     assert np.allclose(out[~keep], 1e-12, rtol=1e-5)
+
+
+def _sym_np(a, op):
+    """The x-y symmetry of mcx_nn_mirror_xy on a [z][y][x] array, from its
+    documented definition: out[z][y][x] = a[z][y'][x'] with (x', y') = (y, x)
+    when op & 4, then x' mirrored when op & 1 and y' when op & 2."""
+    nz, ny, nx = a.shape
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    sx, sy = (y, x) if op & 4 else (x, y)
+    if op & 1:
+        sx = nx - 1 - sx
+    if op & 2:
+        sy = ny - 1 - sy
+    return a[:, sy, sx]
+
+
+@pytest.mark.parametrize("nsym", [2, 4, 8])
+def test_symmetry_averaged_inference(nsym):
+    """mcx_nn_forward_sym equals the mean, in u space, of the network's
+    outputs for the transformed inputs, each mapped back by the inverse
+    transform (found here by search over the 8 ops); composed here from
+    mcx_nn_mirror_xy and mcx_nn_forward.  nsym = 1 is the plain forward."""
+    t = torch()
+    channels, shape = (8, 16), (6, 8, 8)
+    _, flat = make_net(channels, shape, 21)
+    noisy, _ = fluence_pair(shape, 22)
+    inverse = {}
+    probe = np.arange(np.prod(shape), dtype=np.float64).reshape(shape)
+    for op in range(8):
+        inverse[op] = next(k for k in range(8) if np.array_equal(_sym_np(_sym_np(probe, op), k),
+                                                                probe))
+    with nn.Denoiser(channels, shape) as d:
+        d.set_params(flat)
+        x = dev_f32(noisy)
+        acc = np.zeros(shape)
+        for op in range(nsym):
+            xo = x if op == 0 else nn.mcx_nn_mirror_xy(x, op)
+            u = t.empty_like(x)
+            d.forward(xo, u_out=u)
+            t.cuda.synchronize()
+            acc += _sym_np(host(u), inverse[op])
+        u_sym, phi_sym = t.empty_like(x), t.empty_like(x)
+        d.forward(x, phi_out=phi_sym, u_out=u_sym, symmetries=nsym)
+        u1 = t.empty_like(x)
+        d.forward(x, u_out=u1, symmetries=1)
+        t.cuda.synchronize()
+        u_plain = t.empty_like(x)
+        d.forward(x, u_out=u_plain)
+        t.cuda.synchronize()
+    assert np.array_equal(host(u1), host(u_plain))
+    want = acc / nsym
+    assert np.allclose(host(u_sym), want, rtol=0, atol=1e-6 * np.abs(want).max())
+    assert np.allclose(host(phi_sym), np.exp(want * 4.0 - 16.0), rtol=1e-5)
 
 
 def test_checkpoint_round_trip(tmp_path):

@@ -183,18 +183,30 @@ def test_beer_lambert_exact():
     assert abs(energy_residual(st)) < 1e-6
 
 
-def test_fp64_tally_sums_two_million_deposits_exactly():
-    # 2e6 deposits of ~1 into the first voxel, each flushed once per photon
-    # (FP32 visit sum) into the FP64 tally through the LDS window: a plain
-    # FP32 accumulator would be off by ~1e-2 relative at this count, the
-    # FP64 cell is not.
+@pytest.mark.parametrize("window", [0, -1], ids=["lds_window", "direct"])
+def test_map_sums_two_million_deposits_exactly(window):
+    """2e6 deposits of ~1 into each voxel of a column, each flushed once per
+    photon (FP32 visit sum, rounded to 2^-20 units): through the LDS window
+    (moved to the map in 2^31-unit pieces) and directly (2e6 map adds).
+    A cell's sum reaches 2^41 units, so its 32-bit low word carries about
+    500 times; an FP32 accumulator would be off by ~1e-2 relative at this
+    count.  Both kinds of map add give the same bits."""
     p = W.slab_column(nz=4, mua=0.005, mus=0.0)
     N = 2_000_000
-    g = gpu(p, N, 3)
+    maps = []
+    for adds in (mcx.MAP_ADDS_64, mcx.MAP_ADDS_32):
+        say(f"[gpu] slab_column N={N} window={window} map adds {adds}")
+        with mcx.Simulation(p) as sim:
+            sim.set_launch(0, 0, window)
+            sim.set_map_adds(adds)
+            sim.run(N, 3)
+            maps.append(sim.fluence(mcx.MCX_RAW, f64=True))
+    assert np.array_equal(maps[0], maps[1])
     mua = float(p.media[1, 0])
     expect = (-math.expm1(-mua)) / mua
-    assert g["raw"][0, 0, 1, 1] / N == pytest.approx(expect, rel=1e-6)
-    assert g["raw"][0, 3, 1, 1] / N == pytest.approx(math.exp(-3 * mua) * expect, rel=1e-6)
+    raw = maps[0]
+    assert raw[0, 0, 1, 1] / N == pytest.approx(expect, rel=1e-6)
+    assert raw[0, 3, 1, 1] / N == pytest.approx(math.exp(-3 * mua) * expect, rel=1e-6)
 
 
 def test_gates_and_timeout_exact():
@@ -599,6 +611,30 @@ def test_launch_shape_does_not_change_results(opt):
     for k in ["launched", "escaped", "timeout", "scatters", "face_events"]:
         assert g["stats"][k] == base["stats"][k]
     assert np.array_equal(g["raw"], base["raw"])
+
+
+def test_map_adds_do_not_change_results():
+    """The map's integer counts are the same bits whether the kernel adds to
+    them with 64-bit atomics or with 32-bit returning atomics and carries,
+    in a launch where the automatic choice takes either, on the sphere
+    (window, detectors, reflections) at two workgroup sizes."""
+    p = W.cube_sphere(n=30, ngates=10, dt=0.2).replace(name="cube30_sphere")
+    N = 200_000
+    runs = []
+    for block, adds in [(1024, mcx.MAP_ADDS_AUTO), (1024, mcx.MAP_ADDS_64),
+                        (768, mcx.MAP_ADDS_32), (768, mcx.MAP_ADDS_AUTO)]:
+        say(f"[gpu] {p.name} N={N} block {block} map adds {adds}")
+        with mcx.Simulation(p) as sim:
+            sim.set_launch(block, 64, 0)
+            sim.set_map_adds(adds)
+            sim.run(N, 4)
+            runs.append((sim.fluence(mcx.MCX_RAW, f64=True), sim.stats()))
+    raw0, st0 = runs[0]
+    for raw, st in runs[1:]:
+        assert np.array_equal(raw, raw0)
+        for k in ["launched", "escaped", "timeout", "scatters", "face_events", "detected"]:
+            assert st[k] == st0[k], k
+        assert st["tally_sum"] == st0["tally_sum"]
 
 
 def test_window_sums_with_one_running_wave_per_workgroup():
