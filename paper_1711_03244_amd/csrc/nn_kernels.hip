@@ -357,6 +357,180 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
     }
 }
 
+// --------------------------------- 3x3x3 conv, 32 input channels, weights resident
+// kConv3 / kConv3T with cin == 32 on large grids (the full-resolution layers):
+// the reduction is one chunk of 32 channels, so a workgroup's weights (27
+// taps x 16 NB output channels) fit in LDS and stay there while the
+// workgroup walks its tiles (tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// of 4 x 4 x 8 voxels).  Waves 0-3 compute (wave w: z-slices 2w, 2w + 1,
+// NB 16-column MFMA blocks each); wave 4 moves data: it streams the next
+// tile's 6 x 6 x 10 input brick into one of two LDS buffers with direct
+// global-to-LDS loads (zeros outside the volume come from g_zero16) while the
+// compute waves work on the other, and writes the previous tile's outputs,
+// which the compute waves leave in LDS, to global memory.  One barrier per
+// tile; the compute waves issue no global memory operation in the loop.
+// Brick layout: voxel v = (z * 6 + y) * 6 + x of the brick, 64 bytes (its 32
+// channels) each, in the order the loads write them.
+constexpr int kResBV = 360;  // brick voxels: 6 x 6 x 10
+__device__ __align__(16) uint4 g_zero16[1];  // the source of the brick's zero padding
+
+template <int NB>
+__global__ void __launch_bounds__(320) conv3_resident_kernel(ConvArgs a) {
+  constexpr int NC = 16 * NB;                 // output channels of the workgroup
+  __shared__ uint16_t sW[27][NC][kBK + kPadK];
+  __shared__ uint4 sBr[2][kResBV * 4];
+  __shared__ uint4 sOut[2][128 * NC / 4];     // 128 voxels x NC channels, FP32 or BF16
+  __shared__ float sBias[NC];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tx_n = (a.w + 3) >> 2, ty_n = (a.h + 3) >> 2, tz_n = (a.d + 7) >> 3;
+  const int ntiles = tx_n * ty_n * tz_n;
+  const int n0 = blockIdx.y * NC;
+  const int ncols = min(NC, a.cout - n0);
+  const int esize = a.y_f32 ? 4 : 2;
+
+  // weights and bias, once
+  for (int i = tid; i < 27 * NC * 4; i += blockDim.x) {
+    const int tt = i / (NC * 4), rem = i % (NC * 4);
+    const int row = rem >> 2, cc = (rem & 3) * 8;
+    *reinterpret_cast<uint4*>(&sW[tt][row][cc]) = *reinterpret_cast<const uint4*>(
+        a.bt + static_cast<int64_t>(n0 + row) * a.kpad + tt * 32 + cc);
+  }
+  for (int i = tid; i < NC; i += blockDim.x) sBias[i] = (a.bias && i < ncols) ? a.bias[n0 + i] : 0.f;
+
+  auto tile_origin = [&](int t, int& bx, int& by, int& bz) {
+    bx = (t % tx_n) * 4;
+    by = ((t / tx_n) % ty_n) * 4;
+    bz = (t / (tx_n * ty_n)) * 8;
+  };
+  // wave 4: the brick of tile t into buffer b (every lane one 16-byte chunk
+  // per load; chunk j of voxel v at v * 4 + j)
+  auto load_brick = [&](int t, int b) {
+    int bx, by, bz;
+    tile_origin(t, bx, by, bz);
+    for (int base = 0; base < kResBV * 4; base += 64) {
+      const int c = base + lane;
+      if (c < kResBV * 4) {
+        const int v = c >> 2, j = c & 3;
+        const int vx = v % 6, vy = (v / 6) % 6, vz = v / 36;
+        const int gx = bx + vx - 1, gy = by + vy - 1, gz = bz + vz - 1;
+        const bool in = gx >= 0 && gy >= 0 && gz >= 0 && gx < a.in_w && gy < a.in_h &&
+                        gz < a.in_d;
+        const uint16_t* src =
+            in ? a.x + ((static_cast<int64_t>(gz) * a.in_h + gy) * a.in_w + gx) * 32 + j * 8
+               : reinterpret_cast<const uint16_t*>(g_zero16);
+        __builtin_amdgcn_global_load_lds(
+            (__attribute__((address_space(1))) void*)(src),
+            (__attribute__((address_space(3))) void*)(&sBr[b][base]), 16, 0, 0);
+      }
+    }
+  };
+  // wave 4: the outputs of tile t from sOut[b] to y
+  auto store_out = [&](int t, int b) {
+    int bx, by, bz;
+    tile_origin(t, bx, by, bz);
+    const char* src = reinterpret_cast<const char*>(sOut[b]);
+    const int row_bytes = NC * esize;   // one voxel's NC outputs in sOut
+    const int out_bytes = ncols * esize;
+    if (out_bytes % 16 == 0 && (a.cout * esize) % 16 == 0) {
+      const int per = out_bytes / 16;
+      for (int i = lane; i < 128 * per; i += 64) {
+        const int vl = i / per, k = i % per;
+        const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
+        if (x >= a.w || y >= a.h || z >= a.d) continue;
+        const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
+        *reinterpret_cast<uint4*>(static_cast<char*>(a.y) + (o * a.cout + n0) * esize + k * 16) =
+            *reinterpret_cast<const uint4*>(src + vl * row_bytes + k * 16);
+      }
+    } else {
+      for (int i = lane; i < 128 * ncols; i += 64) {
+        const int vl = i / ncols, n = i % ncols;
+        const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
+        if (x >= a.w || y >= a.h || z >= a.d) continue;
+        const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
+        if (a.y_f32)
+          static_cast<float*>(a.y)[o * a.cout + n0 + n] =
+              reinterpret_cast<const float*>(src + vl * row_bytes)[n];
+        else
+          static_cast<uint16_t*>(a.y)[o * a.cout + n0 + n] =
+              reinterpret_cast<const uint16_t*>(src + vl * row_bytes)[n];
+      }
+    }
+  };
+
+  const int first = blockIdx.x;
+  const int step = gridDim.x;
+  if (wave == 4 && first < ntiles) {
+    load_brick(first, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+
+  const int sgn = a.geo == kConv3 ? 1 : -1;
+  const int r = lane & 15;
+  const int ox = r & 3, oy = r >> 2;
+  const int kq = lane >> 4;  // this lane's 16-byte chunk of the 32 channels
+  int i = 0;
+  for (int t = first; t < ntiles; t += step, ++i) {
+    const int b = i & 1;
+    if (wave == 4) {
+      if (i > 0) store_out(t - step, b ^ 1);
+      if (t + step < ntiles) load_brick(t + step, b ^ 1);
+      __builtin_amdgcn_s_waitcnt(0);
+    } else {
+      floatx4 acc[2][NB];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[q][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const char* br = reinterpret_cast<const char*>(sBr[b]);
+#pragma unroll
+      for (int tt = 0; tt < 27; ++tt) {
+        const int dz = sgn * (tt / 9 - 1), dy = sgn * ((tt / 3) % 3 - 1), dx = sgn * (tt % 3 - 1);
+        bf16x8 bc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          bc[j] = *reinterpret_cast<const bf16x8*>(&sW[tt][16 * j + r][kq * 8]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int oz = wave * 2 + q;
+          const int v = ((oz + 1 + dz) * 6 + (oy + 1 + dy)) * 6 + (ox + 1 + dx);
+          const bf16x8 af = *reinterpret_cast<const bf16x8*>(br + v * 64 + kq * 16);
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bc[j], acc[q][j], 0, 0, 0);
+        }
+      }
+      // epilogue into sOut[b]: row 4 (lane >> 4) + e of slice 2 wave + q is
+      // local voxel (x, y, z) = (rr & 3, rr >> 2, 2 wave + q)
+      char* dst = reinterpret_cast<char*>(sOut[b]);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int nl = j * 16 + (lane & 15);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int rr = (lane >> 4) * 4 + e;
+            const int vl = ((wave * 2 + q) * 4 + (rr >> 2)) * 4 + (rr & 3);
+            float v = acc[q][j][e] + sBias[nl];
+            if (a.relu) v = fmaxf(v, 0.f);
+            if (a.y_f32)
+              reinterpret_cast<float*>(dst)[vl * NC + nl] = v;
+            else
+              reinterpret_cast<uint16_t*>(dst)[vl * NC + nl] = to_bf16(v);
+          }
+        }
+    }
+    __syncthreads();
+  }
+  // the last tile's outputs
+  if (wave == 4 && i > 0) {
+    store_out(first + (i - 1) * step, (i - 1) & 1);
+  }
+}
+
 // ------------------------------------------ 3x3x3 conv with one gathered channel
 // kConv3 / kConv3T with cin == 1 (the input layer's forward pass, the output
 // layer's input gradient): the 27 taps are the reduction axis (one MFMA
@@ -1133,6 +1307,30 @@ bool uses_brick(const ConvArgs& a) {
   return (a.geo == kConv3 || a.geo == kConv3T) && a.cin % kBK == 0;
 }
 
+// The resident-weights kernel: 3x3x3 layers gathering exactly 32 channels,
+// without a skip input, on grids of at least kResidentTiles 4 x 4 x 8 tiles
+// (the full-resolution layers; smaller grids keep the brick kernel, whose
+// split reductions fill the chip).
+constexpr int64_t kResidentTiles = 1024;
+int64_t brick_tiles(const ConvArgs& a, int mz);
+bool uses_resident(const ConvArgs& a) {
+  return (a.geo == kConv3 || a.geo == kConv3T) && a.cin == 32 && !a.skip &&
+         brick_tiles(a, 2) >= kResidentTiles;
+}
+
+// compute units of the current device (queried once)
+int device_cus() {
+  static int cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    return n;
+  }();
+  return cus;
+}
+
 int64_t brick_tiles(const ConvArgs& a, int mz) {
   return static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 4 * mz - 1) / (4 * mz));
 }
@@ -1200,6 +1398,17 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
       conv3_scalar_kernel<2><<<grid, 256, 0, s>>>(a);
     else
       conv3_scalar_kernel<1><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+  }
+  if (uses_resident(a)) {
+    const int nbr = a.cout > 16 ? 2 : 1;
+    const int64_t tiles = brick_tiles(a, 2);
+    const dim3 grid(static_cast<unsigned>(std::min<int64_t>(tiles, device_cus())),
+                    static_cast<unsigned>((a.cout + 16 * nbr - 1) / (16 * nbr)), 1);
+    if (nbr == 2)
+      conv3_resident_kernel<2><<<grid, 320, 0, s>>>(a);
+    else
+      conv3_resident_kernel<1><<<grid, 320, 0, s>>>(a);
     return hipGetLastError();
   }
   if (uses_brick(a)) {
