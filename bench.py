@@ -164,7 +164,9 @@ def main():
     last = stats[-1]
     ksec = sum(kernel_ms) / len(kernel_ms) / 1e3
     roof = roofline.binding(last, ksec)
-    roof["traffic"] = roofline.measured_traffic(N, tune["lds_window_cells"])
+    roof["traffic"] = roofline.measured_traffic(
+        N, {"block_size": last["block_size"], "refill_chunk": tune["refill_chunk"],
+            "lds_window_cells": tune["lds_window_cells"], "map_adds": last["map_adds"]})
     roof["traffic_over_algorithmic"] = (roof["traffic"] / roof["algorithmic_bytes"]
                                         if roof["traffic"] else None)
     log(f"timed steps: {value:.1f} photons/ms")

@@ -363,23 +363,26 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
 // taps x 16 NB output channels) fit in LDS and stay there while the
 // workgroup walks its tiles (tiles blockIdx.x, blockIdx.x + gridDim.x, ...
 // of 4 x 4 x 8 voxels).  Waves 0-3 compute (wave w: z-slices 2w, 2w + 1,
-// NB 16-column MFMA blocks each); wave 4 moves data: it streams the next
-// tile's 6 x 6 x 10 input brick into one of two LDS buffers with direct
-// global-to-LDS loads (zeros outside the volume come from g_zero16) while the
-// compute waves work on the other, and writes the previous tile's outputs,
-// which the compute waves leave in LDS, to global memory.  One barrier per
-// tile; the compute waves issue no global memory operation in the loop.
-// Brick layout: voxel v = (z * 6 + y) * 6 + x of the brick, 64 bytes (its 32
-// channels) each, in the order the loads write them.
+// NB 16-column MFMA blocks each) and leave each tile's outputs in LDS;
+// wave 4 streams input bricks (6 x 6 x 10 voxels) into three LDS buffers
+// with direct global-to-LDS loads, two tiles ahead (zeros outside the
+// volume come from g_zero16); wave 5 writes the previous tile's outputs
+// from LDS to global memory.  The compute waves issue no global memory
+// operation in the loop, and each of the two data waves waits only for its
+// own transfers: one barrier per tile.  Brick layout: voxel v = (z * 6 +
+// y) * 6 + x of the brick, 64 bytes each, its 16-byte chunk j (channels
+// 8j .. 8j + 7) in slot j ^ ((z * 6 + y) & 3): the 16 rows of an A fragment
+// (a 4 x 4 patch of voxels) then fall on 16 different 16-byte bank groups.
 constexpr int kResBV = 360;  // brick voxels: 6 x 6 x 10
 __device__ __align__(16) uint4 g_zero16[1];  // the source of the brick's zero padding
 
-template <int NB>
-__global__ void __launch_bounds__(320) conv3_resident_kernel(ConvArgs a) {
+template <int NB, bool kF32>
+__global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
   constexpr int NC = 16 * NB;                 // output channels of the workgroup
+  constexpr int ES = kF32 ? 4 : 2;            // bytes per output
   __shared__ uint16_t sW[27][NC][kBK + kPadK];
-  __shared__ uint4 sBr[2][kResBV * 4];
-  __shared__ uint4 sOut[2][128 * NC / 4];     // 128 voxels x NC channels, FP32 or BF16
+  __shared__ uint4 sBr[3][kResBV * 4];
+  __shared__ uint4 sOut[2][128 * NC * ES / 16];  // 128 voxels x NC outputs
   __shared__ float sBias[NC];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -388,7 +391,6 @@ __global__ void __launch_bounds__(320) conv3_resident_kernel(ConvArgs a) {
   const int ntiles = tx_n * ty_n * tz_n;
   const int n0 = blockIdx.y * NC;
   const int ncols = min(NC, a.cout - n0);
-  const int esize = a.y_f32 ? 4 : 2;
 
   // weights and bias, once
   for (int i = tid; i < 27 * NC * 4; i += blockDim.x) {
@@ -405,42 +407,69 @@ __global__ void __launch_bounds__(320) conv3_resident_kernel(ConvArgs a) {
     bz = (t / (tx_n * ty_n)) * 8;
   };
   // wave 4: the brick of tile t into buffer b (every lane one 16-byte chunk
-  // per load; chunk j of voxel v at v * 4 + j)
+  // per load; chunk j of voxel v at v * 4 + j).  The chunk's offset from the
+  // brick's corner and its position are the same for every tile: computed
+  // once; tiles whose brick lies inside the volume skip the bounds checks.
+  constexpr int kLoads = (kResBV * 4 + 63) / 64;
+  int64_t rel[kLoads];
+  int pos[kLoads];  // vx | vy << 4 | vz << 8, or -1 past the brick
+#pragma unroll
+  for (int k = 0; k < kLoads; ++k) {
+    const int c = k * 64 + lane;  // the LDS slot this load writes
+    const int v = c >> 2, j = (c & 3) ^ ((v / 6) & 3);
+    const int vx = v % 6, vy = (v / 6) % 6, vz = v / 36;
+    rel[k] = ((static_cast<int64_t>(vz) * a.in_h + vy) * a.in_w + vx) * 32 + j * 8;
+    pos[k] = c < kResBV * 4 ? (vx | vy << 4 | vz << 8) : -1;
+  }
+  const uint16_t* zero = reinterpret_cast<const uint16_t*>(g_zero16);
   auto load_brick = [&](int t, int b) {
     int bx, by, bz;
     tile_origin(t, bx, by, bz);
-    for (int base = 0; base < kResBV * 4; base += 64) {
-      const int c = base + lane;
-      if (c < kResBV * 4) {
-        const int v = c >> 2, j = c & 3;
-        const int vx = v % 6, vy = (v / 6) % 6, vz = v / 36;
-        const int gx = bx + vx - 1, gy = by + vy - 1, gz = bz + vz - 1;
-        const bool in = gx >= 0 && gy >= 0 && gz >= 0 && gx < a.in_w && gy < a.in_h &&
-                        gz < a.in_d;
-        const uint16_t* src =
-            in ? a.x + ((static_cast<int64_t>(gz) * a.in_h + gy) * a.in_w + gx) * 32 + j * 8
-               : reinterpret_cast<const uint16_t*>(g_zero16);
-        __builtin_amdgcn_global_load_lds(
-            (__attribute__((address_space(1))) void*)(src),
-            (__attribute__((address_space(3))) void*)(&sBr[b][base]), 16, 0, 0);
+    const int64_t corner =
+        ((static_cast<int64_t>(bz - 1) * a.in_h + (by - 1)) * a.in_w + (bx - 1)) * 32;
+    const bool inside = bx >= 1 && by >= 1 && bz >= 1 && bx + 5 <= a.in_w &&
+                        by + 5 <= a.in_h && bz + 9 <= a.in_d;
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+      if (pos[k] < 0) continue;
+      bool in = inside;
+      if (!inside) {
+        const int gx = bx + (pos[k] & 15) - 1, gy = by + ((pos[k] >> 4) & 15) - 1,
+                  gz = bz + (pos[k] >> 8) - 1;
+        in = gx >= 0 && gy >= 0 && gz >= 0 && gx < a.in_w && gy < a.in_h && gz < a.in_d;
       }
+      const uint16_t* src = in ? a.x + corner + rel[k] : zero;
+      __builtin_amdgcn_global_load_lds(
+          (__attribute__((address_space(1))) void*)(src),
+          (__attribute__((address_space(3))) void*)(&sBr[b][k * 64]), 16, 0, 0);
     }
   };
-  // wave 4: the outputs of tile t from sOut[b] to y
+  // wave 5: the outputs of tile t from sOut[b] to y
   auto store_out = [&](int t, int b) {
     int bx, by, bz;
     tile_origin(t, bx, by, bz);
     const char* src = reinterpret_cast<const char*>(sOut[b]);
-    const int row_bytes = NC * esize;   // one voxel's NC outputs in sOut
-    const int out_bytes = ncols * esize;
-    if (out_bytes % 16 == 0 && (a.cout * esize) % 16 == 0) {
+    constexpr int row_bytes = NC * ES;  // one voxel's NC outputs in sOut
+    const int out_bytes = ncols * ES;
+    if (ncols == NC && (a.cout * ES) % 16 == 0) {  // whole rows of 16-byte pieces
+      constexpr int per = NC * ES / 16;
+#pragma unroll
+      for (int i = lane; i < 128 * per; i += 64) {
+        const int vl = i / per, k = i % per;
+        const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
+        if (x >= a.w || y >= a.h || z >= a.d) continue;
+        const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
+        *reinterpret_cast<uint4*>(static_cast<char*>(a.y) + (o * a.cout + n0) * ES + k * 16) =
+            *reinterpret_cast<const uint4*>(src + vl * row_bytes + k * 16);
+      }
+    } else if (out_bytes % 16 == 0 && (a.cout * ES) % 16 == 0) {
       const int per = out_bytes / 16;
       for (int i = lane; i < 128 * per; i += 64) {
         const int vl = i / per, k = i % per;
         const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
         if (x >= a.w || y >= a.h || z >= a.d) continue;
         const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
-        *reinterpret_cast<uint4*>(static_cast<char*>(a.y) + (o * a.cout + n0) * esize + k * 16) =
+        *reinterpret_cast<uint4*>(static_cast<char*>(a.y) + (o * a.cout + n0) * ES + k * 16) =
             *reinterpret_cast<const uint4*>(src + vl * row_bytes + k * 16);
       }
     } else {
@@ -449,7 +478,7 @@ __global__ void __launch_bounds__(320) conv3_resident_kernel(ConvArgs a) {
         const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
         if (x >= a.w || y >= a.h || z >= a.d) continue;
         const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
-        if (a.y_f32)
+        if constexpr (kF32)
           static_cast<float*>(a.y)[o * a.cout + n0 + n] =
               reinterpret_cast<const float*>(src + vl * row_bytes)[n];
         else
@@ -461,8 +490,9 @@ __global__ void __launch_bounds__(320) conv3_resident_kernel(ConvArgs a) {
 
   const int first = blockIdx.x;
   const int step = gridDim.x;
-  if (wave == 4 && first < ntiles) {
-    load_brick(first, 0);
+  if (wave == 4) {
+    if (first < ntiles) load_brick(first, 0);
+    if (first + step < ntiles) load_brick(first + step, 1);
     __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();
@@ -473,38 +503,52 @@ __global__ void __launch_bounds__(320) conv3_resident_kernel(ConvArgs a) {
   const int kq = lane >> 4;  // this lane's 16-byte chunk of the 32 channels
   int i = 0;
   for (int t = first; t < ntiles; t += step, ++i) {
-    const int b = i & 1;
     if (wave == 4) {
-      if (i > 0) store_out(t - step, b ^ 1);
-      if (t + step < ntiles) load_brick(t + step, b ^ 1);
+      // the brick of the next tile (issued one tile ago) has arrived; the one
+      // after it goes into the buffer the compute waves finished last tile
       __builtin_amdgcn_s_waitcnt(0);
+      if (t + 2 * step < ntiles) load_brick(t + 2 * step, (i + 2) % 3);
+    } else if (wave == 5) {
+      if (i > 0) store_out(t - step, (i - 1) & 1);
     } else {
       floatx4 acc[2][NB];
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[q][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-      const char* br = reinterpret_cast<const char*>(sBr[b]);
-#pragma unroll
-      for (int tt = 0; tt < 27; ++tt) {
+      const char* br = reinterpret_cast<const char*>(sBr[i % 3]);
+      // fragments of tap tt: B from the weights, A from the brick (voxel of
+      // row r shifted by the tap); the next tap's are read while this tap's
+      // matrix instructions run
+      auto frags = [&](int tt, bf16x8 (&bc)[NB], bf16x8 (&af)[2]) {
         const int dz = sgn * (tt / 9 - 1), dy = sgn * ((tt / 3) % 3 - 1), dx = sgn * (tt % 3 - 1);
-        bf16x8 bc[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j)
           bc[j] = *reinterpret_cast<const bf16x8*>(&sW[tt][16 * j + r][kq * 8]);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const int oz = wave * 2 + q;
-          const int v = ((oz + 1 + dz) * 6 + (oy + 1 + dy)) * 6 + (ox + 1 + dx);
-          const bf16x8 af = *reinterpret_cast<const bf16x8*>(br + v * 64 + kq * 16);
+          const int row = (wave * 2 + q + 1 + dz) * 6 + (oy + 1 + dy);
+          const int v = row * 6 + (ox + 1 + dx);
+          af[q] = *reinterpret_cast<const bf16x8*>(br + v * 64 + ((kq ^ (row & 3)) << 4));
+        }
+      };
+      bf16x8 bc[2][NB], af[2][2];
+      frags(0, bc[0], af[0]);
+#pragma unroll
+      for (int tt = 0; tt < 27; ++tt) {
+        const int cur = tt & 1;
+        if (tt + 1 < 27) frags(tt + 1, bc[cur ^ 1], af[cur ^ 1]);
+        __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of the MFMAs below
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
           for (int j = 0; j < NB; ++j)
-            acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bc[j], acc[q][j], 0, 0, 0);
-        }
+            acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[cur][q], bc[cur][j], acc[q][j],
+                                                                0, 0, 0);
       }
-      // epilogue into sOut[b]: row 4 (lane >> 4) + e of slice 2 wave + q is
+      // epilogue into sOut: row 4 (lane >> 4) + e of slice 2 wave + q is
       // local voxel (x, y, z) = (rr & 3, rr >> 2, 2 wave + q)
-      char* dst = reinterpret_cast<char*>(sOut[b]);
+      char* dst = reinterpret_cast<char*>(sOut[i & 1]);
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -516,7 +560,7 @@ __global__ void __launch_bounds__(320) conv3_resident_kernel(ConvArgs a) {
             const int vl = ((wave * 2 + q) * 4 + (rr >> 2)) * 4 + (rr & 3);
             float v = acc[q][j][e] + sBias[nl];
             if (a.relu) v = fmaxf(v, 0.f);
-            if (a.y_f32)
+            if constexpr (kF32)
               reinterpret_cast<float*>(dst)[vl * NC + nl] = v;
             else
               reinterpret_cast<uint16_t*>(dst)[vl * NC + nl] = to_bf16(v);
@@ -526,9 +570,7 @@ __global__ void __launch_bounds__(320) conv3_resident_kernel(ConvArgs a) {
     __syncthreads();
   }
   // the last tile's outputs
-  if (wave == 4 && i > 0) {
-    store_out(first + (i - 1) * step, (i - 1) & 1);
-  }
+  if (wave == 5 && i > 0) store_out(first + (i - 1) * step, (i - 1) & 1);
 }
 
 // ------------------------------------------ 3x3x3 conv with one gathered channel
@@ -1310,12 +1352,13 @@ bool uses_brick(const ConvArgs& a) {
 // The resident-weights kernel: 3x3x3 layers gathering exactly 32 channels,
 // without a skip input, on grids of at least kResidentTiles 4 x 4 x 8 tiles
 // (the full-resolution layers; smaller grids keep the brick kernel, whose
-// split reductions fill the chip).
+// split reductions fill the chip), with FP32 outputs only for up to 16
+// output channels (its LDS holds three bricks and two output tiles).
 constexpr int64_t kResidentTiles = 1024;
 int64_t brick_tiles(const ConvArgs& a, int mz);
 bool uses_resident(const ConvArgs& a) {
   return (a.geo == kConv3 || a.geo == kConv3T) && a.cin == 32 && !a.skip &&
-         brick_tiles(a, 2) >= kResidentTiles;
+         (!a.y_f32 || a.cout <= 16) && brick_tiles(a, 2) >= kResidentTiles;
 }
 
 // compute units of the current device (queried once)
@@ -1406,9 +1449,11 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(std::min<int64_t>(tiles, device_cus())),
                     static_cast<unsigned>((a.cout + 16 * nbr - 1) / (16 * nbr)), 1);
     if (nbr == 2)
-      conv3_resident_kernel<2><<<grid, 320, 0, s>>>(a);
+      conv3_resident_kernel<2, false><<<grid, 384, 0, s>>>(a);
+    else if (a.y_f32)
+      conv3_resident_kernel<1, true><<<grid, 384, 0, s>>>(a);
     else
-      conv3_resident_kernel<1><<<grid, 320, 0, s>>>(a);
+      conv3_resident_kernel<1, false><<<grid, 384, 0, s>>>(a);
     return hipGetLastError();
   }
   if (uses_brick(a)) {

@@ -173,13 +173,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(photons: int, lds_window_cells: int):
+def measured_traffic(photons: int, launch: dict):
     """HBM-side bytes per transport launch from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE counters (one entry per LDS window size they
-    were taken with), scaled by the copy-kernel calibration and by photons;
-    None when the counters were taken on other kernel source or no entry
-    has this LDS window (the window decides how many deposits reach memory
-    as atomics)."""
+    FETCH_SIZE / WRITE_SIZE counters, scaled by the copy-kernel calibration
+    and by photons; None when the counters were taken on other kernel
+    source or with another launch (block size, photons per job, LDS window
+    and kind of map add decide how many deposits reach memory, and how).
+    launch: {"block_size", "refill_chunk", "lds_window_cells", "map_adds"}
+    with map_adds as mcx_run_stats reports it (1: 64-bit, 2: 32-bit)."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -187,8 +188,14 @@ def measured_traffic(photons: int, lds_window_cells: int):
         return None
     if c.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    e = c.get("by_window", {}).get(str(lds_window_cells))
-    if e is None or e["launch"]["lds_window_cells"] != lds_window_cells:
+    e = c.get("by_window", {}).get(str(launch["lds_window_cells"]))
+    if e is None:
+        return None
+    took = e["launch"]
+    adds = {"64-bit": 1, "32-bit with carry": 2}.get(took.get("map_adds"))
+    if (took["block_size"], took["refill_chunk"], took["lds_window_cells"], adds) != (
+            launch["block_size"], launch["refill_chunk"], launch["lds_window_cells"],
+            launch["map_adds"]):
         return None
     per_photon = (e["fetch_kib"] * c["fetch_factor"] + e["write_kib"] * c["write_factor"]) * 1024.0 \
         / c["photons"]
