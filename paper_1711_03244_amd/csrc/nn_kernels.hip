@@ -361,93 +361,92 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
 // kConv3 / kConv3T with cin == 32 on large grids (the full-resolution layers):
 // the reduction is one chunk of 32 channels, so a workgroup's weights (27
 // taps x 16 NB output channels) fit in LDS and stay there while the
-// workgroup walks its tiles (tiles blockIdx.x, blockIdx.x + gridDim.x, ...
-// of 4 x 4 x 8 voxels).  Waves 0-3 compute (wave w: z-slices 2w, 2w + 1,
-// NB 16-column MFMA blocks each) and leave each tile's outputs in LDS;
-// wave 4 streams input bricks (6 x 6 x 10 voxels) into three LDS buffers
-// with direct global-to-LDS loads, two tiles ahead (zeros outside the
-// volume come from g_zero16); wave 5 writes the previous tile's outputs
-// from LDS to global memory.  The compute waves issue no global memory
-// operation in the loop, and each of the two data waves waits only for its
-// own transfers: one barrier per tile.  Brick layout: voxel v = (z * 6 +
-// y) * 6 + x of the brick, 64 bytes each, its 16-byte chunk j (channels
-// 8j .. 8j + 7) in slot j ^ ((z * 6 + y) & 3): the 16 rows of an A fragment
-// (a 4 x 4 patch of voxels) then fall on 16 different 16-byte bank groups.
-constexpr int kResBV = 360;  // brick voxels: 6 x 6 x 10
-__device__ __align__(16) uint4 g_zero16[1];  // the source of the brick's zero padding
+// workgroup walks its columns of tiles (columns blockIdx.x, blockIdx.x +
+// gridDim.x, ... of 4 x 4 x 8-voxel tiles stacked along z).  Waves 0-3
+// compute (wave w: z-slices 2w, 2w + 1 of the tile, NB 16-column MFMA blocks
+// each) and leave each tile's outputs in LDS; wave 4 streams the input
+// planes of the column (6 x 6 voxels of 32 channels, z = -1 .. 8 per tile
+// count + 1) into a ring of plane slots with direct global-to-LDS loads,
+// A tiles ahead (a tile reuses two planes of the previous one and loads
+// eight; zeros outside the volume come from g_zero16); wave 5 writes
+// the previous tile's outputs from LDS to global memory.  The compute
+// waves issue no global memory operation; each data wave waits only for its
+// own transfers (the plane wave for all but the newest A - 1 tiles' loads,
+// which complete in issue order): one barrier per tile.  Plane layout: voxel
+// (y, x) of the plane at (y * 6 + x) * 64 bytes, its 16-byte chunk j
+// (channels 8j .. 8j + 7) in slot j ^ (y & 3), so that the 16 rows of an A
+// fragment (a 4 x 4 patch of voxels) fall on 16 different bank groups; the
+// weights of output channel n likewise at n * 64 bytes, chunk j in slot
+// j ^ ((n >> 2) & 3).
+constexpr int kResPlane = 36 * 64;  // bytes per plane slot
+__device__ __align__(16) uint4 g_zero16[1];  // the source of the zero padding
+
+// tiles of planes in flight: all that fit in LDS beside the weights and
+// two output tiles (three, or two for 32 FP32 output columns)
+constexpr int res_ahead(int nb, bool f32) { return nb == 2 && f32 ? 2 : 3; }
 
 template <int NB, bool kF32>
 __global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
   constexpr int NC = 16 * NB;                 // output channels of the workgroup
   constexpr int ES = kF32 ? 4 : 2;            // bytes per output
-  __shared__ uint16_t sW[27][NC][kBK + kPadK];
-  __shared__ uint4 sBr[3][kResBV * 4];
+  constexpr int A = res_ahead(NB, kF32);
+  constexpr int kRing = 8 * A + 10;           // plane slots: tiles k .. k + A
+  __shared__ uint4 sW[27][NC][4];
+  __shared__ uint4 sRing[kRing * kResPlane / 16];
   __shared__ uint4 sOut[2][128 * NC * ES / 16];  // 128 voxels x NC outputs
   __shared__ float sBias[NC];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int tx_n = (a.w + 3) >> 2, ty_n = (a.h + 3) >> 2, tz_n = (a.d + 7) >> 3;
-  const int ntiles = tx_n * ty_n * tz_n;
+  const int ncol = tx_n * ty_n;
   const int n0 = blockIdx.y * NC;
   const int ncols = min(NC, a.cout - n0);
 
   // weights and bias, once
   for (int i = tid; i < 27 * NC * 4; i += blockDim.x) {
     const int tt = i / (NC * 4), rem = i % (NC * 4);
-    const int row = rem >> 2, cc = (rem & 3) * 8;
-    *reinterpret_cast<uint4*>(&sW[tt][row][cc]) = *reinterpret_cast<const uint4*>(
-        a.bt + static_cast<int64_t>(n0 + row) * a.kpad + tt * 32 + cc);
+    const int row = rem >> 2, j = rem & 3;
+    sW[tt][row][j ^ ((row >> 2) & 3)] = *reinterpret_cast<const uint4*>(
+        a.bt + static_cast<int64_t>(n0 + row) * a.kpad + tt * 32 + j * 8);
   }
   for (int i = tid; i < NC; i += blockDim.x) sBias[i] = (a.bias && i < ncols) ? a.bias[n0 + i] : 0.f;
 
-  auto tile_origin = [&](int t, int& bx, int& by, int& bz) {
-    bx = (t % tx_n) * 4;
-    by = ((t / tx_n) % ty_n) * 4;
-    bz = (t / (tx_n * ty_n)) * 8;
-  };
-  // wave 4: the brick of tile t into buffer b (every lane one 16-byte chunk
-  // per load; chunk j of voxel v at v * 4 + j).  The chunk's offset from the
-  // brick's corner and its position are the same for every tile: computed
-  // once; tiles whose brick lies inside the volume skip the bounds checks.
-  constexpr int kLoads = (kResBV * 4 + 63) / 64;
-  int64_t rel[kLoads];
-  int pos[kLoads];  // vx | vy << 4 | vz << 8, or -1 past the brick
+  // wave 4: plane z of the column at (bx, by) into its ring slot, in three
+  // loads of 64 lanes (144 chunks: the last load has 16 lanes).  A chunk's
+  // offset and position in the plane are the same for every plane.
+  int64_t rel[3];
+  int pos[3];  // x | y << 4 of the chunk's voxel in the plane, or -1 past it
 #pragma unroll
-  for (int k = 0; k < kLoads; ++k) {
-    const int c = k * 64 + lane;  // the LDS slot this load writes
-    const int v = c >> 2, j = (c & 3) ^ ((v / 6) & 3);
-    const int vx = v % 6, vy = (v / 6) % 6, vz = v / 36;
-    rel[k] = ((static_cast<int64_t>(vz) * a.in_h + vy) * a.in_w + vx) * 32 + j * 8;
-    pos[k] = c < kResBV * 4 ? (vx | vy << 4 | vz << 8) : -1;
+  for (int k = 0; k < 3; ++k) {
+    const int c = k * 64 + lane;  // chunk slot within the plane
+    const int vp = c >> 2, y = vp / 6, x = vp % 6, j = (c & 3) ^ (y & 3);
+    rel[k] = (static_cast<int64_t>(y - 1) * a.in_w + (x - 1)) * 32 + j * 8;
+    pos[k] = c < 144 ? (x | y << 4) : -1;
   }
   const uint16_t* zero = reinterpret_cast<const uint16_t*>(g_zero16);
-  auto load_brick = [&](int t, int b) {
-    int bx, by, bz;
-    tile_origin(t, bx, by, bz);
-    const int64_t corner =
-        ((static_cast<int64_t>(bz - 1) * a.in_h + (by - 1)) * a.in_w + (bx - 1)) * 32;
-    const bool inside = bx >= 1 && by >= 1 && bz >= 1 && bx + 5 <= a.in_w &&
-                        by + 5 <= a.in_h && bz + 9 <= a.in_d;
+  auto load_plane = [&](int bx, int by, int z) {
+    const int64_t base = (static_cast<int64_t>(z) * a.in_h + by) * a.in_w * 32 +
+                         static_cast<int64_t>(bx) * 32;
+    const bool zin = z >= 0 && z < a.in_d;
+    const bool xyin = bx >= 1 && by >= 1 && bx + 5 <= a.in_w && by + 5 <= a.in_h;
+    char* slot = reinterpret_cast<char*>(sRing) + ((z + 1) % kRing) * kResPlane;
 #pragma unroll
-    for (int k = 0; k < kLoads; ++k) {
+    for (int k = 0; k < 3; ++k) {
       if (pos[k] < 0) continue;
-      bool in = inside;
-      if (!inside) {
-        const int gx = bx + (pos[k] & 15) - 1, gy = by + ((pos[k] >> 4) & 15) - 1,
-                  gz = bz + (pos[k] >> 8) - 1;
-        in = gx >= 0 && gy >= 0 && gz >= 0 && gx < a.in_w && gy < a.in_h && gz < a.in_d;
+      bool in = zin && xyin;
+      if (zin && !xyin) {
+        const int gx = bx + (pos[k] & 15) - 1, gy = by + (pos[k] >> 4) - 1;
+        in = gx >= 0 && gy >= 0 && gx < a.in_w && gy < a.in_h;
       }
-      const uint16_t* src = in ? a.x + corner + rel[k] : zero;
+      const uint16_t* src = in ? a.x + base + rel[k] : zero;
       __builtin_amdgcn_global_load_lds(
           (__attribute__((address_space(1))) void*)(src),
-          (__attribute__((address_space(3))) void*)(&sBr[b][k * 64]), 16, 0, 0);
+          (__attribute__((address_space(3))) void*)(slot + k * 1024), 16, 0, 0);
     }
   };
-  // wave 5: the outputs of tile t from sOut[b] to y
-  auto store_out = [&](int t, int b) {
-    int bx, by, bz;
-    tile_origin(t, bx, by, bz);
+  // wave 5: the outputs of the tile at (bx, by, bz) from sOut[b] to y
+  auto store_out = [&](int bx, int by, int bz, int b) {
     const char* src = reinterpret_cast<const char*>(sOut[b]);
     constexpr int row_bytes = NC * ES;  // one voxel's NC outputs in sOut
     const int out_bytes = ncols * ES;
@@ -488,89 +487,100 @@ __global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
     }
   };
 
-  const int first = blockIdx.x;
-  const int step = gridDim.x;
-  if (wave == 4) {
-    if (first < ntiles) load_brick(first, 0);
-    if (first + step < ntiles) load_brick(first + step, 1);
-    __builtin_amdgcn_s_waitcnt(0);
-  }
-  __syncthreads();
-
   const int sgn = a.geo == kConv3 ? 1 : -1;
   const int r = lane & 15;
   const int ox = r & 3, oy = r >> 2;
   const int kq = lane >> 4;  // this lane's 16-byte chunk of the 32 channels
-  int i = 0;
-  for (int t = first; t < ntiles; t += step, ++i) {
+  for (int col = blockIdx.x; col < ncol; col += gridDim.x) {
+    const int bx = (col % tx_n) * 4, by = (col / tx_n) * 4;
+    // planes -1 .. 8 min(tz_n, A): the first A tiles
     if (wave == 4) {
-      // the brick of the next tile (issued one tile ago) has arrived; the one
-      // after it goes into the buffer the compute waves finished last tile
+      const int zend = 8 * min(tz_n, A);
+      for (int z = -1; z <= zend; ++z) load_plane(bx, by, z);
       __builtin_amdgcn_s_waitcnt(0);
-      if (t + 2 * step < ntiles) load_brick(t + 2 * step, (i + 2) % 3);
-    } else if (wave == 5) {
-      if (i > 0) store_out(t - step, (i - 1) & 1);
-    } else {
-      floatx4 acc[2][NB];
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) acc[q][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-      const char* br = reinterpret_cast<const char*>(sBr[i % 3]);
-      // fragments of tap tt: B from the weights, A from the brick (voxel of
-      // row r shifted by the tap); the next tap's are read while this tap's
-      // matrix instructions run
-      auto frags = [&](int tt, bf16x8 (&bc)[NB], bf16x8 (&af)[2]) {
-        const int dz = sgn * (tt / 9 - 1), dy = sgn * ((tt / 3) % 3 - 1), dx = sgn * (tt % 3 - 1);
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-          bc[j] = *reinterpret_cast<const bf16x8*>(&sW[tt][16 * j + r][kq * 8]);
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int row = (wave * 2 + q + 1 + dz) * 6 + (oy + 1 + dy);
-          const int v = row * 6 + (ox + 1 + dx);
-          af[q] = *reinterpret_cast<const bf16x8*>(br + v * 64 + ((kq ^ (row & 3)) << 4));
-        }
-      };
-      bf16x8 bc[2][NB], af[2][2];
-      frags(0, bc[0], af[0]);
-#pragma unroll
-      for (int tt = 0; tt < 27; ++tt) {
-        const int cur = tt & 1;
-        if (tt + 1 < 27) frags(tt + 1, bc[cur ^ 1], af[cur ^ 1]);
-        __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of the MFMAs below
+    }
+    __syncthreads();
+    for (int k = 0; k < tz_n; ++k) {
+      if (wave == 4) {
+        // the eight new planes of tile k + A (their slots held planes no tile
+        // from k on needs); then wait until tile k + 1's planes have arrived:
+        // all loads but those of the tiles after it (24 per tile)
+        const int last = min(k + A, tz_n - 1);  // the newest tile loaded
+        if (k + A < tz_n)
+          for (int z = 8 * (k + A) + 1; z <= 8 * (k + A) + 8; ++z) load_plane(bx, by, z);
+        const int pending = last - (k + 1);  // tiles whose loads may stay in flight
+        if (pending >= 2)
+          __builtin_amdgcn_s_waitcnt(0xCF70);  // vmcnt(48), other counters not waited
+        else if (pending == 1)
+          __builtin_amdgcn_s_waitcnt(0x4F78);  // vmcnt(24)
+        else
+          __builtin_amdgcn_s_waitcnt(0);
+      } else if (wave == 5) {
+        if (k > 0) store_out(bx, by, 8 * (k - 1), (k - 1) & 1);
+      } else {
+        floatx4 acc[2][NB];
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
+          for (int j = 0; j < NB; ++j) acc[q][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const char* ring = reinterpret_cast<const char*>(sRing);
+        // fragments of tap tt: B from the weights, A from the planes (voxel
+        // of row r shifted by the tap); the next tap's are read while this
+        // tap's matrix instructions run
+        auto frags = [&](int tt, bf16x8 (&bc)[NB], bf16x8 (&af)[2]) {
+          const int dz = sgn * (tt / 9 - 1), dy = sgn * ((tt / 3) % 3 - 1), dx = sgn * (tt % 3 - 1);
+#pragma unroll
           for (int j = 0; j < NB; ++j)
-            acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[cur][q], bc[cur][j], acc[q][j],
-                                                                0, 0, 0);
-      }
-      // epilogue into sOut: row 4 (lane >> 4) + e of slice 2 wave + q is
-      // local voxel (x, y, z) = (rr & 3, rr >> 2, 2 wave + q)
-      char* dst = reinterpret_cast<char*>(sOut[i & 1]);
+            bc[j] = *reinterpret_cast<const bf16x8*>(&sW[tt][16 * j + r][kq ^ ((r >> 2) & 3)]);
+          const int yy = oy + 1 + dy;
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int nl = j * 16 + (lane & 15);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int rr = (lane >> 4) * 4 + e;
-            const int vl = ((wave * 2 + q) * 4 + (rr >> 2)) * 4 + (rr & 3);
-            float v = acc[q][j][e] + sBias[nl];
-            if (a.relu) v = fmaxf(v, 0.f);
-            if constexpr (kF32)
-              reinterpret_cast<float*>(dst)[vl * NC + nl] = v;
-            else
-              reinterpret_cast<uint16_t*>(dst)[vl * NC + nl] = to_bf16(v);
+          for (int q = 0; q < 2; ++q) {
+            const int zs = (8 * k + wave * 2 + q + 1 + dz) % kRing;  // plane z = 8k + zi - 1
+            af[q] = *reinterpret_cast<const bf16x8*>(
+                ring + zs * kResPlane + (yy * 6 + ox + 1 + dx) * 64 + ((kq ^ (yy & 3)) << 4));
           }
+        };
+        bf16x8 bc[2][NB], af[2][2];
+        frags(0, bc[0], af[0]);
+#pragma unroll
+        for (int tt = 0; tt < 27; ++tt) {
+          const int cur = tt & 1;
+          if (tt + 1 < 27) frags(tt + 1, bc[cur ^ 1], af[cur ^ 1]);
+          __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of the MFMAs below
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+              acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[cur][q], bc[cur][j],
+                                                                  acc[q][j], 0, 0, 0);
         }
+        // epilogue into sOut: row 4 (lane >> 4) + e of slice 2 wave + q is
+        // local voxel (x, y, z) = (rr & 3, rr >> 2, 2 wave + q)
+        char* dst = reinterpret_cast<char*>(sOut[k & 1]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const int nl = j * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int rr = (lane >> 4) * 4 + e;
+              const int vl = ((wave * 2 + q) * 4 + (rr >> 2)) * 4 + (rr & 3);
+              float v = acc[q][j][e] + sBias[nl];
+              if (a.relu) v = fmaxf(v, 0.f);
+              if constexpr (kF32)
+                reinterpret_cast<float*>(dst)[vl * NC + nl] = v;
+              else
+                reinterpret_cast<uint16_t*>(dst)[vl * NC + nl] = to_bf16(v);
+            }
+          }
+      }
+      __syncthreads();
     }
+    // the column's last tile; the ring and the output tiles are reused next
+    if (wave == 5) store_out(bx, by, 8 * (tz_n - 1), (tz_n - 1) & 1);
     __syncthreads();
   }
-  // the last tile's outputs
-  if (wave == 5 && i > 0) store_out(first + (i - 1) * step, (i - 1) & 1);
 }
 
 // ------------------------------------------ 3x3x3 conv with one gathered channel
@@ -1352,13 +1362,12 @@ bool uses_brick(const ConvArgs& a) {
 // The resident-weights kernel: 3x3x3 layers gathering exactly 32 channels,
 // without a skip input, on grids of at least kResidentTiles 4 x 4 x 8 tiles
 // (the full-resolution layers; smaller grids keep the brick kernel, whose
-// split reductions fill the chip), with FP32 outputs only for up to 16
-// output channels (its LDS holds three bricks and two output tiles).
+// split reductions fill the chip).
 constexpr int64_t kResidentTiles = 1024;
 int64_t brick_tiles(const ConvArgs& a, int mz);
 bool uses_resident(const ConvArgs& a) {
   return (a.geo == kConv3 || a.geo == kConv3T) && a.cin == 32 && !a.skip &&
-         (!a.y_f32 || a.cout <= 16) && brick_tiles(a, 2) >= kResidentTiles;
+         brick_tiles(a, 2) >= kResidentTiles;
 }
 
 // compute units of the current device (queried once)
@@ -1445,10 +1454,12 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   }
   if (uses_resident(a)) {
     const int nbr = a.cout > 16 ? 2 : 1;
-    const int64_t tiles = brick_tiles(a, 2);
-    const dim3 grid(static_cast<unsigned>(std::min<int64_t>(tiles, device_cus())),
+    const int64_t columns = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4);
+    const dim3 grid(static_cast<unsigned>(std::min<int64_t>(columns, device_cus())),
                     static_cast<unsigned>((a.cout + 16 * nbr - 1) / (16 * nbr)), 1);
-    if (nbr == 2)
+    if (nbr == 2 && a.y_f32)
+      conv3_resident_kernel<2, true><<<grid, 384, 0, s>>>(a);
+    else if (nbr == 2)
       conv3_resident_kernel<2, false><<<grid, 384, 0, s>>>(a);
     else if (a.y_f32)
       conv3_resident_kernel<1, true><<<grid, 384, 0, s>>>(a);
