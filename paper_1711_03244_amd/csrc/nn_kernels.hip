@@ -368,8 +368,8 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
 // planes of the column (6 x 6 voxels of 32 channels, z = -1 .. 8 per tile
 // count + 1) into a ring of plane slots with direct global-to-LDS loads,
 // A tiles ahead (a tile reuses two planes of the previous one and loads
-// eight; zeros outside the volume come from g_zero16); wave 5 writes
-// the previous tile's outputs from LDS to global memory.  The compute
+// eight; zeros outside the volume come from g_zero16); waves 5 and 6
+// write the previous tile's outputs from LDS to global memory.  The compute
 // waves issue no global memory operation; each data wave waits only for its
 // own transfers (the plane wave for all but the newest A - 1 tiles' loads,
 // which complete in issue order): one barrier per tile.  Plane layout: voxel
@@ -386,7 +386,7 @@ __device__ __align__(16) uint4 g_zero16[1];  // the source of the zero padding
 constexpr int res_ahead(int nb, bool f32) { return nb == 2 && f32 ? 2 : 3; }
 
 template <int NB, bool kF32>
-__global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
+__global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
   constexpr int NC = 16 * NB;                 // output channels of the workgroup
   constexpr int ES = kF32 ? 4 : 2;            // bytes per output
   constexpr int A = res_ahead(NB, kF32);
@@ -445,7 +445,9 @@ __global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
           (__attribute__((address_space(3))) void*)(slot + k * 1024), 16, 0, 0);
     }
   };
-  // wave 5: the outputs of the tile at (bx, by, bz) from sOut[b] to y
+  // waves 5 and 6: the outputs of the tile at (bx, by, bz) from sOut[b] to
+  // y, every other 64 pieces each
+  const int s0 = lane + 64 * (wave - 5);
   auto store_out = [&](int bx, int by, int bz, int b) {
     const char* src = reinterpret_cast<const char*>(sOut[b]);
     constexpr int row_bytes = NC * ES;  // one voxel's NC outputs in sOut
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
     if (ncols == NC && (a.cout * ES) % 16 == 0) {  // whole rows of 16-byte pieces
       constexpr int per = NC * ES / 16;
 #pragma unroll
-      for (int i = lane; i < 128 * per; i += 64) {
+      for (int i = s0; i < 128 * per; i += 128) {
         const int vl = i / per, k = i % per;
         const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
         if (x >= a.w || y >= a.h || z >= a.d) continue;
@@ -463,7 +465,7 @@ __global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
       }
     } else if (out_bytes % 16 == 0 && (a.cout * ES) % 16 == 0) {
       const int per = out_bytes / 16;
-      for (int i = lane; i < 128 * per; i += 64) {
+      for (int i = s0; i < 128 * per; i += 128) {
         const int vl = i / per, k = i % per;
         const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
         if (x >= a.w || y >= a.h || z >= a.d) continue;
@@ -472,7 +474,7 @@ __global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
             *reinterpret_cast<const uint4*>(src + vl * row_bytes + k * 16);
       }
     } else {
-      for (int i = lane; i < 128 * ncols; i += 64) {
+      for (int i = s0; i < 128 * ncols; i += 128) {
         const int vl = i / ncols, n = i % ncols;
         const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
         if (x >= a.w || y >= a.h || z >= a.d) continue;
@@ -515,7 +517,7 @@ __global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
           __builtin_amdgcn_s_waitcnt(0x4F78);  // vmcnt(24)
         else
           __builtin_amdgcn_s_waitcnt(0);
-      } else if (wave == 5) {
+      } else if (wave >= 5) {
         if (k > 0) store_out(bx, by, 8 * (k - 1), (k - 1) & 1);
       } else {
         floatx4 acc[2][NB];
@@ -578,7 +580,7 @@ __global__ void __launch_bounds__(384) conv3_resident_kernel(ConvArgs a) {
       __syncthreads();
     }
     // the column's last tile; the ring and the output tiles are reused next
-    if (wave == 5) store_out(bx, by, 8 * (tz_n - 1), (tz_n - 1) & 1);
+    if (wave >= 5) store_out(bx, by, 8 * (tz_n - 1), (tz_n - 1) & 1);
     __syncthreads();
   }
 }
@@ -1458,13 +1460,13 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(std::min<int64_t>(columns, device_cus())),
                     static_cast<unsigned>((a.cout + 16 * nbr - 1) / (16 * nbr)), 1);
     if (nbr == 2 && a.y_f32)
-      conv3_resident_kernel<2, true><<<grid, 384, 0, s>>>(a);
+      conv3_resident_kernel<2, true><<<grid, 448, 0, s>>>(a);
     else if (nbr == 2)
-      conv3_resident_kernel<2, false><<<grid, 384, 0, s>>>(a);
+      conv3_resident_kernel<2, false><<<grid, 448, 0, s>>>(a);
     else if (a.y_f32)
-      conv3_resident_kernel<1, true><<<grid, 384, 0, s>>>(a);
+      conv3_resident_kernel<1, true><<<grid, 448, 0, s>>>(a);
     else
-      conv3_resident_kernel<1, false><<<grid, 384, 0, s>>>(a);
+      conv3_resident_kernel<1, false><<<grid, 448, 0, s>>>(a);
     return hipGetLastError();
   }
   if (uses_brick(a)) {
