@@ -431,13 +431,46 @@ def summarise(rows, plain_photons, input_photons, batched=None) -> dict:
     return out
 
 
+def time_passes(den: nn.Denoiser, side: int, reps: int = 50, seed: int = 900001) -> dict:
+    """Kernel time (HIP events on the current stream, mean over `reps`
+    calls after three warm-up calls) of one forward pass, of the forward
+    pass averaged over the 8 x-y symmetries, and of one loss-and-gradient
+    pass, on the 1e6-photon map of a held-out volume (target: its 1e7-photon
+    map)."""
+    t = _torch()
+    p = W.denoiser_volume(seed, side)
+    x = t.as_tensor(simulate_one(p, 1e6, seed + 1)[0]).cuda()
+    y = t.as_tensor(simulate_one(p, 1e7, seed + 2)[0]).cuda()
+    out = t.empty_like(x)
+    s = t.cuda.current_stream()
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        t.cuda.synchronize()
+        e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(n):
+            fn()
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    return {"forward_ms": timed(lambda: den.forward(x, phi_out=out, stream=s), reps),
+            "forward_8_symmetries_ms": timed(
+                lambda: den.forward(x, phi_out=out, stream=s, symmetries=8), max(1, reps // 4)),
+            "loss_grad_ms": timed(lambda: den.loss_grad(x, y, want_loss=False, stream=s), reps)}
+
+
 def main(argv=None) -> dict:
     """Command line: simulate a training set, train, evaluate; prints JSON.
 
         python -m paper_1711_03244_amd.denoise [--train 64] [--steps 20000]
             [--side 64] [--inputs 1e5,1e6,1e7] [--target 1e8] [--eval 2]
             [--plain 1e9] [--ref-runs 2] [--lr 1e-3] [--batch 4] [--max-norm 0.1]
-            [--augment 1] [--batch-volumes 32]
+            [--augment 1] [--batch-volumes 32] [--train-first 1] [--init CKPT]
+            [--save CKPT]
+        python -m paper_1711_03244_amd.denoise --time-passes CKPT
     """
     import argparse
     import json
@@ -464,8 +497,17 @@ def main(argv=None) -> dict:
     ap.add_argument("--init", default=None,
                     help="start from this inference checkpoint instead of the seeded weights")
     ap.add_argument("--save", default=None, help="write an inference checkpoint here")
+    ap.add_argument("--time-passes", default=None, metavar="CHECKPOINT",
+                    help="only time forward and loss-and-gradient passes of this inference "
+                         "checkpoint (time_passes) and print them")
     a = ap.parse_args(argv)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
+    if a.time_passes:
+        with nn.Denoiser(W.DENOISER_CHANNELS, (a.side,) * 3) as d:
+            d.load_inference(a.time_passes)
+            res = time_passes(d, a.side)
+        print(json.dumps(res))
+        return res
     inputs = [float(v) for v in a.inputs.split(",")]
     ch = W.DENOISER_CHANNELS
     t0 = time.perf_counter()
