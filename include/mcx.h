@@ -167,8 +167,10 @@ typedef struct {
   int32_t reserved;
 } mcx_tune_result;
 
-/* How the transport kernel adds to the map (mcx_set_map_adds).  The map
- * holds one 64-bit integer per cell: the count of deposit units u (a power
+/* How the transport kernel adds to the map (mcx_set_map_adds): the atomic
+ * accumulation of absorbed weight into the fluence map (the paper's
+ * benchmark B2a, whose atomic operations its B2 variant removes, Fig. 2).
+ * The map holds one 64-bit integer per cell: the count of deposit units u (a power
  * of two, 2^-20 of the voxel size or just below) the cell received; every
  * cell-visit sum is rounded to whole units, so sums are exact and results
  * do not depend on the order of the additions.  MCX_MAP_ADDS_64: one 64-bit
@@ -242,8 +244,9 @@ mcx_status mcx_batch_digest(mcx_ctx *ctx, int32_t sim, double *host_out, uint64_
 mcx_status mcx_set_launch(mcx_ctx *ctx, int32_t block_size, int32_t refill_chunk,
                           int32_t lds_window_cells);
 
-/* How later launches add to the map: MCX_MAP_ADDS_AUTO (the default),
- * MCX_MAP_ADDS_64 or MCX_MAP_ADDS_32.  Only the speed changes, never a
+/* How later launches add to the map (the atomic deposit of the paper's
+ * benchmark B2a, Fig. 2): MCX_MAP_ADDS_AUTO (the default), MCX_MAP_ADDS_64
+ * or MCX_MAP_ADDS_32.  Only the speed changes, never a
  * result.  MCX_EINVAL for another value.  Waits for the stream. */
 mcx_status mcx_set_map_adds(mcx_ctx *ctx, int32_t mode);
 

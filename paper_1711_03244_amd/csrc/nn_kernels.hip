@@ -455,7 +455,8 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
     if (ncols == NC && (a.cout * ES) % 16 == 0) {  // whole rows of 16-byte pieces
       constexpr int per = NC * ES / 16;
 #pragma unroll
-      for (int i = s0; i < 128 * per; i += 128) {
+      for (int mm = 0; mm < per; ++mm) {  // 128 * per pieces, 128 per step
+        const int i = s0 + 128 * mm;
         const int vl = i / per, k = i % per;
         const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
         if (x >= a.w || y >= a.h || z >= a.d) continue;
