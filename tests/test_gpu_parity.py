@@ -342,8 +342,8 @@ def test_cube2_absorbed_difference_is_the_decoupled_photons(cube2):
 
 
 def test_cube2_absorbed_fraction_1e7():
-    """The spec bar as stated: total absorbed fraction within 1e-4
-    relative of the oracle on the same seed, asserted directly.  Run at 1e7
+    """The sphere benchmark's absorbed-fraction bar: total absorbed fraction
+    within 1e-4 relative of the oracle on the same seed, asserted directly.  Run at 1e7
     photons, where the noise of the ~4 % decoupled photons (standard error
     logged beside it) is far below the bar."""
     p = W.cube_sphere()
