@@ -21,8 +21,11 @@
 //
 // Kernels: conv_kernel is the generic implicit GEMM (every geometry);
 // 3x3x3 products get dedicated kernels that stage operands in LDS --
-// conv3_brick_kernel (a multiple of 32 gathered channels), conv3_scalar_kernel
-// (one gathered channel), wgrad_slab_kernel and wgrad_onechannel_kernel
+// conv3_resident_kernel (exactly 32 gathered channels on large grids: the
+// weights stay in LDS, input planes stream in by direct global-to-LDS
+// loads), conv3_brick_kernel (other multiples of 32 gathered channels),
+// conv3_scalar_kernel (one gathered channel), wgrad_slab_kernel and
+// wgrad_onechannel_kernel
 // (weight gradients) -- and wgrad_kernel covers the remaining weight
 // gradients.  Products that launch too few workgroups split their
 // reduction and finish in split_reduce_kernel / wgrad_reduce_kernel, which
