@@ -112,6 +112,21 @@ mcx_status mcx_nn_forward_sym(mcx_nn *nn, const float *phi_in, float *phi_out, f
 mcx_status mcx_nn_loss_grad(mcx_nn *nn, const float *phi_in, const float *phi_target,
                             int32_t accumulate, double *loss, void *hip_stream);
 
+/* Fused backward pass (on by default): where a 3x3x3 layer on a grid of
+ * at least 1024 4x4x8 tiles maps 32 channels to 32 (the full-resolution
+ * layers) and the layer below takes no skip gradient, the layer's
+ * input-gradient product also applies the ReLU mask of the layer below,
+ * rounds to BF16 and sums that layer's bias gradient per workgroup, so
+ * that the layer below's gradient is not written as FP32 and read again
+ * (the chain rule through a ReLU; the denoiser is an addition to the
+ * paper's method).  Gradients equal those of the unfused pass except for
+ * the bias gradients of the folded layers, whose FP32 sums are added in
+ * another order.  on != 0 enables it; *nfolded (may be NULL) receives the
+ * number of layers whose gradient the fold produces (0 when off).
+ * MCX_EINVAL for NULL nn.  Takes effect at the next mcx_nn_loss_grad; do
+ * not call while one runs. */
+mcx_status mcx_nn_set_fused_backward(mcx_nn *nn, int32_t on, int32_t *nfolded);
+
 /* One Adam step with learning rate lr on g = grad_scale * (current
  * gradients), with g scaled down to global L2 norm max_norm when its norm
  * is larger (max_norm <= 0: no clipping).  Async. */

@@ -33,7 +33,20 @@ struct ConvArgs {
   int32_t y_f32, relu;
   float* part;                // FP32 workspace for split reductions, or null (no split)
   int64_t part_cap;           // its size in floats
+  // An input gradient with the next step of the backward pass folded in
+  // (conv_folds_grad): when gmask is set, y receives the BF16 gradient of
+  // the layer below's pre-activation, bf16(sum * (gmask > 0)), and
+  // gpart[workgroup][cout] the per-workgroup channel sums of those BF16
+  // values (its bias gradient, for launch_bias_sums).
+  const uint16_t* gmask = nullptr;  // BF16 [out voxel][cout]: the layer below's output
+  float* gpart = nullptr;
 };
+
+// Whether launch_conv can fold the ReLU mask, BF16 rounding and bias sums
+// into this input-gradient product (see ConvArgs::gmask), and
+// the number of channel-sum rows it then writes to gpart.
+bool conv_folds_grad(const ConvArgs& a);
+int conv_fold_rows(const ConvArgs& a);
 
 // Weight gradient gw[t][ci][n] += sum_m A(m, t, ci) gy(m, n) (FP32 atomics).
 struct WgradArgs {

@@ -48,17 +48,18 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
 constexpr int kBM = 64;   // rows per workgroup tile (4 waves x 16)
 constexpr int kBK = 32;   // reduction step
 constexpr int kPadK = 8;  // LDS row padding (bf16 elements)
 
-// float -> bf16 bits, round to nearest even (NaN kept quiet)
+// float -> bf16 bits, round to nearest even: the kernels run with FP32
+// denormals kept and round-to-nearest-even, so gfx950's conversion
+// instruction gives exactly that rounding, denormals included (NaN stays NaN)
 __device__ __forceinline__ uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f));
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
@@ -384,15 +385,47 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
 constexpr int kResPlane = 36 * 64;  // bytes per plane slot
 __device__ __align__(16) uint4 g_zero16[1];  // the source of the zero padding
 
+// Byte offset of byte `byte` of local voxel vl's outputs in an output tile
+// of the resident kernel (rows of NB 16 outputs of ES bytes).  For NB == 2
+// the rows and 16-byte chunks are permuted within each group of 16 voxels
+// by g = (vl >> 2) & 3, the group of lanes that writes them in the
+// epilogue (lanes 16 g .. 16 g + 15), so that each epilogue write
+// instruction hits 64 different banks: BF16 rows (64 bytes) go to row
+// vl ^ g with the two 32-byte halves swapped for odd g; FP32 rows (128
+// bytes) to row vl ^ (g >> 1) with the halves swapped for odd g.
+template <int NB, int ES>
+__device__ __forceinline__ int sout_off(int vl, int byte) {
+  if constexpr (NB != 2) {
+    return vl * (16 * NB * ES) + byte;
+  } else {
+    const int g = (vl >> 2) & 3;
+    if constexpr (ES == 2)
+      return (vl ^ g) * 64 + (byte ^ ((g & 1) << 5));
+    else
+      return (vl ^ (g >> 1)) * 128 + (byte ^ ((g & 1) << 6));
+  }
+}
+
+// Makes the compiler produce v here (an empty instruction that takes it as
+// input): loads of values used only under a condition are otherwise moved
+// into the conditional code, one load and one wait at a time.
+__device__ __forceinline__ void pin(const uint4& v) {
+  asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+
 // tiles of planes in flight: all that fit in LDS beside the weights and
 // two output tiles (three, or two for 32 FP32 output columns)
 constexpr int res_ahead(int nb, bool f32) { return nb == 2 && f32 ? 2 : 3; }
 
-template <int NB, bool kF32>
+// kGrad: an input gradient with the next backward step folded in
+// (ConvArgs::gmask): the compute waves leave FP32 sums in LDS, the output
+// waves apply the ReLU mask, round to BF16, store, and sum each channel's
+// BF16 values; the workgroup's sums go to gpart.
+template <int NB, bool kF32, bool kGrad>
 __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
   constexpr int NC = 16 * NB;                 // output channels of the workgroup
-  constexpr int ES = kF32 ? 4 : 2;            // bytes per output
-  constexpr int A = res_ahead(NB, kF32);
+  constexpr int ES = kF32 || kGrad ? 4 : 2;   // bytes per output in LDS
+  constexpr int A = res_ahead(NB, kF32 || kGrad);
   constexpr int kRing = 8 * A + 10;           // plane slots: tiles k .. k + A
   __shared__ uint4 sW[27][NC][4];
   __shared__ uint4 sRing[kRing * kResPlane / 16];
@@ -406,12 +439,24 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
   const int n0 = blockIdx.y * NC;
   const int ncols = min(NC, a.cout - n0);
 
-  // weights and bias, once
-  for (int i = tid; i < 27 * NC * 4; i += blockDim.x) {
-    const int tt = i / (NC * 4), rem = i % (NC * 4);
-    const int row = rem >> 2, j = rem & 3;
-    sW[tt][row][j ^ ((row >> 2) & 3)] = *reinterpret_cast<const uint4*>(
-        a.bt + static_cast<int64_t>(n0 + row) * a.kpad + tt * 32 + j * 8);
+  // weights and bias, once.  The weights by direct global-to-LDS loads of
+  // 64 slots (1 KB) each, all in flight together, from every wave but the
+  // plane wave (which starts on the first column's planes meanwhile): lane
+  // L of block bl fills slot 64 bl + L, i.e. row (16 bl + L / 4) of the
+  // flattened [27][NC] rows, chunk slot L % 4, with the chunk
+  // (L % 4) ^ ((row >> 2) & 3) of that row.
+  if (wave != 4) {
+    const int w6 = wave < 4 ? wave : wave - 1;
+    for (int bl = w6; bl < 27 * NC / 16; bl += 6) {
+      const int fr = 16 * bl + (lane >> 2), tt = fr / NC, row = fr % NC;
+      const int j = (lane & 3) ^ ((row >> 2) & 3);
+      __builtin_amdgcn_global_load_lds(
+          (__attribute__((address_space(1))) void*)(a.bt + static_cast<int64_t>(n0 + row) * a.kpad +
+                                                     tt * 32 + j * 8),
+          (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(sW) + bl * 1024), 16, 0,
+          0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's weight transfers have landed
   }
   for (int i = tid; i < NC; i += blockDim.x) sBias[i] = (a.bias && i < ncols) ? a.bias[n0 + i] : 0.f;
 
@@ -451,12 +496,78 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
   // waves 5 and 6: the outputs of the tile at (bx, by, bz) from sOut[b] to
   // y, every other 64 pieces each
   const int s0 = lane + 64 * (wave - 5);
+  // kGrad: this lane's channel sums, and the ReLU mask of its pieces of
+  // the next tile to store (loaded a tile ahead: the output path is the
+  // kernel's bound)
+  constexpr int kGP = NC * 2 / 16;  // 16-byte BF16 pieces per voxel
+  float gsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  uint4 gm[kGP];
+  auto piece = [&](int bx, int by, int bz, int mm, int64_t& e0) {
+    const int i = s0 + 128 * mm;
+    const int vl = i / kGP, k = i % kGP;
+    const int x = bx + (vl & 3), y = by + ((vl >> 2) & 3), z = bz + (vl >> 4);
+    e0 = ((static_cast<int64_t>(z) * a.h + y) * a.w + x) * a.cout + n0 + k * 8;
+    return x < a.w && y < a.h && z < a.d;
+  };
+  auto load_mask = [&](int bx, int by, int bz) {
+#pragma unroll
+    for (int mm = 0; mm < kGP; ++mm) {
+      int64_t e0;
+      gm[mm] = piece(bx, by, bz, mm, e0) ? *reinterpret_cast<const uint4*>(a.gmask + e0)
+                                          : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
   auto store_out = [&](int bx, int by, int bz, int b) {
     const char* src = reinterpret_cast<const char*>(sOut[b]);
-    constexpr int row_bytes = NC * ES;  // one voxel's NC outputs in sOut
+    if constexpr (kGrad) {
+      // 16-byte BF16 pieces of 8 channels (NC == cout): a lane always has
+      // channels 8 (lane % 4) .. + 7; their FP32 sums (32 bytes at byte 32 i
+      // of the tile for piece i) are read from LDS first
+      float fv[kGP][8];
+#pragma unroll
+      for (int mm = 0; mm < kGP; ++mm) {
+        const int i = s0 + 128 * mm;  // piece i: voxel i / kGP, channels 8 (i % kGP) ..
+        const uint4* q = reinterpret_cast<const uint4*>(src + sout_off<NB, 4>(i / kGP, (i % kGP) * 32));
+        *reinterpret_cast<uint4*>(&fv[mm][0]) = q[0];
+        *reinterpret_cast<uint4*>(&fv[mm][4]) = q[1];
+      }
+#pragma unroll
+      for (int mm = 0; mm < kGP; ++mm) {
+        pin(*reinterpret_cast<uint4*>(&fv[mm][0]));
+        pin(*reinterpret_cast<uint4*>(&fv[mm][4]));
+      }
+#pragma unroll
+      for (int mm = 0; mm < kGP; ++mm) {
+        int64_t e0;
+        if (!piece(bx, by, bz, mm, e0)) continue;
+        const float* f = fv[mm];
+        const uint16_t* mh = reinterpret_cast<const uint16_t*>(&gm[mm]);
+        uint4 o;
+        uint16_t* oh = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          float v = f[j];
+          if (!(from_bf16(mh[j]) > 0.f)) v = 0.f;
+          oh[j] = to_bf16(v);
+          gsum[j] += from_bf16(oh[j]);
+        }
+        *reinterpret_cast<uint4*>(static_cast<uint16_t*>(a.y) + e0) = o;
+      }
+      return;
+    }
     const int out_bytes = ncols * ES;
     if (ncols == NC && (a.cout * ES) % 16 == 0) {  // whole rows of 16-byte pieces
       constexpr int per = NC * ES / 16;
+      // all of this lane's pieces from LDS first: one wait for the LDS
+      // reads (which queue behind the compute waves' fragment reads), not
+      // one per piece
+      uint4 v[per];
+#pragma unroll
+      for (int mm = 0; mm < per; ++mm)  // piece i = s0 + 128 mm at byte 16 i of the tile
+        v[mm] = *reinterpret_cast<const uint4*>(
+            src + sout_off<NB, ES>((s0 + 128 * mm) / per, (s0 + 128 * mm) % per * 16));
+#pragma unroll
+      for (int mm = 0; mm < per; ++mm) pin(v[mm]);
 #pragma unroll
       for (int mm = 0; mm < per; ++mm) {  // 128 * per pieces, 128 per step
         const int i = s0 + 128 * mm;
@@ -465,7 +576,7 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
         if (x >= a.w || y >= a.h || z >= a.d) continue;
         const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
         *reinterpret_cast<uint4*>(static_cast<char*>(a.y) + (o * a.cout + n0) * ES + k * 16) =
-            *reinterpret_cast<const uint4*>(src + vl * row_bytes + k * 16);
+            v[mm];
       }
     } else if (out_bytes % 16 == 0 && (a.cout * ES) % 16 == 0) {
       const int per = out_bytes / 16;
@@ -475,7 +586,7 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
         if (x >= a.w || y >= a.h || z >= a.d) continue;
         const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
         *reinterpret_cast<uint4*>(static_cast<char*>(a.y) + (o * a.cout + n0) * ES + k * 16) =
-            *reinterpret_cast<const uint4*>(src + vl * row_bytes + k * 16);
+            *reinterpret_cast<const uint4*>(src + sout_off<NB, ES>(vl, k * 16));
       }
     } else {
       for (int i = s0; i < 128 * ncols; i += 128) {
@@ -485,10 +596,10 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
         const int64_t o = (static_cast<int64_t>(z) * a.h + y) * a.w + x;
         if constexpr (kF32)
           static_cast<float*>(a.y)[o * a.cout + n0 + n] =
-              reinterpret_cast<const float*>(src + vl * row_bytes)[n];
+              *reinterpret_cast<const float*>(src + sout_off<NB, ES>(vl, n * 4));
         else
           static_cast<uint16_t*>(a.y)[o * a.cout + n0 + n] =
-              reinterpret_cast<const uint16_t*>(src + vl * row_bytes)[n];
+              *reinterpret_cast<const uint16_t*>(src + sout_off<NB, ES>(vl, n * 2));
       }
     }
   };
@@ -499,11 +610,18 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
   const int kq = lane >> 4;  // this lane's 16-byte chunk of the 32 channels
   for (int col = blockIdx.x; col < ncol; col += gridDim.x) {
     const int bx = (col % tx_n) * 4, by = (col / tx_n) * 4;
-    // planes -1 .. 8 min(tz_n, A): the first A tiles
+    // planes -1 .. 8 min(tz_n, A): the first A tiles; wait for tile 0's
+    // (all loads but those of the tiles after it, 24 per tile)
     if (wave == 4) {
       const int zend = 8 * min(tz_n, A);
       for (int z = -1; z <= zend; ++z) load_plane(bx, by, z);
-      __builtin_amdgcn_s_waitcnt(0);
+      const int pending = min(tz_n, A) - 1;
+      if (pending >= 2)
+        __builtin_amdgcn_s_waitcnt(0xCF70);  // vmcnt(48), other counters not waited
+      else if (pending == 1)
+        __builtin_amdgcn_s_waitcnt(0x4F78);  // vmcnt(24)
+      else
+        __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
     for (int k = 0; k < tz_n; ++k) {
@@ -523,6 +641,7 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
           __builtin_amdgcn_s_waitcnt(0);
       } else if (wave >= 5) {
         if (k > 0) store_out(bx, by, 8 * (k - 1), (k - 1) & 1);
+        if constexpr (kGrad) load_mask(bx, by, 8 * k);  // for the store of tile k
       } else {
         floatx4 acc[2][NB];
 #pragma unroll
@@ -568,16 +687,33 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
 #pragma unroll
           for (int j = 0; j < NB; ++j) {
             const int nl = j * 16 + (lane & 15);
+            const int vl0 = ((wave * 2 + q) * 4 + (lane >> 4)) * 4;  // the voxel of e = 0
+            float v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const int rr = (lane >> 4) * 4 + e;
-              const int vl = ((wave * 2 + q) * 4 + (rr >> 2)) * 4 + (rr & 3);
-              float v = acc[q][j][e] + sBias[nl];
-              if (a.relu) v = fmaxf(v, 0.f);
-              if constexpr (kF32)
-                reinterpret_cast<float*>(dst)[vl * NC + nl] = v;
-              else
-                reinterpret_cast<uint16_t*>(dst)[vl * NC + nl] = to_bf16(v);
+              v[e] = acc[q][j][e] + sBias[nl];
+              if (a.relu) v[e] = fmaxf(v[e], 0.f);
+            }
+            if constexpr (kF32 || kGrad) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                *reinterpret_cast<float*>(dst + sout_off<NB, 4>(vl0 + e, nl * 4)) = v[e];
+            } else {
+              // two adjacent channels of one voxel per 32-bit write: lanes
+              // 2m and 2m + 1 (channels nl, nl + 1) swap one value, the even
+              // lane then holds voxel e0's pair, the odd lane voxel e0 + 1's
+              const bool odd = lane & 1;
+#pragma unroll
+              for (int e0 = 0; e0 < 4; e0 += 2) {
+                const float send = odd ? v[e0] : v[e0 + 1];
+                const float recv = __int_as_float(
+                    __builtin_amdgcn_mov_dpp(__float_as_int(send), 0xB1, 0xF, 0xF, false));  // quad_perm 1,0,3,2
+                floatx2 pr;
+                pr.x = odd ? recv : v[e0];
+                pr.y = odd ? v[e0 + 1] : recv;
+                *reinterpret_cast<uint32_t*>(dst + sout_off<NB, 2>(vl0 + e0 + (odd ? 1 : 0), (nl & ~1) * 2)) =
+                    __builtin_bit_cast(uint32_t, __builtin_convertvector(pr, bf16x2v));
+              }
             }
           }
       }
@@ -586,6 +722,21 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
     // the column's last tile; the ring and the output tiles are reused next
     if (wave >= 5) store_out(bx, by, 8 * (tz_n - 1), (tz_n - 1) & 1);
     __syncthreads();
+  }
+  if constexpr (kGrad) {
+    // the workgroup's channel sums, added in a fixed order
+    __shared__ float sRed[2][64][8];
+    if (wave >= 5)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sRed[wave - 5][lane][j] = gsum[j];
+    __syncthreads();
+    if (tid < NC) {
+      const int k = tid >> 3, j = tid & 7;
+      float sum = 0.f;
+      for (int w = 0; w < 2; ++w)
+        for (int l = k; l < 64; l += 4) sum += sRed[w][l][j];
+      a.gpart[static_cast<int64_t>(blockIdx.x) * a.cout + n0 + tid] = sum;
+    }
   }
 }
 
@@ -1376,6 +1527,11 @@ bool uses_resident(const ConvArgs& a) {
          brick_tiles(a, 2) >= kResidentTiles;
 }
 
+// 4 x 4 columns of the grid, each a workgroup's unit of work
+int64_t resident_columns(const ConvArgs& a) {
+  return static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4);
+}
+
 // compute units of the current device (queried once)
 int device_cus() {
   static int cus = [] {
@@ -1420,6 +1576,16 @@ int brick_splits(const ConvArgs& a, int64_t cap) {
 
 }  // namespace
 
+// the folded input gradient: resident-weights kConv3T products of 32
+// channels to 32, without bias or ReLU of their own
+bool conv_folds_grad(const ConvArgs& a) {
+  return a.geo == kConv3T && uses_resident(a) && a.cout == 32 && !a.bias && !a.relu && !a.y_f32;
+}
+
+int conv_fold_rows(const ConvArgs& a) {
+  return static_cast<int>(std::min<int64_t>(resident_columns(a), device_cus()));
+}
+
 // splits of the generic kernel's reduction for kDown products (the other
 // geometries are not split): for launches of fewer than two workgroups per
 // CU, enough to fill the chip, at least one stage of 128 per split, within
@@ -1458,19 +1624,21 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
       conv3_scalar_kernel<1><<<grid, 256, 0, s>>>(a);
     return hipGetLastError();
   }
+  if (a.gmask && (!conv_folds_grad(a) || !a.gpart)) return hipErrorInvalidValue;
   if (uses_resident(a)) {
     const int nbr = a.cout > 16 ? 2 : 1;
-    const int64_t columns = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4);
-    const dim3 grid(static_cast<unsigned>(std::min<int64_t>(columns, device_cus())),
+    const dim3 grid(static_cast<unsigned>(std::min<int64_t>(resident_columns(a), device_cus())),
                     static_cast<unsigned>((a.cout + 16 * nbr - 1) / (16 * nbr)), 1);
-    if (nbr == 2 && a.y_f32)
-      conv3_resident_kernel<2, true><<<grid, 448, 0, s>>>(a);
+    if (a.gmask)  // conv_folds_grad: 32 output channels, BF16
+      conv3_resident_kernel<2, false, true><<<grid, 448, 0, s>>>(a);
+    else if (nbr == 2 && a.y_f32)
+      conv3_resident_kernel<2, true, false><<<grid, 448, 0, s>>>(a);
     else if (nbr == 2)
-      conv3_resident_kernel<2, false><<<grid, 448, 0, s>>>(a);
+      conv3_resident_kernel<2, false, false><<<grid, 448, 0, s>>>(a);
     else if (a.y_f32)
-      conv3_resident_kernel<1, true><<<grid, 448, 0, s>>>(a);
+      conv3_resident_kernel<1, true, false><<<grid, 448, 0, s>>>(a);
     else
-      conv3_resident_kernel<1, false><<<grid, 448, 0, s>>>(a);
+      conv3_resident_kernel<1, false, false><<<grid, 448, 0, s>>>(a);
     return hipGetLastError();
   }
   if (uses_brick(a)) {

@@ -222,13 +222,19 @@ struct mcx_nn {
   float* gout = nullptr;     // loss gradient
   float* gx = nullptr;       // FP32 input-gradient scratch
   uint16_t* g16 = nullptr;   // BF16 gradient scratch
+  uint16_t* g16b = nullptr;  // and a second one, for folded input gradients
   std::vector<uint16_t*> skip_grad;  // per level 0..L-2
   double* acc = nullptr;
   float* phimax = nullptr;
   float* bias_partial = nullptr;  // per-block channel sums of the bias gradients, per layer
   std::vector<int64_t> bias_off;  // each layer's region of bias_partial
   BiasJob* bias_jobs = nullptr;   // device table of the deferred bias sums
+  BiasJob* bias_jobs_fold = nullptr;  // the same with the folded layers' sums
   int nbias_jobs = 0, bias_channels = 0;
+  // fold[i]: layer i's output gradient comes from layer i + 1's input-gradient
+  // product with the ReLU mask and bias sums folded in
+  std::vector<char> fold;
+  bool fuse = true;                // use the folds
   double* norm_partial = nullptr; // per-block sums of squares of the gradients
   float* part = nullptr;          // split-reduction workspace of the convolutions
   int64_t part_cap = 0;           // its size in floats
@@ -297,26 +303,55 @@ mcx_status run_forward(mcx_nn* nn, const float* phi_in, hipStream_t s) {
   return MCX_OK;
 }
 
+// the gradient of layer i's output skip connection, or null
+const uint16_t* skip_gradient(const mcx_nn* nn, const Layer& L) {
+  return (L.skip_level >= 0 && L.skip_level < nn->L - 1) ? nn->skip_grad[L.skip_level] : nullptr;
+}
+
+// layer i + 1's input-gradient product with layer i's output-gradient step
+// folded in (mcx_nn::fold), from gy of layer i + 1 into gy of layer i
+ConvArgs fold_args(const mcx_nn* nn, size_t i, const uint16_t* gy_next, uint16_t* gy) {
+  ConvArgs a = dgrad_args(nn->layers[i + 1], gy_next, nullptr);
+  a.y = gy;
+  a.y_f32 = 0;
+  a.gmask = nn->layers[i].act;
+  a.gpart = nn->bias_partial + nn->bias_off[i];
+  return a;
+}
+
 mcx_status run_backward(mcx_nn* nn, bool accumulate, hipStream_t s) {
   const size_t last = nn->layers.size() - 1;
   if (!accumulate) NN_HIP(launch_fill(nn->grads, static_cast<int64_t>(nn->nparam), 0.f, s));
   const float* g = nn->gout;
+  uint16_t* gy_folded = nullptr;  // the gradient the last product folded, or null
   for (size_t k = 0; k <= last; ++k) {
     const size_t i = last - k;
     const Layer& L = nn->layers[i];
     const int64_t nout = L.out.vox() * L.cout;
     // gradient of this layer's output, masked by its ReLU, as BF16
     uint16_t* gy = nn->g16;
-    if (L.kind == MCX_NN_UP) gy = nn->skip_grad[L.up_level];  // also the skip's gradient
-    const uint16_t* skip = (L.skip_level >= 0 && L.skip_level < nn->L - 1)
-                               ? nn->skip_grad[L.skip_level] : nullptr;
-    NN_HIP(launch_relu_grad_deferred(g, skip, i == last ? nullptr : L.act, nout, L.cout, gy,
-                                     nn->grads + L.boff, nn->bias_partial + nn->bias_off[i], s));
+    if (gy_folded) {
+      gy = gy_folded;
+    } else {
+      if (L.kind == MCX_NN_UP) gy = nn->skip_grad[L.up_level];  // also the skip's gradient
+      NN_HIP(launch_relu_grad_deferred(g, skip_gradient(nn, L), i == last ? nullptr : L.act, nout,
+                                       L.cout, gy, nn->grads + L.boff,
+                                       nn->bias_partial + nn->bias_off[i], s));
+    }
     WgradArgs wa = wgrad_args(L, layer_input(nn, i), gy, nn->grads + L.woff);
     wa.part = nn->part;
     wa.part_cap = nn->part_cap;
     NN_HIP(launch_wgrad(wa, s));
-    if (i > 0) {
+    gy_folded = nullptr;
+    if (i > 0 && nn->fuse && nn->fold[i - 1]) {
+      // into the up layer's skip gradient, or the BF16 buffer gy is not in
+      const Layer& B = nn->layers[i - 1];
+      uint16_t* dst = B.kind == MCX_NN_UP ? nn->skip_grad[B.up_level]
+                                          : (gy == nn->g16 ? nn->g16b : nn->g16);
+      ConvArgs a = fold_args(nn, i - 1, gy, dst);
+      NN_HIP(launch_conv(a, s));
+      gy_folded = dst;
+    } else if (i > 0) {
       ConvArgs a = dgrad_args(L, gy, nn->gx);
       a.part = nn->part;
       a.part_cap = nn->part_cap;
@@ -325,8 +360,8 @@ mcx_status run_backward(mcx_nn* nn, bool accumulate, hipStream_t s) {
     }
   }
   // the bias gradients of every layer whose sums were deferred, in one launch
-  NN_HIP(launch_bias_sums(nn->bias_jobs, nn->nbias_jobs, nn->bias_channels, nn->bias_partial,
-                          nn->grads, s));
+  NN_HIP(launch_bias_sums(nn->fuse ? nn->bias_jobs_fold : nn->bias_jobs, nn->nbias_jobs,
+                          nn->bias_channels, nn->bias_partial, nn->grads, s));
   return MCX_OK;
 }
 
@@ -414,22 +449,44 @@ mcx_status mcx_nn_create(const int32_t* channels, int32_t nlevels, int32_t nx, i
     for (int l = 0; l + 1 < L; ++l)
       NN_TRY(nn_alloc(nn, &nn->skip_grad[l], static_cast<size_t>(level(l).vox() * c[l])));
     NN_TRY(nn_alloc(nn, &nn->acc, 2));
-    std::vector<BiasJob> jobs;
+    // the folds: layers with a deferred bias sum and no skip gradient whose
+    // output gradient the next layer's input-gradient product can produce
+    const size_t nl = nn->layers.size();
+    nn->fold.assign(nl, 0);
+    bool any_fold = false;
+    for (size_t i = 0; i + 1 < nl; ++i) {
+      if (!relu_grad_defers(nn->layers[i].cout) || skip_gradient(nn, nn->layers[i])) continue;
+      ConvArgs a = dgrad_args(nn->layers[i + 1], nullptr, nullptr);
+      a.y_f32 = 0;
+      nn->fold[i] = conv_folds_grad(a) ? 1 : 0;
+      any_fold = any_fold || nn->fold[i];
+    }
+    if (any_fold) NN_TRY(nn_alloc(nn, &nn->g16b, max_act));
+    // each layer's partial sums take the rows of either producer
+    std::vector<BiasJob> jobs, jobs_fold;
     int64_t bias_floats = 0;
-    for (const Layer& Ly : nn->layers) {
+    for (size_t i = 0; i < nl; ++i) {
+      const Layer& Ly = nn->layers[i];
       nn->bias_off.push_back(bias_floats);
       if (!relu_grad_defers(Ly.cout)) continue;
       const int blocks = relu_grad_blocks(Ly.out.vox() * Ly.cout);
+      const int fblocks = nn->fold[i] ? conv_fold_rows(dgrad_args(nn->layers[i + 1], nullptr, nullptr))
+                                      : blocks;
       jobs.push_back(BiasJob{bias_floats, static_cast<int64_t>(Ly.boff), blocks, Ly.cout});
-      bias_floats += static_cast<int64_t>(blocks) * Ly.cout;
+      jobs_fold.push_back(BiasJob{bias_floats, static_cast<int64_t>(Ly.boff), fblocks, Ly.cout});
+      bias_floats += static_cast<int64_t>(std::max(blocks, fblocks)) * Ly.cout;
       nn->bias_channels += Ly.cout;
     }
     NN_TRY(nn_alloc(nn, &nn->bias_partial, static_cast<size_t>(std::max<int64_t>(bias_floats, 1))));
     nn->nbias_jobs = static_cast<int>(jobs.size());
     NN_TRY(nn_alloc(nn, &nn->bias_jobs, jobs.size()));
-    if (!jobs.empty())
+    NN_TRY(nn_alloc(nn, &nn->bias_jobs_fold, jobs.size()));
+    if (!jobs.empty()) {
       NN_HIP(hipMemcpy(nn->bias_jobs, jobs.data(), jobs.size() * sizeof(BiasJob),
                        hipMemcpyHostToDevice));
+      NN_HIP(hipMemcpy(nn->bias_jobs_fold, jobs_fold.data(), jobs.size() * sizeof(BiasJob),
+                       hipMemcpyHostToDevice));
+    }
     NN_TRY(nn_alloc(nn, &nn->norm_partial, static_cast<size_t>(kNormBlocks)));
     NN_TRY(nn_alloc(nn, &nn->phimax, 1));
     for (const Layer& Ly : nn->layers) {
@@ -567,6 +624,17 @@ mcx_status mcx_nn_loss_grad(mcx_nn* nn, const float* phi_in, const float* phi_ta
     NN_HIP(hipMemcpyAsync(acc, nn->acc, sizeof(acc), hipMemcpyDeviceToHost, s));
     NN_HIP(hipStreamSynchronize(s));
     *loss = acc[1] > 0 ? acc[0] / acc[1] : 0.0;
+  }
+  return MCX_OK;
+}
+
+mcx_status mcx_nn_set_fused_backward(mcx_nn* nn, int32_t on, int32_t* nfolded) {
+  if (!nn) return nfail(MCX_EINVAL, "network is NULL");
+  nn->fuse = on != 0;
+  if (nfolded) {
+    int32_t n = 0;
+    for (char f : nn->fold) n += f ? 1 : 0;
+    *nfolded = nn->fuse ? n : 0;
   }
   return MCX_OK;
 }

@@ -435,8 +435,8 @@ def time_passes(den: nn.Denoiser, side: int, reps: int = 50, seed: int = 900001)
     """Kernel time (HIP events on the current stream, mean over `reps`
     calls after three warm-up calls) of one forward pass, of the forward
     pass averaged over the 8 x-y symmetries, and of one loss-and-gradient
-    pass, on the 1e6-photon map of a held-out volume (target: its 1e7-photon
-    map)."""
+    pass (fused backward, and without the fusion), on the 1e6-photon map of
+    a held-out volume (target: its 1e7-photon map)."""
     t = _torch()
     p = W.denoiser_volume(seed, side)
     x = t.as_tensor(simulate_one(p, 1e6, seed + 1)[0]).cuda()
@@ -456,10 +456,14 @@ def time_passes(den: nn.Denoiser, side: int, reps: int = 50, seed: int = 900001)
         e1.synchronize()
         return e0.elapsed_time(e1) / n
 
-    return {"forward_ms": timed(lambda: den.forward(x, phi_out=out, stream=s), reps),
-            "forward_8_symmetries_ms": timed(
-                lambda: den.forward(x, phi_out=out, stream=s, symmetries=8), max(1, reps // 4)),
-            "loss_grad_ms": timed(lambda: den.loss_grad(x, y, want_loss=False, stream=s), reps)}
+    r = {"forward_ms": timed(lambda: den.forward(x, phi_out=out, stream=s), reps),
+         "forward_8_symmetries_ms": timed(
+             lambda: den.forward(x, phi_out=out, stream=s, symmetries=8), max(1, reps // 4))}
+    for fused in (False, True):
+        den.set_fused_backward(fused)
+        key = "loss_grad_ms" if fused else "loss_grad_unfused_ms"
+        r[key] = timed(lambda: den.loss_grad(x, y, want_loss=False, stream=s), reps)
+    return r
 
 
 def main(argv=None) -> dict:

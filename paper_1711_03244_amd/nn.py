@@ -16,7 +16,7 @@ from . import mcx
 EXPORTS = ["mcx_nn_create", "mcx_nn_destroy", "mcx_nn_param_count", "mcx_nn_set_params",
            "mcx_nn_get_params", "mcx_nn_get_grads", "mcx_nn_get_adam", "mcx_nn_set_adam",
            "mcx_nn_forward", "mcx_nn_forward_sym", "mcx_nn_loss_grad",
-           "mcx_nn_adam", "mcx_nn_train_step", "mcx_nn_mirror_xy", "mcx_nn_layer_forward",
+           "mcx_nn_set_fused_backward", "mcx_nn_adam", "mcx_nn_train_step", "mcx_nn_mirror_xy", "mcx_nn_layer_forward",
            "mcx_nn_layer_backward"]
 
 MCX_NN_CONV3, MCX_NN_DOWN, MCX_NN_UP = 0, 1, 2
@@ -41,6 +41,7 @@ def lib() -> C.CDLL:
             "mcx_nn_forward": (C.c_int, [vp, vp, vp, vp, vp]),
             "mcx_nn_forward_sym": (C.c_int, [vp, vp, vp, vp, i32, vp]),
             "mcx_nn_loss_grad": (C.c_int, [vp, vp, vp, i32, C.POINTER(C.c_double), vp]),
+            "mcx_nn_set_fused_backward": (C.c_int, [vp, i32, C.POINTER(i32)]),
             "mcx_nn_adam": (C.c_int, [vp, f32, f32, f32, vp]),
             "mcx_nn_train_step": (C.c_int, [vp, vp, vp, f32, C.POINTER(C.c_double), vp]),
             "mcx_nn_mirror_xy": (C.c_int, [vp, vp, i32, i32, i32, i32, vp]),
@@ -138,6 +139,13 @@ def mcx_nn_loss_grad(h, phi_in, phi_target, want_loss=True, stream=None,
     mcx._check(lib().mcx_nn_loss_grad(h, _ptr(phi_in), _ptr(phi_target), int(bool(accumulate)),
                                       C.byref(loss) if want_loss else None, _stream(stream)))
     return loss.value if want_loss else None
+
+
+def mcx_nn_set_fused_backward(h, on: bool) -> int:
+    """Switch the fused backward pass; returns the number of folded layers."""
+    n = C.c_int32()
+    mcx._check(lib().mcx_nn_set_fused_backward(h, int(bool(on)), C.byref(n)))
+    return n.value
 
 
 def mcx_nn_adam(h, lr: float, grad_scale: float = 1.0, max_norm: float = 0.0, stream=None):
@@ -289,6 +297,9 @@ class Denoiser:
     def loss_grad(self, phi_in, phi_target, want_loss=True, stream=None, accumulate=False):
         return mcx_nn_loss_grad(self.h, self._vol(phi_in), self._vol(phi_target), want_loss, stream,
                                 accumulate)
+
+    def set_fused_backward(self, on: bool) -> int:
+        return mcx_nn_set_fused_backward(self.h, on)
 
     def adam(self, lr, grad_scale=1.0, max_norm=0.0, stream=None):
         mcx_nn_adam(self.h, lr, grad_scale, max_norm, stream)

@@ -195,6 +195,7 @@ def test_denoiser_arguments_checked_before_the_gpu():
                                   None, None) == mcx.MCX_EINVAL
     assert "even" in mcx.mcx_last_error()
     assert L.mcx_nn_param_count(None) == 0
+    assert L.mcx_nn_set_fused_backward(None, 1, None) == mcx.MCX_EINVAL
     # augmentation op (fake addresses: the checks run before any HIP call)
     a, b = C.c_void_p(4096), C.c_void_p(8192)
     assert L.mcx_nn_mirror_xy(a, a, 4, 4, 4, 1, None) == mcx.MCX_EINVAL

@@ -284,6 +284,62 @@ def test_network_64cube_every_layer_backward_on_the_chains_operands():
             assert np.all(d <= 1e-5 * sc + 1e-30), (name, what)
 
 
+def test_fused_backward_gives_the_unfused_gradients():
+    """The (32, 64, 128, 256) network on a 64^3 volume: with the fused
+    backward pass the 64^3 layers' input-gradient products apply the ReLU
+    mask, round to BF16 and sum the bias gradient of the layer below.  The
+    BF16 gradients are then the same values (the same FP32 sums, masked
+    and rounded the same way), so every 3x3x3 layer's weight gradient
+    (summed in a fixed order) and every bias gradient outside the folded
+    layers must be the same bits.  The down and up layers' weight gradients
+    are summed with FP32 atomics, in an order that changes from call to
+    call (within 1e-5 of the layer's largest); a folded layer's bias
+    gradient sums its values in another order (within 1e-3 of the layer's
+    largest, FP32 accumulation over 64^3 voxels)."""
+    t = torch()
+    channels, shape = W.DENOISER_CHANNELS, (64, 64, 64)
+    ws, flat = make_net(channels, shape, 21)
+    noisy, clean = fluence_pair(shape, 22)
+    x, y = dev_f32(noisy), dev_f32(clean)
+    folded = {"in", "up0"}  # the layers below the two 64^3 32 -> 32 layers (enc0, dec0)
+
+    def compare(g1, g0, fold):
+        off, seen = 0, set()
+        for name, kind, ci, co in O.layers(channels):
+            n = TAPS[kind] * ci * co
+            w1, w0 = g1[off:off + n], g0[off:off + n]
+            if kind == "conv3":
+                assert np.array_equal(w1, w0), name
+            else:
+                assert np.abs(w1 - w0).max() <= 1e-5 * np.abs(w0).max(), name
+            b1, b0 = g1[off + n:off + n + co], g0[off + n:off + n + co]
+            if fold and name in folded:
+                seen.add(name)
+                err = np.abs(b1 - b0).max() / (np.abs(b0).max() + 1e-30)
+                print(f"  {name}: bias gradient max difference {err:.2e} of the largest", flush=True)
+                assert err <= 1e-3, name
+            else:
+                assert np.array_equal(b1, b0), name
+            off += n + co
+        assert off == g0.size and seen == (folded if fold else set())
+
+    got = {}
+    with nn.Denoiser(channels, shape) as d:
+        d.set_params(flat)
+        for on in (False, True, False, True):
+            nfold = d.set_fused_backward(on)
+            print(f"[gpu] fused backward {on}: {nfold} folded layers", flush=True)
+            assert nfold == (2 if on else 0)
+            loss = d.loss_grad(x, y)
+            g = d.grads()
+            if on in got:  # the same call again
+                assert loss == pytest.approx(got[on][0], rel=1e-12)
+                compare(g, got[on][1], False)
+            got[on] = (loss, g)
+    assert got[True][0] == pytest.approx(got[False][0], rel=1e-12)
+    compare(got[True][1], got[False][1], True)
+
+
 def test_adam_step_matches_oracle():
     t = torch()
     channels, shape = (4, 8), (8, 8, 8)
