@@ -383,7 +383,12 @@ __global__ void __launch_bounds__(256) conv3_brick_kernel(ConvArgs a) {
 // weights of output channel n likewise at n * 64 bytes, chunk j in slot
 // j ^ ((n >> 2) & 3).
 constexpr int kResPlane = 36 * 64;  // bytes per plane slot
-__device__ __align__(16) uint4 g_zero16[1];  // the source of the zero padding
+// The source of the zero padding: 64 KB of zeros, each lane reading its
+// own 16 bytes (offset by workgroup and load), so that the zero chunks --
+// whole planes at z = -1 and z = d, and the volume's sides -- spread over
+// many cache lines instead of sending every compute unit to one address.
+constexpr int kZeroChunks = 4096;
+__device__ __align__(16) uint4 g_zero16[kZeroChunks];
 
 // Byte offset of byte `byte` of local voxel vl's outputs in an output tile
 // of the resident kernel (rows of NB 16 outputs of ES bytes).  For NB == 2
@@ -487,7 +492,8 @@ __global__ void __launch_bounds__(448) conv3_resident_kernel(ConvArgs a) {
         const int gx = bx + (pos[k] & 15) - 1, gy = by + (pos[k] >> 4) - 1;
         in = gx >= 0 && gy >= 0 && gx < a.in_w && gy < a.in_h;
       }
-      const uint16_t* src = in ? a.x + base + rel[k] : zero;
+      const uint16_t* src =
+          in ? a.x + base + rel[k] : zero + ((blockIdx.x * 192 + k * 64 + lane) & (kZeroChunks - 1)) * 8;
       __builtin_amdgcn_global_load_lds(
           (__attribute__((address_space(1))) void*)(src),
           (__attribute__((address_space(3))) void*)(slot + k * 1024), 16, 0, 0);
