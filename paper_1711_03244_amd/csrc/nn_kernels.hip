@@ -966,15 +966,20 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
 // of taps (the 9 taps t = 9 dz + 3 dy + dx) and 32 NBW output channels
 // (blockIdx.z), and walks the 4 x 4 x 4 voxel tiles blockIdx.x,
 // blockIdx.x + gridDim.x, ...  Per tile it stages the 4 x 6 x 6 slab of x
-// the plane's taps read (channels-last, zero outside the volume) and the
-// tile's gy transposed to [n][m]; wave w then accumulates the 16 input
-// channels 16 (w & 1).. and 16 NBW output channels of its half (w >> 1)
-// for all 9 taps, with the tile's 64 voxels on the MFMA's reduction axis
-// (two steps of 32).  The sums are stored to part[blockIdx.x][t][ci][n]
-// and wgrad_reduce_kernel adds them to gw in a fixed order.
+// the plane's taps read (zero outside the volume), transposed to channel
+// rows in three copies, one per tap column dx, each holding the 4 x
+// positions dx .. dx + 3 of every (z, y) row of the slab -- so that an A
+// fragment (8 voxels: two rows of 4 in x) is two aligned 8-byte reads --
+// and the tile's gy transposed to [n][m]; wave w then accumulates the 16
+// input channels 16 (w & 1).. and 16 NBW output channels of its half
+// (w >> 1) for all 9 taps, with the tile's 64 voxels on the MFMA's
+// reduction axis (two steps of 32).  The sums are stored to
+// part[blockIdx.x][t][ci][n] and wgrad_reduce_kernel adds them to gw in a
+// fixed order.
+constexpr int kSlabRow = 4 * 6 * 4 + 4;  // one channel's (z, y, 4 x) of a copy, padded
 template <int NBW>
 __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
-  __shared__ uint16_t sX[144][kBK + kPadK];          // slab voxel, channel of the chunk
+  __shared__ __align__(16) uint16_t sXT[3][32][kSlabRow];  // copy dx, channel, (z, y, x - dx)
   __shared__ uint16_t sG[32 * NBW][64 + kPadK];      // output channel, tile voxel
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1001,15 +1006,35 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
     const int by = ((tile / tx_n) % ty_n) * 4;
     const int bz = (tile / (tx_n * ty_n)) * 4;
     __syncthreads();  // the previous tile's fragments have been read
-    for (int i = tid; i < 144 * 4; i += 256) {
-      const int v = i >> 2, cc = (i & 3) * 8;
-      const int xx = v % 6, yy = (v / 6) % 6, zz = v / 36;
-      const int gx = bx + xx - 1, gy = by + yy - 1, gz = bz + zz + dz - 1;
-      uint4 val = make_uint4(0u, 0u, 0u, 0u);
-      if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.g.in_w && gy < a.g.in_h && gz < a.g.in_d)
-        val = *reinterpret_cast<const uint4*>(
-            a.x + ((static_cast<int64_t>(gz) * a.g.in_h + gy) * a.g.in_w + gx) * a.cin + c0 + cc);
-      *reinterpret_cast<uint4*>(&sX[v][cc]) = val;
+    // slab rows (z, y) x 8-channel chunks: the row's 6 voxels of the chunk,
+    // then for each channel its 4-voxel runs starting at x = 0, 1, 2
+    for (int it = tid; it < 4 * 6 * 4; it += 256) {
+      const int oc = it & 3, yy = (it >> 2) % 6, zz = (it >> 2) / 6;
+      const int gy = by + yy - 1, gz = bz + zz + dz - 1;
+      const bool row_in = gy >= 0 && gz >= 0 && gy < a.g.in_h && gz < a.g.in_d;
+      uint4 v[6];
+#pragma unroll
+      for (int xx = 0; xx < 6; ++xx) {
+        const int gx = bx + xx - 1;
+        v[xx] = make_uint4(0u, 0u, 0u, 0u);
+        if (row_in && gx >= 0 && gx < a.g.in_w)
+          v[xx] = *reinterpret_cast<const uint4*>(
+              a.x + ((static_cast<int64_t>(gz) * a.g.in_h + gy) * a.g.in_w + gx) * a.cin + c0 +
+              oc * 8);
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        uint32_t e[6];  // channel oc * 8 + c of the row's 6 voxels
+#pragma unroll
+        for (int xx = 0; xx < 6; ++xx) {
+          const uint32_t w32 = (&v[xx].x)[c >> 1];
+          e[xx] = (c & 1) ? (w32 >> 16) : (w32 & 0xffffu);
+        }
+#pragma unroll
+        for (int d0 = 0; d0 < 3; ++d0)
+          *reinterpret_cast<uint2*>(&sXT[d0][oc * 8 + c][(zz * 6 + yy) * 4]) =
+              make_uint2(e[d0] | (e[d0 + 1] << 16), e[d0 + 2] | (e[d0 + 3] << 16));
+      }
     }
     for (int i = tid; i < 64 * 4 * NBW; i += 256) {
       const int m = i / (4 * NBW), nc = (i % (4 * NBW)) * 8;
@@ -1041,7 +1066,8 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
       for (int j = 0; j < NBW; ++j)
         bf[ks][j] = *reinterpret_cast<const bf16x8*>(&sG[nw + 16 * j + r][32 * ks + 8 * g]);
     // A fragments: channel 16 cb + r of the slab at voxel m + tap offset,
-    // m = 32 ks + 8 g + j: x = j & 3, y = 2 (g & 1) + (j >> 2), z = 2 ks + (g >> 1)
+    // m = 32 ks + 8 g + j: x = j & 3, y = 2 (g & 1) + (j >> 2), z = 2 ks + (g >> 1);
+    // slab rows y0 + dy and y0 + dy + 1 of copy dx
     const int ci = cb * 16 + r;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
@@ -1050,13 +1076,10 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const int dy = t / 3, dx = t % 3;
-        const int base0 = (zz * 6 + y0 + dy) * 6 + dx;  // row y0: x = 0..3
-        bf16x8 af;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          af[j] = __builtin_bit_cast(__bf16, sX[base0 + j][ci]);
-          af[4 + j] = __builtin_bit_cast(__bf16, sX[base0 + 6 + j][ci]);
-        }
+        const uint16_t* row = &sXT[dx][ci][(zz * 6 + y0 + dy) * 4];
+        const uint2 lo = *reinterpret_cast<const uint2*>(row);
+        const uint2 hi = *reinterpret_cast<const uint2*>(row + 4);
+        const bf16x8 af = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
 #pragma unroll
         for (int j = 0; j < NBW; ++j)
           acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[ks][j], acc[t][j], 0, 0, 0);
