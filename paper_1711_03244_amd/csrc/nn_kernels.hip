@@ -964,23 +964,26 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
 // kConv3 layers with cin a multiple of 32.  A workgroup owns one chunk of 32
 // input channels (blockIdx.y % chunks), one plane dz = blockIdx.y / chunks
 // of taps (the 9 taps t = 9 dz + 3 dy + dx) and 32 NBW output channels
-// (blockIdx.z), and walks the 4 x 4 x 4 voxel tiles blockIdx.x,
-// blockIdx.x + gridDim.x, ...  Per tile it stages the 4 x 6 x 6 slab of x
+// (blockIdx.z), and walks the 4 x 4 x kSlabTZ voxel tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ...  Per tile it stages the kSlabTZ x 6 x 6 slab of x
 // the plane's taps read (zero outside the volume), transposed to channel
 // rows in three copies, one per tap column dx, each holding the 4 x
 // positions dx .. dx + 3 of every (z, y) row of the slab -- so that an A
 // fragment (8 voxels: two rows of 4 in x) is two aligned 8-byte reads --
 // and the tile's gy transposed to [n][m]; wave w then accumulates the 16
 // input channels 16 (w & 1).. and 16 NBW output channels of its half
-// (w >> 1) for all 9 taps, with the tile's 64 voxels on the MFMA's
-// reduction axis (two steps of 32).  The sums are stored to
+// (w >> 1) for all 9 taps, with the tile's 16 kSlabTZ voxels on the MFMA's
+// reduction axis (kSlabTZ / 2 steps of 32: tiles of 8 z-slices halve the
+// staging round trips -- global loads, the transpose, two barriers -- per
+// matrix instruction against 4).  The sums are stored to
 // part[blockIdx.x][t][ci][n] and wgrad_reduce_kernel adds them to gw in a
 // fixed order.
-constexpr int kSlabRow = 4 * 6 * 4 + 4;  // one channel's (z, y, 4 x) of a copy, padded
+constexpr int kSlabTZ = 8;                     // z-slices per tile
+constexpr int kSlabRow = kSlabTZ * 6 * 4 + 4;  // one channel's (z, y, 4 x) of a copy, padded
 template <int NBW>
 __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
   __shared__ __align__(16) uint16_t sXT[3][32][kSlabRow];  // copy dx, channel, (z, y, x - dx)
-  __shared__ uint16_t sG[32 * NBW][64 + kPadK];      // output channel, tile voxel
+  __shared__ uint16_t sG[32 * NBW][16 * kSlabTZ + kPadK];  // output channel, tile voxel
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -991,7 +994,7 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
   const int n0 = static_cast<int>(blockIdx.z) * 32 * NBW;
   const int cb = wave & 1;
   const int nw = (wave >> 1) * 16 * NBW;  // this wave's first channel within the group
-  const int tx_n = (a.w + 3) >> 2, ty_n = (a.h + 3) >> 2, tz_n = (a.d + 3) >> 2;
+  const int tx_n = (a.w + 3) >> 2, ty_n = (a.h + 3) >> 2, tz_n = (a.d + kSlabTZ - 1) / kSlabTZ;
   const int tiles = tx_n * ty_n * tz_n;
   const int P = a.taps * a.cin;
 
@@ -1004,11 +1007,11 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int bx = (tile % tx_n) * 4;
     const int by = ((tile / tx_n) % ty_n) * 4;
-    const int bz = (tile / (tx_n * ty_n)) * 4;
+    const int bz = (tile / (tx_n * ty_n)) * kSlabTZ;
     __syncthreads();  // the previous tile's fragments have been read
     // slab rows (z, y) x 8-channel chunks: the row's 6 voxels of the chunk,
     // then for each channel its 4-voxel runs starting at x = 0, 1, 2
-    for (int it = tid; it < 4 * 6 * 4; it += 256) {
+    for (int it = tid; it < kSlabTZ * 6 * 4; it += 256) {
       const int oc = it & 3, yy = (it >> 2) % 6, zz = (it >> 2) / 6;
       const int gy = by + yy - 1, gz = bz + zz + dz - 1;
       const bool row_in = gy >= 0 && gz >= 0 && gy < a.g.in_h && gz < a.g.in_d;
@@ -1036,7 +1039,7 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
               make_uint2(e[d0] | (e[d0 + 1] << 16), e[d0 + 2] | (e[d0 + 3] << 16));
       }
     }
-    for (int i = tid; i < 64 * 4 * NBW; i += 256) {
+    for (int i = tid; i < 16 * kSlabTZ * 4 * NBW; i += 256) {
       const int m = i / (4 * NBW), nc = (i % (4 * NBW)) * 8;
       const int x = bx + (m & 3), y = by + ((m >> 2) & 3), z = bz + (m >> 4);
       uint16_t e[8];
@@ -1059,9 +1062,9 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
     }
     __syncthreads();
     // B fragments: voxels 32 ks + 8 g .. + 7 of output channel nw + 16 j + r
-    bf16x8 bf[2][NBW];
+    bf16x8 bf[kSlabTZ / 2][NBW];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
+    for (int ks = 0; ks < kSlabTZ / 2; ++ks)
 #pragma unroll
       for (int j = 0; j < NBW; ++j)
         bf[ks][j] = *reinterpret_cast<const bf16x8*>(&sG[nw + 16 * j + r][32 * ks + 8 * g]);
@@ -1070,7 +1073,7 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
     // slab rows y0 + dy and y0 + dy + 1 of copy dx
     const int ci = cb * 16 + r;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
+    for (int ks = 0; ks < kSlabTZ / 2; ++ks) {
       const int zz = 2 * ks + (g >> 1);
       const int y0 = 2 * (g & 1);
 #pragma unroll
@@ -1731,7 +1734,8 @@ int slab_nbw(const WgradArgs& a) { return a.cout > 32 ? 2 : 1; }
 // workgroups along the voxel tiles: about kSlabTargetGroups in all, at most
 // one per tile, with the partial sums within `cap` floats
 int slab_groups(const WgradArgs& a, int64_t cap) {
-  const int64_t tiles = static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + 3) / 4);
+  const int64_t tiles =
+      static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + kSlabTZ - 1) / kSlabTZ);
   const int nbw = slab_nbw(a);
   const int64_t other = static_cast<int64_t>(a.cin / kBK) * 3 * ((a.cout + 32 * nbw - 1) / (32 * nbw));
   int64_t G = std::min<int64_t>(tiles, (kSlabTargetGroups + other - 1) / other);
