@@ -1731,14 +1731,16 @@ int onechannel_groups(const WgradArgs& a, int64_t cap) {
 }
 int slab_nbw(const WgradArgs& a) { return a.cout > 32 ? 2 : 1; }
 
-// workgroups along the voxel tiles: about kSlabTargetGroups in all, at most
-// one per tile, with the partial sums within `cap` floats
+// workgroups along the voxel tiles: about kSlabKernelGroups in all (three
+// per CU: the slab kernel's loads are latency-bound), at most one per tile,
+// with the partial sums within `cap` floats
+constexpr int64_t kSlabKernelGroups = 768;
 int slab_groups(const WgradArgs& a, int64_t cap) {
   const int64_t tiles =
       static_cast<int64_t>((a.w + 3) / 4) * ((a.h + 3) / 4) * ((a.d + kSlabTZ - 1) / kSlabTZ);
   const int nbw = slab_nbw(a);
   const int64_t other = static_cast<int64_t>(a.cin / kBK) * 3 * ((a.cout + 32 * nbw - 1) / (32 * nbw));
-  int64_t G = std::min<int64_t>(tiles, (kSlabTargetGroups + other - 1) / other);
+  int64_t G = std::min<int64_t>(tiles, (kSlabKernelGroups + other - 1) / other);
   const int64_t per = static_cast<int64_t>(a.taps) * a.cin * a.cout;
   while (G > 1 && G * per > cap) G = (G + 1) / 2;
   return static_cast<int>(G < 1 ? 1 : G);
