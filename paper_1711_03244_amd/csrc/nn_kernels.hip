@@ -1357,13 +1357,17 @@ __global__ void __launch_bounds__(256) relu_grad_kernel(const float* g, const ui
     s += from_bf16(h);
   }
   if (!partial) return;
+  // thread j's sums are of channel j % cout (cout a power of two dividing
+  // 256): halve the block's 256 sums down to cout, pairing threads of one
+  // channel (a tree, not one thread adding 256 / cout values in a row)
   sh[threadIdx.x] = s;
   __syncthreads();
-  if (static_cast<int>(threadIdx.x) < cout) {
-    float t = 0.f;
-    for (int j = threadIdx.x; j < 256; j += cout) t += sh[j];
-    partial[static_cast<int64_t>(blockIdx.x) * cout + threadIdx.x] = t;
+  for (int off = 128; off >= cout; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
   }
+  if (static_cast<int>(threadIdx.x) < cout)
+    partial[static_cast<int64_t>(blockIdx.x) * cout + threadIdx.x] = sh[threadIdx.x];
 }
 
 // gb[c] += sum over blocks of partial[block][c]; one workgroup per channel
@@ -1866,10 +1870,13 @@ hipError_t launch_from_log(const float* r, const float* u, int64_t n, float* out
 hipError_t launch_mse(const float* out, const float* target_u, const float* target_phi,
                       float rel_floor, int64_t n, float* grad, double* acc, float* phi_max,
                       hipStream_t s) {
+  // at most 128 blocks: each ends with atomics on one address (one per
+  // block for the maximum, two for the sums), which the memory side takes
+  // one at a time
   zero2_kernel<<<1, 1, 0, s>>>(acc, phi_max);
-  max_kernel<<<blocks_for(n, 256, 1024), 256, 0, s>>>(target_phi, n, phi_max);
-  mse_kernel<<<blocks_for(n, 256, 1024), 256, 0, s>>>(out, target_u, target_phi, rel_floor,
-                                                     phi_max, n, grad, acc);
+  max_kernel<<<blocks_for(n, 256, 128), 256, 0, s>>>(target_phi, n, phi_max);
+  mse_kernel<<<blocks_for(n, 256, 128), 256, 0, s>>>(out, target_u, target_phi, rel_floor,
+                                                    phi_max, n, grad, acc);
   scale_grad_kernel<<<blocks_for(n), 256, 0, s>>>(grad, n, acc);
   return hipGetLastError();
 }

@@ -459,10 +459,15 @@ def time_passes(den: nn.Denoiser, side: int, reps: int = 50, seed: int = 900001)
     r = {"forward_ms": timed(lambda: den.forward(x, phi_out=out, stream=s), reps),
          "forward_8_symmetries_ms": timed(
              lambda: den.forward(x, phi_out=out, stream=s, symmetries=8), max(1, reps // 4))}
-    for fused in (False, True):
+    # the two backward modes alternately, twice each (clock drift over a
+    # run otherwise favours whichever is timed second)
+    times = {True: [], False: []}
+    for fused in (False, True, True, False):
         den.set_fused_backward(fused)
-        key = "loss_grad_ms" if fused else "loss_grad_unfused_ms"
-        r[key] = timed(lambda: den.loss_grad(x, y, want_loss=False, stream=s), reps)
+        times[fused].append(timed(lambda: den.loss_grad(x, y, want_loss=False, stream=s), reps))
+    den.set_fused_backward(True)
+    r["loss_grad_ms"] = float(np.mean(times[True]))
+    r["loss_grad_unfused_ms"] = float(np.mean(times[False]))
     return r
 
 
