@@ -1004,33 +1004,65 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
 #pragma unroll
     for (int j = 0; j < NBW; ++j) acc[t][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+  // This thread's staging loads of one tile, held in registers so that the
+  // next tile's loads are in flight while the current one is computed:
+  // slab item tid (< kSlabTZ * 6 * 4): one (z, y) row of the slab and
+  // 8-channel chunk, its 6 voxels; output-gradient items tid + 256 u: one
+  // voxel of the tile and 8 output channels.
+  constexpr int kXI = kSlabTZ * 6 * 4;
+  constexpr int kGI = 16 * kSlabTZ * 4 * NBW / 256;
+  static_assert(kXI <= 256 && kGI * 256 == 16 * kSlabTZ * 4 * NBW, "staging items per thread");
+  uint4 xv[6], gv[kGI];
+  auto load = [&](int tile) {
     const int bx = (tile % tx_n) * 4;
     const int by = ((tile / tx_n) % ty_n) * 4;
     const int bz = (tile / (tx_n * ty_n)) * kSlabTZ;
-    __syncthreads();  // the previous tile's fragments have been read
-    // slab rows (z, y) x 8-channel chunks: the row's 6 voxels of the chunk,
-    // then for each channel its 4-voxel runs starting at x = 0, 1, 2
-    for (int it = tid; it < kSlabTZ * 6 * 4; it += 256) {
-      const int oc = it & 3, yy = (it >> 2) % 6, zz = (it >> 2) / 6;
+    if (tid < kXI) {
+      const int oc = tid & 3, yy = (tid >> 2) % 6, zz = (tid >> 2) / 6;
       const int gy = by + yy - 1, gz = bz + zz + dz - 1;
       const bool row_in = gy >= 0 && gz >= 0 && gy < a.g.in_h && gz < a.g.in_d;
-      uint4 v[6];
 #pragma unroll
       for (int xx = 0; xx < 6; ++xx) {
         const int gx = bx + xx - 1;
-        v[xx] = make_uint4(0u, 0u, 0u, 0u);
+        xv[xx] = make_uint4(0u, 0u, 0u, 0u);
         if (row_in && gx >= 0 && gx < a.g.in_w)
-          v[xx] = *reinterpret_cast<const uint4*>(
+          xv[xx] = *reinterpret_cast<const uint4*>(
               a.x + ((static_cast<int64_t>(gz) * a.g.in_h + gy) * a.g.in_w + gx) * a.cin + c0 +
               oc * 8);
       }
+    }
+#pragma unroll
+    for (int u = 0; u < kGI; ++u) {
+      const int i = tid + 256 * u;
+      const int m = i / (4 * NBW), nc = (i % (4 * NBW)) * 8;
+      const int x = bx + (m & 3), y = by + ((m >> 2) & 3), z = bz + (m >> 4);
+      gv[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (x < a.w && y < a.h && z < a.d) {
+        const uint16_t* row =
+            a.gy + ((static_cast<int64_t>(z) * a.h + y) * a.w + x) * a.cout + n0 + nc;
+        if (a.cout % 8 == 0 && n0 + nc + 8 <= a.cout) {
+          gv[u] = *reinterpret_cast<const uint4*>(row);
+        } else {
+          uint32_t h[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) h[j] = (n0 + nc + j < a.cout) ? row[j] : 0u;
+          gv[u] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                             h[6] | (h[7] << 16));
+        }
+      }
+    }
+  };
+  // the registers into LDS: each channel of the slab row as its 4-voxel runs
+  // starting at x = 0, 1, 2; the output gradient transposed to [n][m]
+  auto store = [&]() {
+    if (tid < kXI) {
+      const int oc = tid & 3, yy = (tid >> 2) % 6, zz = (tid >> 2) / 6;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         uint32_t e[6];  // channel oc * 8 + c of the row's 6 voxels
 #pragma unroll
         for (int xx = 0; xx < 6; ++xx) {
-          const uint32_t w32 = (&v[xx].x)[c >> 1];
+          const uint32_t w32 = (&xv[xx].x)[c >> 1];
           e[xx] = (c & 1) ? (w32 >> 16) : (w32 & 0xffffu);
         }
 #pragma unroll
@@ -1039,28 +1071,24 @@ __global__ void __launch_bounds__(256) wgrad_slab_kernel(WgradArgs a) {
               make_uint2(e[d0] | (e[d0 + 1] << 16), e[d0 + 2] | (e[d0 + 3] << 16));
       }
     }
-    for (int i = tid; i < 16 * kSlabTZ * 4 * NBW; i += 256) {
+#pragma unroll
+    for (int u = 0; u < kGI; ++u) {
+      const int i = tid + 256 * u;
       const int m = i / (4 * NBW), nc = (i % (4 * NBW)) * 8;
-      const int x = bx + (m & 3), y = by + ((m >> 2) & 3), z = bz + (m >> 4);
-      uint16_t e[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) e[j] = 0;
-      if (x < a.w && y < a.h && z < a.d) {
-        const uint16_t* row =
-            a.gy + ((static_cast<int64_t>(z) * a.h + y) * a.w + x) * a.cout + n0 + nc;
-        if (a.cout % 8 == 0 && n0 + nc + 8 <= a.cout) {
-          const uint4 q = *reinterpret_cast<const uint4*>(row);
-          e[0] = q.x & 0xffff; e[1] = q.x >> 16; e[2] = q.y & 0xffff; e[3] = q.y >> 16;
-          e[4] = q.z & 0xffff; e[5] = q.z >> 16; e[6] = q.w & 0xffff; e[7] = q.w >> 16;
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) e[j] = (n0 + nc + j < a.cout) ? row[j] : 0;
-        }
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t w32 = (&gv[u].x)[j >> 1];
+        sG[nc + j][m] = static_cast<uint16_t>((j & 1) ? (w32 >> 16) : (w32 & 0xffffu));
       }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) sG[nc + j][m] = e[j];
     }
+  };
+
+  if (static_cast<int>(blockIdx.x) < tiles) load(blockIdx.x);
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    __syncthreads();  // the previous tile's fragments have been read
+    store();
     __syncthreads();
+    if (tile + static_cast<int>(gridDim.x) < tiles) load(tile + gridDim.x);
     // B fragments: voxels 32 ks + 8 g .. + 7 of output channel nw + 16 j + r
     bf16x8 bf[kSlabTZ / 2][NBW];
 #pragma unroll
