@@ -23,7 +23,8 @@ the kernel's HIP-event time) attached, and the kernel's HBM traffic against
 its algorithmic bytes; `cpu_baseline` the FP64 oracle on the host cores
 available to this process over a prefix of the same photons, best of 3.  The launch shape of the timed steps is the one the library's
 autotuner picks (before the timed region) from pilot launches of 1/20 of the
-photons; the rate of the default shape is reported beside it.  Two further workloads are reported beside the main one, each
+photons, with the kind of map add decided by one untimed full-size run of
+each; the rate of the default shape is reported beside it.  Two further workloads are reported beside the main one, each
 timed once after a warm-up launch: `head_volume` (the seeded 181 x 217 x
 181 layered head phantom, 10 gates of 0.5 ns, 1e8 photons) and `batched`
 (256 generated cubes of 32-128 mm with 1-3 inclusions and 1e5-1e7 photons
@@ -137,8 +138,9 @@ def main():
         default_rate = N / sim.stats()["kernel_ms"]
         t_tune = time.perf_counter()
         tune = sim.autotune(max(1000, N // 20), args.seed + 3000)
+        adds_note = map_adds_at_full_size(mcx, sim, N, args.seed + 4000)
         chosen_by = (f"autotuner, {tune['candidates']} shapes, pilots of {N // 20} photons, "
-                     f"{time.perf_counter() - t_tune:.1f} s before the timed steps")
+                     f"{time.perf_counter() - t_tune:.1f} s before the timed steps; {adds_note}")
 
     def step(i):
         mcx.mcx_reset(sim.ctx)
@@ -334,6 +336,22 @@ def cube1_leg(mcx, W):
                                       "photons_per_ms": (N // 10) / base["kernel_ms"]}}
 
 
+def map_adds_at_full_size(mcx, sim, N, seed):
+    """The kind of map add for the timed runs, from one untimed run of N
+    photons with each kind at the tuned shape: on the autotuner's short
+    pilots the two kinds come within timing noise of each other, at full
+    size they do not (sphere: 32-bit adds ahead; head phantom: 64-bit)."""
+    ms = {}
+    for kind in (mcx.MAP_ADDS_32, mcx.MAP_ADDS_64):
+        sim.set_map_adds(kind)
+        sim.run(N, seed)
+        ms[kind] = sim.stats()["kernel_ms"]
+    kind = min(ms, key=ms.get)
+    sim.set_map_adds(kind)
+    return (f"map adds from one full-size run of each kind: 32-bit {ms[mcx.MAP_ADDS_32]:.1f} ms, "
+            f"64-bit {ms[mcx.MAP_ADDS_64]:.1f} ms")
+
+
 def head_leg(mcx, roofline, W, N, seed, launch=None):
     p = W.head_phantom(1)
     with mcx.Simulation(p) as sim:
@@ -349,6 +367,7 @@ def head_leg(mcx, roofline, W, N, seed, launch=None):
             sim.run(N // 100, seed + 1000)  # warm-up
             _, default_med, _ = best_median(mcx, sim, N, [seed, seed + 1, seed + 2])
             tune = sim.autotune(max(1000, N // 50), seed + 3000)
+            map_adds_at_full_size(mcx, sim, N, seed + 4000)
         best, med, runs = best_median(mcx, sim, N, [seed, seed + 1, seed + 2])
         st = runs[0]
     ksec = st["kernel_ms"] / 1e3

@@ -267,7 +267,9 @@ mcx_status mcx_shape_window(mcx_ctx *ctx, const uint64_t *pilot_photons, const u
  * global atomics, LDS window of 8192, 16384, 32768 or 36864 cells} (shapes that
  * do not fit on a compute unit are skipped; each timed with the map adds
  * MCX_MAP_ADDS_AUTO picks for it, and the four fastest again with the other
- * kind), keeps the fastest shape and map adds, and fits
+ * kind), keeps the fastest shape -- with the map adds MCX_MAP_ADDS_AUTO picks
+ * for it unless the other kind is more than 10 % faster over three alternate
+ * re-timings of both -- and fits
  * (single simulations without digests and with hardware math: the window boxes
  * are first shaped by a flush census -- one pilot counting, per map cell, the
  * cell visits the kernel adds to the map -- per gate the box grown from its

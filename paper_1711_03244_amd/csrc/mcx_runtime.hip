@@ -1418,8 +1418,32 @@ mcx_status mcx_autotune(mcx_ctx* c, const uint64_t* pilot_photons, const uint64_
     c->map_adds = MCX_MAP_ADDS_AUTO;
     timed.push_back(t);
   }
-  const Cand best = *std::min_element(
+  Cand best = *std::min_element(
       timed.begin(), timed.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+  // the kind of map add at that shape, from both kinds timed again three
+  // times, alternately: on pilots the two kinds are within the timing noise
+  // of each other where at full size the rule's kind is ahead (sphere
+  // benchmark, 1e8 photons: 32-bit adds 6.5 % faster; head phantom: 64-bit
+  // adds 7 % faster, where pilots had favoured 32-bit ones by 3 %), so the
+  // rule's kind stays unless the other is more than 10 % faster
+  if (mcx_set_launch(c, best.block, best.chunk, best.window) == MCX_OK) {
+    c->map_adds = MCX_MAP_ADDS_AUTO;
+    const int rule = map32(c) ? MCX_MAP_ADDS_32 : MCX_MAP_ADDS_64;
+    const int other = rule == MCX_MAP_ADDS_32 ? MCX_MAP_ADDS_64 : MCX_MAP_ADDS_32;
+    float t_rule = 3.4e38f, t_other = 3.4e38f;
+    for (int rep = 0; rep < 3; ++rep) {
+      c->map_adds = rule;
+      MCX_TRY(pilot(pilot_photons, &ms));
+      t_rule = std::min(t_rule, ms);
+      c->map_adds = other;
+      MCX_TRY(pilot(pilot_photons, &ms));
+      t_other = std::min(t_other, ms);
+    }
+    c->map_adds = MCX_MAP_ADDS_AUTO;
+    const bool keep = !(t_other < 0.90f * t_rule);
+    best.adds = keep ? rule : other;
+    best.ms = keep ? t_rule : t_other;
+  }
   out->block_size = best.block;
   out->refill_chunk = best.chunk;
   out->lds_window_cells = best.window;
